@@ -1,0 +1,164 @@
+"""Seeded synthetic inputs: initial lattices and parameter sets.
+
+This module holds no arithmetic of the method itself: it only places cells
+on a lattice and lists parameter values.  Both the GPU library's tests and the
+oracle's tests draw their inputs from here, so the two sides see the same
+initial states.  Random placement uses NumPy's PCG64 with the given seed.
+
+Lattice convention: int32, shape (Lz, Ly, Lx) (x fastest in memory), values
+-1 = obstacle, 0 = medium, 1..C = cells.  ``cell_type`` has C+1 entries;
+entry 0 is the medium type 0.
+"""
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+
+# Moore-26 interface count of the digitised ball x^2+y^2+z^2 <= 24 (485
+# voxels), the ball whose volume is nearest to 500 (the r^2 <= 25 ball has
+# 515 voxels; the tie is broken towards the smaller ball).  Checked by a test
+# against the oracle's recount.
+S_TARGET_BALL_V500 = 2690
+
+
+@dataclass
+class Workload:
+    """A lattice, its cells' types and the model parameters for one run."""
+    name: str
+    ndim: int
+    dims: tuple                 # (Lx, Ly, Lz); Lz = 1 in 2D
+    lattice: np.ndarray         # int32, shape (Lz, Ly, Lx)
+    cell_type: np.ndarray       # int32, C+1 entries
+    J: np.ndarray               # float64, n_types x n_types
+    lambda_V: np.ndarray
+    V_target: np.ndarray
+    lambda_S: np.ndarray
+    S_target: np.ndarray
+    T: float
+    n_mcs: int
+    seed: int = 1
+    lattice_id: int = 0
+    s: int = 2
+    k: int = 1
+    obstacle_type: int = -1
+    lambda_act: Optional[np.ndarray] = None
+    max_act: Optional[np.ndarray] = None
+    act: Optional[np.ndarray] = None   # uint8, same shape as lattice
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def n_cells(self) -> int:
+        return len(self.cell_type) - 1
+
+    @property
+    def n_sites(self) -> int:
+        return int(self.dims[0]) * int(self.dims[1]) * int(self.dims[2])
+
+
+def _two_type(j_cc, j_cm, lam_v, v_t, lam_s=0.0, s_t=0):
+    J = np.array([[0.0, j_cm], [j_cm, j_cc]])
+    return (J, np.array([0.0, lam_v]), np.array([0, v_t], dtype=np.int32),
+            np.array([0.0, lam_s]), np.array([0, s_t], dtype=np.int32))
+
+
+def squares_2d(L=100, n_cells=20, side=10, seed=1):
+    """n_cells squares of side `side` at seeded random non-overlapping
+    positions on an L x L periodic lattice (squares may wrap around)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    lat = np.zeros((L, L), dtype=np.int32)
+    placed = 0
+    tries = 0
+    while placed < n_cells:
+        tries += 1
+        if tries > 100000:
+            raise RuntimeError("could not place squares")
+        x0, y0 = rng.integers(0, L, size=2)
+        ys = (y0 + np.arange(side)) % L
+        xs = (x0 + np.arange(side)) % L
+        if np.any(lat[np.ix_(ys, xs)] != 0):
+            continue
+        placed += 1
+        lat[np.ix_(ys, xs)] = placed
+    return lat.reshape(1, L, L)
+
+
+def jittered_cubes(L=256, grid=27, edge=8, seed=1):
+    """grid^3 cubes of edge `edge` on an L^3 periodic lattice: cell (i,j,k)
+    sits in the box starting at floor(i*L/grid) (per axis), shifted by an
+    integer jitter drawn uniformly from [0, w - edge] where w is the box
+    width."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    starts = [(i * L) // grid for i in range(grid)] + [L]
+    widths = np.diff(starts)
+    if widths.min() < edge:
+        raise ValueError("cubes do not fit their grid boxes")
+    lat = np.zeros((L, L, L), dtype=np.int32)
+    cid = 0
+    for kz in range(grid):
+        for jy in range(grid):
+            for ix in range(grid):
+                cid += 1
+                jit = rng.integers(0, np.array([widths[ix], widths[jy], widths[kz]]) - edge + 1)
+                x0 = starts[ix] + jit[0]
+                y0 = starts[jy] + jit[1]
+                z0 = starts[kz] + jit[2]
+                lat[z0:z0 + edge, y0:y0 + edge, x0:x0 + edge] = cid
+    return lat
+
+
+def config0(seed=1):
+    """2D, 100x100 periodic, 20 cells as 10x10 squares, J(cell,cell)=20,
+    J(cell,medium)=10, lambda_V=50, V_target=100, T=20, 100 MCS."""
+    lat = squares_2d(100, 20, 10, seed)
+    J, lv, vt, ls, st = _two_type(20.0, 10.0, 50.0, 100)
+    return Workload("2d-100x100-20cells", 2, (100, 100, 1), lat,
+                    np.array([0] + [1] * 20, dtype=np.int32), J, lv, vt, ls, st,
+                    T=20.0, n_mcs=100, seed=seed)
+
+
+def config1(L=256, grid=27, seed=1, n_mcs=1000):
+    """3D, L^3 periodic, grid^3 cubes of 8^3 on a jittered grid,
+    J(cell,cell)=40, J(cell,medium)=20, lambda_V=25, V_target=500,
+    lambda_S=0.5, S_target=2690, T=20.  L=256, grid=27 is the full-size
+    workload (19,683 cells); smaller L / grid give the same structure for
+    quick parity runs."""
+    lat = jittered_cubes(L, grid, 8, seed)
+    n = grid ** 3
+    J, lv, vt, ls, st = _two_type(40.0, 20.0, 25.0, 500, 0.5, S_TARGET_BALL_V500)
+    return Workload(f"3d-{L}^3-{n}cells", 3, (L, L, L), lat,
+                    np.array([0] + [1] * n, dtype=np.int32), J, lv, vt, ls, st,
+                    T=20.0, n_mcs=n_mcs, seed=seed)
+
+
+def random_labels(dims, n_labels, seed, p_obstacle=0.0):
+    """Uniform random labels 0..n_labels-1 (and -1 with probability
+    p_obstacle): a maximally rough state that exercises every branch."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    Lx, Ly, Lz = dims
+    lat = rng.integers(0, n_labels, size=(Lz, Ly, Lx)).astype(np.int32)
+    if p_obstacle > 0:
+        lat[rng.random(lat.shape) < p_obstacle] = -1
+    return lat
+
+
+def random_blobs(dims, n_cells, seed, fill=0.6, p_obstacle=0.0):
+    """Cells grown as random boxes on a medium background: realistic
+    interfaces at small sizes.  Boxes may overlap; later ones overwrite."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    Lx, Ly, Lz = dims
+    lat = np.zeros((Lz, Ly, Lx), dtype=np.int32)
+    n_sites = Lx * Ly * Lz
+    per = max(1, int(fill * n_sites / max(n_cells, 1)))
+    edge = max(1, int(round(per ** (1.0 / (3 if Lz > 1 else 2)))))
+    for c in range(1, n_cells + 1):
+        x0, y0, z0 = rng.integers(0, Lx), rng.integers(0, Ly), rng.integers(0, Lz)
+        ex = rng.integers(max(1, edge - 1), edge + 2)
+        ey = rng.integers(max(1, edge - 1), edge + 2)
+        ez = rng.integers(max(1, edge - 1), edge + 2) if Lz > 1 else 1
+        xs = (x0 + np.arange(ex)) % Lx
+        ys = (y0 + np.arange(ey)) % Ly
+        zs = (z0 + np.arange(ez)) % Lz
+        lat[np.ix_(zs, ys, xs)] = c
+    if p_obstacle > 0:
+        lat[(lat == 0) & (rng.random(lat.shape) < p_obstacle)] = -1
+    return lat
