@@ -1,0 +1,144 @@
+"""Benchmark: site copy-attempts per second of the CPM sweep on one MI355X.
+
+Workload: 3D 256^3 periodic lattice, 19,683 cells seeded as 8^3 cubes on a
+jittered 27^3 grid, Moore-26 neighbourhood, J(cell,cell)=40, J(cell,medium)=20,
+lambda_V=25, V_target=500, lambda_S=0.5, S_target=2690, T=20, checkerboard
+scheme with s=2 (4^3 thread areas, 2x2x2 colours), k=1, Philox seed 1.
+
+One step = one Monte Carlo step (MCS) = 256^3 copy attempts = 64
+activations.  W warm-up steps, then K timed steps (default K=1000, the full
+1000-MCS run), bracketed by device synchronisation; the tracked cell
+volumes / surfaces are recounted from the lattice once at the end of the
+timed region.  Inputs are resident in HBM before timing starts.
+
+Prints one JSON line.  Also reports the roofline position of the dominant
+kernel (the activation kernel) and the CPU oracle's throughput on a bounded
+sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "site copy-attempts/s on 3D 256³ (HBM % peak); emulator vs CPM cost per point"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def bytes_per_attempt(ndim, s, k, p_acc):
+    # per activation each thread area stages the halo box of its active
+    # sub-area, (s+2)^d int32 sites, which at s = 2 is the whole (2s)^d area,
+    # and writes back its accepted copy
+    f = min(1.0, (s + 2.0) / (2.0 * s)) ** ndim
+    return 4.0 * f * (2 * s) ** ndim / k + 4.0 * p_acc
+
+
+def cpu_baseline(w, n_mcs):
+    import oracle
+    m = oracle.Model(w.ndim, w.dims[:w.ndim], w.J, w.lambda_V, w.V_target, w.lambda_S, w.S_target,
+                     T=w.T, seed=w.seed, s=w.s, k=w.k)
+    st = oracle.State(m, w.lattice, w.cell_type)
+    t0 = time.perf_counter()
+    st.sweep(n_mcs)
+    dt = time.perf_counter() - t0
+    attempts = int(st.stats[0])
+    return {"value": attempts / dt, "unit": "attempts/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n_mcs} MCS of the same 256^3 workload ({attempts} attempts, "
+                      f"{dt:.1f} s, one thread, initial recount excluded)",
+            "p_acc": float(st.stats[2]) / max(1, attempts)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--cpu-mcs", type=int, default=4, help="MCS of the oracle sample (0 to skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        log("bench.py runs on one GPU only: the sweep is not sharded across GPUs")
+        sys.exit(2)
+
+    import torch
+    from paper_2312_09317_amd import cpm, inputs
+
+    if not torch.cuda.is_available():
+        log("bench.py needs a GPU")
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    w = inputs.config1(n_mcs=args.steps)
+    log(f"workload {w.name}: {w.n_sites} sites, {w.n_cells} cells")
+    sim = cpm.Simulation(cpm.Params.from_workload(w), w.lattice, w.cell_type, device="cuda:0")
+    torch.cuda.synchronize()
+    sim.sweep(args.warmup)
+    torch.cuda.synchronize()
+    log(f"warm-up done ({args.warmup} MCS)")
+
+    n_act = (2 * w.s) ** w.ndim // w.k
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev2 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    sim.sweep(args.steps)
+    ev1.record()
+    v, s, c = sim.cell_stats(centroids=True)
+    ev2.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sweep_ms = ev0.elapsed_time(ev1)
+    total_ms = ev0.elapsed_time(ev2)
+    log(f"timed {args.steps} MCS: {total_ms:.1f} ms (sweep {sweep_ms:.1f} ms, wall {wall * 1e3:.1f} ms)")
+
+    # sanity: tracked counters equal the recount
+    tv, ts = sim.counters()
+    torch.cuda.synchronize()
+    if not (torch.equal(tv[1:], v[1:]) and torch.equal(ts[1:], s[1:])):
+        log("ERROR: tracked counters differ from the lattice recount")
+        sys.exit(3)
+
+    attempts = args.steps * w.n_sites
+    value = attempts / (total_ms / 1e3)
+    cpu = cpu_baseline(w, args.cpu_mcs) if args.cpu_mcs > 0 else None
+    p_acc = cpu["p_acc"] if cpu else 0.0
+    launches = args.steps * n_act
+    avg_launch_s = (sweep_ms / 1e3) / launches
+    per_launch_bytes = bytes_per_attempt(w.ndim, w.s, w.k, p_acc) * (w.n_sites // n_act)
+    achieved = per_launch_bytes / avg_launch_s / 1e9
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "attempts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": total_ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "lattice": list(w.dims), "n_cells": w.n_cells, "sub": w.s,
+                   "attempts_per_activation": w.k, "mcs_per_step": 1, "activations_per_mcs": n_act,
+                   "temperature": w.T, "seed": w.seed},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "activation_kernel", "avg_launch_us": avg_launch_s * 1e6,
+                     "bytes_per_attempt": bytes_per_attempt(w.ndim, w.s, w.k, p_acc)},
+        "cpu_baseline": {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")} if cpu else None,
+    }
+    print(json.dumps(out), flush=True)
+    sim.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,164 @@
+/*
+ * cpm.h - C ABI of the MI355X cellular Potts model sweep library (libcpm.so).
+ *
+ * The library advances a cellular Potts model (CPM) lattice by Monte Carlo
+ * steps (MCS) under the checkerboard parallel update scheme of Sultan, Devi,
+ * Mueller & Textor (2023), "A parallelized cellular Potts model that enables
+ * simulations at tissue scale", on an AMD Instinct MI355X (gfx950).
+ *
+ * Model (paper, Methods):
+ *   H = sum_{i,j Moore neighbours} J(tau(sigma_i), tau(sigma_j)) (1 - delta(sigma_i, sigma_j))
+ *     + sum_sigma lambda_V(tau) (V(sigma) - V_t(tau))^2                           (eq. 1)
+ *     + sum_sigma lambda_S(tau) (S(sigma) - S_t(tau))^2                           (eq. 3)
+ *   with S(sigma) the number of (site of sigma, Moore neighbour not of sigma)
+ *   pairs; optional Act term dH_act (eq. 7) with the geometric mean of eq. 8.
+ *   A copy attempt at site t from a Moore neighbour is accepted with
+ *   probability 1 if dH <= 0, else exp(-dH/T) (eq. 2).
+ *
+ * Parallel scheme (paper, Results, "Designing a parallel execution scheme"
+ * and "Aligning the lattice update statistics"; Fig. 2A-B, Fig. 3):
+ *   the lattice is cut into thread areas of edge 2s; each area holds 2^d
+ *   sub-areas of edge s, one per colour.  One MCS is (2s)^d / k activations;
+ *   activation a activates colour a mod 2^d and every area makes k copy
+ *   attempts inside its sub-area of that colour.  All attempts of one
+ *   activation read the per-cell volume / surface counters as they stood at
+ *   the start of the activation (plus the attempting thread's own earlier
+ *   deltas); all accepted copies' deltas are summed into the counters before
+ *   the next activation, so tracked volumes always equal lattice counts.
+ *
+ * Determinism: every copy attempt draws its random numbers from Philox4x32-10
+ * (Salmon et al., SC'11) with key (seed lo, seed hi) and counter
+ * (area index, MCS, activation << 8 | attempt, lattice_id).  Results depend
+ * only on the initial state, the quantised parameters, s, k, seed, lattice_id
+ * and the MCS counter - never on launch geometry or timing - and equal, bit
+ * for bit, those of a serial run of the same scheme.
+ *
+ * Fixed point: energies are int64 in units of 2^-16; every energy parameter
+ * (J, lambda_*) is rounded half away from zero to that grid at init.
+ * Acceptance compares a uniform 32-bit draw u with
+ * THR(q) = floor(TI[h] * TM[m] * TL[l] / 2^64), q = dH * 2^16 = h*2^16 + m*2^8 + l,
+ * TI[h] = floor(2^32 exp(-h/T)), TM[m] = floor(2^32 exp(-m/(256 T))),
+ * TL[l] = floor(2^32 exp(-l/(65536 T))), built in FP64 on the host;
+ * accept iff q <= 0 or u < THR(q).
+ *
+ * Memory: every device buffer (lattice, cell types, activity, workspace,
+ * outputs) is allocated and owned by the caller (e.g. as torch tensors) and
+ * borrowed by the handle until cpm_destroy.  The library allocates no device
+ * memory.  The handle owns host state only.
+ *
+ * Streams: calls taking `stream` (a hipStream_t) enqueue work on it and
+ * return without waiting; the caller synchronises.  Calls on one handle must
+ * be issued on one stream (or be ordered by the caller).
+ *
+ * Errors: every call returns CPM_OK (0) or a CPM_E* code; cpm_last_error()
+ * returns a thread-local message for the last failure.  No call aborts or
+ * throws across the ABI.  A failed call leaves the handle usable unless it
+ * returned CPM_EDEVICE.
+ */
+#ifndef CPM_H
+#define CPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CPM_OK 0
+#define CPM_EINVAL 1  /* invalid argument: dims, s, k, labels, null pointers */
+#define CPM_ERANGE 2  /* a fixed-point energy could overflow int64 */
+#define CPM_ENOMEM 3  /* workspace smaller than cpm_workspace_bytes() */
+#define CPM_EDEVICE 4 /* HIP runtime error */
+#define CPM_ENOTSUP 5 /* valid model this build does not run */
+
+#define CPM_MAX_TYPES 16
+
+/*
+ * Model and scheme description.  All pointers are host memory, read during
+ * cpm_validate / cpm_workspace_bytes / cpm_init only.
+ *
+ * Lattice values: -1 = static obstacle (never copied, never overwritten),
+ * 0 = medium, 1..n_cells = cells.  Type 0 is the medium's type.
+ */
+typedef struct cpm_params {
+    int32_t ndim;          /* 2 or 3 */
+    int32_t dims[3];       /* Lx, Ly, Lz; Lz = 1 when ndim == 2; each divisible by 2*sub */
+    int32_t sub;           /* s, sub-area edge (>= 1; >= 2 when act_enabled) */
+    int32_t attempts;      /* k, copy attempts per thread area per activation; divides s^ndim */
+    int32_t n_types;       /* 1..CPM_MAX_TYPES, including the medium type 0 */
+    int32_t obstacle_type; /* type used for J against obstacle sites; -1 if the lattice has none */
+    double temperature;    /* T > 0 (eq. 2) */
+    uint64_t seed;         /* Philox key */
+    uint32_t lattice_id;   /* fourth Philox counter word: tells replicate lattices apart */
+    int32_t act_enabled;   /* 1: Act term (eq. 7-8) and activity bookkeeping */
+    const double *J;              /* n_types * n_types, row-major, symmetric */
+    const double *lambda_volume;  /* n_types */
+    const int32_t *volume_target; /* n_types */
+    const double *lambda_surface; /* n_types (may be NULL: no surface term) */
+    const int32_t *surface_target;/* n_types (may be NULL when lambda_surface is NULL) */
+    const double *lambda_act;     /* n_types (read when act_enabled) */
+    const int32_t *max_act;       /* n_types, 0..255; a type is motile iff max_act > 0 */
+} cpm_params;
+
+typedef struct cpm_handle cpm_handle;
+
+/* Checks a model description without touching any device.  n_cells is the
+ * largest cell label.  Returns CPM_OK, CPM_EINVAL, CPM_ERANGE or
+ * CPM_ENOTSUP. */
+int cpm_validate(const cpm_params *params, int32_t n_cells);
+
+/* Device workspace size (bytes) cpm_init needs for this model; host only. */
+int cpm_workspace_bytes(const cpm_params *params, int32_t n_cells, size_t *bytes);
+
+/*
+ * Binds a lattice to a new handle and counts every cell's volume and surface
+ * from the lattice (the counters the sweep then keeps exact).
+ *   d_lattice   int32[Lz][Ly][Lx] device, read/write; labels in [-1, n_cells]
+ *   d_cell_type int32[n_cells + 1] device, read only; entry 0 must be 0
+ *   d_act       uint8[Lz][Ly][Lx] device activity field when act_enabled,
+ *               else NULL; read/write
+ *   d_workspace device buffer of at least cpm_workspace_bytes(), 256-byte
+ *               aligned, contents arbitrary; owned by the library until
+ *               cpm_destroy
+ * Labels outside [-1, n_cells] are not checked on the device; the caller
+ * guarantees them.  The MCS counter starts at 0.
+ */
+int cpm_init(const cpm_params *params, int32_t *d_lattice, const int32_t *d_cell_type,
+             int32_t n_cells, uint8_t *d_act, void *d_workspace, size_t workspace_bytes,
+             void *stream, cpm_handle **out);
+
+/* Advances the lattice by n_mcs Monte Carlo steps (n_mcs >= 0) and the MCS
+ * counter with it.  Asynchronous on `stream`. */
+int cpm_sweep(cpm_handle *h, int32_t n_mcs, void *stream);
+
+/*
+ * Recounts, from the lattice alone, every label's volume V and surface S
+ * (d_volume, d_surface: int32[n_cells + 1] device; entry 0 is the medium's)
+ * and, if d_centroid_sum is not NULL, int64[(n_cells + 1) * ndim] sums of
+ * each cell's site coordinates, each site taken as the periodic image nearest
+ * to the cell's lowest-index site (entry 0 is zero).  Asynchronous.
+ */
+int cpm_cell_stats(cpm_handle *h, int32_t *d_volume, int32_t *d_surface, int64_t *d_centroid_sum,
+                   void *stream);
+
+/* Copies the volume / surface counters the sweep tracks (int32[n_cells + 1]
+ * each, device; entry 0 unused and written as 0).  Asynchronous. */
+int cpm_counters(cpm_handle *h, int32_t *d_volume, int32_t *d_surface, void *stream);
+
+/* MCS counter (the second Philox counter word of the next MCS).  Setting it
+ * lets a run resume bit-exactly from a saved lattice / activity state. */
+int cpm_set_mcs(cpm_handle *h, uint64_t mcs);
+int cpm_get_mcs(const cpm_handle *h, uint64_t *mcs);
+
+/* Releases host state; the caller's device buffers are untouched. */
+int cpm_destroy(cpm_handle *h);
+
+const char *cpm_strerror(int code);
+const char *cpm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CPM_H */

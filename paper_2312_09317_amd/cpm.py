@@ -1,0 +1,260 @@
+"""Python binding of libcpm (include/cpm.h): argument marshalling only.
+
+Every function here forwards to the C ABI of the same name; device buffers
+are torch tensors on the GPU (torch supplies memory and streams only, all
+model arithmetic runs in the HIP kernels of libcpm).  There is no CPU
+fallback: if the library is not built, loading raises.
+"""
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_build", "libcpm.so")
+
+CPM_OK, CPM_EINVAL, CPM_ERANGE, CPM_ENOMEM, CPM_EDEVICE, CPM_ENOTSUP = range(6)
+
+_lib = None
+
+
+class CpmError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        msg = ""
+        if _lib is not None:
+            msg = _lib.cpm_last_error().decode()
+        super().__init__(f"{where}: error {code} ({msg})")
+
+
+class cpm_params(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int32),
+        ("dims", ctypes.c_int32 * 3),
+        ("sub", ctypes.c_int32),
+        ("attempts", ctypes.c_int32),
+        ("n_types", ctypes.c_int32),
+        ("obstacle_type", ctypes.c_int32),
+        ("temperature", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+        ("lattice_id", ctypes.c_uint32),
+        ("act_enabled", ctypes.c_int32),
+        ("J", ctypes.POINTER(ctypes.c_double)),
+        ("lambda_volume", ctypes.POINTER(ctypes.c_double)),
+        ("volume_target", ctypes.POINTER(ctypes.c_int32)),
+        ("lambda_surface", ctypes.POINTER(ctypes.c_double)),
+        ("surface_target", ctypes.POINTER(ctypes.c_int32)),
+        ("lambda_act", ctypes.POINTER(ctypes.c_double)),
+        ("max_act", ctypes.POINTER(ctypes.c_int32)),
+    ]
+
+
+EXPORTS = ("cpm_validate", "cpm_workspace_bytes", "cpm_init", "cpm_sweep", "cpm_cell_stats",
+           "cpm_counters", "cpm_set_mcs", "cpm_get_mcs", "cpm_destroy", "cpm_strerror",
+           "cpm_last_error")
+
+
+def load(path: str = LIB_PATH):
+    """Load libcpm.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libcpm.so not built at {path}: run __graft_entry__.build()")
+    l = ctypes.CDLL(path)
+    P, I32, U64, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64, ctypes.c_size_t
+    pp = ctypes.POINTER(cpm_params)
+    l.cpm_validate.argtypes = [pp, I32]
+    l.cpm_workspace_bytes.argtypes = [pp, I32, ctypes.POINTER(SZ)]
+    l.cpm_init.argtypes = [pp, P, P, I32, P, P, SZ, P, ctypes.POINTER(P)]
+    l.cpm_sweep.argtypes = [P, I32, P]
+    l.cpm_cell_stats.argtypes = [P, P, P, P, P]
+    l.cpm_counters.argtypes = [P, P, P, P]
+    l.cpm_set_mcs.argtypes = [P, U64]
+    l.cpm_get_mcs.argtypes = [P, ctypes.POINTER(U64)]
+    l.cpm_destroy.argtypes = [P]
+    l.cpm_strerror.argtypes = [ctypes.c_int]
+    l.cpm_strerror.restype = ctypes.c_char_p
+    l.cpm_last_error.argtypes = []
+    l.cpm_last_error.restype = ctypes.c_char_p
+    for f in EXPORTS[:9]:
+        getattr(l, f).restype = ctypes.c_int
+    _lib = l
+    return l
+
+
+def _check(rc, where):
+    if rc != CPM_OK:
+        raise CpmError(rc, where)
+
+
+class Params:
+    """Owns the host arrays a cpm_params struct points at."""
+
+    def __init__(self, ndim: int, dims: Sequence[int], J, lambda_volume, volume_target,
+                 lambda_surface=None, surface_target=None, lambda_act=None, max_act=None,
+                 temperature: float = 20.0, seed: int = 1, lattice_id: int = 0, sub: int = 2,
+                 attempts: int = 1, obstacle_type: int = -1):
+        n = len(lambda_volume)
+        self._J = np.ascontiguousarray(np.asarray(J, dtype=np.float64).reshape(n, n))
+        self._lv = np.ascontiguousarray(lambda_volume, dtype=np.float64)
+        self._vt = np.ascontiguousarray(volume_target, dtype=np.int32)
+        self._ls = None if lambda_surface is None else np.ascontiguousarray(lambda_surface, dtype=np.float64)
+        self._st = None if surface_target is None else np.ascontiguousarray(surface_target, dtype=np.int32)
+        self._la = None if lambda_act is None else np.ascontiguousarray(lambda_act, dtype=np.float64)
+        self._ma = None if max_act is None else np.ascontiguousarray(max_act, dtype=np.int32)
+        d = list(dims) + [1] * (3 - len(dims))
+        c = cpm_params()
+        c.ndim = ndim
+        c.dims = (ctypes.c_int32 * 3)(*d)
+        c.sub = sub
+        c.attempts = attempts
+        c.n_types = n
+        c.obstacle_type = obstacle_type
+        c.temperature = temperature
+        c.seed = seed
+        c.lattice_id = lattice_id
+        c.act_enabled = 1 if lambda_act is not None else 0
+        dp, ip = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)
+        c.J = self._J.ctypes.data_as(dp)
+        c.lambda_volume = self._lv.ctypes.data_as(dp)
+        c.volume_target = self._vt.ctypes.data_as(ip)
+        c.lambda_surface = self._ls.ctypes.data_as(dp) if self._ls is not None else None
+        c.surface_target = self._st.ctypes.data_as(ip) if self._st is not None else None
+        c.lambda_act = self._la.ctypes.data_as(dp) if self._la is not None else None
+        c.max_act = self._ma.ctypes.data_as(ip) if self._ma is not None else None
+        self.c = c
+
+    @property
+    def act_enabled(self) -> bool:
+        return bool(self.c.act_enabled)
+
+    @classmethod
+    def from_workload(cls, w, **over):
+        kw = dict(ndim=w.ndim, dims=w.dims, J=w.J, lambda_volume=w.lambda_V, volume_target=w.V_target,
+                  lambda_surface=w.lambda_S, surface_target=w.S_target, lambda_act=w.lambda_act,
+                  max_act=w.max_act, temperature=w.T, seed=w.seed, lattice_id=w.lattice_id, sub=w.s,
+                  attempts=w.k, obstacle_type=w.obstacle_type)
+        kw.update(over)
+        return cls(**kw)
+
+
+# ---------------------------------------------------------------- C ABI, same names
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def cpm_validate(params: Params, n_cells: int) -> int:
+    return load().cpm_validate(ctypes.byref(params.c), n_cells)
+
+
+def cpm_workspace_bytes(params: Params, n_cells: int) -> int:
+    b = ctypes.c_size_t(0)
+    _check(load().cpm_workspace_bytes(ctypes.byref(params.c), n_cells, ctypes.byref(b)), "cpm_workspace_bytes")
+    return b.value
+
+
+def cpm_init(params: Params, d_lattice, d_cell_type, n_cells: int, d_act, d_workspace, workspace_bytes: int,
+             stream: int) -> int:
+    h = ctypes.c_void_p(0)
+    _check(load().cpm_init(ctypes.byref(params.c), _ptr(d_lattice), _ptr(d_cell_type), n_cells, _ptr(d_act),
+                           _ptr(d_workspace), workspace_bytes, stream, ctypes.byref(h)), "cpm_init")
+    return h.value
+
+
+def cpm_sweep(h: int, n_mcs: int, stream: int) -> None:
+    _check(load().cpm_sweep(h, n_mcs, stream), "cpm_sweep")
+
+
+def cpm_cell_stats(h: int, d_volume, d_surface, d_centroid_sum, stream: int) -> None:
+    _check(load().cpm_cell_stats(h, _ptr(d_volume), _ptr(d_surface), _ptr(d_centroid_sum), stream),
+           "cpm_cell_stats")
+
+
+def cpm_counters(h: int, d_volume, d_surface, stream: int) -> None:
+    _check(load().cpm_counters(h, _ptr(d_volume), _ptr(d_surface), stream), "cpm_counters")
+
+
+def cpm_set_mcs(h: int, mcs: int) -> None:
+    _check(load().cpm_set_mcs(h, mcs), "cpm_set_mcs")
+
+
+def cpm_get_mcs(h: int) -> int:
+    v = ctypes.c_uint64(0)
+    _check(load().cpm_get_mcs(h, ctypes.byref(v)), "cpm_get_mcs")
+    return v.value
+
+
+def cpm_destroy(h: int) -> None:
+    load().cpm_destroy(h)
+
+
+# ---------------------------------------------------------------- convenience wrapper
+
+class Simulation:
+    """A lattice resident on the GPU plus the handle that sweeps it.
+
+    Tensors are allocated with torch on `device`; calls enqueue on torch's
+    current stream of that device.
+    """
+
+    def __init__(self, params: Params, lattice, cell_type, act=None, device="cuda"):
+        import torch
+        self.torch = torch
+        self.params = params
+        self.device = torch.device(device)
+        self.lattice = torch.as_tensor(np.ascontiguousarray(lattice, dtype=np.int32)).to(self.device).contiguous()
+        self.cell_type = torch.as_tensor(np.ascontiguousarray(cell_type, dtype=np.int32)).to(self.device)
+        self.n_cells = int(self.cell_type.numel()) - 1
+        if params.act_enabled:
+            a = np.zeros(self.lattice.shape, np.uint8) if act is None else np.ascontiguousarray(act, dtype=np.uint8)
+            self.act = torch.as_tensor(a).to(self.device).contiguous()
+        else:
+            self.act = None
+        nbytes = cpm_workspace_bytes(params, self.n_cells)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.handle = cpm_init(params, self.lattice, self.cell_type, self.n_cells, self.act, self.workspace,
+                               nbytes, self.stream)
+
+    @property
+    def stream(self) -> int:
+        return self.torch.cuda.current_stream(self.device).cuda_stream
+
+    def sweep(self, n_mcs: int) -> None:
+        cpm_sweep(self.handle, n_mcs, self.stream)
+
+    def counters(self):
+        v = self.torch.empty(self.n_cells + 1, dtype=self.torch.int32, device=self.device)
+        s = self.torch.empty_like(v)
+        cpm_counters(self.handle, v, s, self.stream)
+        return v, s
+
+    def cell_stats(self, centroids: bool = True):
+        torch = self.torch
+        v = torch.empty(self.n_cells + 1, dtype=torch.int32, device=self.device)
+        s = torch.empty_like(v)
+        c = torch.empty((self.n_cells + 1, self.params.c.ndim), dtype=torch.int64, device=self.device) \
+            if centroids else None
+        cpm_cell_stats(self.handle, v, s, c, self.stream)
+        return v, s, c
+
+    @property
+    def mcs(self) -> int:
+        return cpm_get_mcs(self.handle)
+
+    @mcs.setter
+    def mcs(self, value: int) -> None:
+        cpm_set_mcs(self.handle, value)
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            cpm_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

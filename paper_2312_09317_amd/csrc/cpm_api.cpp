@@ -1,0 +1,357 @@
+// Host side of libcpm: parameter validation, fixed-point quantisation,
+// FP64-built acceptance / activity tables, workspace carving and the C ABI
+// declared in include/cpm.h.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+
+#include "../../include/cpm.h"
+#include "cpm_internal.hpp"
+
+using cpm::DeviceModel;
+using cpm::SweepArgs;
+
+struct cpm_handle {
+    int32_t ndim = 0;
+    int32_t L[3] = {1, 1, 1};
+    int32_t s = 0, k = 0;
+    int32_t n_cells = 0;
+    bool act = false;
+    SweepArgs args{};
+    int32_t *ref = nullptr;          // centroid reference sites, n_cells + 1
+    uint64_t mcs = 0;                // next MCS index
+    uint64_t activation = 0;         // activations run so far (buffer parity)
+    std::unique_ptr<DeviceModel> host_model;  // source of the async upload
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+int device_fail(hipError_t e, const char *where)
+{
+    return fail(CPM_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+// Round half away from zero onto the 2^-16 grid.
+int64_t to_fixed(double x) { return (int64_t)std::llround(x * 65536.0); }
+
+size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct Layout {
+    size_t model, counters0, counters1, prev, ref, total;
+};
+
+Layout layout_of(const cpm_params *p, int32_t n_cells)
+{
+    Layout l{};
+    int64_t areas = 1;
+    for (int d = 0; d < p->ndim; ++d) areas *= p->dims[d] / (2 * p->sub);
+    size_t off = 0;
+    l.model = off;
+    off = align_up(off + sizeof(DeviceModel));
+    l.counters0 = off;
+    off = align_up(off + sizeof(int32_t) * 2 * ((size_t)n_cells + 1));
+    l.counters1 = off;
+    off = align_up(off + sizeof(int32_t) * 2 * ((size_t)n_cells + 1));
+    l.prev = off;
+    off = align_up(off + sizeof(int4) * (size_t)areas * (size_t)p->attempts);
+    l.ref = off;
+    off = align_up(off + sizeof(int32_t) * ((size_t)n_cells + 1));
+    l.total = off;
+    return l;
+}
+
+int n_neighbours(int ndim) { return ndim == 2 ? 8 : 26; }
+
+// Largest h with floor(2^32 exp(-h/T)) >= 1, plus one.
+int table_length(double T)
+{
+    int h = 0;
+    while (h <= cpm::kMaxTI && std::floor(std::exp(-(double)h / T) * 4294967296.0) >= 1.0) ++h;
+    return h;
+}
+
+int validate(const cpm_params *p, int32_t n_cells)
+{
+    if (!p) return fail(CPM_EINVAL, "params is NULL");
+    if (p->ndim != 2 && p->ndim != 3) return fail(CPM_EINVAL, "ndim must be 2 or 3");
+    if (p->ndim == 2 && p->dims[2] != 1) return fail(CPM_EINVAL, "dims[2] must be 1 in 2D");
+    if (p->sub < 1) return fail(CPM_EINVAL, "sub (s) must be >= 1");
+    int64_t n_sites = 1;
+    for (int d = 0; d < 3; ++d) {
+        if (p->dims[d] < 1) return fail(CPM_EINVAL, "dims must be positive");
+        n_sites *= p->dims[d];
+    }
+    for (int d = 0; d < p->ndim; ++d)
+        if (p->dims[d] % (2 * p->sub) != 0) return fail(CPM_EINVAL, "every dim must be divisible by 2*sub");
+    if (n_sites > ((int64_t)1 << 31) - 1) return fail(CPM_EINVAL, "lattice has more than 2^31-1 sites");
+    int64_t sd = 1;
+    for (int d = 0; d < p->ndim; ++d) sd *= p->sub;
+    if (p->attempts < 1 || sd % p->attempts != 0)
+        return fail(CPM_EINVAL, "attempts (k) must be >= 1 and divide sub^ndim");
+    if (((int64_t)1 << p->ndim) * sd / p->attempts > ((int64_t)1 << 24))
+        return fail(CPM_EINVAL, "too many activations per MCS");
+    if (p->attempts > 255) return fail(CPM_EINVAL, "attempts (k) must be <= 255");
+    if (n_cells < 0 || n_cells > INT32_MAX - 1) return fail(CPM_EINVAL, "n_cells out of range");
+    if (p->n_types < 1 || p->n_types > CPM_MAX_TYPES) return fail(CPM_EINVAL, "n_types must be in 1..16");
+    if (p->obstacle_type < -1 || p->obstacle_type >= p->n_types) return fail(CPM_EINVAL, "bad obstacle_type");
+    if (!(p->temperature > 0.0) || !std::isfinite(p->temperature))
+        return fail(CPM_EINVAL, "temperature must be positive and finite");
+    if (!p->J || !p->lambda_volume || !p->volume_target) return fail(CPM_EINVAL, "J / lambda_volume / volume_target NULL");
+    if (p->lambda_surface && !p->surface_target) return fail(CPM_EINVAL, "surface_target NULL");
+    if (p->act_enabled) {
+        if (!p->lambda_act || !p->max_act) return fail(CPM_EINVAL, "lambda_act / max_act NULL with act enabled");
+        if (p->sub < 2) return fail(CPM_EINVAL, "the Act term reads two sites out: sub must be >= 2");
+    }
+    const int n = p->n_types;
+    const int nnb = n_neighbours(p->ndim);
+    const double lim = 2147483647.0 / 65536.0;  // |parameter| < 2^15
+    double jmax = 0, lvmax = 0, lsmax = 0, ramax = 0, vtmax = 0, stmax = 0;
+    for (int a = 0; a < n; ++a) {
+        for (int b = 0; b < n; ++b) {
+            const double j = p->J[a * n + b];
+            if (!std::isfinite(j) || std::fabs(j) >= lim) return fail(CPM_ERANGE, "J out of range");
+            if (to_fixed(j) != to_fixed(p->J[b * n + a])) return fail(CPM_EINVAL, "J must be symmetric");
+            jmax = std::fmax(jmax, std::fabs(j));
+        }
+        const double lv = p->lambda_volume[a];
+        const double ls = p->lambda_surface ? p->lambda_surface[a] : 0.0;
+        if (!std::isfinite(lv) || std::fabs(lv) >= lim || !std::isfinite(ls) || std::fabs(ls) >= lim)
+            return fail(CPM_ERANGE, "lambda out of range");
+        lvmax = std::fmax(lvmax, std::fabs(lv));
+        lsmax = std::fmax(lsmax, std::fabs(ls));
+        vtmax = std::fmax(vtmax, std::fabs((double)p->volume_target[a]));
+        if (p->lambda_surface) stmax = std::fmax(stmax, std::fabs((double)p->surface_target[a]));
+        if (p->act_enabled) {
+            if (p->max_act[a] < 0 || p->max_act[a] > 255) return fail(CPM_EINVAL, "max_act must be in 0..255");
+            if (a == 0 && p->max_act[a] != 0) return fail(CPM_EINVAL, "the medium type cannot be motile");
+            const double la = p->lambda_act[a];
+            if (!std::isfinite(la) || std::fabs(la) >= lim) return fail(CPM_ERANGE, "lambda_act out of range");
+            if (p->max_act[a] > 0) ramax = std::fmax(ramax, std::fabs(la / p->max_act[a]));
+        }
+    }
+    // worst case |dH| in 2^-16 units must stay well inside int64
+    const double N = (double)n_sites;
+    // |V - Vt| <= N + |Vt|, |S - St| <= nnb N + |St|, |dS| <= nnb
+    const double bound = 65536.0 * (2.0 * nnb * 2.0 * jmax + 2.0 * lvmax * (2.0 * (N + vtmax) + 1.0) +
+                                    2.0 * lsmax * (2.0 * nnb * (nnb * N + stmax) + nnb * nnb) +
+                                    2.0 * ramax * 256.0);
+    if (bound >= 4.0e18) return fail(CPM_ERANGE, "fixed-point energy change could overflow int64");
+    if (table_length(p->temperature) > cpm::kMaxTI) return fail(CPM_ENOTSUP, "temperature too high for the threshold table");
+    if (p->attempts > cpm::kMaxAttempts) return fail(CPM_ENOTSUP, "this build runs at most 8 attempts per activation");
+    return CPM_OK;
+}
+
+void build_model(const cpm_params *p, DeviceModel *m)
+{
+    std::memset(m, 0, sizeof(*m));
+    const int n = p->n_types;
+    for (int a = 0; a < n; ++a) {
+        for (int b = 0; b < n; ++b) m->J[a * cpm::kMaxTypes + b] = to_fixed(p->J[a * n + b]);
+        m->lam_v[a] = to_fixed(p->lambda_volume[a]);
+        m->v_target[a] = p->volume_target[a];
+        m->lam_s[a] = p->lambda_surface ? to_fixed(p->lambda_surface[a]) : 0;
+        m->s_target[a] = p->lambda_surface ? p->surface_target[a] : 0;
+        if (p->act_enabled && p->max_act[a] > 0) {
+            m->max_act[a] = p->max_act[a];
+            m->r_act[a] = to_fixed(p->lambda_act[a] / (double)p->max_act[a]);
+        }
+    }
+    // Acceptance: TI[h] = floor(2^32 e^{-h/T}) while nonzero, TM, TL finer steps.
+    const double T = p->temperature;
+    const double two32 = 4294967296.0;
+    m->n_ti = table_length(T);
+    for (int h = 0; h < m->n_ti; ++h) m->TI[h] = (uint64_t)std::floor(std::exp(-(double)h / T) * two32);
+    for (int i = 0; i < 256; ++i) {
+        m->TM[i] = (uint64_t)std::floor(std::exp(-(double)i / (256.0 * T)) * two32);
+        m->TL[i] = (uint64_t)std::floor(std::exp(-(double)i / (65536.0 * T)) * two32);
+    }
+    // Activity geometric mean tables.
+    for (int a = 1; a < 256; ++a) m->LG[a] = (int64_t)std::llround(std::log((double)a) * 16777216.0);
+    for (int i = 0; i < 2048; ++i) m->EH[i] = (uint64_t)std::floor(std::exp((double)i / 256.0) * 16777216.0);
+    for (int i = 0; i < 256; ++i) {
+        m->EM[i] = (uint64_t)std::floor(std::exp((double)i / 65536.0) * 2147483648.0);
+        m->EL[i] = (uint64_t)std::floor(std::exp((double)i / 16777216.0) * 1073741824.0);
+    }
+}
+
+hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+}  // namespace
+
+extern "C" {
+
+int cpm_validate(const cpm_params *params, int32_t n_cells) { return validate(params, n_cells); }
+
+int cpm_workspace_bytes(const cpm_params *params, int32_t n_cells, size_t *bytes)
+{
+    const int rc = validate(params, n_cells);
+    if (rc != CPM_OK) return rc;
+    if (!bytes) return fail(CPM_EINVAL, "bytes is NULL");
+    *bytes = layout_of(params, n_cells).total;
+    return CPM_OK;
+}
+
+int cpm_init(const cpm_params *params, int32_t *d_lattice, const int32_t *d_cell_type, int32_t n_cells,
+             uint8_t *d_act, void *d_workspace, size_t workspace_bytes, void *stream, cpm_handle **out)
+{
+    if (!out) return fail(CPM_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate(params, n_cells);
+    if (rc != CPM_OK) return rc;
+    if (!d_lattice || !d_cell_type || !d_workspace) return fail(CPM_EINVAL, "NULL device buffer");
+    if (params->act_enabled && !d_act) return fail(CPM_EINVAL, "act enabled but d_act is NULL");
+    if (reinterpret_cast<uintptr_t>(d_workspace) % 256 != 0) return fail(CPM_EINVAL, "workspace not 256-byte aligned");
+    const Layout lay = layout_of(params, n_cells);
+    if (workspace_bytes < lay.total) return fail(CPM_ENOMEM, "workspace smaller than cpm_workspace_bytes()");
+
+    std::unique_ptr<cpm_handle> h(new (std::nothrow) cpm_handle());
+    if (!h) return fail(CPM_EINVAL, "host allocation failed");
+    h->host_model.reset(new (std::nothrow) DeviceModel);
+    if (!h->host_model) return fail(CPM_EINVAL, "host allocation failed");
+    build_model(params, h->host_model.get());
+
+    char *ws = static_cast<char *>(d_workspace);
+    h->ndim = params->ndim;
+    for (int d = 0; d < 3; ++d) h->L[d] = params->dims[d];
+    h->s = params->sub;
+    h->k = params->attempts;
+    h->n_cells = n_cells;
+    h->act = params->act_enabled != 0;
+    SweepArgs &a = h->args;
+    a.lat = d_lattice;
+    a.cell_type = d_cell_type;
+    a.act = h->act ? d_act : nullptr;
+    a.model = reinterpret_cast<const DeviceModel *>(ws + lay.model);
+    a.counters[0] = reinterpret_cast<int32_t *>(ws + lay.counters0);
+    a.counters[1] = reinterpret_cast<int32_t *>(ws + lay.counters1);
+    a.prev = reinterpret_cast<int4 *>(ws + lay.prev);
+    h->ref = reinterpret_cast<int32_t *>(ws + lay.ref);
+    uint32_t n_areas = 1;
+    for (int d = 0; d < 3; ++d) {
+        a.L[d] = params->dims[d];
+        a.na[d] = d < params->ndim ? params->dims[d] / (2 * params->sub) : 1;
+        n_areas *= (uint32_t)a.na[d];
+    }
+    a.n_areas = n_areas;
+    a.s = params->sub;
+    a.k = params->attempts;
+    a.obstacle_type = params->obstacle_type < 0 ? 0 : params->obstacle_type;
+    a.key0 = (uint32_t)params->seed;
+    a.key1 = (uint32_t)(params->seed >> 32);
+    a.lattice_id = params->lattice_id;
+
+    hipStream_t st = as_stream(stream);
+    hipError_t e = hipMemcpyAsync(ws + lay.model, h->host_model.get(), sizeof(DeviceModel), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return device_fail(e, "upload model");
+    const size_t pairs = 2 * ((size_t)n_cells + 1);
+    if ((e = cpm::launch_fill_i32(a.counters[0], 0, pairs, st)) != hipSuccess) return device_fail(e, "clear counters");
+    if ((e = cpm::launch_fill_i32(reinterpret_cast<int32_t *>(a.prev), 0,
+                                  4 * (size_t)n_areas * (size_t)params->attempts, st)) != hipSuccess)
+        return device_fail(e, "clear deltas");
+    if ((e = cpm::launch_count(a, h->ndim, a.counters[0], a.counters[0] + 1, 2, st)) != hipSuccess)
+        return device_fail(e, "count");
+    e = hipMemcpyAsync(a.counters[1], a.counters[0], sizeof(int32_t) * pairs, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return device_fail(e, "copy counters");
+    *out = h.release();
+    return CPM_OK;
+}
+
+int cpm_sweep(cpm_handle *h, int32_t n_mcs, void *stream)
+{
+    if (!h) return fail(CPM_EINVAL, "handle is NULL");
+    if (n_mcs < 0) return fail(CPM_EINVAL, "n_mcs must be >= 0");
+    hipStream_t st = as_stream(stream);
+    int64_t sd = 1;
+    for (int d = 0; d < h->ndim; ++d) sd *= h->s;
+    const uint32_t n_act = (uint32_t)(((int64_t)1 << h->ndim) * sd / h->k);
+    const size_t n_sites = (size_t)h->L[0] * h->L[1] * h->L[2];
+    for (int32_t i = 0; i < n_mcs; ++i) {
+        const uint32_t mcs = (uint32_t)h->mcs;
+        for (uint32_t alpha = 0; alpha < n_act; ++alpha) {
+            const hipError_t e = cpm::launch_activation(h->args, h->ndim, h->act, mcs, alpha,
+                                                        (int)(h->activation & 1), st);
+            if (e != hipSuccess) return device_fail(e, "activation");
+            ++h->activation;
+        }
+        if (h->act) {
+            const hipError_t e = cpm::launch_act_decay(h->args.act, n_sites, st);
+            if (e != hipSuccess) return device_fail(e, "act decay");
+        }
+        ++h->mcs;
+    }
+    return CPM_OK;
+}
+
+int cpm_cell_stats(cpm_handle *h, int32_t *d_volume, int32_t *d_surface, int64_t *d_centroid_sum, void *stream)
+{
+    if (!h || !d_volume || !d_surface) return fail(CPM_EINVAL, "NULL argument");
+    hipStream_t st = as_stream(stream);
+    const size_t n = (size_t)h->n_cells + 1;
+    hipError_t e;
+    if ((e = cpm::launch_fill_i32(d_volume, 0, n, st)) != hipSuccess) return device_fail(e, "clear volume");
+    if ((e = cpm::launch_fill_i32(d_surface, 0, n, st)) != hipSuccess) return device_fail(e, "clear surface");
+    if ((e = cpm::launch_count(h->args, h->ndim, d_volume, d_surface, 1, st)) != hipSuccess)
+        return device_fail(e, "count");
+    if (d_centroid_sum) {
+        if ((e = cpm::launch_centroids(h->args, h->ndim, h->n_cells, h->ref, d_centroid_sum, st)) != hipSuccess)
+            return device_fail(e, "centroids");
+    }
+    return CPM_OK;
+}
+
+int cpm_counters(cpm_handle *h, int32_t *d_volume, int32_t *d_surface, void *stream)
+{
+    if (!h || !d_volume || !d_surface) return fail(CPM_EINVAL, "NULL argument");
+    const hipError_t e = cpm::launch_copy_counters(h->args.counters[h->activation & 1], h->n_cells + 1, d_volume,
+                                                   d_surface, as_stream(stream));
+    if (e != hipSuccess) return device_fail(e, "copy counters");
+    return CPM_OK;
+}
+
+int cpm_set_mcs(cpm_handle *h, uint64_t mcs)
+{
+    if (!h) return fail(CPM_EINVAL, "handle is NULL");
+    h->mcs = mcs;
+    return CPM_OK;
+}
+
+int cpm_get_mcs(const cpm_handle *h, uint64_t *mcs)
+{
+    if (!h || !mcs) return fail(CPM_EINVAL, "NULL argument");
+    *mcs = h->mcs;
+    return CPM_OK;
+}
+
+int cpm_destroy(cpm_handle *h)
+{
+    delete h;
+    return CPM_OK;
+}
+
+const char *cpm_strerror(int code)
+{
+    switch (code) {
+    case CPM_OK: return "ok";
+    case CPM_EINVAL: return "invalid argument";
+    case CPM_ERANGE: return "fixed-point range exceeded";
+    case CPM_ENOMEM: return "workspace too small";
+    case CPM_EDEVICE: return "HIP runtime error";
+    case CPM_ENOTSUP: return "not supported by this build";
+    default: return "unknown error";
+    }
+}
+
+const char *cpm_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,105 @@
+"""Host-side checks of the C ABI: the library loads, exports every entry
+point include/cpm.h declares, and validates models without a device."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2312_09317_amd import cpm, inputs
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "cpm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char \*|void)\s*\**\s*(cpm_\w+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = cpm.load()
+    names = declared_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(cpm.EXPORTS)
+
+
+def test_params_struct_layout_matches_header(tmp_path):
+    # offsets of cpm_params as the C compiler lays them out from include/cpm.h
+    fields = [f[0] for f in cpm.cpm_params._fields_]
+    src = tmp_path / "layout.c"
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', 'int main(void) {']
+    lines.append('printf("%zu\\n", sizeof(cpm_params));')
+    for f in fields:
+        lines.append(f'printf("%zu\\n", offsetof(cpm_params, {f}));')
+    lines.append('return 0; }')
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", str(src), "-o", str(exe)], check=True)
+    vals = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert vals[0] == ctypes.sizeof(cpm.cpm_params)
+    for f, off in zip(fields, vals[1:]):
+        assert getattr(cpm.cpm_params, f).offset == off, f
+
+
+def _params(**kw):
+    w = inputs.config1(L=32, grid=3, n_mcs=1)
+    return cpm.Params.from_workload(w, **kw), w
+
+
+def test_validate_accepts_workloads():
+    p, w = _params()
+    assert cpm.cpm_validate(p, w.n_cells) == cpm.CPM_OK
+    w0 = inputs.config0()
+    assert cpm.cpm_validate(cpm.Params.from_workload(w0), w0.n_cells) == cpm.CPM_OK
+    nbytes = cpm.cpm_workspace_bytes(p, w.n_cells)
+    assert nbytes > 8 * (w.n_cells + 1) * 2
+    assert nbytes % 256 == 0
+
+
+@pytest.mark.parametrize("change,code", [
+    (dict(sub=3), cpm.CPM_EINVAL),             # 32 not divisible by 6
+    (dict(attempts=3), cpm.CPM_EINVAL),        # 3 does not divide 8
+    (dict(ndim=4), cpm.CPM_EINVAL),
+    (dict(temperature=0.0), cpm.CPM_EINVAL),
+    (dict(temperature=float("nan")), cpm.CPM_EINVAL),
+    (dict(temperature=500.0), cpm.CPM_ENOTSUP),
+    (dict(obstacle_type=7), cpm.CPM_EINVAL),
+    (dict(J=[[0, 1e6], [1e6, 0]]), cpm.CPM_ERANGE),
+    (dict(J=[[0, 1.0], [2.0, 0]]), cpm.CPM_EINVAL),  # asymmetric
+    (dict(lambda_act=[0, 1.0], max_act=[0, 5], sub=1), cpm.CPM_EINVAL),
+    (dict(lambda_act=[0, 1.0], max_act=[0, 300]), cpm.CPM_EINVAL),
+    (dict(lambda_act=[0, 1.0], max_act=[3, 5]), cpm.CPM_EINVAL),
+])
+def test_validate_rejects(change, code):
+    p, w = _params(**change)
+    assert cpm.cpm_validate(p, w.n_cells) == code
+    with pytest.raises(cpm.CpmError) as e:
+        cpm.cpm_workspace_bytes(p, w.n_cells)
+    assert e.value.code == code
+    assert cpm.load().cpm_last_error()  # a message is set
+
+
+def test_validate_rejects_bad_cell_count_and_null():
+    p, w = _params()
+    assert cpm.cpm_validate(p, -1) == cpm.CPM_EINVAL
+    assert cpm.load().cpm_validate(None, 5) == cpm.CPM_EINVAL
+
+
+def test_init_rejects_small_workspace_without_touching_device():
+    p, w = _params()
+    lib = cpm.load()
+    h = ctypes.c_void_p(0)
+    fake = ctypes.c_void_p(4096)  # never dereferenced: the size check fails first
+    rc = lib.cpm_init(ctypes.byref(p.c), fake, fake, w.n_cells, None, fake, 16, None, ctypes.byref(h))
+    assert rc == cpm.CPM_ENOMEM
+    assert h.value is None
+
+
+def test_strerror():
+    lib = cpm.load()
+    for c in range(6):
+        assert lib.cpm_strerror(c)
