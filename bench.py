@@ -55,13 +55,30 @@ def cpu_baseline(w, n_mcs):
             "p_acc": float(st.stats[2]) / max(1, attempts)}
 
 
+def copy_calibration(nbytes):
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.int32, device="cuda:0").fill_(1)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "reads_per_copy": nbytes, "writes_per_copy": nbytes, "copies": 5}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--cpu-mcs", type=int, default=4, help="MCS of the oracle sample (0 to skip)")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="only run a plain device copy of this many bytes, 5 times (calibrates "
+                         "the HBM byte counters of a profiler against a known traffic)")
     args = ap.parse_args()
+    if args.copy_bytes:
+        copy_calibration(args.copy_bytes)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         log("bench.py runs on one GPU only: the sweep is not sharded across GPUs")

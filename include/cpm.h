@@ -146,6 +146,11 @@ int cpm_cell_stats(cpm_handle *h, int32_t *d_volume, int32_t *d_surface, int64_t
  * each, device; entry 0 unused and written as 0).  Asynchronous. */
 int cpm_counters(cpm_handle *h, int32_t *d_volume, int32_t *d_surface, void *stream);
 
+/* Copy-attempt statistics since cpm_init, read synchronously on `stream`
+ * (waits for the stream): out[0] attempts, out[1] attempts past the early
+ * rejection (distinct, non-obstacle labels), out[2] accepted copies. */
+int cpm_attempt_stats(cpm_handle *h, uint64_t *out, void *stream);
+
 /* MCS counter (the second Philox counter word of the next MCS).  Setting it
  * lets a run resume bit-exactly from a saved lattice / activity state. */
 int cpm_set_mcs(cpm_handle *h, uint64_t mcs);

@@ -51,8 +51,8 @@ class cpm_params(ctypes.Structure):
 
 
 EXPORTS = ("cpm_validate", "cpm_workspace_bytes", "cpm_init", "cpm_sweep", "cpm_cell_stats",
-           "cpm_counters", "cpm_set_mcs", "cpm_get_mcs", "cpm_destroy", "cpm_strerror",
-           "cpm_last_error")
+           "cpm_counters", "cpm_attempt_stats", "cpm_set_mcs", "cpm_get_mcs", "cpm_destroy",
+           "cpm_strerror", "cpm_last_error")
 
 
 def load(path: str = LIB_PATH):
@@ -71,6 +71,7 @@ def load(path: str = LIB_PATH):
     l.cpm_sweep.argtypes = [P, I32, P]
     l.cpm_cell_stats.argtypes = [P, P, P, P, P]
     l.cpm_counters.argtypes = [P, P, P, P]
+    l.cpm_attempt_stats.argtypes = [P, P, P]
     l.cpm_set_mcs.argtypes = [P, U64]
     l.cpm_get_mcs.argtypes = [P, ctypes.POINTER(U64)]
     l.cpm_destroy.argtypes = [P]
@@ -78,7 +79,7 @@ def load(path: str = LIB_PATH):
     l.cpm_strerror.restype = ctypes.c_char_p
     l.cpm_last_error.argtypes = []
     l.cpm_last_error.restype = ctypes.c_char_p
-    for f in EXPORTS[:9]:
+    for f in EXPORTS[:10]:
         getattr(l, f).restype = ctypes.c_int
     _lib = l
     return l
@@ -177,6 +178,12 @@ def cpm_counters(h: int, d_volume, d_surface, stream: int) -> None:
     _check(load().cpm_counters(h, _ptr(d_volume), _ptr(d_surface), stream), "cpm_counters")
 
 
+def cpm_attempt_stats(h: int, stream: int):
+    out = (ctypes.c_uint64 * 3)()
+    _check(load().cpm_attempt_stats(h, out, stream), "cpm_attempt_stats")
+    return tuple(int(v) for v in out)
+
+
 def cpm_set_mcs(h: int, mcs: int) -> None:
     _check(load().cpm_set_mcs(h, mcs), "cpm_set_mcs")
 
@@ -239,6 +246,10 @@ class Simulation:
             if centroids else None
         cpm_cell_stats(self.handle, v, s, c, self.stream)
         return v, s, c
+
+    def attempt_stats(self):
+        """(attempts, attempts past the early rejection, accepted copies)."""
+        return cpm_attempt_stats(self.handle, self.stream)
 
     @property
     def mcs(self) -> int:

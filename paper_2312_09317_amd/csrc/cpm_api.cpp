@@ -1,7 +1,9 @@
 // Host side of libcpm: parameter validation, fixed-point quantisation,
 // FP64-built acceptance / activity tables, workspace carving and the C ABI
 // declared in include/cpm.h.
+#include <algorithm>
 #include <cmath>
+#include <vector>
 #include <cstdio>
 #include <cstring>
 #include <memory>
@@ -20,10 +22,13 @@ struct cpm_handle {
     int32_t s = 0, k = 0;
     int32_t n_cells = 0;
     bool act = false;
+    bool mirror = false;             // sweeps run on an int16 copy of the lattice
+    int16_t *mirror_cells = nullptr;
     SweepArgs args{};
     int32_t *ref = nullptr;          // centroid reference sites, n_cells + 1
     uint64_t mcs = 0;                // next MCS index
     uint64_t activation = 0;         // activations run so far (buffer parity)
+    uint64_t attempts_run = 0;       // copy attempts run since init
     std::unique_ptr<DeviceModel> host_model;  // source of the async upload
 };
 
@@ -48,25 +53,101 @@ int64_t to_fixed(double x) { return (int64_t)std::llround(x * 65536.0); }
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t model, counters0, counters1, prev, ref, total;
+    size_t model, counters0, counters1, dlist, dcount, stats, ref, mirror, total;
+    cpm::TileGeometry tg;
+    bool mirror_on;
+    int32_t dlist_cap;
 };
+
+// Labels fit the int16 working copy: cells 1..32767, medium 0, obstacle -1.
+bool use_mirror(int32_t n_cells) { return n_cells <= 32767; }
+
+// Thread areas per workgroup tile.  Preferred: whole rows of areas along x
+// (full-row LDS layout: every staged row is one aligned lattice row, no row
+// staged twice), growing along y then z up to kBlock areas while the staged
+// rows fit 64 KiB of LDS.  Otherwise a box tile, shrunk until it fits.
+cpm::TileGeometry choose_tiles(const cpm_params *p, bool mirror)
+{
+    cpm::TileGeometry g{};
+    const int s = p->sub, R = p->act_enabled ? 2 : 1;
+    const bool act = p->act_enabled != 0;
+    const int cell = mirror ? 2 : 4;
+    int na[3] = {1, 1, 1};
+    for (int d = 0; d < p->ndim; ++d) na[d] = p->dims[d] / (2 * s);
+    auto extent = [&](int T) { return 2 * s * (T - 1) + s + 2 * R; };
+    const size_t budget = 65536;
+    int T[3] = {1, 1, 1};
+    const int L0 = p->dims[0];
+    bool full = p->attempts == 1 && na[0] <= cpm::kBlock && (L0 * cell) % 16 == 0 && (!act || L0 % 16 == 0);
+    if (full) {
+        auto lds_for = [&](int t1, int t2) {
+            const int rows = extent(t1) * (p->ndim == 3 ? extent(t2) : 1);
+            return cpm::sweep_lds_bytes(p->ndim, act, mirror, rows * L0);
+        };
+        T[0] = na[0];
+        if (lds_for(1, 1) > budget) {
+            full = false;
+        } else {
+            while (T[1] < na[1] && T[0] * (T[1] + 1) <= cpm::kBlock && lds_for(T[1] + 1, 1) <= budget) ++T[1];
+            if (p->ndim == 3)
+                while (T[2] < na[2] && T[0] * T[1] * (T[2] + 1) <= cpm::kBlock && lds_for(T[1], T[2] + 1) <= budget)
+                    ++T[2];
+            const int rows = extent(T[1]) * (p->ndim == 3 ? extent(T[2]) : 1);
+            g.box_sites = rows * L0;
+            g.lds_bytes = (int32_t)lds_for(T[1], T[2]);
+        }
+    }
+    if (!full) {
+        T[0] = std::min(na[0], cpm::kBlock);
+        T[1] = std::min(na[1], cpm::kBlock / T[0]);
+        T[2] = p->ndim == 3 ? std::min(na[2], cpm::kBlock / (T[0] * T[1])) : 1;
+        for (;;) {
+            int box = 1;
+            for (int d = 0; d < p->ndim; ++d) box *= extent(T[d]);
+            const size_t bytes = cpm::sweep_lds_bytes(p->ndim, act, mirror, box);
+            if (bytes <= budget || (T[0] == 1 && T[1] == 1 && T[2] == 1)) {
+                g.box_sites = box;
+                g.lds_bytes = (int32_t)bytes;
+                break;
+            }
+            if (T[2] > 1) T[2] = (T[2] + 1) / 2;
+            else if (T[1] > 1) T[1] = (T[1] + 1) / 2;
+            else T[0] = (T[0] + 1) / 2;
+        }
+    }
+    g.full_rows = full ? 1 : 0;
+    g.n_tiles = 1;
+    for (int d = 0; d < 3; ++d) {
+        g.T[d] = T[d];
+        g.nt[d] = (na[d] + T[d] - 1) / T[d];
+        g.n_tiles *= g.nt[d];
+    }
+    g.tiles_per_xcd = (g.n_tiles + cpm::kXcds - 1) / cpm::kXcds;
+    g.grid = g.tiles_per_xcd * cpm::kXcds;
+    return g;
+}
 
 Layout layout_of(const cpm_params *p, int32_t n_cells)
 {
     Layout l{};
-    int64_t areas = 1;
-    for (int d = 0; d < p->ndim; ++d) areas *= p->dims[d] / (2 * p->sub);
+    l.mirror_on = use_mirror(n_cells);
+    l.tg = choose_tiles(p, l.mirror_on);
+    l.dlist_cap = l.tg.T[0] * l.tg.T[1] * l.tg.T[2] * p->attempts;
+    int64_t n_sites = (int64_t)p->dims[0] * p->dims[1] * p->dims[2];
     size_t off = 0;
-    l.model = off;
-    off = align_up(off + sizeof(DeviceModel));
-    l.counters0 = off;
-    off = align_up(off + sizeof(int32_t) * 2 * ((size_t)n_cells + 1));
-    l.counters1 = off;
-    off = align_up(off + sizeof(int32_t) * 2 * ((size_t)n_cells + 1));
-    l.prev = off;
-    off = align_up(off + sizeof(int4) * (size_t)areas * (size_t)p->attempts);
-    l.ref = off;
-    off = align_up(off + sizeof(int32_t) * ((size_t)n_cells + 1));
+    auto take = [&off](size_t bytes) {
+        const size_t at = off;
+        off = align_up(off + bytes);
+        return at;
+    };
+    l.model = take(sizeof(DeviceModel));
+    l.counters0 = take(sizeof(int32_t) * 2 * ((size_t)n_cells + 1));
+    l.counters1 = take(sizeof(int32_t) * 2 * ((size_t)n_cells + 1));
+    l.dlist = take(sizeof(int4) * (size_t)l.tg.n_tiles * (size_t)l.dlist_cap);
+    l.dcount = take(sizeof(int32_t) * (size_t)l.tg.n_tiles);
+    l.stats = take(sizeof(uint64_t) * 2 * (size_t)l.tg.n_tiles);
+    l.ref = take(sizeof(int32_t) * ((size_t)n_cells + 1));
+    l.mirror = take(l.mirror_on ? sizeof(int16_t) * (size_t)n_sites : 0);
     l.total = off;
     return l;
 }
@@ -221,6 +302,24 @@ int cpm_init(const cpm_params *params, int32_t *d_lattice, const int32_t *d_cell
     if (!h->host_model) return fail(CPM_EINVAL, "host allocation failed");
     build_model(params, h->host_model.get());
 
+    // every cell's type must be a valid type; note whether all cells share one
+    std::vector<int32_t> types((size_t)n_cells + 1);
+    hipStream_t st = as_stream(stream);
+    hipError_t e = hipMemcpyAsync(types.data(), d_cell_type, sizeof(int32_t) * types.size(), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return device_fail(e, "read cell types");
+    if (types[0] != 0) return fail(CPM_EINVAL, "cell_type[0] must be 0 (the medium's type)");
+    int32_t single = n_cells >= 1 ? types[1] : 0;
+    for (int32_t c = 1; c <= n_cells; ++c) {
+        if (types[c] < 0 || types[c] >= params->n_types) return fail(CPM_EINVAL, "cell type out of range");
+        if (types[c] != single) single = -1;
+    }
+    if (params->act_enabled) {
+        for (int32_t c = 1; c <= n_cells; ++c)
+            if (params->max_act[types[c]] > 0 && params->lambda_act == nullptr)
+                return fail(CPM_EINVAL, "motile type without lambda_act");
+    }
+
     char *ws = static_cast<char *>(d_workspace);
     h->ndim = params->ndim;
     for (int d = 0; d < 3; ++d) h->L[d] = params->dims[d];
@@ -228,14 +327,19 @@ int cpm_init(const cpm_params *params, int32_t *d_lattice, const int32_t *d_cell
     h->k = params->attempts;
     h->n_cells = n_cells;
     h->act = params->act_enabled != 0;
+    h->mirror = lay.mirror_on;
+    h->mirror_cells = lay.mirror_on ? reinterpret_cast<int16_t *>(ws + lay.mirror) : nullptr;
     SweepArgs &a = h->args;
     a.lat = d_lattice;
+    a.cells = h->mirror ? static_cast<void *>(h->mirror_cells) : static_cast<void *>(d_lattice);
     a.cell_type = d_cell_type;
     a.act = h->act ? d_act : nullptr;
     a.model = reinterpret_cast<const DeviceModel *>(ws + lay.model);
     a.counters[0] = reinterpret_cast<int32_t *>(ws + lay.counters0);
     a.counters[1] = reinterpret_cast<int32_t *>(ws + lay.counters1);
-    a.prev = reinterpret_cast<int4 *>(ws + lay.prev);
+    a.dlist = reinterpret_cast<int4 *>(ws + lay.dlist);
+    a.dcount = reinterpret_cast<int32_t *>(ws + lay.dcount);
+    a.stats = reinterpret_cast<uint64_t *>(ws + lay.stats);
     h->ref = reinterpret_cast<int32_t *>(ws + lay.ref);
     uint32_t n_areas = 1;
     for (int d = 0; d < 3; ++d) {
@@ -246,19 +350,23 @@ int cpm_init(const cpm_params *params, int32_t *d_lattice, const int32_t *d_cell
     a.n_areas = n_areas;
     a.s = params->sub;
     a.k = params->attempts;
+    a.dlist_cap = lay.dlist_cap;
     a.obstacle_type = params->obstacle_type < 0 ? 0 : params->obstacle_type;
+    a.single_type = single;
     a.key0 = (uint32_t)params->seed;
     a.key1 = (uint32_t)(params->seed >> 32);
     a.lattice_id = params->lattice_id;
+    a.tg = lay.tg;
 
-    hipStream_t st = as_stream(stream);
-    hipError_t e = hipMemcpyAsync(ws + lay.model, h->host_model.get(), sizeof(DeviceModel), hipMemcpyHostToDevice, st);
+    e = hipMemcpyAsync(ws + lay.model, h->host_model.get(), sizeof(DeviceModel), hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return device_fail(e, "upload model");
     const size_t pairs = 2 * ((size_t)n_cells + 1);
     if ((e = cpm::launch_fill_i32(a.counters[0], 0, pairs, st)) != hipSuccess) return device_fail(e, "clear counters");
-    if ((e = cpm::launch_fill_i32(reinterpret_cast<int32_t *>(a.prev), 0,
-                                  4 * (size_t)n_areas * (size_t)params->attempts, st)) != hipSuccess)
-        return device_fail(e, "clear deltas");
+    if ((e = cpm::launch_fill_i32(a.dcount, 0, (size_t)lay.tg.n_tiles, st)) != hipSuccess)
+        return device_fail(e, "clear delta lists");
+    if ((e = cpm::launch_fill_i32(reinterpret_cast<int32_t *>(a.stats), 0, 4 * (size_t)lay.tg.n_tiles, st)) !=
+        hipSuccess)
+        return device_fail(e, "clear stats");
     if ((e = cpm::launch_count(a, h->ndim, a.counters[0], a.counters[0] + 1, 2, st)) != hipSuccess)
         return device_fail(e, "count");
     e = hipMemcpyAsync(a.counters[1], a.counters[0], sizeof(int32_t) * pairs, hipMemcpyDeviceToDevice, st);
@@ -271,24 +379,47 @@ int cpm_sweep(cpm_handle *h, int32_t n_mcs, void *stream)
 {
     if (!h) return fail(CPM_EINVAL, "handle is NULL");
     if (n_mcs < 0) return fail(CPM_EINVAL, "n_mcs must be >= 0");
+    if (n_mcs == 0) return CPM_OK;
     hipStream_t st = as_stream(stream);
     int64_t sd = 1;
     for (int d = 0; d < h->ndim; ++d) sd *= h->s;
     const uint32_t n_act = (uint32_t)(((int64_t)1 << h->ndim) * sd / h->k);
     const size_t n_sites = (size_t)h->L[0] * h->L[1] * h->L[2];
+    hipError_t e;
+    if (h->mirror && (e = cpm::launch_to_mirror(h->args.lat, h->mirror_cells, n_sites, st)) != hipSuccess)
+        return device_fail(e, "to int16 working copy");
     for (int32_t i = 0; i < n_mcs; ++i) {
         const uint32_t mcs = (uint32_t)h->mcs;
         for (uint32_t alpha = 0; alpha < n_act; ++alpha) {
-            const hipError_t e = cpm::launch_activation(h->args, h->ndim, h->act, mcs, alpha,
-                                                        (int)(h->activation & 1), st);
+            e = cpm::launch_activation(h->args, h->ndim, h->act, h->mirror, mcs, alpha, (int)(h->activation & 1), st);
             if (e != hipSuccess) return device_fail(e, "activation");
             ++h->activation;
         }
-        if (h->act) {
-            const hipError_t e = cpm::launch_act_decay(h->args.act, n_sites, st);
-            if (e != hipSuccess) return device_fail(e, "act decay");
-        }
+        if (h->act && (e = cpm::launch_act_decay(h->args.act, n_sites, st)) != hipSuccess)
+            return device_fail(e, "act decay");
         ++h->mcs;
+        h->attempts_run += (uint64_t)n_sites;
+    }
+    if (h->mirror && (e = cpm::launch_from_mirror(h->mirror_cells, h->args.lat, n_sites, st)) != hipSuccess)
+        return device_fail(e, "from int16 working copy");
+    return CPM_OK;
+}
+
+int cpm_attempt_stats(cpm_handle *h, uint64_t *out, void *stream)
+{
+    if (!h || !out) return fail(CPM_EINVAL, "NULL argument");
+    hipStream_t st = as_stream(stream);
+    const int n = h->args.tg.n_tiles;
+    std::vector<uint64_t> per(2 * (size_t)n);
+    hipError_t e = hipMemcpyAsync(per.data(), h->args.stats, sizeof(uint64_t) * per.size(), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return device_fail(e, "read stats");
+    out[0] = h->attempts_run;
+    out[1] = 0;
+    out[2] = 0;
+    for (int i = 0; i < n; ++i) {
+        out[1] += per[2 * (size_t)i];
+        out[2] += per[2 * (size_t)i + 1];
     }
     return CPM_OK;
 }

@@ -1,0 +1,59 @@
+// Device-side building blocks of the CPM sweep: Philox, the Moore
+// neighbourhood, the Metropolis threshold and the Act geometric mean.
+#pragma once
+
+#include "cpm_internal.hpp"
+
+namespace cpm {
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 32x32->64-bit products, key bumped by the Weyl constants between rounds.
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+__device__ __forceinline__ int wrap_once(int v, int L) { return v < 0 ? v + L : (v >= L ? v - L : v); }
+
+// Moore offset n (lexicographic, z slowest, x fastest, the centre left out).
+template <int D>
+__device__ __forceinline__ constexpr int nb_dx(int n) { return (D == 2 ? (n < 4 ? n : n + 1) : (n < 13 ? n : n + 1)) % 3 - 1; }
+template <int D>
+__device__ __forceinline__ constexpr int nb_dy(int n) { return (D == 2 ? (n < 4 ? n : n + 1) / 3 : ((n < 13 ? n : n + 1) / 3) % 3) - 1; }
+template <int D>
+__device__ __forceinline__ constexpr int nb_dz(int n) { return D == 2 ? 0 : (n < 13 ? n : n + 1) / 9 - 1; }
+
+// Accept iff q <= 0 or u < floor(TI[h] TM[m] TL[l] / 2^64), q = h*2^16 + m*2^8 + l.
+__device__ __forceinline__ bool metropolis(const DeviceModel *m, int64_t q, uint32_t u)
+{
+    if (q <= 0) return true;
+    const uint64_t h = (uint64_t)q >> 16;
+    if (h >= (uint64_t)m->n_ti) return false;
+    uint64_t thr;
+    if ((q & 0xFFFF) == 0) {
+        thr = m->TI[h];
+    } else {
+        // TM[m] * TL[l] < 2^64 whenever (m, l) != (0, 0)
+        const uint64_t p = m->TM[(q >> 8) & 255] * m->TL[q & 255];
+        thr = __umul64hi(m->TI[h], p);
+    }
+    return (uint64_t)u < thr;
+}
+
+// exp(l * 2^-24) in 2^16 fixed point, floor-composed from the split tables.
+__device__ __forceinline__ int64_t exp_log24(const DeviceModel *m, uint64_t ell)
+{
+    const uint64_t p1 = (m->EH[ell >> 16] * m->EM[(ell >> 8) & 255]) >> 31;
+    const uint64_t p2 = (p1 * m->EL[ell & 255]) >> 30;
+    return (int64_t)(p2 >> 8);
+}
+
+}  // namespace cpm

@@ -11,6 +11,8 @@ namespace cpm {
 constexpr int kMaxTypes = 16;
 constexpr int kMaxTI = 4096;  // TI entries: enough for T up to ~184
 constexpr int kMaxAttempts = 8;
+constexpr int kBlock = 256;   // threads per sweep workgroup (one per thread area)
+constexpr int kXcds = 8;      // MI355X: workgroups go round-robin to 8 XCDs, each with its own L2
 
 // Quantised model + acceptance / activity tables, copied once into the
 // workspace at init.  Energies in units of 2^-16.
@@ -36,34 +38,58 @@ struct DeviceModel {
     uint64_t EL[256];
 };
 
+// How thread areas are grouped into workgroup tiles.  Tiles are numbered x
+// fastest; the tiles of XCD x are the contiguous range
+// [x * tiles_per_xcd, (x + 1) * tiles_per_xcd), so each XCD sweeps one slab
+// of the lattice in every activation and its L2 keeps that slab.
+struct TileGeometry {
+    int32_t T[3];          // thread areas per tile per axis
+    int32_t nt[3];         // tiles per axis
+    int32_t n_tiles;
+    int32_t tiles_per_xcd;
+    int32_t grid;          // workgroups launched: kXcds * tiles_per_xcd
+    int32_t box_sites;     // LDS sites of the largest staged box
+    int32_t lds_bytes;
+    int32_t full_rows;     // 1: tiles span whole rows along x (full-row LDS layout)
+};
+
 // Everything a sweep kernel needs, passed by value.
 struct SweepArgs {
-    int32_t *lat;
+    void *cells;           // lattice the sweep works on: the caller's int32 one or the int16 mirror
+    int32_t *lat;          // the caller's int32 lattice
     const int32_t *cell_type;
     uint8_t *act;
     const DeviceModel *model;
     int32_t *counters[2];  // ping-pong (V, S) pairs per label
-    int4 *prev;            // per area and attempt: deltas of the previous activation
+    int4 *dlist;           // per tile: accepted copies of the previous activation
+    int32_t *dcount;       // per tile: number of records in dlist
+    uint64_t *stats;       // per tile: attempts past the early rejection, accepted copies
     int32_t L[3];
     int32_t na[3];         // thread areas per axis
     uint32_t n_areas;
     int32_t s;
     int32_t k;
+    int32_t dlist_cap;     // records per tile
     int32_t obstacle_type;
+    int32_t single_type;   // the one type of every cell, or -1 when cells differ in type
     uint32_t key0, key1;
     uint32_t lattice_id;
+    TileGeometry tg;
 };
 
-// Launchers (cpm_kernels.hip).  All asynchronous on `stream`.
+// Launchers.  All asynchronous on `stream`.
 hipError_t launch_fill_i32(int32_t *p, int32_t value, size_t n, hipStream_t stream);
 hipError_t launch_count(const SweepArgs &a, int ndim, int32_t *v_out, int32_t *s_out, int stride,
                         hipStream_t stream);
-hipError_t launch_activation(const SweepArgs &a, int ndim, bool act, uint32_t mcs, uint32_t alpha,
-                             int parity, hipStream_t stream);
+hipError_t launch_activation(const SweepArgs &a, int ndim, bool act, bool mirror, uint32_t mcs,
+                             uint32_t alpha, int parity, hipStream_t stream);
+hipError_t launch_to_mirror(const int32_t *lat, int16_t *mirror, size_t n, hipStream_t stream);
+hipError_t launch_from_mirror(const int16_t *mirror, int32_t *lat, size_t n, hipStream_t stream);
 hipError_t launch_act_decay(uint8_t *act, size_t n, hipStream_t stream);
 hipError_t launch_centroids(const SweepArgs &a, int ndim, int32_t n_cells, int32_t *ref,
                             int64_t *out, hipStream_t stream);
 hipError_t launch_copy_counters(const int32_t *pairs, int32_t n_labels, int32_t *v_out,
                                 int32_t *s_out, hipStream_t stream);
+size_t sweep_lds_bytes(int ndim, bool act, bool mirror, int box_sites);
 
 }  // namespace cpm

@@ -1,0 +1,467 @@
+// The activation kernel of the CPM sweep for gfx950.
+//
+// One launch runs one activation of the checkerboard scheme (paper, Results,
+// "Designing a parallel execution scheme", Fig. 2A; one barrier per copy
+// attempt, Fig. 3A): every thread area makes k copy attempts inside its
+// sub-area of the active colour.
+//
+// Work split: one workgroup per tile of up to 256 thread areas (one thread
+// per area).  The tile's active sub-areas plus their read halo are staged
+// into LDS with coalesced loads (paper, Methods, "GPU implementation
+// details": shared-memory caching of the active regions, write-through on
+// accepted copies).  Two LDS layouts:
+//   full rows - the tile spans whole lattice rows along x; each LDS row holds
+//               one whole lattice row, copied with aligned 16-byte loads, and
+//               neighbours wrap around x inside LDS;
+//   box       - any tile shape; the staged box is the tile's sub-areas plus
+//               the halo, copied element by element.
+// Tiles go to XCDs in contiguous slabs (workgroups are dispatched to the 8
+// XCDs round-robin), so every activation of a sweep finds the XCD's slab in
+// the same L2.
+//
+// For k = 1 the copy attempts of a workgroup run in two phases: all threads
+// draw their attempt and drop the trivial ones (equal labels or an
+// obstacle); the rest are compacted into an LDS queue and worked off by the
+// first threads, so the energy evaluation runs on as few waves as needed.
+//
+// Per-cell counters are double buffered: activation g reads buffer g&1 (the
+// exact state at its start) and adds its own deltas plus those of activation
+// g-1 (kept per tile in `dlist`) into buffer (g+1)&1, which so becomes the
+// exact state at the start of g+1.
+#include "cpm_device.hpp"
+
+namespace cpm {
+namespace {
+
+__device__ __forceinline__ void add_deltas(int32_t *wr, int4 d)
+{
+    if (d.x >= 1) {
+        atomicAdd(&wr[2 * d.x], -1);
+        atomicAdd(&wr[2 * d.x + 1], d.z);
+    }
+    if (d.y >= 1) {
+        atomicAdd(&wr[2 * d.y], 1);
+        atomicAdd(&wr[2 * d.y + 1], d.w);
+    }
+}
+
+__host__ __device__ constexpr int align16(int v) { return (v + 15) & ~15; }
+
+// Where a lattice site lives in LDS.  Full-row layout: x is the global
+// coordinate and wraps; box layout: x is box-local.  y, z are box-local.
+template <bool FULLROW>
+struct LdsMap {
+    int pitch;  // sites per LDS row
+    int rows;   // LDS rows per z plane
+    int L0;
+    __device__ __forceinline__ int x(int v) const { return FULLROW ? wrap_once(v, L0) : v; }
+    __device__ __forceinline__ int at(int vx, int vy, int vz) const { return x(vx) + pitch * (vy + rows * vz); }
+};
+
+// Geometric mean of the activity over the site at (x,y,z) (label `cell`) and
+// its Moore neighbours of the same cell (eq. 8), 2^16 fixed point.
+template <typename Cell, int D, bool FULLROW>
+__device__ __forceinline__ int64_t gm_lds(const DeviceModel *m, const Cell *lab, const uint8_t *lact,
+                                          const LdsMap<FULLROW> &map, int x, int y, int z, int cell, bool motile)
+{
+    if (cell <= 0 || !motile) return 0;
+    const int c = map.at(x, y, z);
+    const uint32_t a0 = lact[c];
+    uint64_t sum = (uint64_t)m->LG[a0];
+    uint32_t cnt = 1;
+    bool zero = a0 == 0;
+    constexpr int NNB = D == 2 ? 8 : 26;
+#pragma unroll
+    for (int n = 0; n < NNB; ++n) {
+        const int u = map.at(x + nb_dx<D>(n), y + nb_dy<D>(n), z + nb_dz<D>(n));
+        if ((int)lab[u] == cell) {
+            const uint32_t au = lact[u];
+            zero |= au == 0;
+            sum += (uint64_t)m->LG[au];
+            ++cnt;
+        }
+    }
+    return zero ? 0 : exp_log24(m, sum / cnt);
+}
+
+// One copy attempt past the early rejection: energy change, Metropolis test,
+// commit.  Returns the delta record (labels, surface deltas) if accepted.
+template <typename Cell, int D, bool ACT, bool SINGLE, bool FULLROW, int NOWN>
+__device__ __forceinline__ bool evaluate(const SweepArgs &a, const int32_t *rd, Cell *lab, uint8_t *lact,
+                                         const LdsMap<FULLROW> &map,
+                                         int tx_, int ty_, int tz_, int sx_, int sy_, int sz_, int lt, int ls,
+                                         uint32_t u2, const int4 *own, int n_own, int64_t &dso_out,
+                                         int64_t &dsn_out)
+{
+    constexpr int NNB = D == 2 ? 8 : 26;
+    const DeviceModel *m = a.model;
+    const int tc = a.single_type, to = a.obstacle_type;
+    const int tt = lt == 0 ? 0 : (SINGLE ? tc : a.cell_type[lt]);
+    const int ts = ls == 0 ? 0 : (SINGLE ? tc : a.cell_type[ls]);
+    // the three x positions and the row offsets of the target's neighbourhood
+    const int xm = map.x(tx_ - 1), x0 = map.x(tx_), xp = map.x(tx_ + 1);
+    int k_old = 0, k_new = 0;
+    int n_cell = 0, n_med = 0, n_obs = 0;
+    int64_t adh = 0;
+#pragma unroll
+    for (int n = 0; n < NNB; ++n) {
+        const int dx = nb_dx<D>(n);
+        const int xx = dx < 0 ? xm : (dx > 0 ? xp : x0);
+        const int lu = lab[xx + map.pitch * (ty_ + nb_dy<D>(n) + map.rows * (tz_ + nb_dz<D>(n)))];
+        k_old += lu == lt;
+        k_new += lu == ls;
+        if (SINGLE) {
+            n_cell += lu > 0;
+            n_med += lu == 0;
+            n_obs += lu < 0;
+        } else {
+            const int tu = lu < 0 ? to : a.cell_type[lu];
+            if (lu != ls) adh += m->J[ts * kMaxTypes + tu];
+            if (lu != lt) adh -= m->J[tt * kMaxTypes + tu];
+        }
+    }
+    if (SINGLE) {
+        // neighbours unlike the label, weighted by J(label type, their type)
+        const int64_t cs = n_cell - (ls > 0 ? k_new : 0), ms = n_med - (ls == 0 ? k_new : 0);
+        const int64_t ct = n_cell - (lt > 0 ? k_old : 0), mt = n_med - (lt == 0 ? k_old : 0);
+        const int64_t *Js = m->J + ts * kMaxTypes, *Jt = m->J + tt * kMaxTypes;
+        adh = Js[tc] * cs + Js[0] * ms + Js[to] * n_obs - (Jt[tc] * ct + Jt[0] * mt + Jt[to] * n_obs);
+    }
+    const int64_t dso = 2 * k_old - NNB;
+    const int64_t dsn = NNB - 2 * k_new;
+    int64_t q = adh;
+    if (lt >= 1) {
+        const int2 vs = reinterpret_cast<const int2 *>(rd)[lt];
+        int64_t v = vs.x, sf = vs.y;
+#pragma unroll
+        for (int jj = 0; jj < NOWN; ++jj) {
+            if (jj < n_own && own[jj].x == lt) { v -= 1; sf += own[jj].z; }
+            if (jj < n_own && own[jj].y == lt) { v += 1; sf += own[jj].w; }
+        }
+        q += m->lam_v[tt] * (1 - 2 * (v - m->v_target[tt]));
+        q += m->lam_s[tt] * (2 * dso * (sf - m->s_target[tt]) + dso * dso);
+    }
+    if (ls >= 1) {
+        const int2 vs = reinterpret_cast<const int2 *>(rd)[ls];
+        int64_t v = vs.x, sf = vs.y;
+#pragma unroll
+        for (int jj = 0; jj < NOWN; ++jj) {
+            if (jj < n_own && own[jj].x == ls) { v -= 1; sf += own[jj].z; }
+            if (jj < n_own && own[jj].y == ls) { v += 1; sf += own[jj].w; }
+        }
+        q += m->lam_v[ts] * (2 * (v - m->v_target[ts]) + 1);
+        q += m->lam_s[ts] * (2 * dsn * (sf - m->s_target[ts]) + dsn * dsn);
+    }
+    if (ACT) {
+        const int64_t gt = gm_lds<Cell, D, FULLROW>(m, lab, lact, map, tx_, ty_, tz_, lt, lt > 0 && m->max_act[tt] > 0);
+        const int64_t gs = gm_lds<Cell, D, FULLROW>(m, lab, lact, map, sx_, sy_, sz_, ls, ls > 0 && m->max_act[ts] > 0);
+        const int64_t rt = lt >= 1 ? m->r_act[tt] : 0;
+        const int64_t rs = ls >= 1 ? m->r_act[ts] : 0;
+        q += (rt * gt - rs * gs) >> 16;
+    }
+    dso_out = dso;
+    dsn_out = dsn;
+    return metropolis(m, q, u2);
+}
+
+template <typename Cell, int D, bool ACT, bool SINGLE, bool K1, bool FULLROW>
+__global__ void __launch_bounds__(kBlock) tile_sweep_kernel(SweepArgs a, uint32_t mcs, uint32_t alpha, int parity)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int list_n, queue_n;
+    __shared__ uint32_t n_nontrivial, n_accepted;
+    __shared__ int4 queue[K1 ? kBlock : 1];  // compacted attempts: (target, source, draw, global index)
+    constexpr int R = ACT ? 2 : 1;           // read radius: the Act term reads neighbours of the source
+    constexpr int NNB = D == 2 ? 8 : 26;
+
+    const TileGeometry &tg = a.tg;
+    const int tile = (int)(blockIdx.x % kXcds) * tg.tiles_per_xcd + (int)(blockIdx.x / kXcds);
+    if (tile >= tg.n_tiles) return;  // uniform over the block
+    const int tid = threadIdx.x;
+    const int L0 = a.L[0], L1 = a.L[1], L2 = a.L[2];
+    const int s = a.s;
+    const uint32_t phi = alpha & ((1u << D) - 1);
+    const int cx = (int)(phi & 1), cy = (int)((phi >> 1) & 1), cz = (int)((phi >> 2) & 1);
+    const int tx = tile % tg.nt[0], ty = (tile / tg.nt[0]) % tg.nt[1], tz = tile / (tg.nt[0] * tg.nt[1]);
+    const int A0 = tx * tg.T[0], A1 = ty * tg.T[1], A2 = tz * tg.T[2];
+    const int n0 = min(tg.T[0], a.na[0] - A0), n1 = min(tg.T[1], a.na[1] - A1);
+    const int n2 = D == 3 ? min(tg.T[2], a.na[2] - A2) : 1;
+    // staged box: sub-areas of the active colour plus the read halo
+    const int b0 = FULLROW ? L0 : 2 * s * (n0 - 1) + s + 2 * R;
+    const int b1 = 2 * s * (n1 - 1) + s + 2 * R;
+    const int b2 = D == 3 ? 2 * s * (n2 - 1) + s + 2 * R : 1;
+    const int o0 = FULLROW ? 0 : 2 * s * A0 + s * cx - R;
+    const int o1 = 2 * s * A1 + s * cy - R;
+    const int o2 = D == 3 ? 2 * s * A2 + s * cz - R : 0;
+    const LdsMap<FULLROW> map{b0, b1, L0};
+    Cell *lab = reinterpret_cast<Cell *>(smem);
+    uint8_t *lact = smem + align16(tg.box_sites * (int)sizeof(Cell));
+    Cell *cells = reinterpret_cast<Cell *>(a.cells);
+    const int32_t *rd = a.counters[parity];
+    int32_t *wr = a.counters[parity ^ 1];
+    int4 *dl = a.dlist + (size_t)tile * a.dlist_cap;
+
+    if (tid == 0) {
+        list_n = 0;
+        queue_n = 0;
+        n_nontrivial = 0;
+        n_accepted = 0;
+    }
+    // deltas of the previous activation go into the write buffer as well
+    const int prev_n = a.dcount[tile];
+    for (int i = tid; i < prev_n; i += kBlock) add_deltas(wr, dl[i]);
+
+    // stage the box (labels, and activity for the Act term)
+    const int rows = b1 * b2;
+    if (FULLROW) {
+        // whole rows: 16-byte chunks, eight loads in flight per thread
+        const int cpr = L0 * (int)sizeof(Cell) / 16;
+        auto row_chunk = [&](int c, int per_row) {
+            const int r = c / per_row, off = c - r * per_row;
+            const int gy = wrap_once(o1 + r % b1, L1);
+            const int gz = D == 3 ? wrap_once(o2 + r / b1, L2) : 0;
+            return ((size_t)gz * L1 + gy) * per_row + off;
+        };
+        auto copy_rows = [&](const uint4 *src, uint4 *dst, int per_row) {
+            const int total = rows * per_row;
+            int c0 = tid;
+            for (; c0 + 7 * kBlock < total; c0 += 8 * kBlock) {
+                // eight independent loads before the first LDS store
+                const uint4 v0 = src[row_chunk(c0, per_row)];
+                const uint4 v1 = src[row_chunk(c0 + kBlock, per_row)];
+                const uint4 v2 = src[row_chunk(c0 + 2 * kBlock, per_row)];
+                const uint4 v3 = src[row_chunk(c0 + 3 * kBlock, per_row)];
+                const uint4 v4 = src[row_chunk(c0 + 4 * kBlock, per_row)];
+                const uint4 v5 = src[row_chunk(c0 + 5 * kBlock, per_row)];
+                const uint4 v6 = src[row_chunk(c0 + 6 * kBlock, per_row)];
+                const uint4 v7 = src[row_chunk(c0 + 7 * kBlock, per_row)];
+                dst[c0] = v0;
+                dst[c0 + kBlock] = v1;
+                dst[c0 + 2 * kBlock] = v2;
+                dst[c0 + 3 * kBlock] = v3;
+                dst[c0 + 4 * kBlock] = v4;
+                dst[c0 + 5 * kBlock] = v5;
+                dst[c0 + 6 * kBlock] = v6;
+                dst[c0 + 7 * kBlock] = v7;
+            }
+            for (; c0 < total; c0 += kBlock) dst[c0] = src[row_chunk(c0, per_row)];
+        };
+        copy_rows(reinterpret_cast<const uint4 *>(cells), reinterpret_cast<uint4 *>(lab), cpr);
+        if (ACT) copy_rows(reinterpret_cast<const uint4 *>(a.act), reinterpret_cast<uint4 *>(lact), L0 / 16);
+    } else {
+        const int wave = tid >> 6, lane = tid & 63;
+        for (int r = wave; r < rows; r += kBlock / 64) {
+            const int gy = wrap_once(o1 + r % b1, L1);
+            const int gz = D == 3 ? wrap_once(o2 + r / b1, L2) : 0;
+            const size_t base = ((size_t)gz * L1 + gy) * L0;
+            for (int x = lane; x < b0; x += 64) {
+                const int gx = wrap_once(o0 + x, L0);
+                lab[r * b0 + x] = cells[base + gx];
+                if (ACT) lact[r * b0 + x] = a.act[base + gx];
+            }
+        }
+    }
+    __syncthreads();
+
+    const int areas = n0 * n1 * n2;
+    const uint32_t sd = D == 2 ? (uint32_t)(s * s) : (uint32_t)(s * s * s);
+    // draw of one attempt: target and source in LDS coordinates
+    auto draw = [&](int area_local, int j, int &ttx, int &tty, int &ttz, int &ssx, int &ssy, int &ssz, uint32_t &u2,
+                    uint32_t &area_id) {
+        const int ax = area_local % n0, ay = (area_local / n0) % n1, az = area_local / (n0 * n1);
+        area_id = (uint32_t)(A0 + ax) + (uint32_t)a.na[0] * ((uint32_t)(A1 + ay) + (uint32_t)a.na[1] * (uint32_t)(A2 + az));
+        const uint4 u = philox4x32_10(make_uint4(area_id, mcs, (alpha << 8) | (uint32_t)j, a.lattice_id), a.key0, a.key1);
+        const uint32_t o = (uint32_t)(((uint64_t)u.x * sd) >> 32);
+        const int ox = (int)(o % (uint32_t)s), oy = (int)((o / (uint32_t)s) % (uint32_t)s);
+        const int oz = D == 3 ? (int)(o / (uint32_t)(s * s)) : 0;
+        ttx = FULLROW ? 2 * s * ax + s * cx + ox : 2 * s * ax + R + ox;
+        tty = 2 * s * ay + R + oy;
+        ttz = D == 3 ? 2 * s * az + R + oz : 0;
+        const int nsel = (int)(((uint64_t)u.y * (uint32_t)NNB) >> 32);
+        const int msel = nsel < NNB / 2 ? nsel : nsel + 1;
+        ssx = ttx + msel % 3 - 1;
+        ssy = tty + (msel / 3) % 3 - 1;
+        ssz = D == 3 ? ttz + msel / 9 - 1 : 0;
+        u2 = u.z;
+    };
+    auto global_index = [&](int vx, int vy, int vz) {
+        const int gx = FULLROW ? vx : wrap_once(o0 + vx, L0);
+        const int gy = wrap_once(o1 + vy, L1);
+        const int gz = D == 3 ? wrap_once(o2 + vz, L2) : 0;
+        return (int)(((size_t)gz * L1 + gy) * L0 + gx);
+    };
+    auto commit = [&](int t, int gi, int lt, int ls, int64_t dso, int64_t dsn) {
+        lab[t] = (Cell)ls;
+        cells[gi] = (Cell)ls;
+        if (ACT) {
+            const int ts = ls == 0 ? 0 : (a.single_type >= 0 ? a.single_type : a.cell_type[ls]);
+            const uint8_t na = (ls >= 1 && a.model->max_act[ts] > 0) ? (uint8_t)a.model->max_act[ts] : (uint8_t)0;
+            lact[t] = na;
+            a.act[gi] = na;
+        }
+        const int4 rec = make_int4(lt, ls, (int)dso, (int)dsn);
+        add_deltas(wr, rec);
+        dl[atomicAdd(&list_n, 1)] = rec;
+        return rec;
+    };
+
+    uint32_t my_accepted = 0;
+    if (K1) {
+        // phase 1: draw, drop trivial attempts, queue the rest
+        if (tid < areas) {
+            int ttx, tty, ttz, ssx, ssy, ssz;
+            uint32_t u2, area_id;
+            draw(tid, 0, ttx, tty, ttz, ssx, ssy, ssz, u2, area_id);
+            const int t = map.at(ttx, tty, ttz), sidx = map.at(ssx, ssy, ssz);
+            const int lt = lab[t], ls = lab[sidx];
+            if (lt != ls && lt >= 0 && ls >= 0) {
+                const int slot = atomicAdd(&queue_n, 1);
+                // pack the LDS coordinates of target and source
+                queue[slot] = make_int4(ttx | (tty << 16), ttz | (ssz << 16), (ssx & 0xFFFF) | (ssy << 16), (int)u2);
+            }
+        }
+        __syncthreads();
+        // phase 2: energy change and Metropolis test of the queued attempts
+        const int qn = queue_n;
+        for (int i = tid; i < qn; i += kBlock) {
+            const int4 e = queue[i];
+            const int ttx = e.x & 0xFFFF, tty = e.x >> 16, ttz = e.y & 0xFFFF;
+            const int ssz = e.y >> 16, ssx = (int)(int16_t)(e.z & 0xFFFF), ssy = e.z >> 16;
+            const int t = map.at(ttx, tty, ttz);
+            const int lt = lab[t], ls = lab[map.at(ssx, ssy, ssz)];
+            int64_t dso, dsn;
+            if (evaluate<Cell, D, ACT, SINGLE, FULLROW, 0>(a, rd, lab, lact, map, ttx, tty, ttz, ssx, ssy, ssz, lt,
+                                                           ls, (uint32_t)e.w, nullptr, 0, dso, dsn)) {
+                ++my_accepted;
+                commit(t, global_index(ttx, tty, ttz), lt, ls, dso, dsn);
+            }
+        }
+        if (tid == 0) n_nontrivial = (uint32_t)qn;
+    } else {
+        uint32_t my_nontrivial = 0;
+        if (tid < areas) {
+            int4 own[kMaxAttempts];
+            for (int j = 0; j < a.k; ++j) {
+                int ttx, tty, ttz, ssx, ssy, ssz;
+                uint32_t u2, area_id;
+                draw(tid, j, ttx, tty, ttz, ssx, ssy, ssz, u2, area_id);
+                const int t = map.at(ttx, tty, ttz);
+                const int lt = lab[t], ls = lab[map.at(ssx, ssy, ssz)];
+                int4 rec = make_int4(0, 0, 0, 0);
+                if (lt != ls && lt >= 0 && ls >= 0) {
+                    ++my_nontrivial;
+                    int64_t dso, dsn;
+                    if (evaluate<Cell, D, ACT, SINGLE, FULLROW, kMaxAttempts>(a, rd, lab, lact, map, ttx, tty, ttz,
+                                                                              ssx, ssy, ssz, lt, ls, u2, own, j,
+                                                                              dso, dsn)) {
+                        ++my_accepted;
+                        rec = commit(t, global_index(ttx, tty, ttz), lt, ls, dso, dsn);
+                    }
+                }
+#pragma unroll
+                for (int jj = 0; jj < kMaxAttempts; ++jj)
+                    if (jj == j) own[jj] = rec;
+            }
+        }
+        if (my_nontrivial) atomicAdd(&n_nontrivial, my_nontrivial);
+    }
+    if (my_accepted) atomicAdd(&n_accepted, my_accepted);
+    __syncthreads();
+    if (tid == 0) {
+        a.dcount[tile] = list_n;
+        a.stats[2 * tile] += n_nontrivial;
+        a.stats[2 * tile + 1] += n_accepted;
+    }
+}
+
+template <typename Cell, int D, bool ACT, bool SINGLE>
+hipError_t launch_k(const SweepArgs &a, bool k1, bool fullrow, uint32_t mcs, uint32_t alpha, int parity, size_t lds,
+                    hipStream_t st)
+{
+    if (k1 && fullrow)
+        tile_sweep_kernel<Cell, D, ACT, SINGLE, true, true><<<a.tg.grid, kBlock, lds, st>>>(a, mcs, alpha, parity);
+    else if (k1)
+        tile_sweep_kernel<Cell, D, ACT, SINGLE, true, false><<<a.tg.grid, kBlock, lds, st>>>(a, mcs, alpha, parity);
+    else
+        tile_sweep_kernel<Cell, D, ACT, SINGLE, false, false><<<a.tg.grid, kBlock, lds, st>>>(a, mcs, alpha, parity);
+    return hipGetLastError();
+}
+
+template <typename Cell, int D, bool ACT>
+hipError_t launch_s(const SweepArgs &a, uint32_t mcs, uint32_t alpha, int parity, size_t lds, hipStream_t st)
+{
+    const bool k1 = a.k == 1, fr = a.tg.full_rows != 0;
+    return a.single_type >= 0 ? launch_k<Cell, D, ACT, true>(a, k1, fr, mcs, alpha, parity, lds, st)
+                              : launch_k<Cell, D, ACT, false>(a, k1, fr, mcs, alpha, parity, lds, st);
+}
+
+template <typename Cell>
+hipError_t launch_c(const SweepArgs &a, int ndim, bool act, uint32_t mcs, uint32_t alpha, int parity, size_t lds,
+                    hipStream_t st)
+{
+    if (ndim == 2)
+        return act ? launch_s<Cell, 2, true>(a, mcs, alpha, parity, lds, st)
+                   : launch_s<Cell, 2, false>(a, mcs, alpha, parity, lds, st);
+    return act ? launch_s<Cell, 3, true>(a, mcs, alpha, parity, lds, st)
+               : launch_s<Cell, 3, false>(a, mcs, alpha, parity, lds, st);
+}
+
+__global__ void to_mirror_kernel(const int32_t *__restrict__ lat, int16_t *__restrict__ mir, size_t n)
+{
+    const size_t i = ((size_t)blockIdx.x * kBlock + threadIdx.x) * 4;
+    if (i + 4 <= n) {
+        const int4 v = *reinterpret_cast<const int4 *>(lat + i);
+        short4 w;
+        w.x = (short)v.x;
+        w.y = (short)v.y;
+        w.z = (short)v.z;
+        w.w = (short)v.w;
+        *reinterpret_cast<short4 *>(mir + i) = w;
+    } else {
+        for (size_t j = i; j < n; ++j) mir[j] = (int16_t)lat[j];
+    }
+}
+
+__global__ void from_mirror_kernel(const int16_t *__restrict__ mir, int32_t *__restrict__ lat, size_t n)
+{
+    const size_t i = ((size_t)blockIdx.x * kBlock + threadIdx.x) * 4;
+    if (i + 4 <= n) {
+        const short4 w = *reinterpret_cast<const short4 *>(mir + i);
+        *reinterpret_cast<int4 *>(lat + i) = make_int4(w.x, w.y, w.z, w.w);
+    } else {
+        for (size_t j = i; j < n; ++j) lat[j] = mir[j];
+    }
+}
+
+}  // namespace
+
+size_t sweep_lds_bytes(int ndim, bool act, bool mirror, int box_sites)
+{
+    (void)ndim;
+    const int cell = mirror ? 2 : 4;
+    return (size_t)align16(box_sites * cell) + (act ? (size_t)align16(box_sites) : 0);
+}
+
+hipError_t launch_activation(const SweepArgs &a, int ndim, bool act, bool mirror, uint32_t mcs, uint32_t alpha,
+                             int parity, hipStream_t stream)
+{
+    const size_t lds = (size_t)a.tg.lds_bytes;
+    return mirror ? launch_c<int16_t>(a, ndim, act, mcs, alpha, parity, lds, stream)
+                  : launch_c<int32_t>(a, ndim, act, mcs, alpha, parity, lds, stream);
+}
+
+hipError_t launch_to_mirror(const int32_t *lat, int16_t *mirror, size_t n, hipStream_t stream)
+{
+    const size_t threads = (n + 3) / 4;
+    to_mirror_kernel<<<(unsigned)((threads + kBlock - 1) / kBlock), kBlock, 0, stream>>>(lat, mirror, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_from_mirror(const int16_t *mirror, int32_t *lat, size_t n, hipStream_t stream)
+{
+    const size_t threads = (n + 3) / 4;
+    from_mirror_kernel<<<(unsigned)((threads + kBlock - 1) / kBlock), kBlock, 0, stream>>>(mirror, lat, n);
+    return hipGetLastError();
+}
+
+}  // namespace cpm

@@ -43,7 +43,7 @@ def run_both(torch, w, n_mcs, chunks=None):
     return st, sim
 
 
-def assert_same(st, sim, torch):
+def assert_same(st, sim, torch, check_stats=True):
     lat = sim.lattice.cpu().numpy().reshape(-1)
     diff = np.flatnonzero(lat != st.lattice)
     assert diff.size == 0, f"{diff.size} sites differ, first at {diff[:5]}"
@@ -53,6 +53,8 @@ def assert_same(st, sim, torch):
     torch.cuda.synchronize()
     np.testing.assert_array_equal(v.cpu().numpy()[1:], st.V[1:])
     np.testing.assert_array_equal(s.cpu().numpy()[1:], st.S[1:])
+    if check_stats:  # attempts, attempts past the early rejection, accepted copies
+        assert tuple(sim.attempt_stats()) == tuple(int(x) for x in st.stats)
 
 
 def _multi(dims, ndim, seed, s=2, k=1, act=False, obstacles=0.05, n_cells=12, T=8.0):
@@ -117,7 +119,20 @@ def test_resume_and_chunking(torch_cuda):
     sim2.sweep(3)
     st.sweep(3)
     torch_cuda.cuda.synchronize()
-    assert_same(st, sim2, torch_cuda)
+    assert_same(st, sim2, torch_cuda, check_stats=False)
+
+
+@pytest.mark.parametrize("single", [True, False])
+def test_wide_labels_int32_path(torch_cuda, single):
+    # more than 32767 cell labels: the sweep works on the int32 lattice itself
+    dims = (32, 32, 32)
+    n_cells = 40000
+    w = _multi(dims, 3, seed=12, n_cells=n_cells, obstacles=0.02)
+    if single:
+        w.cell_type = np.array([0] + [2] * n_cells, dtype=np.int32)
+    assert w.lattice.max() > 32767
+    st, sim = run_both(torch_cuda, w, 4)
+    assert_same(st, sim, torch_cuda)
 
 
 def test_edge_cases(torch_cuda):
