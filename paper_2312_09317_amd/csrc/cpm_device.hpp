@@ -23,6 +23,16 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
 
 __device__ __forceinline__ int wrap_once(int v, int L) { return v < 0 ? v + L : (v >= L ? v - L : v); }
 
+// Division by a divisor fixed for a whole workgroup: q = floor(n / d) as one
+// multiply-high, exact whenever n * d < 2^32 (m = floor((2^32 - 1) / d) + 1
+// overshoots 2^32 / d by less than 1, so the error n / 2^32 stays below the
+// gap 1 / d between floor(n / d) + 1 and the largest fraction).
+struct FastDiv {
+    uint32_t d, m;
+    __device__ __forceinline__ explicit FastDiv(uint32_t div) : d(div), m(div > 1 ? 0xFFFFFFFFu / div + 1u : 0u) {}
+    __device__ __forceinline__ uint32_t div(uint32_t n) const { return d > 1 ? __umulhi(n, m) : n; }
+};
+
 // Moore offset n (lexicographic, z slowest, x fastest, the centre left out).
 template <int D>
 __device__ __forceinline__ constexpr int nb_dx(int n) { return (D == 2 ? (n < 4 ? n : n + 1) : (n < 13 ? n : n + 1)) % 3 - 1; }

@@ -216,25 +216,28 @@ __global__ void __launch_bounds__(kBlock) tile_sweep_kernel(SweepArgs a, uint32_
     if (FULLROW) {
         // whole rows: 16-byte chunks, eight loads in flight per thread
         const int cpr = L0 * (int)sizeof(Cell) / 16;
-        auto row_chunk = [&](int c, int per_row) {
-            const int r = c / per_row, off = c - r * per_row;
-            const int gy = wrap_once(o1 + r % b1, L1);
-            const int gz = D == 3 ? wrap_once(o2 + r / b1, L2) : 0;
-            return ((size_t)gz * L1 + gy) * per_row + off;
-        };
+        const FastDiv by_b1((uint32_t)b1);
         auto copy_rows = [&](const uint4 *src, uint4 *dst, int per_row) {
+            const FastDiv by_row((uint32_t)per_row);
+            auto row_chunk = [&](int c) {
+                const int r = (int)by_row.div((uint32_t)c), off = c - r * per_row;
+                const int rz = (int)by_b1.div((uint32_t)r), ry = r - rz * b1;
+                const int gy = wrap_once(o1 + ry, L1);
+                const int gz = D == 3 ? wrap_once(o2 + rz, L2) : 0;
+                return ((size_t)gz * L1 + gy) * per_row + off;
+            };
             const int total = rows * per_row;
             int c0 = tid;
             for (; c0 + 7 * kBlock < total; c0 += 8 * kBlock) {
                 // eight independent loads before the first LDS store
-                const uint4 v0 = src[row_chunk(c0, per_row)];
-                const uint4 v1 = src[row_chunk(c0 + kBlock, per_row)];
-                const uint4 v2 = src[row_chunk(c0 + 2 * kBlock, per_row)];
-                const uint4 v3 = src[row_chunk(c0 + 3 * kBlock, per_row)];
-                const uint4 v4 = src[row_chunk(c0 + 4 * kBlock, per_row)];
-                const uint4 v5 = src[row_chunk(c0 + 5 * kBlock, per_row)];
-                const uint4 v6 = src[row_chunk(c0 + 6 * kBlock, per_row)];
-                const uint4 v7 = src[row_chunk(c0 + 7 * kBlock, per_row)];
+                const uint4 v0 = src[row_chunk(c0)];
+                const uint4 v1 = src[row_chunk(c0 + kBlock)];
+                const uint4 v2 = src[row_chunk(c0 + 2 * kBlock)];
+                const uint4 v3 = src[row_chunk(c0 + 3 * kBlock)];
+                const uint4 v4 = src[row_chunk(c0 + 4 * kBlock)];
+                const uint4 v5 = src[row_chunk(c0 + 5 * kBlock)];
+                const uint4 v6 = src[row_chunk(c0 + 6 * kBlock)];
+                const uint4 v7 = src[row_chunk(c0 + 7 * kBlock)];
                 dst[c0] = v0;
                 dst[c0 + kBlock] = v1;
                 dst[c0 + 2 * kBlock] = v2;
@@ -244,15 +247,17 @@ __global__ void __launch_bounds__(kBlock) tile_sweep_kernel(SweepArgs a, uint32_
                 dst[c0 + 6 * kBlock] = v6;
                 dst[c0 + 7 * kBlock] = v7;
             }
-            for (; c0 < total; c0 += kBlock) dst[c0] = src[row_chunk(c0, per_row)];
+            for (; c0 < total; c0 += kBlock) dst[c0] = src[row_chunk(c0)];
         };
         copy_rows(reinterpret_cast<const uint4 *>(cells), reinterpret_cast<uint4 *>(lab), cpr);
         if (ACT) copy_rows(reinterpret_cast<const uint4 *>(a.act), reinterpret_cast<uint4 *>(lact), L0 / 16);
     } else {
         const int wave = tid >> 6, lane = tid & 63;
+        const FastDiv by_b1((uint32_t)b1);
         for (int r = wave; r < rows; r += kBlock / 64) {
-            const int gy = wrap_once(o1 + r % b1, L1);
-            const int gz = D == 3 ? wrap_once(o2 + r / b1, L2) : 0;
+            const int rz = (int)by_b1.div((uint32_t)r), ry = r - rz * b1;
+            const int gy = wrap_once(o1 + ry, L1);
+            const int gz = D == 3 ? wrap_once(o2 + rz, L2) : 0;
             const size_t base = ((size_t)gz * L1 + gy) * L0;
             for (int x = lane; x < b0; x += 64) {
                 const int gx = wrap_once(o0 + x, L0);
@@ -266,14 +271,16 @@ __global__ void __launch_bounds__(kBlock) tile_sweep_kernel(SweepArgs a, uint32_
     const int areas = n0 * n1 * n2;
     const uint32_t sd = D == 2 ? (uint32_t)(s * s) : (uint32_t)(s * s * s);
     // draw of one attempt: target and source in LDS coordinates
+    const FastDiv by_n0((uint32_t)n0), by_n1((uint32_t)n1), by_s((uint32_t)s);
     auto draw = [&](int area_local, int j, int &ttx, int &tty, int &ttz, int &ssx, int &ssy, int &ssz, uint32_t &u2,
                     uint32_t &area_id) {
-        const int ax = area_local % n0, ay = (area_local / n0) % n1, az = area_local / (n0 * n1);
+        const int q0 = (int)by_n0.div((uint32_t)area_local), ax = area_local - q0 * n0;
+        const int az = (int)by_n1.div((uint32_t)q0), ay = q0 - az * n1;
         area_id = (uint32_t)(A0 + ax) + (uint32_t)a.na[0] * ((uint32_t)(A1 + ay) + (uint32_t)a.na[1] * (uint32_t)(A2 + az));
         const uint4 u = philox4x32_10(make_uint4(area_id, mcs, (alpha << 8) | (uint32_t)j, a.lattice_id), a.key0, a.key1);
         const uint32_t o = (uint32_t)(((uint64_t)u.x * sd) >> 32);
-        const int ox = (int)(o % (uint32_t)s), oy = (int)((o / (uint32_t)s) % (uint32_t)s);
-        const int oz = D == 3 ? (int)(o / (uint32_t)(s * s)) : 0;
+        const int q1 = (int)by_s.div(o), ox = (int)o - q1 * s;
+        const int oz = D == 3 ? (int)by_s.div((uint32_t)q1) : 0, oy = q1 - oz * s;
         ttx = FULLROW ? 2 * s * ax + s * cx + ox : 2 * s * ax + R + ox;
         tty = 2 * s * ay + R + oy;
         ttz = D == 3 ? 2 * s * az + R + oz : 0;
