@@ -62,6 +62,13 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"libcpm.so not built at {path}: run __graft_entry__.build()")
+    # torch ships its own HIP runtime under the same soname; loading torch
+    # first makes libcpm bind to that runtime, so the streams and device
+    # pointers torch hands over belong to the runtime libcpm uses
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     l = ctypes.CDLL(path)
     P, I32, U64, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64, ctypes.c_size_t
     pp = ctypes.POINTER(cpm_params)

@@ -5,32 +5,107 @@
 namespace cpm {
 namespace {
 
-template <int D>
-struct Geo {
-    int L0, L1, L2;
-    __device__ __forceinline__ int idx(int x, int y, int z) const { return x + L0 * (y + L1 * z); }
+// Per-workgroup label map in LDS: sums per cell label are combined in LDS
+// and flushed with one global atomic per label and workgroup.  A label that
+// finds no free slot within kProbe probes goes straight to global memory.
+constexpr int kMapSize = 1024;
+constexpr int kProbe = 32;
+constexpr int kSitesPerThread = 16;
+constexpr int kSitesPerBlock = kBlock * kSitesPerThread;
+
+enum ReduceMode { kCount = 0, kRef = 1, kCentroid = 2 };
+
+struct LabelMap {
+    int32_t key[kMapSize];
+    int32_t a[kMapSize];                // volume, or minimum site index
+    int32_t b[kMapSize];                // surface
+    unsigned long long c[kMapSize][3];  // centroid sums
 };
 
-template <int D>
-__global__ void __launch_bounds__(kBlock) count_kernel(SweepArgs a, int32_t *v_out, int32_t *s_out, int stride)
+__device__ __forceinline__ int map_slot(LabelMap &m, int label)
 {
-    const int64_t n_sites = (int64_t)a.L[0] * a.L[1] * a.L[2];
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n_sites) return;
-    const int32_t c = a.lat[i];
-    if (c <= 0) return;
-    const Geo<D> g{a.L[0], a.L[1], a.L[2]};
-    const int x = (int)(i % g.L0), y = (int)((i / g.L0) % g.L1), z = (int)(i / ((int64_t)g.L0 * g.L1));
-    constexpr int NNB = D == 2 ? 8 : 26;
-    int unlike = 0;
-#pragma unroll
-    for (int n = 0; n < NNB; ++n) {
-        int dx, dy, dz;
-        dx = nb_dx<D>(n); dy = nb_dy<D>(n); dz = nb_dz<D>(n);
-        unlike += a.lat[g.idx(wrap_once(x + dx, g.L0), wrap_once(y + dy, g.L1), D == 3 ? wrap_once(z + dz, g.L2) : 0)] != c;
+    uint32_t h = ((uint32_t)label * 2654435761u) & (kMapSize - 1);
+    for (int p = 0; p < kProbe; ++p) {
+        const int k = atomicCAS(&m.key[h], -1, label);
+        if (k == -1 || k == label) return (int)h;
+        h = (h + 1) & (kMapSize - 1);
     }
-    atomicAdd(&v_out[(size_t)c * stride], 1);
-    atomicAdd(&s_out[(size_t)c * stride], unlike);
+    return -1;
+}
+
+template <int D, int MODE>
+__global__ void __launch_bounds__(kBlock) reduce_kernel(SweepArgs a, int32_t *v_out, int32_t *s_out, int stride,
+                                                        int32_t *ref, int64_t *cent)
+{
+    __shared__ LabelMap m;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < kMapSize; i += kBlock) {
+        m.key[i] = -1;
+        m.a[i] = MODE == kRef ? INT32_MAX : 0;
+        m.b[i] = 0;
+        m.c[i][0] = m.c[i][1] = m.c[i][2] = 0;
+    }
+    __syncthreads();
+    const int L0 = a.L[0], L1 = a.L[1], L2 = a.L[2];
+    const int64_t n_sites = (int64_t)L0 * L1 * L2;
+    const int64_t base = (int64_t)blockIdx.x * kSitesPerBlock;
+    constexpr int NNB = D == 2 ? 8 : 26;
+    for (int j = 0; j < kSitesPerThread; ++j) {
+        const int64_t i = base + tid + (int64_t)j * kBlock;
+        if (i >= n_sites) break;
+        const int32_t c = a.lat[i];
+        if (c <= 0) continue;
+        const int x = (int)(i % L0), y = (int)((i / L0) % L1), z = (int)(i / ((int64_t)L0 * L1));
+        const int slot = map_slot(m, c);
+        if (MODE == kCount) {
+            int unlike = 0;
+#pragma unroll
+            for (int n = 0; n < NNB; ++n) {
+                const int u = wrap_once(x + nb_dx<D>(n), L0) +
+                              L0 * (wrap_once(y + nb_dy<D>(n), L1) + L1 * (D == 3 ? wrap_once(z + nb_dz<D>(n), L2) : 0));
+                unlike += a.lat[u] != c;
+            }
+            if (slot >= 0) {
+                atomicAdd(&m.a[slot], 1);
+                atomicAdd(&m.b[slot], unlike);
+            } else {
+                atomicAdd(&v_out[(size_t)c * stride], 1);
+                atomicAdd(&s_out[(size_t)c * stride], unlike);
+            }
+        } else if (MODE == kRef) {
+            if (slot >= 0) atomicMin(&m.a[slot], (int32_t)i);
+            else atomicMin(&ref[c], (int32_t)i);
+        } else {
+            const int p[3] = {x, y, z};
+            const int L[3] = {L0, L1, L2};
+            const int r0 = ref[c];
+            const int r[3] = {r0 % L0, (r0 / L0) % L1, r0 / (L0 * L1)};
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                int diff = p[d] - r[d];
+                if (diff > L[d] / 2) diff -= L[d];
+                if (diff < -(L[d] - 1) / 2) diff += L[d];
+                const unsigned long long v = (unsigned long long)(int64_t)(r[d] + diff);
+                if (slot >= 0) atomicAdd(&m.c[slot][d], v);
+                else atomicAdd(reinterpret_cast<unsigned long long *>(&cent[(size_t)c * D + d]), v);
+            }
+        }
+    }
+    __syncthreads();
+    for (int h = tid; h < kMapSize; h += kBlock) {
+        const int c = m.key[h];
+        if (c < 0) continue;
+        if (MODE == kCount) {
+            atomicAdd(&v_out[(size_t)c * stride], m.a[h]);
+            atomicAdd(&s_out[(size_t)c * stride], m.b[h]);
+        } else if (MODE == kRef) {
+            atomicMin(&ref[c], m.a[h]);
+        } else {
+#pragma unroll
+            for (int d = 0; d < D; ++d)
+                atomicAdd(reinterpret_cast<unsigned long long *>(&cent[(size_t)c * D + d]), m.c[h][d]);
+        }
+    }
 }
 
 __global__ void fill_i32_kernel(int32_t *p, int32_t value, size_t n)
@@ -59,38 +134,6 @@ __global__ void act_decay_kernel(uint8_t *act, size_t n)
     }
 }
 
-template <int D>
-__global__ void __launch_bounds__(kBlock) centroid_ref_kernel(SweepArgs a, int32_t *ref)
-{
-    const int64_t n_sites = (int64_t)a.L[0] * a.L[1] * a.L[2];
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n_sites) return;
-    const int32_t c = a.lat[i];
-    if (c >= 1) atomicMin(&ref[c], (int32_t)i);
-}
-
-template <int D>
-__global__ void __launch_bounds__(kBlock) centroid_sum_kernel(SweepArgs a, const int32_t *ref, int64_t *out)
-{
-    const int64_t n_sites = (int64_t)a.L[0] * a.L[1] * a.L[2];
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n_sites) return;
-    const int32_t c = a.lat[i];
-    if (c < 1) return;
-    const int L[3] = {a.L[0], a.L[1], a.L[2]};
-    const int p[3] = {(int)(i % L[0]), (int)((i / L[0]) % L[1]), (int)(i / ((int64_t)L[0] * L[1]))};
-    const int r0 = ref[c];
-    const int r[3] = {r0 % L[0], (r0 / L[0]) % L[1], r0 / (L[0] * L[1])};
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-        int diff = p[d] - r[d];
-        if (diff > L[d] / 2) diff -= L[d];
-        if (diff < -(L[d] - 1) / 2) diff += L[d];
-        atomicAdd(reinterpret_cast<unsigned long long *>(&out[(size_t)c * D + d]),
-                  (unsigned long long)(int64_t)(r[d] + diff));
-    }
-}
-
 __global__ void copy_counters_kernel(const int32_t *pairs, int32_t n_labels, int32_t *v_out, int32_t *s_out)
 {
     const int i = blockIdx.x * kBlock + threadIdx.x;
@@ -114,10 +157,11 @@ hipError_t launch_count(const SweepArgs &a, int ndim, int32_t *v_out, int32_t *s
                         hipStream_t stream)
 {
     const size_t n = (size_t)a.L[0] * a.L[1] * a.L[2];
+    const unsigned grid = (unsigned)((n + kSitesPerBlock - 1) / kSitesPerBlock);
     if (ndim == 2)
-        count_kernel<2><<<blocks_for(n), kBlock, 0, stream>>>(a, v_out, s_out, stride);
+        reduce_kernel<2, kCount><<<grid, kBlock, 0, stream>>>(a, v_out, s_out, stride, nullptr, nullptr);
     else
-        count_kernel<3><<<blocks_for(n), kBlock, 0, stream>>>(a, v_out, s_out, stride);
+        reduce_kernel<3, kCount><<<grid, kBlock, 0, stream>>>(a, v_out, s_out, stride, nullptr, nullptr);
     return hipGetLastError();
 }
 
@@ -132,16 +176,17 @@ hipError_t launch_centroids(const SweepArgs &a, int ndim, int32_t n_cells, int32
                             hipStream_t stream)
 {
     const size_t n = (size_t)a.L[0] * a.L[1] * a.L[2];
+    const unsigned grid = (unsigned)((n + kSitesPerBlock - 1) / kSitesPerBlock);
     hipError_t e = launch_fill_i32(ref, INT32_MAX, (size_t)n_cells + 1, stream);
     if (e != hipSuccess) return e;
     e = launch_fill_i32(reinterpret_cast<int32_t *>(out), 0, ((size_t)n_cells + 1) * ndim * 2, stream);
     if (e != hipSuccess) return e;
     if (ndim == 2) {
-        centroid_ref_kernel<2><<<blocks_for(n), kBlock, 0, stream>>>(a, ref);
-        centroid_sum_kernel<2><<<blocks_for(n), kBlock, 0, stream>>>(a, ref, out);
+        reduce_kernel<2, kRef><<<grid, kBlock, 0, stream>>>(a, nullptr, nullptr, 0, ref, nullptr);
+        reduce_kernel<2, kCentroid><<<grid, kBlock, 0, stream>>>(a, nullptr, nullptr, 0, ref, out);
     } else {
-        centroid_ref_kernel<3><<<blocks_for(n), kBlock, 0, stream>>>(a, ref);
-        centroid_sum_kernel<3><<<blocks_for(n), kBlock, 0, stream>>>(a, ref, out);
+        reduce_kernel<3, kRef><<<grid, kBlock, 0, stream>>>(a, nullptr, nullptr, 0, ref, nullptr);
+        reduce_kernel<3, kCentroid><<<grid, kBlock, 0, stream>>>(a, nullptr, nullptr, 0, ref, out);
     }
     return hipGetLastError();
 }
