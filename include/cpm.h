@@ -162,6 +162,58 @@ int cpm_destroy(cpm_handle *h);
 const char *cpm_strerror(int code);
 const char *cpm_last_error(void);
 
+/*
+ * Batches: n independent lattices (replicates or parameter sweeps, paper,
+ * Results, "Serial Cellular Potts Models are limited to sub-millimetre scale",
+ * Fig. 1B) advanced together, every activation of all of them in one launch.
+ * Lattice i follows params[i] (its own dims, energies, temperature, seed,
+ * lattice_id); all share ndim, sub, attempts and act_enabled.  Each lattice
+ * evolves exactly as it would alone under cpm_sweep.
+ *
+ * Device buffers are packed back to back in params order:
+ *   d_lattices   int32, lattice i occupies dims[0]*dims[1]*dims[2] sites
+ *   d_cell_types int32, lattice i occupies n_cells[i] + 1 entries
+ *   d_act        uint8 activity, packed like d_lattices (NULL unless act)
+ * Per-cell outputs (counters, cell stats) are packed like d_cell_types
+ * (centroid sums: ndim entries per label).  The batch shares one MCS counter.
+ * Ownership, streams and errors as for single lattices.
+ */
+typedef struct cpm_batch cpm_batch;
+
+int cpm_batch_workspace_bytes(const cpm_params *params, int32_t n, const int32_t *n_cells, size_t *bytes);
+int cpm_batch_init(const cpm_params *params, int32_t n, const int32_t *n_cells, int32_t *d_lattices,
+                   const int32_t *d_cell_types, uint8_t *d_act, void *d_workspace, size_t workspace_bytes,
+                   void *stream, cpm_batch **out);
+int cpm_batch_sweep(cpm_batch *b, int32_t n_mcs, void *stream);
+int cpm_batch_counters(cpm_batch *b, int32_t *d_volume, int32_t *d_surface, void *stream);
+int cpm_batch_cell_stats(cpm_batch *b, int32_t *d_volume, int32_t *d_surface, int64_t *d_centroid_sum,
+                         void *stream);
+/* out: 3 entries per lattice, as cpm_attempt_stats; waits for the stream. */
+int cpm_batch_attempt_stats(cpm_batch *b, uint64_t *out, void *stream);
+/*
+ * Cell-level summary statistics of a batch.  cpm_batch_sample records, for
+ * every lattice i and label c, the record (V, S, x, y, z) of sample k:
+ * volume and surface recounted from the lattice and the centroid
+ * (centroid sum / V, reduced into [0, L) per axis; 0 for dead cells).
+ * d_samples is a device array of doubles packed per lattice: lattice i starts
+ * at label_offset(i) * n_samples * 5 and holds [n_samples][n_cells_i + 1][5].
+ * cpm_batch_summary reduces n_samples samples taken `interval` MCS apart to
+ * 8 doubles per lattice (d_out[8 i + j]): mean and population variance of
+ * volume, of surface (cells alive at a sample), of speed (minimum-image
+ * centroid displacement between consecutive samples / interval) and of
+ * persistence time (per cell, the first lag at which the mean dot product of
+ * unit displacements drops below 1/e, linearly interpolated, in MCS; the
+ * longest defined lag if it never does).  The paper's motility read-outs are
+ * speed and directional autocorrelation (Results, Fig. 5B); these formulas
+ * are this library's reading.
+ */
+int cpm_batch_sample(cpm_batch *b, double *d_samples, int32_t k, int32_t n_samples, void *stream);
+int cpm_batch_summary(cpm_batch *b, const double *d_samples, int32_t n_samples, double interval, double *d_out,
+                      void *stream);
+int cpm_batch_set_mcs(cpm_batch *b, uint64_t mcs);
+int cpm_batch_get_mcs(const cpm_batch *b, uint64_t *mcs);
+int cpm_batch_destroy(cpm_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -52,7 +52,10 @@ class cpm_params(ctypes.Structure):
 
 EXPORTS = ("cpm_validate", "cpm_workspace_bytes", "cpm_init", "cpm_sweep", "cpm_cell_stats",
            "cpm_counters", "cpm_attempt_stats", "cpm_set_mcs", "cpm_get_mcs", "cpm_destroy",
-           "cpm_strerror", "cpm_last_error")
+           "cpm_batch_workspace_bytes", "cpm_batch_init", "cpm_batch_sweep", "cpm_batch_counters",
+           "cpm_batch_cell_stats", "cpm_batch_attempt_stats", "cpm_batch_sample", "cpm_batch_summary",
+           "cpm_batch_set_mcs", "cpm_batch_get_mcs",
+           "cpm_batch_destroy", "cpm_strerror", "cpm_last_error")
 
 
 def load(path: str = LIB_PATH):
@@ -82,11 +85,22 @@ def load(path: str = LIB_PATH):
     l.cpm_set_mcs.argtypes = [P, U64]
     l.cpm_get_mcs.argtypes = [P, ctypes.POINTER(U64)]
     l.cpm_destroy.argtypes = [P]
+    l.cpm_batch_workspace_bytes.argtypes = [pp, I32, P, ctypes.POINTER(SZ)]
+    l.cpm_batch_init.argtypes = [pp, I32, P, P, P, P, P, SZ, P, ctypes.POINTER(P)]
+    l.cpm_batch_sweep.argtypes = [P, I32, P]
+    l.cpm_batch_counters.argtypes = [P, P, P, P]
+    l.cpm_batch_cell_stats.argtypes = [P, P, P, P, P]
+    l.cpm_batch_attempt_stats.argtypes = [P, P, P]
+    l.cpm_batch_sample.argtypes = [P, P, I32, I32, P]
+    l.cpm_batch_summary.argtypes = [P, P, I32, ctypes.c_double, P, P]
+    l.cpm_batch_set_mcs.argtypes = [P, U64]
+    l.cpm_batch_get_mcs.argtypes = [P, ctypes.POINTER(U64)]
+    l.cpm_batch_destroy.argtypes = [P]
     l.cpm_strerror.argtypes = [ctypes.c_int]
     l.cpm_strerror.restype = ctypes.c_char_p
     l.cpm_last_error.argtypes = []
     l.cpm_last_error.restype = ctypes.c_char_p
-    for f in EXPORTS[:10]:
+    for f in EXPORTS[:-2]:
         getattr(l, f).restype = ctypes.c_int
     _lib = l
     return l
@@ -269,6 +283,183 @@ class Simulation:
     def close(self) -> None:
         if getattr(self, "handle", None):
             cpm_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- batches
+
+def _params_array(params):
+    arr = (cpm_params * len(params))()
+    for i, p in enumerate(params):
+        arr[i] = p.c
+    return arr
+
+
+def _i32_array(v):
+    return np.ascontiguousarray(v, dtype=np.int32)
+
+
+def cpm_batch_workspace_bytes(params, n_cells) -> int:
+    arr = _params_array(params)
+    nc = _i32_array(n_cells)
+    b = ctypes.c_size_t(0)
+    _check(load().cpm_batch_workspace_bytes(arr, len(params), nc.ctypes.data, ctypes.byref(b)),
+           "cpm_batch_workspace_bytes")
+    return b.value
+
+
+def cpm_batch_init(params, n_cells, d_lattices, d_cell_types, d_act, d_workspace, workspace_bytes, stream) -> int:
+    arr = _params_array(params)
+    nc = _i32_array(n_cells)
+    h = ctypes.c_void_p(0)
+    _check(load().cpm_batch_init(arr, len(params), nc.ctypes.data, _ptr(d_lattices), _ptr(d_cell_types),
+                                 _ptr(d_act), _ptr(d_workspace), workspace_bytes, stream, ctypes.byref(h)),
+           "cpm_batch_init")
+    return h.value
+
+
+def cpm_batch_sweep(h: int, n_mcs: int, stream: int) -> None:
+    _check(load().cpm_batch_sweep(h, n_mcs, stream), "cpm_batch_sweep")
+
+
+def cpm_batch_counters(h: int, d_volume, d_surface, stream: int) -> None:
+    _check(load().cpm_batch_counters(h, _ptr(d_volume), _ptr(d_surface), stream), "cpm_batch_counters")
+
+
+def cpm_batch_cell_stats(h: int, d_volume, d_surface, d_centroid_sum, stream: int) -> None:
+    _check(load().cpm_batch_cell_stats(h, _ptr(d_volume), _ptr(d_surface), _ptr(d_centroid_sum), stream),
+           "cpm_batch_cell_stats")
+
+
+def cpm_batch_attempt_stats(h: int, n: int, stream: int):
+    out = (ctypes.c_uint64 * (3 * n))()
+    _check(load().cpm_batch_attempt_stats(h, out, stream), "cpm_batch_attempt_stats")
+    return np.array(list(out), dtype=np.uint64).reshape(n, 3)
+
+
+def cpm_batch_sample(h: int, d_samples, k: int, n_samples: int, stream: int) -> None:
+    _check(load().cpm_batch_sample(h, _ptr(d_samples), k, n_samples, stream), "cpm_batch_sample")
+
+
+def cpm_batch_summary(h: int, d_samples, n_samples: int, interval: float, d_out, stream: int) -> None:
+    _check(load().cpm_batch_summary(h, _ptr(d_samples), n_samples, interval, _ptr(d_out), stream),
+           "cpm_batch_summary")
+
+
+def cpm_batch_set_mcs(h: int, mcs: int) -> None:
+    _check(load().cpm_batch_set_mcs(h, mcs), "cpm_batch_set_mcs")
+
+
+def cpm_batch_get_mcs(h: int) -> int:
+    v = ctypes.c_uint64(0)
+    _check(load().cpm_batch_get_mcs(h, ctypes.byref(v)), "cpm_batch_get_mcs")
+    return v.value
+
+
+def cpm_batch_destroy(h: int) -> None:
+    load().cpm_batch_destroy(h)
+
+
+class Batch:
+    """Many lattices on the GPU advanced together (one launch per activation).
+
+    `lattices` and `cell_types` are lists of arrays; they are packed back to
+    back on the device.
+    """
+
+    def __init__(self, params, lattices, cell_types, acts=None, device="cuda"):
+        import torch
+        self.torch = torch
+        self.params = list(params)
+        self.device = torch.device(device)
+        self.n = len(self.params)
+        self.sizes = [int(np.asarray(l).size) for l in lattices]
+        self.n_cells = [int(len(t)) - 1 for t in cell_types]
+        self.site_off = np.concatenate([[0], np.cumsum(self.sizes)]).astype(np.int64)
+        self.label_off = np.concatenate([[0], np.cumsum([c + 1 for c in self.n_cells])]).astype(np.int64)
+        flat = np.concatenate([np.ascontiguousarray(l, dtype=np.int32).reshape(-1) for l in lattices])
+        types = np.concatenate([np.ascontiguousarray(t, dtype=np.int32) for t in cell_types])
+        self.lattices = torch.as_tensor(flat).to(self.device)
+        self.cell_types = torch.as_tensor(types).to(self.device)
+        if self.params[0].act_enabled:
+            if acts is None:
+                a = np.zeros(flat.size, np.uint8)
+            else:
+                a = np.concatenate([np.ascontiguousarray(x, dtype=np.uint8).reshape(-1) for x in acts])
+            self.act = torch.as_tensor(a).to(self.device)
+        else:
+            self.act = None
+        nbytes = cpm_batch_workspace_bytes(self.params, self.n_cells)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.handle = cpm_batch_init(self.params, self.n_cells, self.lattices, self.cell_types, self.act,
+                                     self.workspace, nbytes, self.stream)
+
+    @property
+    def stream(self) -> int:
+        return self.torch.cuda.current_stream(self.device).cuda_stream
+
+    def sweep(self, n_mcs: int) -> None:
+        cpm_batch_sweep(self.handle, n_mcs, self.stream)
+
+    def lattice(self, i):
+        return self.lattices[int(self.site_off[i]):int(self.site_off[i + 1])]
+
+    def activity(self, i):
+        return self.act[int(self.site_off[i]):int(self.site_off[i + 1])]
+
+    def counters(self):
+        v = self.torch.empty(int(self.label_off[-1]), dtype=self.torch.int32, device=self.device)
+        s = self.torch.empty_like(v)
+        cpm_batch_counters(self.handle, v, s, self.stream)
+        return v, s
+
+    def cell_stats(self, centroids=True):
+        torch = self.torch
+        v = torch.empty(int(self.label_off[-1]), dtype=torch.int32, device=self.device)
+        s = torch.empty_like(v)
+        c = torch.empty((int(self.label_off[-1]), self.params[0].c.ndim), dtype=torch.int64, device=self.device) \
+            if centroids else None
+        cpm_batch_cell_stats(self.handle, v, s, c, self.stream)
+        return v, s, c
+
+    def attempt_stats(self):
+        return cpm_batch_attempt_stats(self.handle, self.n, self.stream)
+
+    def run_with_samples(self, burn_in: int, n_samples: int, interval: int):
+        """Sweep burn_in MCS, then take n_samples samples interval MCS apart
+        (the first at the end of the burn-in); returns the sample buffer."""
+        samples = self.torch.empty(int(self.label_off[-1]) * n_samples * 5, dtype=self.torch.float64,
+                                   device=self.device)
+        self.sweep(burn_in)
+        for k in range(n_samples):
+            if k:
+                self.sweep(interval)
+            cpm_batch_sample(self.handle, samples, k, n_samples, self.stream)
+        return samples
+
+    def summary(self, samples, n_samples: int, interval: float):
+        """Per lattice: mean / variance of volume, surface, speed, persistence."""
+        out = self.torch.empty(self.n * 8, dtype=self.torch.float64, device=self.device)
+        cpm_batch_summary(self.handle, samples, n_samples, interval, out, self.stream)
+        return out.view(self.n, 8)
+
+    @property
+    def mcs(self) -> int:
+        return cpm_batch_get_mcs(self.handle)
+
+    @mcs.setter
+    def mcs(self, value: int) -> None:
+        cpm_batch_set_mcs(self.handle, value)
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            cpm_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -32,6 +32,34 @@ struct cpm_handle {
     std::unique_ptr<DeviceModel> host_model;  // source of the async upload
 };
 
+struct cpm_batch {
+    int32_t n = 0;
+    int32_t ndim = 0, s = 0, k = 0;
+    bool act = false, mirror = false, single = false, full_rows = false;
+    std::vector<SweepArgs> args;                     // host copies, one per lattice
+    std::vector<int32_t> n_cells;
+    std::vector<size_t> site_off, label_off;         // packed offsets of lattices / cell-type arrays
+    std::vector<int32_t *> ref;
+    std::vector<int16_t *> mirror_cells;
+    std::vector<std::unique_ptr<DeviceModel>> models;
+    std::vector<int2> work;
+    SweepArgs *d_args = nullptr;
+    int2 *d_work = nullptr;
+    uint32_t *d_mcs = nullptr;
+    int32_t *lattices = nullptr;
+    uint8_t *act_field = nullptr;
+    size_t total_sites = 0;
+    cpm::BatchLaunch launch{};
+    cpm::StatsTables stats_tables{};
+    int32_t *scratch_v = nullptr, *scratch_s = nullptr;
+    int64_t *scratch_c = nullptr;
+    std::vector<int64_t> host_label_off;
+    std::vector<int32_t> host_dims;
+    uint64_t mcs = 0;
+    uint64_t activation = 0;
+    uint64_t mcs_run = 0;
+};
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -62,11 +90,18 @@ struct Layout {
 // Labels fit the int16 working copy: cells 1..32767, medium 0, obstacle -1.
 bool use_mirror(int32_t n_cells) { return n_cells <= 32767; }
 
+// Widest load (16, 8 or 4 bytes) that divides both a row and the base address.
+int32_t chunk_for(const void *base, size_t row_bytes)
+{
+    const uintptr_t v = reinterpret_cast<uintptr_t>(base) | (uintptr_t)row_bytes;
+    return (v % 16 == 0) ? 16 : (v % 8 == 0 ? 8 : 4);
+}
+
 // Thread areas per workgroup tile.  Preferred: whole rows of areas along x
 // (full-row LDS layout: every staged row is one aligned lattice row, no row
 // staged twice), growing along y then z up to kBlock areas while the staged
 // rows fit 64 KiB of LDS.  Otherwise a box tile, shrunk until it fits.
-cpm::TileGeometry choose_tiles(const cpm_params *p, bool mirror)
+cpm::TileGeometry choose_tiles(const cpm_params *p, bool mirror, bool force_box = false)
 {
     cpm::TileGeometry g{};
     const int s = p->sub, R = p->act_enabled ? 2 : 1;
@@ -78,7 +113,10 @@ cpm::TileGeometry choose_tiles(const cpm_params *p, bool mirror)
     const size_t budget = 65536;
     int T[3] = {1, 1, 1};
     const int L0 = p->dims[0];
-    bool full = p->attempts == 1 && na[0] <= cpm::kBlock && (L0 * cell) % 16 == 0 && (!act || L0 % 16 == 0);
+    // rows are staged in 16-, 8- or 4-byte chunks: int16 rows are even-length
+    // (L0 is a multiple of 2s), activity rows a multiple of 4 bytes (s >= 2)
+    bool full = !force_box && p->attempts == 1 && na[0] <= cpm::kBlock && (L0 * cell) % 4 == 0 &&
+                (!act || L0 % 4 == 0);
     if (full) {
         auto lds_for = [&](int t1, int t2) {
             const int rows = extent(t1) * (p->ndim == 3 ? extent(t2) : 1);
@@ -127,11 +165,11 @@ cpm::TileGeometry choose_tiles(const cpm_params *p, bool mirror)
     return g;
 }
 
-Layout layout_of(const cpm_params *p, int32_t n_cells)
+Layout layout_of(const cpm_params *p, int32_t n_cells, int mirror = -1, bool force_box = false)
 {
     Layout l{};
-    l.mirror_on = use_mirror(n_cells);
-    l.tg = choose_tiles(p, l.mirror_on);
+    l.mirror_on = mirror < 0 ? use_mirror(n_cells) : mirror != 0;
+    l.tg = choose_tiles(p, l.mirror_on, force_box);
     l.dlist_cap = l.tg.T[0] * l.tg.T[1] * l.tg.T[2] * p->attempts;
     int64_t n_sites = (int64_t)p->dims[0] * p->dims[1] * p->dims[2];
     size_t off = 0;
@@ -257,6 +295,11 @@ void build_model(const cpm_params *p, DeviceModel *m)
         m->TM[i] = (uint64_t)std::floor(std::exp(-(double)i / (256.0 * T)) * two32);
         m->TL[i] = (uint64_t)std::floor(std::exp(-(double)i / (65536.0 * T)) * two32);
     }
+    for (int h = 1; h < m->n_ti; ++h) m->TI32[h] = (uint32_t)m->TI[h];
+    for (int i = 1; i < 256; ++i) {
+        m->TM32[i] = (uint32_t)m->TM[i];
+        m->TL32[i] = (uint32_t)m->TL[i];
+    }
     // Activity geometric mean tables.
     for (int a = 1; a < 256; ++a) m->LG[a] = (int64_t)std::llround(std::log((double)a) * 16777216.0);
     for (int i = 0; i < 2048; ++i) m->EH[i] = (uint64_t)std::floor(std::exp((double)i / 256.0) * 16777216.0);
@@ -264,6 +307,70 @@ void build_model(const cpm_params *p, DeviceModel *m)
         m->EM[i] = (uint64_t)std::floor(std::exp((double)i / 65536.0) * 2147483648.0);
         m->EL[i] = (uint64_t)std::floor(std::exp((double)i / 16777216.0) * 1073741824.0);
     }
+}
+
+// Cell types read back from the device: entry 0 is the medium's type 0, every
+// cell's type is valid; *single gets the type all cells share, or -1.
+int check_types(const cpm_params *p, const int32_t *types, int32_t n_cells, int32_t *single)
+{
+    if (types[0] != 0) return fail(CPM_EINVAL, "cell_type[0] must be 0 (the medium's type)");
+    int32_t one = n_cells >= 1 ? types[1] : 0;
+    for (int32_t c = 1; c <= n_cells; ++c) {
+        if (types[c] < 0 || types[c] >= p->n_types) return fail(CPM_EINVAL, "cell type out of range");
+        if (types[c] != one) one = -1;
+    }
+    *single = one;
+    return CPM_OK;
+}
+
+// The kernel arguments of one lattice whose workspace sections start at ws.
+void fill_args(SweepArgs &a, const cpm_params *p, const Layout &lay, char *ws, int32_t *d_lattice,
+               const int32_t *d_cell_type, uint8_t *d_act, int32_t single)
+{
+    a = SweepArgs{};
+    a.lat = d_lattice;
+    a.cells = lay.mirror_on ? static_cast<void *>(ws + lay.mirror) : static_cast<void *>(d_lattice);
+    a.cell_type = d_cell_type;
+    a.act = p->act_enabled ? d_act : nullptr;
+    a.model = reinterpret_cast<const DeviceModel *>(ws + lay.model);
+    a.counters[0] = reinterpret_cast<int32_t *>(ws + lay.counters0);
+    a.counters[1] = reinterpret_cast<int32_t *>(ws + lay.counters1);
+    a.dlist = reinterpret_cast<int4 *>(ws + lay.dlist);
+    a.dcount = reinterpret_cast<int32_t *>(ws + lay.dcount);
+    a.stats = reinterpret_cast<uint64_t *>(ws + lay.stats);
+    uint32_t n_areas = 1;
+    for (int d = 0; d < 3; ++d) {
+        a.L[d] = p->dims[d];
+        a.na[d] = d < p->ndim ? p->dims[d] / (2 * p->sub) : 1;
+        n_areas *= (uint32_t)a.na[d];
+    }
+    a.n_areas = n_areas;
+    a.s = p->sub;
+    a.k = p->attempts;
+    a.dlist_cap = lay.dlist_cap;
+    a.obstacle_type = p->obstacle_type < 0 ? 0 : p->obstacle_type;
+    a.single_type = single;
+    a.key0 = (uint32_t)p->seed;
+    a.key1 = (uint32_t)(p->seed >> 32);
+    a.lattice_id = p->lattice_id;
+    a.tg = lay.tg;
+    a.tg.row_chunk = chunk_for(a.cells, (size_t)p->dims[0] * (lay.mirror_on ? 2 : 4));
+    a.tg.act_chunk = p->act_enabled ? chunk_for(d_act, (size_t)p->dims[0]) : 4;
+}
+
+// Uploads the model, clears the bookkeeping and counts V, S from the lattice.
+hipError_t start_lattice(const SweepArgs &a, const Layout &lay, char *ws, const DeviceModel *host_model, int ndim,
+                         int32_t n_cells, hipStream_t st)
+{
+    hipError_t e = hipMemcpyAsync(ws + lay.model, host_model, sizeof(DeviceModel), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return e;
+    const size_t pairs = 2 * ((size_t)n_cells + 1);
+    if ((e = cpm::launch_fill_i32(a.counters[0], 0, pairs, st)) != hipSuccess) return e;
+    if ((e = cpm::launch_fill_i32(a.dcount, 0, (size_t)lay.tg.n_tiles, st)) != hipSuccess) return e;
+    if ((e = cpm::launch_fill_i32(reinterpret_cast<int32_t *>(a.stats), 0, 4 * (size_t)lay.tg.n_tiles, st)) != hipSuccess)
+        return e;
+    if ((e = cpm::launch_count(a, ndim, a.counters[0], a.counters[0] + 1, 2, st)) != hipSuccess) return e;
+    return hipMemcpyAsync(a.counters[1], a.counters[0], sizeof(int32_t) * pairs, hipMemcpyDeviceToDevice, st);
 }
 
 hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
@@ -302,23 +409,13 @@ int cpm_init(const cpm_params *params, int32_t *d_lattice, const int32_t *d_cell
     if (!h->host_model) return fail(CPM_EINVAL, "host allocation failed");
     build_model(params, h->host_model.get());
 
-    // every cell's type must be a valid type; note whether all cells share one
     std::vector<int32_t> types((size_t)n_cells + 1);
     hipStream_t st = as_stream(stream);
     hipError_t e = hipMemcpyAsync(types.data(), d_cell_type, sizeof(int32_t) * types.size(), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return device_fail(e, "read cell types");
-    if (types[0] != 0) return fail(CPM_EINVAL, "cell_type[0] must be 0 (the medium's type)");
-    int32_t single = n_cells >= 1 ? types[1] : 0;
-    for (int32_t c = 1; c <= n_cells; ++c) {
-        if (types[c] < 0 || types[c] >= params->n_types) return fail(CPM_EINVAL, "cell type out of range");
-        if (types[c] != single) single = -1;
-    }
-    if (params->act_enabled) {
-        for (int32_t c = 1; c <= n_cells; ++c)
-            if (params->max_act[types[c]] > 0 && params->lambda_act == nullptr)
-                return fail(CPM_EINVAL, "motile type without lambda_act");
-    }
+    int32_t single = -1;
+    if ((rc = check_types(params, types.data(), n_cells, &single)) != CPM_OK) return rc;
 
     char *ws = static_cast<char *>(d_workspace);
     h->ndim = params->ndim;
@@ -329,48 +426,10 @@ int cpm_init(const cpm_params *params, int32_t *d_lattice, const int32_t *d_cell
     h->act = params->act_enabled != 0;
     h->mirror = lay.mirror_on;
     h->mirror_cells = lay.mirror_on ? reinterpret_cast<int16_t *>(ws + lay.mirror) : nullptr;
-    SweepArgs &a = h->args;
-    a.lat = d_lattice;
-    a.cells = h->mirror ? static_cast<void *>(h->mirror_cells) : static_cast<void *>(d_lattice);
-    a.cell_type = d_cell_type;
-    a.act = h->act ? d_act : nullptr;
-    a.model = reinterpret_cast<const DeviceModel *>(ws + lay.model);
-    a.counters[0] = reinterpret_cast<int32_t *>(ws + lay.counters0);
-    a.counters[1] = reinterpret_cast<int32_t *>(ws + lay.counters1);
-    a.dlist = reinterpret_cast<int4 *>(ws + lay.dlist);
-    a.dcount = reinterpret_cast<int32_t *>(ws + lay.dcount);
-    a.stats = reinterpret_cast<uint64_t *>(ws + lay.stats);
     h->ref = reinterpret_cast<int32_t *>(ws + lay.ref);
-    uint32_t n_areas = 1;
-    for (int d = 0; d < 3; ++d) {
-        a.L[d] = params->dims[d];
-        a.na[d] = d < params->ndim ? params->dims[d] / (2 * params->sub) : 1;
-        n_areas *= (uint32_t)a.na[d];
-    }
-    a.n_areas = n_areas;
-    a.s = params->sub;
-    a.k = params->attempts;
-    a.dlist_cap = lay.dlist_cap;
-    a.obstacle_type = params->obstacle_type < 0 ? 0 : params->obstacle_type;
-    a.single_type = single;
-    a.key0 = (uint32_t)params->seed;
-    a.key1 = (uint32_t)(params->seed >> 32);
-    a.lattice_id = params->lattice_id;
-    a.tg = lay.tg;
-
-    e = hipMemcpyAsync(ws + lay.model, h->host_model.get(), sizeof(DeviceModel), hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) return device_fail(e, "upload model");
-    const size_t pairs = 2 * ((size_t)n_cells + 1);
-    if ((e = cpm::launch_fill_i32(a.counters[0], 0, pairs, st)) != hipSuccess) return device_fail(e, "clear counters");
-    if ((e = cpm::launch_fill_i32(a.dcount, 0, (size_t)lay.tg.n_tiles, st)) != hipSuccess)
-        return device_fail(e, "clear delta lists");
-    if ((e = cpm::launch_fill_i32(reinterpret_cast<int32_t *>(a.stats), 0, 4 * (size_t)lay.tg.n_tiles, st)) !=
-        hipSuccess)
-        return device_fail(e, "clear stats");
-    if ((e = cpm::launch_count(a, h->ndim, a.counters[0], a.counters[0] + 1, 2, st)) != hipSuccess)
-        return device_fail(e, "count");
-    e = hipMemcpyAsync(a.counters[1], a.counters[0], sizeof(int32_t) * pairs, hipMemcpyDeviceToDevice, st);
-    if (e != hipSuccess) return device_fail(e, "copy counters");
+    fill_args(h->args, params, lay, ws, d_lattice, d_cell_type, d_act, single);
+    if ((e = start_lattice(h->args, lay, ws, h->host_model.get(), params->ndim, n_cells, st)) != hipSuccess)
+        return device_fail(e, "init");
     *out = h.release();
     return CPM_OK;
 }
@@ -484,5 +543,319 @@ const char *cpm_strerror(int code)
 }
 
 const char *cpm_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batches
+
+namespace {
+
+struct BatchLayout {
+    std::vector<Layout> lat;
+    std::vector<size_t> base;  // workspace offset of each lattice's sections
+    size_t args, work, mcs, label_off, dims, scratch_v, scratch_s, scratch_c, total;
+    size_t total_labels;
+    int grid;
+    bool mirror, full_rows;
+};
+
+int validate_batch(const cpm_params *p, int32_t n, const int32_t *n_cells)
+{
+    if (!p || !n_cells || n < 1) return fail(CPM_EINVAL, "empty batch");
+    for (int32_t i = 0; i < n; ++i) {
+        const int rc = validate(&p[i], n_cells[i]);
+        if (rc != CPM_OK) return rc;
+        if (p[i].ndim != p[0].ndim || p[i].sub != p[0].sub || p[i].attempts != p[0].attempts ||
+            (p[i].act_enabled != 0) != (p[0].act_enabled != 0))
+            return fail(CPM_EINVAL, "lattices of a batch must share ndim, sub, attempts and act_enabled");
+    }
+    return CPM_OK;
+}
+
+BatchLayout batch_layout_of(const cpm_params *p, int32_t n, const int32_t *n_cells)
+{
+    BatchLayout b{};
+    b.mirror = true;
+    for (int32_t i = 0; i < n; ++i) b.mirror = b.mirror && use_mirror(n_cells[i]);
+    b.full_rows = true;
+    for (int32_t i = 0; i < n; ++i) {
+        b.lat.push_back(layout_of(&p[i], n_cells[i], b.mirror ? 1 : 0));
+        b.full_rows = b.full_rows && b.lat.back().tg.full_rows;
+    }
+    if (!b.full_rows)  // one kernel variant for the whole batch
+        for (int32_t i = 0; i < n; ++i) b.lat[i] = layout_of(&p[i], n_cells[i], b.mirror ? 1 : 0, true);
+    b.grid = 0;
+    for (const Layout &l : b.lat) b.grid += l.tg.n_tiles;
+    size_t off = 0;
+    b.args = off;
+    off = align_up(off + sizeof(SweepArgs) * (size_t)n);
+    b.work = off;
+    off = align_up(off + sizeof(int2) * (size_t)b.grid);
+    b.mcs = off;
+    off = align_up(off + sizeof(uint32_t));
+    b.total_labels = 0;
+    for (int32_t i = 0; i < n; ++i) b.total_labels += (size_t)n_cells[i] + 1;
+    b.label_off = off;
+    off = align_up(off + sizeof(int64_t) * ((size_t)n + 1));
+    b.dims = off;
+    off = align_up(off + sizeof(int32_t) * 3 * (size_t)n);
+    b.scratch_v = off;
+    off = align_up(off + sizeof(int32_t) * b.total_labels);
+    b.scratch_s = off;
+    off = align_up(off + sizeof(int32_t) * b.total_labels);
+    b.scratch_c = off;
+    off = align_up(off + sizeof(int64_t) * 3 * b.total_labels);
+    for (const Layout &l : b.lat) {
+        b.base.push_back(off);
+        off = align_up(off + l.total);
+    }
+    b.total = off;
+    return b;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cpm_batch_workspace_bytes(const cpm_params *params, int32_t n, const int32_t *n_cells, size_t *bytes)
+{
+    const int rc = validate_batch(params, n, n_cells);
+    if (rc != CPM_OK) return rc;
+    if (!bytes) return fail(CPM_EINVAL, "bytes is NULL");
+    *bytes = batch_layout_of(params, n, n_cells).total;
+    return CPM_OK;
+}
+
+int cpm_batch_init(const cpm_params *params, int32_t n, const int32_t *n_cells, int32_t *d_lattices,
+                   const int32_t *d_cell_types, uint8_t *d_act, void *d_workspace, size_t workspace_bytes,
+                   void *stream, cpm_batch **out)
+{
+    if (!out) return fail(CPM_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate_batch(params, n, n_cells);
+    if (rc != CPM_OK) return rc;
+    if (!d_lattices || !d_cell_types || !d_workspace) return fail(CPM_EINVAL, "NULL device buffer");
+    if (params[0].act_enabled && !d_act) return fail(CPM_EINVAL, "act enabled but d_act is NULL");
+    if (reinterpret_cast<uintptr_t>(d_workspace) % 256 != 0) return fail(CPM_EINVAL, "workspace not 256-byte aligned");
+    const BatchLayout bl = batch_layout_of(params, n, n_cells);
+    if (workspace_bytes < bl.total) return fail(CPM_ENOMEM, "workspace smaller than cpm_batch_workspace_bytes()");
+
+    std::unique_ptr<cpm_batch> b(new (std::nothrow) cpm_batch());
+    if (!b) return fail(CPM_EINVAL, "host allocation failed");
+    b->n = n;
+    b->ndim = params[0].ndim;
+    b->s = params[0].sub;
+    b->k = params[0].attempts;
+    b->act = params[0].act_enabled != 0;
+    b->mirror = bl.mirror;
+    b->full_rows = bl.full_rows;
+    b->lattices = d_lattices;
+    b->act_field = d_act;
+    size_t sites = 0, labels = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        b->site_off.push_back(sites);
+        b->label_off.push_back(labels);
+        sites += (size_t)params[i].dims[0] * params[i].dims[1] * params[i].dims[2];
+        labels += (size_t)n_cells[i] + 1;
+        b->n_cells.push_back(n_cells[i]);
+    }
+    b->total_sites = sites;
+
+    std::vector<int32_t> types(labels);
+    hipStream_t st = as_stream(stream);
+    hipError_t e = hipMemcpyAsync(types.data(), d_cell_types, sizeof(int32_t) * labels, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return device_fail(e, "read cell types");
+
+    char *ws = static_cast<char *>(d_workspace);
+    b->single = true;
+    size_t lds = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        int32_t single = -1;
+        if ((rc = check_types(&params[i], types.data() + b->label_off[i], n_cells[i], &single)) != CPM_OK) return rc;
+        b->single = b->single && single >= 0;
+        char *lws = ws + bl.base[i];
+        const Layout &lay = bl.lat[i];
+        SweepArgs a;
+        fill_args(a, &params[i], lay, lws, d_lattices + b->site_off[i], d_cell_types + b->label_off[i],
+                  b->act ? d_act + b->site_off[i] : nullptr, single);
+        b->args.push_back(a);
+        b->ref.push_back(reinterpret_cast<int32_t *>(lws + lay.ref));
+        b->mirror_cells.push_back(lay.mirror_on ? reinterpret_cast<int16_t *>(lws + lay.mirror) : nullptr);
+        b->models.emplace_back(new (std::nothrow) DeviceModel);
+        if (!b->models.back()) return fail(CPM_EINVAL, "host allocation failed");
+        build_model(&params[i], b->models.back().get());
+        for (int32_t t = 0; t < lay.tg.n_tiles; ++t) b->work.push_back(make_int2(i, t));
+        lds = std::max(lds, (size_t)lay.tg.lds_bytes);
+        if ((e = start_lattice(a, lay, lws, b->models.back().get(), b->ndim, n_cells[i], st)) != hipSuccess)
+            return device_fail(e, "init");
+    }
+    b->d_args = reinterpret_cast<SweepArgs *>(ws + bl.args);
+    b->d_work = reinterpret_cast<int2 *>(ws + bl.work);
+    b->d_mcs = reinterpret_cast<uint32_t *>(ws + bl.mcs);
+    e = hipMemcpyAsync(b->d_args, b->args.data(), sizeof(SweepArgs) * (size_t)n, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_work, b->work.data(), sizeof(int2) * b->work.size(), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return device_fail(e, "upload batch tables");
+    for (int32_t i = 0; i <= n; ++i) b->host_label_off.push_back(i < n ? (int64_t)b->label_off[i] : (int64_t)labels);
+    for (int32_t i = 0; i < n; ++i)
+        for (int d = 0; d < 3; ++d) b->host_dims.push_back(params[i].dims[d]);
+    int64_t *d_label_off = reinterpret_cast<int64_t *>(ws + bl.label_off);
+    int32_t *d_dims = reinterpret_cast<int32_t *>(ws + bl.dims);
+    e = hipMemcpyAsync(d_label_off, b->host_label_off.data(), sizeof(int64_t) * b->host_label_off.size(),
+                       hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_dims, b->host_dims.data(), sizeof(int32_t) * b->host_dims.size(), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return device_fail(e, "upload stats tables");
+    b->stats_tables = cpm::StatsTables{d_label_off, d_dims, n, b->ndim, (int64_t)labels};
+    b->scratch_v = reinterpret_cast<int32_t *>(ws + bl.scratch_v);
+    b->scratch_s = reinterpret_cast<int32_t *>(ws + bl.scratch_s);
+    b->scratch_c = reinterpret_cast<int64_t *>(ws + bl.scratch_c);
+    cpm::BatchLaunch &L = b->launch;
+    L.args = b->d_args;
+    L.work = b->d_work;
+    L.mcs = b->d_mcs;
+    L.grid = bl.grid;
+    L.lds = lds;
+    L.ndim = b->ndim;
+    L.act = b->act;
+    L.mirror = b->mirror;
+    L.single = b->single;
+    L.k1 = b->k == 1;
+    L.full_rows = b->full_rows;
+    *out = b.release();
+    return CPM_OK;
+}
+
+int cpm_batch_sweep(cpm_batch *b, int32_t n_mcs, void *stream)
+{
+    if (!b) return fail(CPM_EINVAL, "batch is NULL");
+    if (n_mcs < 0) return fail(CPM_EINVAL, "n_mcs must be >= 0");
+    if (n_mcs == 0) return CPM_OK;
+    hipStream_t st = as_stream(stream);
+    int64_t sd = 1;
+    for (int d = 0; d < b->ndim; ++d) sd *= b->s;
+    const uint32_t n_act = (uint32_t)(((int64_t)1 << b->ndim) * sd / b->k);
+    hipError_t e;
+    for (int32_t i = 0; i < b->n && b->mirror; ++i) {
+        const SweepArgs &a = b->args[i];
+        if ((e = cpm::launch_to_mirror(a.lat, b->mirror_cells[i], (size_t)a.L[0] * a.L[1] * a.L[2], st)) != hipSuccess)
+            return device_fail(e, "to int16 working copy");
+    }
+    if ((e = cpm::launch_set_u32(b->d_mcs, (uint32_t)b->mcs, st)) != hipSuccess) return device_fail(e, "set mcs");
+    for (int32_t m = 0; m < n_mcs; ++m) {
+        for (uint32_t alpha = 0; alpha < n_act; ++alpha) {
+            if ((e = cpm::launch_batch_activation(b->launch, alpha, (int)(b->activation & 1), st)) != hipSuccess)
+                return device_fail(e, "batch activation");
+            ++b->activation;
+        }
+        if (b->act && (e = cpm::launch_act_decay(b->act_field, b->total_sites, st)) != hipSuccess)
+            return device_fail(e, "act decay");
+        if ((e = cpm::launch_add_u32(b->d_mcs, 1u, st)) != hipSuccess) return device_fail(e, "advance mcs");
+        ++b->mcs;
+        ++b->mcs_run;
+    }
+    for (int32_t i = 0; i < b->n && b->mirror; ++i) {
+        const SweepArgs &a = b->args[i];
+        if ((e = cpm::launch_from_mirror(b->mirror_cells[i], a.lat, (size_t)a.L[0] * a.L[1] * a.L[2], st)) != hipSuccess)
+            return device_fail(e, "from int16 working copy");
+    }
+    return CPM_OK;
+}
+
+int cpm_batch_counters(cpm_batch *b, int32_t *d_volume, int32_t *d_surface, void *stream)
+{
+    if (!b || !d_volume || !d_surface) return fail(CPM_EINVAL, "NULL argument");
+    for (int32_t i = 0; i < b->n; ++i) {
+        const hipError_t e = cpm::launch_copy_counters(b->args[i].counters[b->activation & 1], b->n_cells[i] + 1,
+                                                       d_volume + b->label_off[i], d_surface + b->label_off[i],
+                                                       as_stream(stream));
+        if (e != hipSuccess) return device_fail(e, "copy counters");
+    }
+    return CPM_OK;
+}
+
+int cpm_batch_cell_stats(cpm_batch *b, int32_t *d_volume, int32_t *d_surface, int64_t *d_centroid_sum, void *stream)
+{
+    if (!b || !d_volume || !d_surface) return fail(CPM_EINVAL, "NULL argument");
+    hipStream_t st = as_stream(stream);
+    hipError_t e;
+    for (int32_t i = 0; i < b->n; ++i) {
+        const SweepArgs &a = b->args[i];
+        const size_t nl = (size_t)b->n_cells[i] + 1;
+        int32_t *v = d_volume + b->label_off[i], *s = d_surface + b->label_off[i];
+        if ((e = cpm::launch_fill_i32(v, 0, nl, st)) != hipSuccess) return device_fail(e, "clear volume");
+        if ((e = cpm::launch_fill_i32(s, 0, nl, st)) != hipSuccess) return device_fail(e, "clear surface");
+        if ((e = cpm::launch_count(a, b->ndim, v, s, 1, st)) != hipSuccess) return device_fail(e, "count");
+        if (d_centroid_sum &&
+            (e = cpm::launch_centroids(a, b->ndim, b->n_cells[i], b->ref[i],
+                                       d_centroid_sum + b->label_off[i] * (size_t)b->ndim, st)) != hipSuccess)
+            return device_fail(e, "centroids");
+    }
+    return CPM_OK;
+}
+
+int cpm_batch_attempt_stats(cpm_batch *b, uint64_t *out, void *stream)
+{
+    if (!b || !out) return fail(CPM_EINVAL, "NULL argument");
+    hipStream_t st = as_stream(stream);
+    for (int32_t i = 0; i < b->n; ++i) {
+        const SweepArgs &a = b->args[i];
+        std::vector<uint64_t> per(2 * (size_t)a.tg.n_tiles);
+        hipError_t e = hipMemcpyAsync(per.data(), a.stats, sizeof(uint64_t) * per.size(), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return device_fail(e, "read stats");
+        out[3 * i] = b->mcs_run * (uint64_t)a.L[0] * a.L[1] * a.L[2];
+        out[3 * i + 1] = 0;
+        out[3 * i + 2] = 0;
+        for (int t = 0; t < a.tg.n_tiles; ++t) {
+            out[3 * i + 1] += per[2 * (size_t)t];
+            out[3 * i + 2] += per[2 * (size_t)t + 1];
+        }
+    }
+    return CPM_OK;
+}
+
+int cpm_batch_sample(cpm_batch *b, double *d_samples, int32_t k, int32_t n_samples, void *stream)
+{
+    if (!b || !d_samples) return fail(CPM_EINVAL, "NULL argument");
+    if (n_samples < 1 || k < 0 || k >= n_samples) return fail(CPM_EINVAL, "sample index out of range");
+    const int rc = cpm_batch_cell_stats(b, b->scratch_v, b->scratch_s, b->scratch_c, stream);
+    if (rc != CPM_OK) return rc;
+    const hipError_t e = cpm::launch_sample(b->stats_tables, b->scratch_v, b->scratch_s, b->scratch_c, d_samples, k,
+                                            n_samples, as_stream(stream));
+    if (e != hipSuccess) return device_fail(e, "sample");
+    return CPM_OK;
+}
+
+int cpm_batch_summary(cpm_batch *b, const double *d_samples, int32_t n_samples, double interval, double *d_out,
+                      void *stream)
+{
+    if (!b || !d_samples || !d_out) return fail(CPM_EINVAL, "NULL argument");
+    if (n_samples < 1 || !(interval > 0.0)) return fail(CPM_EINVAL, "need samples and a positive interval");
+    const hipError_t e = cpm::launch_summary(b->stats_tables, d_samples, n_samples, interval, d_out, as_stream(stream));
+    if (e != hipSuccess) return device_fail(e, "summary");
+    return CPM_OK;
+}
+
+int cpm_batch_set_mcs(cpm_batch *b, uint64_t mcs)
+{
+    if (!b) return fail(CPM_EINVAL, "batch is NULL");
+    b->mcs = mcs;
+    return CPM_OK;
+}
+
+int cpm_batch_get_mcs(const cpm_batch *b, uint64_t *mcs)
+{
+    if (!b || !mcs) return fail(CPM_EINVAL, "NULL argument");
+    *mcs = b->mcs;
+    return CPM_OK;
+}
+
+int cpm_batch_destroy(cpm_batch *b)
+{
+    delete b;
+    return CPM_OK;
+}
 
 }  // extern "C"

@@ -41,23 +41,6 @@ __device__ __forceinline__ constexpr int nb_dy(int n) { return (D == 2 ? (n < 4 
 template <int D>
 __device__ __forceinline__ constexpr int nb_dz(int n) { return D == 2 ? 0 : (n < 13 ? n : n + 1) / 9 - 1; }
 
-// Accept iff q <= 0 or u < floor(TI[h] TM[m] TL[l] / 2^64), q = h*2^16 + m*2^8 + l.
-__device__ __forceinline__ bool metropolis(const DeviceModel *m, int64_t q, uint32_t u)
-{
-    if (q <= 0) return true;
-    const uint64_t h = (uint64_t)q >> 16;
-    if (h >= (uint64_t)m->n_ti) return false;
-    uint64_t thr;
-    if ((q & 0xFFFF) == 0) {
-        thr = m->TI[h];
-    } else {
-        // TM[m] * TL[l] < 2^64 whenever (m, l) != (0, 0)
-        const uint64_t p = m->TM[(q >> 8) & 255] * m->TL[q & 255];
-        thr = __umul64hi(m->TI[h], p);
-    }
-    return (uint64_t)u < thr;
-}
-
 // exp(l * 2^-24) in 2^16 fixed point, floor-composed from the split tables.
 __device__ __forceinline__ int64_t exp_log24(const DeviceModel *m, uint64_t ell)
 {

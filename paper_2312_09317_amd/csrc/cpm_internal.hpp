@@ -29,6 +29,10 @@ struct DeviceModel {
     uint64_t TI[kMaxTI];
     uint64_t TM[256];
     uint64_t TL[256];
+    // the same tables as 32-bit words (entry 0, which is 2^32, left 0)
+    uint32_t TI32[kMaxTI];
+    uint32_t TM32[256];
+    uint32_t TL32[256];
     // Act geometric mean in the log domain: LG[a] = round(ln a * 2^24);
     // exp(l * 2^-24) = EH[l >> 16] * EM[(l >> 8) & 255] * EL[l & 255] with
     // EH in 2^24, EM in 2^31 and EL in 2^30 units.
@@ -51,6 +55,8 @@ struct TileGeometry {
     int32_t box_sites;     // LDS sites of the largest staged box
     int32_t lds_bytes;
     int32_t full_rows;     // 1: tiles span whole rows along x (full-row LDS layout)
+    int32_t row_chunk;     // bytes per load when staging label rows (16, 8 or 4)
+    int32_t act_chunk;     // bytes per load when staging activity rows
 };
 
 // Everything a sweep kernel needs, passed by value.
@@ -77,6 +83,26 @@ struct SweepArgs {
     TileGeometry tg;
 };
 
+// A batched activation: all lattices of a batch in one launch.
+struct BatchLaunch {
+    const SweepArgs *args;  // device array, one per lattice
+    const int2 *work;       // device array, (lattice, tile) per workgroup
+    const uint32_t *mcs;    // device MCS counter shared by the batch
+    int grid;
+    size_t lds;
+    int ndim;
+    bool act, mirror, single, k1, full_rows;
+};
+
+// Per-lattice tables for the summary statistics of a batch (device arrays).
+struct StatsTables {
+    const int64_t *label_off;  // n + 1 label offsets (labels of lattice i: [off[i], off[i+1]))
+    const int32_t *dims;       // 3 per lattice
+    int n;
+    int ndim;
+    int64_t total_labels;
+};
+
 // Launchers.  All asynchronous on `stream`.
 hipError_t launch_fill_i32(int32_t *p, int32_t value, size_t n, hipStream_t stream);
 hipError_t launch_count(const SweepArgs &a, int ndim, int32_t *v_out, int32_t *s_out, int stride,
@@ -90,6 +116,13 @@ hipError_t launch_centroids(const SweepArgs &a, int ndim, int32_t n_cells, int32
                             int64_t *out, hipStream_t stream);
 hipError_t launch_copy_counters(const int32_t *pairs, int32_t n_labels, int32_t *v_out,
                                 int32_t *s_out, hipStream_t stream);
+hipError_t launch_batch_activation(const BatchLaunch &b, uint32_t alpha, int parity, hipStream_t stream);
+hipError_t launch_set_u32(uint32_t *p, uint32_t value, hipStream_t stream);
+hipError_t launch_add_u32(uint32_t *p, uint32_t value, hipStream_t stream);
+hipError_t launch_sample(const StatsTables &t, const int32_t *vol, const int32_t *surf, const int64_t *csum,
+                         double *samples, int k, int n_samples, hipStream_t stream);
+hipError_t launch_summary(const StatsTables &t, const double *samples, int n_samples, double interval, double *out,
+                          hipStream_t stream);
 size_t sweep_lds_bytes(int ndim, bool act, bool mirror, int box_sites);
 
 }  // namespace cpm

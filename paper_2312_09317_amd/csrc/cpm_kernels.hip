@@ -142,6 +142,9 @@ __global__ void copy_counters_kernel(const int32_t *pairs, int32_t n_labels, int
     s_out[i] = i == 0 ? 0 : pairs[2 * i + 1];
 }
 
+__global__ void set_u32_kernel(uint32_t *p, uint32_t v) { *p = v; }
+__global__ void add_u32_kernel(uint32_t *p, uint32_t v) { *p += v; }
+
 inline unsigned blocks_for(size_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 }  // namespace
@@ -195,6 +198,18 @@ hipError_t launch_copy_counters(const int32_t *pairs, int32_t n_labels, int32_t 
                                 hipStream_t stream)
 {
     copy_counters_kernel<<<blocks_for((size_t)n_labels), kBlock, 0, stream>>>(pairs, n_labels, v_out, s_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_u32(uint32_t *p, uint32_t value, hipStream_t stream)
+{
+    set_u32_kernel<<<1, 1, 0, stream>>>(p, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_u32(uint32_t *p, uint32_t value, hipStream_t stream)
+{
+    add_u32_kernel<<<1, 1, 0, stream>>>(p, value);
     return hipGetLastError();
 }
 

@@ -47,6 +47,8 @@ __device__ __forceinline__ void add_deltas(int32_t *wr, int4 d)
 
 __host__ __device__ constexpr int align16(int v) { return (v + 15) & ~15; }
 
+constexpr int kQueue = 128;  // queued attempts per workgroup; the rest are evaluated where drawn
+
 // Where a lattice site lives in LDS.  Full-row layout: x is the global
 // coordinate and wraps; box layout: x is box-local.  y, z are box-local.
 template <bool FULLROW>
@@ -84,21 +86,47 @@ __device__ __forceinline__ int64_t gm_lds(const DeviceModel *m, const Cell *lab,
     return zero ? 0 : exp_log24(m, sum / cnt);
 }
 
-// One copy attempt past the early rejection: energy change, Metropolis test,
-// commit.  Returns the delta record (labels, surface deltas) if accepted.
-template <typename Cell, int D, bool ACT, bool SINGLE, bool FULLROW, int NOWN>
-__device__ __forceinline__ bool evaluate(const SweepArgs &a, const int32_t *rd, Cell *lab, uint8_t *lact,
-                                         const LdsMap<FULLROW> &map,
-                                         int tx_, int ty_, int tz_, int sx_, int sy_, int sz_, int lt, int ls,
-                                         uint32_t u2, const int4 *own, int n_own, int64_t &dso_out,
-                                         int64_t &dsn_out)
+// Threshold tables as 32-bit words; entry 0 of each stands for 2^32 and is
+// never read.
+struct ThrTables {
+    const uint32_t *tm, *tl, *ti;
+    int n_ti;
+};
+
+// Accept iff q <= 0 or u < floor(TI[h] TM[m] TL[l] / 2^64), q = h*2^16 + m*2^8 + l.
+__device__ __forceinline__ bool metropolis32(const ThrTables &tb, int64_t q, uint32_t u)
+{
+    if (q <= 0) return true;
+    const uint64_t h = (uint64_t)q >> 16;
+    if (h >= (uint64_t)tb.n_ti) return false;
+    const uint64_t two32 = (uint64_t)1 << 32;
+    const uint64_t ti = h == 0 ? two32 : (uint64_t)tb.ti[h];
+    if ((q & 0xFFFF) == 0) return (uint64_t)u < ti;
+    const int mm = (int)((q >> 8) & 255), ll = (int)(q & 255);
+    const uint64_t tm = mm ? (uint64_t)tb.tm[mm] : two32, tl = ll ? (uint64_t)tb.tl[ll] : two32;
+    return (uint64_t)u < __umul64hi(ti, tm * tl);  // tm * tl < 2^64 since (mm, ll) != (0, 0)
+}
+
+// J rows of the medium type and of the single cell type (when all cells share one type).
+struct JRows {
+    int64_t cc, cm, co, mc, mm, mo;
+};
+
+// One copy attempt past the early rejection: energy change of copying label
+// ls into the target (x,y,z) (eq. 1, eq. 3, eq. 7) and the Metropolis test
+// (eq. 2).  cnt_t / cnt_s are the (V, S) counters of the two cells as the
+// attempt sees them.  Returns acceptance; dso / dsn are the surface deltas.
+template <typename Cell, int D, bool ACT, bool SINGLE, bool FULLROW>
+__device__ __forceinline__ bool evaluate(const SweepArgs &a, const ThrTables &tb, const JRows &jr, Cell *lab,
+                                         uint8_t *lact, const LdsMap<FULLROW> &map, int tx_, int ty_, int tz_,
+                                         int sx_, int sy_, int sz_, int lt, int ls, int2 cnt_t, int2 cnt_s,
+                                         uint32_t u2, int64_t &dso_out, int64_t &dsn_out)
 {
     constexpr int NNB = D == 2 ? 8 : 26;
     const DeviceModel *m = a.model;
     const int tc = a.single_type, to = a.obstacle_type;
     const int tt = lt == 0 ? 0 : (SINGLE ? tc : a.cell_type[lt]);
     const int ts = ls == 0 ? 0 : (SINGLE ? tc : a.cell_type[ls]);
-    // the three x positions and the row offsets of the target's neighbourhood
     const int xm = map.x(tx_ - 1), x0 = map.x(tx_), xp = map.x(tx_ + 1);
     int k_old = 0, k_new = 0;
     int n_cell = 0, n_med = 0, n_obs = 0;
@@ -124,33 +152,19 @@ __device__ __forceinline__ bool evaluate(const SweepArgs &a, const int32_t *rd, 
         // neighbours unlike the label, weighted by J(label type, their type)
         const int64_t cs = n_cell - (ls > 0 ? k_new : 0), ms = n_med - (ls == 0 ? k_new : 0);
         const int64_t ct = n_cell - (lt > 0 ? k_old : 0), mt = n_med - (lt == 0 ? k_old : 0);
-        const int64_t *Js = m->J + ts * kMaxTypes, *Jt = m->J + tt * kMaxTypes;
-        adh = Js[tc] * cs + Js[0] * ms + Js[to] * n_obs - (Jt[tc] * ct + Jt[0] * mt + Jt[to] * n_obs);
+        adh = (ls > 0 ? jr.cc * cs + jr.cm * ms + jr.co * n_obs : jr.mc * cs + jr.mm * ms + jr.mo * n_obs) -
+              (lt > 0 ? jr.cc * ct + jr.cm * mt + jr.co * n_obs : jr.mc * ct + jr.mm * mt + jr.mo * n_obs);
     }
     const int64_t dso = 2 * k_old - NNB;
     const int64_t dsn = NNB - 2 * k_new;
     int64_t q = adh;
     if (lt >= 1) {
-        const int2 vs = reinterpret_cast<const int2 *>(rd)[lt];
-        int64_t v = vs.x, sf = vs.y;
-#pragma unroll
-        for (int jj = 0; jj < NOWN; ++jj) {
-            if (jj < n_own && own[jj].x == lt) { v -= 1; sf += own[jj].z; }
-            if (jj < n_own && own[jj].y == lt) { v += 1; sf += own[jj].w; }
-        }
-        q += m->lam_v[tt] * (1 - 2 * (v - m->v_target[tt]));
-        q += m->lam_s[tt] * (2 * dso * (sf - m->s_target[tt]) + dso * dso);
+        q += m->lam_v[tt] * (1 - 2 * ((int64_t)cnt_t.x - m->v_target[tt]));
+        q += m->lam_s[tt] * (2 * dso * ((int64_t)cnt_t.y - m->s_target[tt]) + dso * dso);
     }
     if (ls >= 1) {
-        const int2 vs = reinterpret_cast<const int2 *>(rd)[ls];
-        int64_t v = vs.x, sf = vs.y;
-#pragma unroll
-        for (int jj = 0; jj < NOWN; ++jj) {
-            if (jj < n_own && own[jj].x == ls) { v -= 1; sf += own[jj].z; }
-            if (jj < n_own && own[jj].y == ls) { v += 1; sf += own[jj].w; }
-        }
-        q += m->lam_v[ts] * (2 * (v - m->v_target[ts]) + 1);
-        q += m->lam_s[ts] * (2 * dsn * (sf - m->s_target[ts]) + dsn * dsn);
+        q += m->lam_v[ts] * (2 * ((int64_t)cnt_s.x - m->v_target[ts]) + 1);
+        q += m->lam_s[ts] * (2 * dsn * ((int64_t)cnt_s.y - m->s_target[ts]) + dsn * dsn);
     }
     if (ACT) {
         const int64_t gt = gm_lds<Cell, D, FULLROW>(m, lab, lact, map, tx_, ty_, tz_, lt, lt > 0 && m->max_act[tt] > 0);
@@ -161,22 +175,38 @@ __device__ __forceinline__ bool evaluate(const SweepArgs &a, const int32_t *rd, 
     }
     dso_out = dso;
     dsn_out = dsn;
-    return metropolis(m, q, u2);
+    return metropolis32(tb, q, u2);
 }
 
+// Counters of label c as an attempt of this thread sees them: the read
+// buffer plus the thread's own earlier deltas in this activation.
+__device__ __forceinline__ int2 seen_counters(const int32_t *rd, int c, const int4 *own, int n_own)
+{
+    if (c < 1) return make_int2(0, 0);
+    int2 v = reinterpret_cast<const int2 *>(rd)[c];
+#pragma unroll
+    for (int jj = 0; jj < kMaxAttempts; ++jj) {
+        if (jj < n_own && own[jj].x == c) { v.x -= 1; v.y += own[jj].z; }
+        if (jj < n_own && own[jj].y == c) { v.x += 1; v.y += own[jj].w; }
+    }
+    return v;
+}
+
+// One workgroup's share of one activation: tile `tile` of the lattice `a`.
 template <typename Cell, int D, bool ACT, bool SINGLE, bool K1, bool FULLROW>
-__global__ void __launch_bounds__(kBlock) tile_sweep_kernel(SweepArgs a, uint32_t mcs, uint32_t alpha, int parity)
+__device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_t mcs, uint32_t alpha, int parity)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int list_n, queue_n;
     __shared__ uint32_t n_nontrivial, n_accepted;
-    __shared__ int4 queue[K1 ? kBlock : 1];  // compacted attempts: (target, source, draw, global index)
+    // compacted attempts: packed target / source coordinates and draw, and the
+    // counters (V, S) of both cells fetched while drawing
+    __shared__ int4 queue[K1 ? kQueue : 1];
+    __shared__ int4 queue_cnt[K1 ? kQueue : 1];
     constexpr int R = ACT ? 2 : 1;           // read radius: the Act term reads neighbours of the source
     constexpr int NNB = D == 2 ? 8 : 26;
 
     const TileGeometry &tg = a.tg;
-    const int tile = (int)(blockIdx.x % kXcds) * tg.tiles_per_xcd + (int)(blockIdx.x / kXcds);
-    if (tile >= tg.n_tiles) return;  // uniform over the block
     const int tid = threadIdx.x;
     const int L0 = a.L[0], L1 = a.L[1], L2 = a.L[2];
     const int s = a.s;
@@ -210,63 +240,8 @@ __global__ void __launch_bounds__(kBlock) tile_sweep_kernel(SweepArgs a, uint32_
     // deltas of the previous activation go into the write buffer as well
     const int prev_n = a.dcount[tile];
     for (int i = tid; i < prev_n; i += kBlock) add_deltas(wr, dl[i]);
-
-    // stage the box (labels, and activity for the Act term)
-    const int rows = b1 * b2;
-    if (FULLROW) {
-        // whole rows: 16-byte chunks, eight loads in flight per thread
-        const int cpr = L0 * (int)sizeof(Cell) / 16;
-        const FastDiv by_b1((uint32_t)b1);
-        auto copy_rows = [&](const uint4 *src, uint4 *dst, int per_row) {
-            const FastDiv by_row((uint32_t)per_row);
-            auto row_chunk = [&](int c) {
-                const int r = (int)by_row.div((uint32_t)c), off = c - r * per_row;
-                const int rz = (int)by_b1.div((uint32_t)r), ry = r - rz * b1;
-                const int gy = wrap_once(o1 + ry, L1);
-                const int gz = D == 3 ? wrap_once(o2 + rz, L2) : 0;
-                return ((size_t)gz * L1 + gy) * per_row + off;
-            };
-            const int total = rows * per_row;
-            int c0 = tid;
-            for (; c0 + 7 * kBlock < total; c0 += 8 * kBlock) {
-                // eight independent loads before the first LDS store
-                const uint4 v0 = src[row_chunk(c0)];
-                const uint4 v1 = src[row_chunk(c0 + kBlock)];
-                const uint4 v2 = src[row_chunk(c0 + 2 * kBlock)];
-                const uint4 v3 = src[row_chunk(c0 + 3 * kBlock)];
-                const uint4 v4 = src[row_chunk(c0 + 4 * kBlock)];
-                const uint4 v5 = src[row_chunk(c0 + 5 * kBlock)];
-                const uint4 v6 = src[row_chunk(c0 + 6 * kBlock)];
-                const uint4 v7 = src[row_chunk(c0 + 7 * kBlock)];
-                dst[c0] = v0;
-                dst[c0 + kBlock] = v1;
-                dst[c0 + 2 * kBlock] = v2;
-                dst[c0 + 3 * kBlock] = v3;
-                dst[c0 + 4 * kBlock] = v4;
-                dst[c0 + 5 * kBlock] = v5;
-                dst[c0 + 6 * kBlock] = v6;
-                dst[c0 + 7 * kBlock] = v7;
-            }
-            for (; c0 < total; c0 += kBlock) dst[c0] = src[row_chunk(c0)];
-        };
-        copy_rows(reinterpret_cast<const uint4 *>(cells), reinterpret_cast<uint4 *>(lab), cpr);
-        if (ACT) copy_rows(reinterpret_cast<const uint4 *>(a.act), reinterpret_cast<uint4 *>(lact), L0 / 16);
-    } else {
-        const int wave = tid >> 6, lane = tid & 63;
-        const FastDiv by_b1((uint32_t)b1);
-        for (int r = wave; r < rows; r += kBlock / 64) {
-            const int rz = (int)by_b1.div((uint32_t)r), ry = r - rz * b1;
-            const int gy = wrap_once(o1 + ry, L1);
-            const int gz = D == 3 ? wrap_once(o2 + rz, L2) : 0;
-            const size_t base = ((size_t)gz * L1 + gy) * L0;
-            for (int x = lane; x < b0; x += 64) {
-                const int gx = wrap_once(o0 + x, L0);
-                lab[r * b0 + x] = cells[base + gx];
-                if (ACT) lact[r * b0 + x] = a.act[base + gx];
-            }
-        }
-    }
-    __syncthreads();
+    // threshold tables, read from the model (they stay in L2: every tile reads them)
+    const ThrTables tb{a.model->TM32, a.model->TL32, a.model->TI32, a.model->n_ti};
 
     const int areas = n0 * n1 * n2;
     const uint32_t sd = D == 2 ? (uint32_t)(s * s) : (uint32_t)(s * s * s);
@@ -292,7 +267,7 @@ __global__ void __launch_bounds__(kBlock) tile_sweep_kernel(SweepArgs a, uint32_
         u2 = u.z;
     };
     auto global_index = [&](int vx, int vy, int vz) {
-        const int gx = FULLROW ? vx : wrap_once(o0 + vx, L0);
+        const int gx = FULLROW ? wrap_once(vx, L0) : wrap_once(o0 + vx, L0);
         const int gy = wrap_once(o1 + vy, L1);
         const int gz = D == 3 ? wrap_once(o2 + vz, L2) : 0;
         return (int)(((size_t)gz * L1 + gy) * L0 + gx);
@@ -312,33 +287,139 @@ __global__ void __launch_bounds__(kBlock) tile_sweep_kernel(SweepArgs a, uint32_
         return rec;
     };
 
+    // k = 1: draw the attempt and read the two labels and their counters from
+    // global memory while the staging loads are in flight (no other attempt
+    // of this activation writes this sub-area or reads it)
+    int d_ttx = 0, d_tty = 0, d_ttz = 0, d_ssx = 0, d_ssy = 0, d_ssz = 0, d_lt = 0, d_ls = 0;
+    uint32_t d_u2 = 0;
+    bool d_nontrivial = false;
+    int2 d_ct = make_int2(0, 0), d_cs = make_int2(0, 0);
+    auto draw_k1 = [&]() {
+        if (!K1 || tid >= areas) return;
+        uint32_t area_id;
+        draw(tid, 0, d_ttx, d_tty, d_ttz, d_ssx, d_ssy, d_ssz, d_u2, area_id);
+        d_lt = cells[global_index(d_ttx, d_tty, d_ttz)];
+        d_ls = cells[global_index(d_ssx, d_ssy, d_ssz)];
+        d_nontrivial = d_lt != d_ls && d_lt >= 0 && d_ls >= 0;
+        if (d_nontrivial) {
+            d_ct = seen_counters(rd, d_lt, nullptr, 0);
+            d_cs = seen_counters(rd, d_ls, nullptr, 0);
+        }
+    };
+
+    // stage the box (labels, and activity for the Act term)
+    const int rows = b1 * b2;
+    if (FULLROW) {
+        // whole rows in the widest chunks (16, 8 or 4 bytes) that tile a row,
+        // eight loads in flight per thread
+        const FastDiv by_b1((uint32_t)b1);
+        auto copy_rows = [&](auto chunk, const void *src_v, void *dst_v, int row_bytes, auto &&in_flight) {
+            using Chunk = decltype(chunk);
+            const Chunk *src = reinterpret_cast<const Chunk *>(src_v);
+            Chunk *dst = reinterpret_cast<Chunk *>(dst_v);
+            const int per_row = row_bytes / (int)sizeof(Chunk);
+            const FastDiv by_row((uint32_t)per_row);
+            auto row_chunk = [&](int c) {
+                const int r = (int)by_row.div((uint32_t)c), off = c - r * per_row;
+                const int rz = (int)by_b1.div((uint32_t)r), ry = r - rz * b1;
+                const int gy = wrap_once(o1 + ry, L1);
+                const int gz = D == 3 ? wrap_once(o2 + rz, L2) : 0;
+                return ((size_t)gz * L1 + gy) * per_row + off;
+            };
+            const int total = rows * per_row;
+            int c0 = tid;
+            bool pending = true;
+            for (; c0 + 7 * kBlock < total; c0 += 8 * kBlock) {
+                // eight independent loads before the first LDS store
+                const Chunk v0 = src[row_chunk(c0)];
+                const Chunk v1 = src[row_chunk(c0 + kBlock)];
+                const Chunk v2 = src[row_chunk(c0 + 2 * kBlock)];
+                const Chunk v3 = src[row_chunk(c0 + 3 * kBlock)];
+                const Chunk v4 = src[row_chunk(c0 + 4 * kBlock)];
+                const Chunk v5 = src[row_chunk(c0 + 5 * kBlock)];
+                const Chunk v6 = src[row_chunk(c0 + 6 * kBlock)];
+                const Chunk v7 = src[row_chunk(c0 + 7 * kBlock)];
+                if (pending) {
+                    in_flight();
+                    pending = false;
+                }
+                dst[c0] = v0;
+                dst[c0 + kBlock] = v1;
+                dst[c0 + 2 * kBlock] = v2;
+                dst[c0 + 3 * kBlock] = v3;
+                dst[c0 + 4 * kBlock] = v4;
+                dst[c0 + 5 * kBlock] = v5;
+                dst[c0 + 6 * kBlock] = v6;
+                dst[c0 + 7 * kBlock] = v7;
+            }
+            if (pending) in_flight();
+            for (; c0 < total; c0 += kBlock) dst[c0] = src[row_chunk(c0)];
+        };
+        auto copy_any = [&](int chunk, const void *src, void *dst, int row_bytes, auto &&in_flight) {
+            if (chunk == 16) copy_rows(uint4{}, src, dst, row_bytes, in_flight);
+            else if (chunk == 8) copy_rows(uint2{}, src, dst, row_bytes, in_flight);
+            else copy_rows(uint32_t{}, src, dst, row_bytes, in_flight);
+        };
+        copy_any(tg.row_chunk, cells, lab, L0 * (int)sizeof(Cell), draw_k1);
+        if (ACT) copy_any(tg.act_chunk, a.act, lact, L0, [] {});
+    } else {
+        draw_k1();
+        const int wave = tid >> 6, lane = tid & 63;
+        const FastDiv by_b1((uint32_t)b1);
+        for (int r = wave; r < rows; r += kBlock / 64) {
+            const int rz = (int)by_b1.div((uint32_t)r), ry = r - rz * b1;
+            const int gy = wrap_once(o1 + ry, L1);
+            const int gz = D == 3 ? wrap_once(o2 + rz, L2) : 0;
+            const size_t base = ((size_t)gz * L1 + gy) * L0;
+            for (int x = lane; x < b0; x += 64) {
+                const int gx = wrap_once(o0 + x, L0);
+                lab[r * b0 + x] = cells[base + gx];
+                if (ACT) lact[r * b0 + x] = a.act[base + gx];
+            }
+        }
+    }
+    __syncthreads();
+
     uint32_t my_accepted = 0;
+    JRows jr{0, 0, 0, 0, 0, 0};
+    if (SINGLE) {
+        const int64_t *J = a.model->J;
+        const int tc = a.single_type, to = a.obstacle_type;
+        jr = JRows{J[tc * kMaxTypes + tc], J[tc * kMaxTypes], J[tc * kMaxTypes + to],
+                   J[tc], J[0], J[to]};
+    }
     if (K1) {
-        // phase 1: draw, drop trivial attempts, queue the rest
-        if (tid < areas) {
-            int ttx, tty, ttz, ssx, ssy, ssz;
-            uint32_t u2, area_id;
-            draw(tid, 0, ttx, tty, ttz, ssx, ssy, ssz, u2, area_id);
-            const int t = map.at(ttx, tty, ttz), sidx = map.at(ssx, ssy, ssz);
-            const int lt = lab[t], ls = lab[sidx];
-            if (lt != ls && lt >= 0 && ls >= 0) {
-                const int slot = atomicAdd(&queue_n, 1);
-                // pack the LDS coordinates of target and source
-                queue[slot] = make_int4(ttx | (tty << 16), ttz | (ssz << 16), (ssx & 0xFFFF) | (ssy << 16), (int)u2);
+        // phase 1: queue the nontrivial attempts with their counters
+        if (d_nontrivial) {
+            const int slot = atomicAdd(&queue_n, 1);
+            if (slot < kQueue) {
+                queue[slot] = make_int4(d_ttx | (d_tty << 16), d_ttz | (d_ssz << 16), (d_ssx & 0xFFFF) | (d_ssy << 16),
+                                        (int)d_u2);
+                queue_cnt[slot] = make_int4(d_ct.x, d_ct.y, d_cs.x, d_cs.y);
+            } else {
+                // queue full: evaluate here (no other attempt reads this sub-area)
+                int64_t dso, dsn;
+                if (evaluate<Cell, D, ACT, SINGLE, FULLROW>(a, tb, jr, lab, lact, map, d_ttx, d_tty, d_ttz, d_ssx,
+                                                            d_ssy, d_ssz, d_lt, d_ls, d_ct, d_cs, d_u2, dso, dsn)) {
+                    ++my_accepted;
+                    commit(map.at(d_ttx, d_tty, d_ttz), global_index(d_ttx, d_tty, d_ttz), d_lt, d_ls, dso, dsn);
+                }
             }
         }
         __syncthreads();
         // phase 2: energy change and Metropolis test of the queued attempts
         const int qn = queue_n;
-        for (int i = tid; i < qn; i += kBlock) {
-            const int4 e = queue[i];
+        // entry i goes to lane i / 4 of wave i % 4: the work spreads over all waves
+        for (int i = ((tid & 63) << 2) | (tid >> 6); i < min(qn, kQueue); i += kBlock) {
+            const int4 e = queue[i], c = queue_cnt[i];
             const int ttx = e.x & 0xFFFF, tty = e.x >> 16, ttz = e.y & 0xFFFF;
             const int ssz = e.y >> 16, ssx = (int)(int16_t)(e.z & 0xFFFF), ssy = e.z >> 16;
             const int t = map.at(ttx, tty, ttz);
             const int lt = lab[t], ls = lab[map.at(ssx, ssy, ssz)];
             int64_t dso, dsn;
-            if (evaluate<Cell, D, ACT, SINGLE, FULLROW, 0>(a, rd, lab, lact, map, ttx, tty, ttz, ssx, ssy, ssz, lt,
-                                                           ls, (uint32_t)e.w, nullptr, 0, dso, dsn)) {
+            if (evaluate<Cell, D, ACT, SINGLE, FULLROW>(a, tb, jr, lab, lact, map, ttx, tty, ttz, ssx, ssy, ssz, lt,
+                                                        ls, make_int2(c.x, c.y), make_int2(c.z, c.w), (uint32_t)e.w,
+                                                        dso, dsn)) {
                 ++my_accepted;
                 commit(t, global_index(ttx, tty, ttz), lt, ls, dso, dsn);
             }
@@ -358,9 +439,9 @@ __global__ void __launch_bounds__(kBlock) tile_sweep_kernel(SweepArgs a, uint32_
                 if (lt != ls && lt >= 0 && ls >= 0) {
                     ++my_nontrivial;
                     int64_t dso, dsn;
-                    if (evaluate<Cell, D, ACT, SINGLE, FULLROW, kMaxAttempts>(a, rd, lab, lact, map, ttx, tty, ttz,
-                                                                              ssx, ssy, ssz, lt, ls, u2, own, j,
-                                                                              dso, dsn)) {
+                    if (evaluate<Cell, D, ACT, SINGLE, FULLROW>(a, tb, jr, lab, lact, map, ttx, tty, ttz, ssx, ssy,
+                                                                ssz, lt, ls, seen_counters(rd, lt, own, j),
+                                                                seen_counters(rd, ls, own, j), u2, dso, dsn)) {
                         ++my_accepted;
                         rec = commit(t, global_index(ttx, tty, ttz), lt, ls, dso, dsn);
                     }
@@ -379,6 +460,26 @@ __global__ void __launch_bounds__(kBlock) tile_sweep_kernel(SweepArgs a, uint32_
         a.stats[2 * tile] += n_nontrivial;
         a.stats[2 * tile + 1] += n_accepted;
     }
+}
+
+// One lattice: workgroup b takes tile (b mod 8) * tiles_per_xcd + b div 8, so
+// each XCD sweeps one contiguous slab of tiles in every activation.
+template <typename Cell, int D, bool ACT, bool SINGLE, bool K1, bool FULLROW>
+__global__ void __launch_bounds__(kBlock) tile_sweep_kernel(SweepArgs a, uint32_t mcs, uint32_t alpha, int parity)
+{
+    const int tile = (int)(blockIdx.x % kXcds) * a.tg.tiles_per_xcd + (int)(blockIdx.x / kXcds);
+    if (tile >= a.tg.n_tiles) return;  // uniform over the block
+    sweep_tile<Cell, D, ACT, SINGLE, K1, FULLROW>(a, tile, mcs, alpha, parity);
+}
+
+// Many lattices advanced together: work[b] = (lattice, tile) of workgroup b;
+// all lattices share the MCS counter at *mcs.
+template <typename Cell, int D, bool ACT, bool SINGLE, bool K1, bool FULLROW>
+__global__ void __launch_bounds__(kBlock) batch_sweep_kernel(const SweepArgs *args, const int2 *work,
+                                                             const uint32_t *mcs, uint32_t alpha, int parity)
+{
+    const int2 w = work[blockIdx.x];
+    sweep_tile<Cell, D, ACT, SINGLE, K1, FULLROW>(args[w.x], w.y, *mcs, alpha, parity);
 }
 
 template <typename Cell, int D, bool ACT, bool SINGLE>
@@ -455,6 +556,42 @@ hipError_t launch_activation(const SweepArgs &a, int ndim, bool act, bool mirror
     const size_t lds = (size_t)a.tg.lds_bytes;
     return mirror ? launch_c<int16_t>(a, ndim, act, mcs, alpha, parity, lds, stream)
                   : launch_c<int32_t>(a, ndim, act, mcs, alpha, parity, lds, stream);
+}
+
+namespace {
+
+template <typename Cell, int D, bool ACT, bool SINGLE>
+hipError_t launch_batch_k(const BatchLaunch &b, uint32_t alpha, int parity, hipStream_t st)
+{
+    if (b.k1 && b.full_rows)
+        batch_sweep_kernel<Cell, D, ACT, SINGLE, true, true><<<b.grid, kBlock, b.lds, st>>>(b.args, b.work, b.mcs, alpha, parity);
+    else if (b.k1)
+        batch_sweep_kernel<Cell, D, ACT, SINGLE, true, false><<<b.grid, kBlock, b.lds, st>>>(b.args, b.work, b.mcs, alpha, parity);
+    else
+        batch_sweep_kernel<Cell, D, ACT, SINGLE, false, false><<<b.grid, kBlock, b.lds, st>>>(b.args, b.work, b.mcs, alpha, parity);
+    return hipGetLastError();
+}
+
+template <typename Cell, int D, bool ACT>
+hipError_t launch_batch_s(const BatchLaunch &b, uint32_t alpha, int parity, hipStream_t st)
+{
+    return b.single ? launch_batch_k<Cell, D, ACT, true>(b, alpha, parity, st)
+                    : launch_batch_k<Cell, D, ACT, false>(b, alpha, parity, st);
+}
+
+template <typename Cell>
+hipError_t launch_batch_c(const BatchLaunch &b, uint32_t alpha, int parity, hipStream_t st)
+{
+    if (b.ndim == 2)
+        return b.act ? launch_batch_s<Cell, 2, true>(b, alpha, parity, st) : launch_batch_s<Cell, 2, false>(b, alpha, parity, st);
+    return b.act ? launch_batch_s<Cell, 3, true>(b, alpha, parity, st) : launch_batch_s<Cell, 3, false>(b, alpha, parity, st);
+}
+
+}  // namespace
+
+hipError_t launch_batch_activation(const BatchLaunch &b, uint32_t alpha, int parity, hipStream_t stream)
+{
+    return b.mirror ? launch_batch_c<int16_t>(b, alpha, parity, stream) : launch_batch_c<int32_t>(b, alpha, parity, stream);
 }
 
 hipError_t launch_to_mirror(const int32_t *lat, int16_t *mirror, size_t n, hipStream_t stream)

@@ -162,3 +162,49 @@ def random_blobs(dims, n_cells, seed, fill=0.6, p_obstacle=0.0):
     if p_obstacle > 0:
         lat[(lat == 0) & (rng.random(lat.shape) < p_obstacle)] = -1
     return lat
+
+
+def squares_jittered_2d(L, density=0.3, side=10, seed=1):
+    """Squares of `side` on a jittered grid of an L x L lattice, filling about
+    `density` of it: n = round(L sqrt(density) / side) squares per axis, one in
+    each grid box, with an integer jitter drawn from [0, box - side]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = max(1, int(round(L * np.sqrt(density) / side)))
+    starts = [(i * L) // n for i in range(n)] + [L]
+    widths = np.diff(starts)
+    if widths.min() < side:
+        raise ValueError("squares do not fit their grid boxes")
+    lat = np.zeros((L, L), dtype=np.int32)
+    cid = 0
+    for j in range(n):
+        for i in range(n):
+            cid += 1
+            jx = rng.integers(0, widths[i] - side + 1)
+            jy = rng.integers(0, widths[j] - side + 1)
+            y0, x0 = starts[j] + jy, starts[i] + jx
+            lat[y0:y0 + side, x0:x0 + side] = cid
+    return lat.reshape(1, L, L), cid
+
+
+def config3(n_lattices=512, L_min=64, L_max=512, seed=1, n_mcs=500, max_act=30):
+    """Batched 2D CPM: n_lattices independent lattices with side lengths drawn
+    uniformly from the multiples of 4 in [L_min, L_max], cells seeded at 30%
+    density as 10x10 squares (V_target = 100), and per-lattice lambda_V, J_cc,
+    J_cm, T and lambda_act drawn log-uniformly within a factor 4 of the 2D
+    base values (lambda_V 50, J_cc 20, J_cm 10, T 20, lambda_act 300);
+    Max_act = 30, s = 2, k = 1.  Lattice i has lattice_id i."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sides = np.arange(L_min, L_max + 1, 4)
+    out = []
+    for i in range(n_lattices):
+        L = int(rng.choice(sides))
+        f = np.exp(rng.uniform(np.log(0.25), np.log(4.0), size=5))
+        lam_v, j_cc, j_cm, T, lam_act = 50.0 * f[0], 20.0 * f[1], 10.0 * f[2], 20.0 * f[3], 300.0 * f[4]
+        lat, n = squares_jittered_2d(L, 0.3, 10, seed=seed * 100003 + i)
+        J, lv, vt, ls, st = _two_type(j_cc, j_cm, lam_v, 100)
+        w = Workload(f"2d-{L}x{L}-batch{i}", 2, (L, L, 1), lat, np.array([0] + [1] * n, dtype=np.int32),
+                     J, lv, vt, ls, st, T=float(T), n_mcs=n_mcs, seed=seed, lattice_id=i,
+                     lambda_act=np.array([0.0, lam_act]), max_act=np.array([0, max_act], dtype=np.int32))
+        w.extra["params"] = dict(lambda_V=lam_v, J_cc=j_cc, J_cm=j_cm, T=float(T), lambda_act=lam_act, L=L)
+        out.append(w)
+    return out

@@ -1,0 +1,124 @@
+"""GPU parity of batched lattices: every lattice of a batch must evolve bit
+for bit as the oracle evolves it alone."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2312_09317_amd import cpm, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available()
+    cpm.load()
+    return torch
+
+
+def _oracle_state(w):
+    m = oracle.Model(w.ndim, w.dims[:w.ndim], w.J, w.lambda_V, w.V_target, w.lambda_S, w.S_target,
+                     lambda_act=w.lambda_act, max_act=w.max_act, T=w.T, seed=w.seed, lattice_id=w.lattice_id,
+                     s=w.s, k=w.k, obstacle_type=w.obstacle_type)
+    return oracle.State(m, w.lattice, w.cell_type, w.act)
+
+
+def _check(torch, ws, batch, n_mcs):
+    v, s = batch.counters()
+    stats = batch.attempt_stats()
+    torch.cuda.synchronize()
+    v, s = v.cpu().numpy(), s.cpu().numpy()
+    for i, w in enumerate(ws):
+        st = _oracle_state(w)
+        st.sweep(n_mcs)
+        lat = batch.lattice(i).cpu().numpy()
+        assert np.array_equal(lat, st.lattice), f"lattice {i} ({w.name}) differs at {np.flatnonzero(lat != st.lattice)[:5]}"
+        if st.act is not None:
+            np.testing.assert_array_equal(batch.activity(i).cpu().numpy(), st.act)
+        lo, hi = int(batch.label_off[i]), int(batch.label_off[i + 1])
+        np.testing.assert_array_equal(v[lo + 1:hi], st.V[1:])
+        np.testing.assert_array_equal(s[lo + 1:hi], st.S[1:])
+        assert tuple(int(x) for x in stats[i]) == tuple(int(x) for x in st.stats)
+
+
+@pytest.mark.parametrize("act", [True, False])
+def test_batch_uneven_2d(torch_cuda, act):
+    ws = inputs.config3(n_lattices=10, L_min=20, L_max=96, seed=3, n_mcs=5)
+    if not act:
+        for w in ws:
+            w.lambda_act = None
+            w.max_act = None
+    _say(f"batch of {len(ws)}: sides {[w.dims[0] for w in ws]} act={act}")
+    b = cpm.Batch([cpm.Params.from_workload(w) for w in ws], [w.lattice for w in ws], [w.cell_type for w in ws])
+    b.sweep(2)
+    b.sweep(3)
+    torch_cuda.cuda.synchronize()
+    assert b.mcs == 5
+    _check(torch_cuda, ws, b, 5)
+
+
+def test_batch_3d_mixed_types(torch_cuda):
+    rng = np.random.default_rng(4)
+    ws = []
+    for i, dims in enumerate([(8, 8, 8), (12, 8, 16), (16, 16, 8), (4, 4, 4)]):
+        lat = inputs.random_blobs(dims, 6, seed=40 + i, fill=0.6, p_obstacle=0.03)
+        J = np.array([[0, 3, 5, 1.5], [3, 7, 1.25, -2], [5, 1.25, 9, 0.5], [1.5, -2, 0.5, 0]]) * (1 + 0.1 * i)
+        w = inputs.Workload(f"3d-{dims}", 3, dims, lat, np.array([0, 1, 2, 1, 2, 1, 2], dtype=np.int32), J,
+                            np.array([0, 2.5, 1.0, 0]), np.array([0, 30, 40, 0], dtype=np.int32),
+                            np.array([0, 0.5, 0.25, 0]), np.array([0, 90, 120, 0], dtype=np.int32),
+                            T=6.0 + i, n_mcs=3, seed=7, lattice_id=100 + i, obstacle_type=3)
+        ws.append(w)
+    _say("batch 3d mixed types")
+    b = cpm.Batch([cpm.Params.from_workload(w) for w in ws], [w.lattice for w in ws], [w.cell_type for w in ws])
+    b.sweep(3)
+    torch_cuda.cuda.synchronize()
+    _check(torch_cuda, ws, b, 3)
+
+
+def test_batch_cell_stats(torch_cuda):
+    ws = inputs.config3(n_lattices=4, L_min=24, L_max=64, seed=9, n_mcs=3)
+    b = cpm.Batch([cpm.Params.from_workload(w) for w in ws], [w.lattice for w in ws], [w.cell_type for w in ws])
+    b.sweep(3)
+    v, s, c = b.cell_stats()
+    torch_cuda.cuda.synchronize()
+    v, s, c = v.cpu().numpy(), s.cpu().numpy(), c.cpu().numpy()
+    for i, w in enumerate(ws):
+        st = _oracle_state(w)
+        st.sweep(3)
+        m = st.model
+        V, S, C = oracle.cell_stats(m, st.lattice, w.n_cells)
+        lo, hi = int(b.label_off[i]), int(b.label_off[i + 1])
+        np.testing.assert_array_equal(v[lo + 1:hi], V[1:])
+        np.testing.assert_array_equal(s[lo + 1:hi], S[1:])
+        np.testing.assert_array_equal(c[lo + 1:hi], C[1:])
+
+
+def test_batch_summary_statistics(torch_cuda):
+    from oracle import summary
+    ws = inputs.config3(n_lattices=5, L_min=32, L_max=80, seed=21, n_mcs=0)
+    burn, n_samples, interval = 6, 5, 3
+    b = cpm.Batch([cpm.Params.from_workload(w) for w in ws], [w.lattice for w in ws], [w.cell_type for w in ws])
+    samples = b.run_with_samples(burn, n_samples, interval)
+    out = b.summary(samples, n_samples, float(interval))
+    torch_cuda.cuda.synchronize()
+    out = out.cpu().numpy()
+    for i, w in enumerate(ws):
+        st = _oracle_state(w)
+        st.sweep(burn)
+        Vs, Ss, Ps = [], [], []
+        for k in range(n_samples):
+            if k:
+                st.sweep(interval)
+            V, S, C = oracle.cell_stats(st.model, st.lattice, w.n_cells)
+            Vs.append(V)
+            Ss.append(S)
+            Ps.append(summary.centroids(V, C, w.dims))
+        ref = summary.summary(np.array(Vs), np.array(Ss), np.array(Ps), w.dims, float(interval))
+        np.testing.assert_allclose(out[i], ref, rtol=1e-9, atol=1e-9)
