@@ -1,4 +1,5 @@
 """Build libcpm.so (HIP kernels + C ABI) in-tree for gfx950 with hipcc."""
+import concurrent.futures
 import os
 import subprocess
 import sys
@@ -9,7 +10,7 @@ OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libcpm.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
-SOURCES = ["cpm_sweep.hip", "cpm_kernels.hip", "cpm_stats.hip", "cpm_api.cpp"]
+SOURCES = ["cpm_sweep.hip", "cpm_kernels.hip", "cpm_stats.hip", "emu_kernels.hip", "cpm_api.cpp", "emu_api.cpp"]
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
     # keep the compiler from emitting packed FP32 instructions
@@ -24,15 +25,18 @@ def sources():
 
 def build(verbose: bool = False) -> str:
     os.makedirs(OUT_DIR, exist_ok=True)
-    objs = []
+    jobs = []
     for src in sources():
         obj = os.path.join(OUT_DIR, os.path.basename(src) + ".o")
-        lang = ["-x", "hip"]
-        cmd = ["hipcc", *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC, *lang, "-c", src, "-o", obj]
+        cmd = ["hipcc", *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC, "-x", "hip", "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd))
-        subprocess.run(cmd, check=True)
-        objs.append(obj)
+        jobs.append((cmd, obj))
+    # one compiler process per source, at most four at a time
+    with concurrent.futures.ThreadPoolExecutor(max_workers=4) as pool:
+        for f in [pool.submit(subprocess.run, cmd, check=True) for cmd, _ in jobs]:
+            f.result()
+    objs = [obj for _, obj in jobs]
     tmp = LIB + ".tmp"
     cmd = ["hipcc", "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp]
     if verbose:
@@ -47,7 +51,7 @@ def is_stale() -> bool:
         return True
     t = os.path.getmtime(LIB)
     deps = sources() + [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h"))]
-    deps.append(os.path.join(INCLUDE, "cpm.h"))
+    deps += [os.path.join(INCLUDE, f) for f in os.listdir(INCLUDE) if f.endswith(".h")]
     return any(os.path.getmtime(d) > t for d in deps)
 
 

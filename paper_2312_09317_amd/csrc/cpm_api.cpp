@@ -75,6 +75,12 @@ int device_fail(hipError_t e, const char *where)
     return fail(CPM_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
 }
 
+}  // namespace
+
+int cpm::report_error(int code, const char *msg) { return fail(code, msg); }
+
+namespace {
+
 // Round half away from zero onto the 2^-16 grid.
 int64_t to_fixed(double x) { return (int64_t)std::llround(x * 65536.0); }
 

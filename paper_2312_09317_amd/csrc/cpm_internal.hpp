@@ -14,6 +14,9 @@ constexpr int kMaxAttempts = 8;
 constexpr int kBlock = 256;   // threads per sweep workgroup (one per thread area)
 constexpr int kXcds = 8;      // MI355X: workgroups go round-robin to 8 XCDs, each with its own L2
 
+// Records msg as the calling thread's last error (cpm_last_error) and returns code.
+int report_error(int code, const char *msg);
+
 // Quantised model + acceptance / activity tables, copied once into the
 // workspace at init.  Energies in units of 2^-16.
 struct DeviceModel {

@@ -1,0 +1,142 @@
+"""Emulator workflow: parameter points -> batched CPM runs -> summary
+statistics -> training of the MLP emulator -> prediction with the plain model
+as fallback.
+
+Every arithmetic step runs in libcpm's kernels (the batched sweep, the
+sampling and summary kernels, the emulator's forward, backward and Adam
+kernels); this module only chooses parameter points, builds the initial
+lattices (paper_2312_09317_amd.inputs) and moves buffers between calls.
+
+A parameter point is one 2D lattice of the batched workload: per-lattice
+lambda_V, J(cell,cell), J(cell,medium), T and lambda_act drawn log-uniformly
+within a factor 4 of the base values, side L from the multiples of 4 in
+[L_min, L_max], cells seeded at 30% density as 10 x 10 squares.  Its
+emulator input is (ln lambda_V, ln J_cc, ln J_cm, ln T, ln lambda_act,
+L / 512).
+"""
+import time
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import cpm, emu, inputs
+
+
+@dataclass
+class RunPlan:
+    """Sampling schedule of one CPM run: burn_in MCS, then n_samples samples
+    interval MCS apart."""
+    burn_in: int = 100
+    n_samples: int = 41
+    interval: int = 10
+
+    @property
+    def n_mcs(self) -> int:
+        return self.burn_in + (self.n_samples - 1) * self.interval
+
+
+def features(workloads) -> np.ndarray:
+    """Emulator inputs of a list of batched-workload lattices."""
+    out = np.empty((len(workloads), emu.N_IN))
+    for i, w in enumerate(workloads):
+        p = w.extra["params"]
+        out[i] = [np.log(p["lambda_V"]), np.log(p["J_cc"]), np.log(p["J_cm"]), np.log(p["T"]),
+                  np.log(p["lambda_act"]), p["L"] / 512.0]
+    return out
+
+
+def points(n, seed, L_min=64, L_max=512, max_act=30):
+    """n parameter points (the batched workload's lattices) from seed."""
+    return inputs.config3(n_lattices=n, L_min=L_min, L_max=L_max, seed=seed, n_mcs=0, max_act=max_act)
+
+
+def reseed(workloads, seed):
+    """The same parameter points with another Philox seed (fresh replicates)."""
+    out = []
+    for w in workloads:
+        c = inputs.Workload(**{**w.__dict__, "seed": seed, "extra": dict(w.extra)})
+        out.append(c)
+    return out
+
+
+def simulate(workloads, plan: RunPlan, batch: int = 512, device="cuda", log=None):
+    """Summary statistics (n x 8, float64 on the host) of one run per
+    workload, batch lattices per launch.  Returns (stats, gpu_seconds)."""
+    import torch
+    stats = np.empty((len(workloads), 8))
+    seconds = 0.0
+    for s in range(0, len(workloads), batch):
+        part = workloads[s:s + batch]
+        params = [cpm.Params.from_workload(w) for w in part]
+        b = cpm.Batch(params, [w.lattice for w in part], [w.cell_type for w in part], device=device)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        samples = b.run_with_samples(plan.burn_in, plan.n_samples, plan.interval)
+        out = b.summary(samples, plan.n_samples, float(plan.interval))
+        torch.cuda.synchronize()
+        seconds += time.perf_counter() - t0
+        stats[s:s + len(part)] = out.cpu().numpy()
+        b.close()
+        del samples
+        if log:
+            log(f"simulated {s + len(part)}/{len(workloads)} points, {seconds:.2f} s GPU")
+    return stats, seconds
+
+
+class Surrogate:
+    """A trained emulator and the input domain it was trained on.
+
+    predict() answers with the network for points inside the box spanned by
+    the training inputs and runs the plain model (simulate) for the rest.
+    """
+
+    def __init__(self, max_batch=65536, device="cuda"):
+        self.device = device
+        self.net = emu.Emulator(max_batch, device)
+        self.lo = None
+        self.hi = None
+
+    def train(self, x, t, epochs=200, batch=512, lr=2e-3, lr_final=5e-5, seed=0):
+        """Fit the network to inputs x (n x 6) and statistics t (n x 8) from
+        fresh weights; returns the per-epoch mean losses."""
+        x = np.asarray(x, dtype=np.float64)
+        W, b = inputs.mlp_weights(seed)
+        self.net.set_params(emu.pack(W, b))
+        self.net.fit_norm(x, t)
+        self.lo, self.hi = x.min(axis=0), x.max(axis=0)
+        return self.net.fit(x, t, epochs=epochs, batch=batch, lr=lr, seed=seed, lr_final=lr_final)
+
+    def inside(self, x) -> np.ndarray:
+        x = np.asarray(x, dtype=np.float64)
+        return np.all((x >= self.lo) & (x <= self.hi), axis=1)
+
+    def predict(self, x, workloads=None, plan: RunPlan = None):
+        """Statistics for inputs x; rows outside the training domain come
+        from CPM runs of the matching workloads (required then)."""
+        x = np.asarray(x, dtype=np.float64)
+        y = np.empty((len(x), 8))
+        for s in range(0, len(x), self.net.max_batch):
+            y[s:s + self.net.max_batch] = self.net.forward(x[s:s + self.net.max_batch]).cpu().numpy()
+        out = ~self.inside(x)
+        if out.any():
+            if workloads is None or plan is None:
+                raise ValueError("points outside the training domain need their workloads and a run plan")
+            idx = np.nonzero(out)[0]
+            y[idx], _ = simulate([workloads[i] for i in idx], plan, device=self.device)
+        return y, out
+
+    def close(self):
+        self.net.close()
+
+
+def linear_baseline(x_train, t_train, x_test):
+    """Least-squares affine fit of the statistics on the inputs (host
+    numpy): the reference the emulator has to beat."""
+    A = np.hstack([x_train, np.ones((len(x_train), 1))])
+    coef, *_ = np.linalg.lstsq(A, t_train, rcond=None)
+    return np.hstack([x_test, np.ones((len(x_test), 1))]) @ coef
+
+
+def relative_error(pred, ref):
+    """Per point and statistic |pred - ref| / |ref|."""
+    return np.abs(pred - ref) / np.maximum(np.abs(ref), 1e-300)

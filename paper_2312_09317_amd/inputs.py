@@ -208,3 +208,15 @@ def config3(n_lattices=512, L_min=64, L_max=512, seed=1, n_mcs=500, max_act=30):
         w.extra["params"] = dict(lambda_V=lam_v, J_cc=j_cc, J_cm=j_cm, T=float(T), lambda_act=lam_act, L=L)
         out.append(w)
     return out
+
+
+def mlp_weights(seed=0, sizes=(6, 256, 256, 256, 8)):
+    """Initial weights of a multilayer perceptron: W[l] (out x in) uniform in
+    +-sqrt(6 / in) (He-style), b[l] zero, drawn from a seeded PCG64 stream."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    W, b = [], []
+    for i in range(len(sizes) - 1):
+        bound = np.sqrt(6.0 / sizes[i])
+        W.append(rng.uniform(-bound, bound, size=(sizes[i + 1], sizes[i])))
+        b.append(np.zeros(sizes[i + 1]))
+    return W, b

@@ -103,3 +103,47 @@ def test_strerror():
     lib = cpm.load()
     for c in range(6):
         assert lib.cpm_strerror(c)
+
+
+EMU_HEADER = os.path.join(os.path.dirname(HEADER), "emu.h")
+
+
+def test_emu_exports_every_declared_symbol():
+    from paper_2312_09317_amd import emu
+    text = open(EMU_HEADER).read()
+    names = sorted(set(re.findall(r"^\s*int\s+(emu_\w+)\s*\(", text, re.M)))
+    assert len(names) >= 10
+    lib = emu.lib()
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(emu.EXPORTS)
+
+
+def test_emu_host_calls_without_device():
+    from paper_2312_09317_amd import emu
+    # 6*256 + 256 + 2 * (256*256 + 256) + 8*256 + 8
+    assert emu.emu_param_count() == 135432
+    small, big = emu.emu_workspace_bytes(1), emu.emu_workspace_bytes(65536)
+    assert small % 256 == 0 and big > 256 * 65536 * 2 * 6
+    assert small < big
+    for bad in (0, -1, (1 << 20) + 1):
+        with pytest.raises(cpm.CpmError) as e:
+            emu.emu_workspace_bytes(bad)
+        assert e.value.code == cpm.CPM_EINVAL
+    lib = emu.lib()
+    h = ctypes.c_void_p(0)
+    assert lib.emu_init(64, None, 1 << 20, None, ctypes.byref(h)) == cpm.CPM_EINVAL
+    assert lib.emu_forward(None, None, 1, None, None) == cpm.CPM_EINVAL
+    assert lib.emu_adam(None, None, 1e-3, None) == cpm.CPM_EINVAL
+
+
+def test_emu_pack_round_trip():
+    from paper_2312_09317_amd import emu
+    from oracle import mlp
+    W, b = mlp.init(seed=2)
+    p = emu.pack(W, b)
+    assert p.size == 135432 and p.dtype == np.float32
+    W2, b2 = emu.unpack(p)
+    for l in range(4):
+        np.testing.assert_array_equal(W2[l], W[l].astype(np.float32))
+        np.testing.assert_array_equal(b2[l], b[l].astype(np.float32))

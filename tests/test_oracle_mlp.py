@@ -65,3 +65,45 @@ def test_training_reduces_loss():
         new = opt.step(W + b, gW + gb)
         W, b = new[:4], new[4:]
     assert mlp.loss(W, b, x, t) < 0.2 * l0
+
+
+def test_bf16_rounding_matches_torch():
+    # torch's float32 -> bfloat16 conversion rounds to nearest, ties to even
+    import torch
+    rng = np.random.default_rng(5)
+    v = np.concatenate([rng.normal(size=4000) * 10.0 ** rng.integers(-30, 30, size=4000),
+                        [0.0, -0.0, 1.0, -1.0, 3.0e38, -3.0e38, 1e-40, -1e-40, 1e-45]]).astype(np.float32)
+    # exact ties: the 16 dropped bits are 0x8000, with even and odd kept parts
+    u = rng.integers(0, 2 ** 31, size=1000, dtype=np.uint64).astype(np.uint32)
+    ties = ((u & np.uint32(0xFFFF0000)) | np.uint32(0x8000)).view(np.float32)
+    v = np.concatenate([v, ties[np.isfinite(ties)]])
+    ref = torch.from_numpy(v.copy()).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(mlp.bf16(v), ref)
+
+
+def test_bf16_mode_within_rounding_bound_of_exact():
+    W, b = mlp.init(seed=4)
+    rng = np.random.default_rng(6)
+    x = rng.normal(size=(40, 6))
+    t = rng.normal(size=(40, 8))
+    y = mlp.forward(W, b, x)
+    yb = mlp.forward(W, b, x, rnd=mlp.bf16)
+    u = 2.0 ** -9  # bf16 unit roundoff
+    rel = np.linalg.norm(yb - y) / np.linalg.norm(y)
+    assert 0 < rel < 8 * u
+    gW, gb = mlp.grads(W, b, x, t)
+    gWb, gbb = mlp.grads(W, b, x, t, rnd=mlp.bf16)
+    for l in range(4):
+        assert np.linalg.norm(gWb[l] - gW[l]) / np.linalg.norm(gW[l]) < 16 * u
+        assert np.linalg.norm(gbb[l] - gb[l]) / np.linalg.norm(gb[l]) < 16 * u
+
+
+def test_bf16_mode_exact_on_representable_first_layer():
+    # with bf16-representable inputs and weights the rounding of the operands
+    # changes nothing in the first pre-activation
+    W, b = mlp.init(seed=7)
+    W = [mlp.bf16(w) for w in W]
+    x = mlp.bf16(np.random.default_rng(8).normal(size=(5, 6)))
+    _, _, pre = mlp.forward(W, b, x, keep=True)
+    _, _, preb = mlp.forward(W, b, x, keep=True, rnd=mlp.bf16)
+    np.testing.assert_array_equal(pre[0], preb[0])
