@@ -132,6 +132,13 @@ int cpm_init(const cpm_params *params, int32_t *d_lattice, const int32_t *d_cell
  * counter with it.  Asynchronous on `stream`. */
 int cpm_sweep(cpm_handle *h, int32_t n_mcs, void *stream);
 
+/* cpm_sweep for benchmarks (n_mcs >= 1): the same launches and results, with
+ * a HIP event pair recorded on `stream` around every activation launch.
+ * Waits for the stream after each MCS and stores in *mean_us the mean
+ * elapsed time of the pairs, the activation kernel's average duration in
+ * microseconds. */
+int cpm_sweep_profiled(cpm_handle *h, int32_t n_mcs, void *stream, double *mean_us);
+
 /*
  * Recounts, from the lattice alone, every label's volume V and surface S
  * (d_volume, d_surface: int32[n_cells + 1] device; entry 0 is the medium's)
@@ -184,7 +191,14 @@ int cpm_batch_workspace_bytes(const cpm_params *params, int32_t n, const int32_t
 int cpm_batch_init(const cpm_params *params, int32_t n, const int32_t *n_cells, int32_t *d_lattices,
                    const int32_t *d_cell_types, uint8_t *d_act, void *d_workspace, size_t workspace_bytes,
                    void *stream, cpm_batch **out);
+/* Runs n_mcs MCS of every lattice.  By default each MCS is one launch of an
+ * executable HIP graph captured at the first call (the activations, the Act
+ * decay and the MCS counter update, kernel nodes only); the graph is
+ * captured on a private stream and launched on `stream`. */
 int cpm_batch_sweep(cpm_batch *b, int32_t n_mcs, void *stream);
+/* enabled = 0: cpm_batch_sweep launches the same kernels one by one instead
+ * of the graph (same results).  Pure host. */
+int cpm_batch_use_graph(cpm_batch *b, int32_t enabled);
 int cpm_batch_counters(cpm_batch *b, int32_t *d_volume, int32_t *d_surface, void *stream);
 int cpm_batch_cell_stats(cpm_batch *b, int32_t *d_volume, int32_t *d_surface, int64_t *d_centroid_sum,
                          void *stream);

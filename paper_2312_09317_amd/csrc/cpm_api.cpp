@@ -53,11 +53,19 @@ struct cpm_batch {
     cpm::StatsTables stats_tables{};
     int32_t *scratch_v = nullptr, *scratch_s = nullptr;
     int64_t *scratch_c = nullptr;
+    int32_t *scratch_ref = nullptr;  // centroid reference sites, packed per label
     std::vector<int64_t> host_label_off;
     std::vector<int32_t> host_dims;
     uint64_t mcs = 0;
     uint64_t activation = 0;
     uint64_t mcs_run = 0;
+    size_t max_sites = 0;
+    bool use_graph = true;
+    hipGraphExec_t mcs_graph = nullptr;  // one MCS: every activation, act decay, MCS counter
+    ~cpm_batch()
+    {
+        if (mcs_graph) (void)hipGraphExecDestroy(mcs_graph);
+    }
 };
 
 namespace {
@@ -440,12 +448,15 @@ int cpm_init(const cpm_params *params, int32_t *d_lattice, const int32_t *d_cell
     return CPM_OK;
 }
 
-int cpm_sweep(cpm_handle *h, int32_t n_mcs, void *stream)
+}  // extern "C"
+
+namespace {
+
+// n_mcs MCS of a single lattice.  With `ev` (2 * activations-per-MCS events)
+// every activation launch is bracketed by an event pair; the stream is then
+// waited for after each MCS and the pairs' elapsed times added to *kernel_ms.
+int sweep_impl(cpm_handle *h, int32_t n_mcs, hipStream_t st, hipEvent_t *ev, double *kernel_ms)
 {
-    if (!h) return fail(CPM_EINVAL, "handle is NULL");
-    if (n_mcs < 0) return fail(CPM_EINVAL, "n_mcs must be >= 0");
-    if (n_mcs == 0) return CPM_OK;
-    hipStream_t st = as_stream(stream);
     int64_t sd = 1;
     for (int d = 0; d < h->ndim; ++d) sd *= h->s;
     const uint32_t n_act = (uint32_t)(((int64_t)1 << h->ndim) * sd / h->k);
@@ -456,18 +467,60 @@ int cpm_sweep(cpm_handle *h, int32_t n_mcs, void *stream)
     for (int32_t i = 0; i < n_mcs; ++i) {
         const uint32_t mcs = (uint32_t)h->mcs;
         for (uint32_t alpha = 0; alpha < n_act; ++alpha) {
+            if (ev && (e = hipEventRecord(ev[2 * alpha], st)) != hipSuccess) return device_fail(e, "event");
             e = cpm::launch_activation(h->args, h->ndim, h->act, h->mirror, mcs, alpha, (int)(h->activation & 1), st);
             if (e != hipSuccess) return device_fail(e, "activation");
+            if (ev && (e = hipEventRecord(ev[2 * alpha + 1], st)) != hipSuccess) return device_fail(e, "event");
             ++h->activation;
         }
         if (h->act && (e = cpm::launch_act_decay(h->args.act, n_sites, st)) != hipSuccess)
             return device_fail(e, "act decay");
         ++h->mcs;
         h->attempts_run += (uint64_t)n_sites;
+        if (ev) {
+            if ((e = hipStreamSynchronize(st)) != hipSuccess) return device_fail(e, "synchronize");
+            for (uint32_t alpha = 0; alpha < n_act; ++alpha) {
+                float ms = 0.f;
+                if ((e = hipEventElapsedTime(&ms, ev[2 * alpha], ev[2 * alpha + 1])) != hipSuccess)
+                    return device_fail(e, "event time");
+                *kernel_ms += ms;
+            }
+        }
     }
     if (h->mirror && (e = cpm::launch_from_mirror(h->mirror_cells, h->args.lat, n_sites, st)) != hipSuccess)
         return device_fail(e, "from int16 working copy");
     return CPM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cpm_sweep(cpm_handle *h, int32_t n_mcs, void *stream)
+{
+    if (!h) return fail(CPM_EINVAL, "handle is NULL");
+    if (n_mcs < 0) return fail(CPM_EINVAL, "n_mcs must be >= 0");
+    if (n_mcs == 0) return CPM_OK;
+    return sweep_impl(h, n_mcs, as_stream(stream), nullptr, nullptr);
+}
+
+int cpm_sweep_profiled(cpm_handle *h, int32_t n_mcs, void *stream, double *mean_us)
+{
+    if (!h || !mean_us) return fail(CPM_EINVAL, "NULL argument");
+    if (n_mcs < 1) return fail(CPM_EINVAL, "n_mcs must be >= 1");
+    int64_t sd = 1;
+    for (int d = 0; d < h->ndim; ++d) sd *= h->s;
+    const uint32_t n_act = (uint32_t)(((int64_t)1 << h->ndim) * sd / h->k);
+    std::vector<hipEvent_t> ev(2 * (size_t)n_act, nullptr);
+    hipError_t e = hipSuccess;
+    for (size_t i = 0; i < ev.size() && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
+    int rc = e == hipSuccess ? CPM_OK : device_fail(e, "create events");
+    double ms = 0.0;
+    if (rc == CPM_OK) rc = sweep_impl(h, n_mcs, as_stream(stream), ev.data(), &ms);
+    for (hipEvent_t x : ev)
+        if (x) (void)hipEventDestroy(x);
+    if (rc == CPM_OK) *mean_us = ms * 1e3 / ((double)n_mcs * n_act);
+    return rc;
 }
 
 int cpm_attempt_stats(cpm_handle *h, uint64_t *out, void *stream)
@@ -559,7 +612,7 @@ namespace {
 struct BatchLayout {
     std::vector<Layout> lat;
     std::vector<size_t> base;  // workspace offset of each lattice's sections
-    size_t args, work, mcs, label_off, dims, scratch_v, scratch_s, scratch_c, total;
+    size_t args, work, mcs, label_off, dims, scratch_v, scratch_s, scratch_c, scratch_ref, total;
     size_t total_labels;
     int grid;
     bool mirror, full_rows;
@@ -611,6 +664,8 @@ BatchLayout batch_layout_of(const cpm_params *p, int32_t n, const int32_t *n_cel
     off = align_up(off + sizeof(int32_t) * b.total_labels);
     b.scratch_c = off;
     off = align_up(off + sizeof(int64_t) * 3 * b.total_labels);
+    b.scratch_ref = off;
+    off = align_up(off + sizeof(int32_t) * b.total_labels);
     for (const Layout &l : b.lat) {
         b.base.push_back(off);
         off = align_up(off + l.total);
@@ -666,6 +721,8 @@ int cpm_batch_init(const cpm_params *params, int32_t n, const int32_t *n_cells, 
         b->n_cells.push_back(n_cells[i]);
     }
     b->total_sites = sites;
+    for (int32_t i = 0; i < n; ++i)
+        b->max_sites = std::max(b->max_sites, (size_t)params[i].dims[0] * params[i].dims[1] * params[i].dims[2]);
 
     std::vector<int32_t> types(labels);
     hipStream_t st = as_stream(stream);
@@ -717,6 +774,7 @@ int cpm_batch_init(const cpm_params *params, int32_t n, const int32_t *n_cells, 
     b->scratch_v = reinterpret_cast<int32_t *>(ws + bl.scratch_v);
     b->scratch_s = reinterpret_cast<int32_t *>(ws + bl.scratch_s);
     b->scratch_c = reinterpret_cast<int64_t *>(ws + bl.scratch_c);
+    b->scratch_ref = reinterpret_cast<int32_t *>(ws + bl.scratch_ref);
     cpm::BatchLaunch &L = b->launch;
     L.args = b->d_args;
     L.work = b->d_work;
@@ -733,6 +791,45 @@ int cpm_batch_init(const cpm_params *params, int32_t n, const int32_t *n_cells, 
     return CPM_OK;
 }
 
+namespace {
+
+// The kernels of one MCS of a batch, in order.  Every MCS has an even number
+// of activations and sweeps always run whole MCS, so activation alpha of an
+// MCS always reads counter buffer alpha & 1 and the sequence is the same for
+// every MCS (the MCS index comes from the device counter).
+hipError_t enqueue_mcs(const cpm_batch *b, uint32_t n_act, hipStream_t st)
+{
+    hipError_t e;
+    for (uint32_t alpha = 0; alpha < n_act; ++alpha)
+        if ((e = cpm::launch_batch_activation(b->launch, alpha, (int)(alpha & 1), st)) != hipSuccess) return e;
+    if (b->act && (e = cpm::launch_act_decay(b->act_field, b->total_sites, st)) != hipSuccess) return e;
+    return cpm::launch_add_u32(b->d_mcs, 1u, st);
+}
+
+// Capture one MCS into an executable graph, on a private stream of default
+// priority (the caller's stream is never put into capture mode).  The graph
+// holds kernel nodes only.
+hipError_t capture_mcs(cpm_batch *b, uint32_t n_act)
+{
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    hipGraph_t g = nullptr;
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        const hipError_t launched = enqueue_mcs(b, n_act, cs);
+        e = hipStreamEndCapture(cs, &g);
+        if (launched != hipSuccess) e = launched;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->mcs_graph, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) b->mcs_graph = nullptr;
+    return e;
+}
+
+}  // namespace
+
 int cpm_batch_sweep(cpm_batch *b, int32_t n_mcs, void *stream)
 {
     if (!b) return fail(CPM_EINVAL, "batch is NULL");
@@ -743,29 +840,27 @@ int cpm_batch_sweep(cpm_batch *b, int32_t n_mcs, void *stream)
     for (int d = 0; d < b->ndim; ++d) sd *= b->s;
     const uint32_t n_act = (uint32_t)(((int64_t)1 << b->ndim) * sd / b->k);
     hipError_t e;
-    for (int32_t i = 0; i < b->n && b->mirror; ++i) {
-        const SweepArgs &a = b->args[i];
-        if ((e = cpm::launch_to_mirror(a.lat, b->mirror_cells[i], (size_t)a.L[0] * a.L[1] * a.L[2], st)) != hipSuccess)
-            return device_fail(e, "to int16 working copy");
-    }
+    if (b->use_graph && !b->mcs_graph && (e = capture_mcs(b, n_act)) != hipSuccess)
+        return device_fail(e, "capture MCS graph");
+    if (b->mirror && (e = cpm::launch_batch_mirror(b->d_args, b->n, b->max_sites, true, st)) != hipSuccess)
+        return device_fail(e, "to int16 working copy");
     if ((e = cpm::launch_set_u32(b->d_mcs, (uint32_t)b->mcs, st)) != hipSuccess) return device_fail(e, "set mcs");
     for (int32_t m = 0; m < n_mcs; ++m) {
-        for (uint32_t alpha = 0; alpha < n_act; ++alpha) {
-            if ((e = cpm::launch_batch_activation(b->launch, alpha, (int)(b->activation & 1), st)) != hipSuccess)
-                return device_fail(e, "batch activation");
-            ++b->activation;
-        }
-        if (b->act && (e = cpm::launch_act_decay(b->act_field, b->total_sites, st)) != hipSuccess)
-            return device_fail(e, "act decay");
-        if ((e = cpm::launch_add_u32(b->d_mcs, 1u, st)) != hipSuccess) return device_fail(e, "advance mcs");
+        e = b->use_graph ? hipGraphLaunch(b->mcs_graph, st) : enqueue_mcs(b, n_act, st);
+        if (e != hipSuccess) return device_fail(e, "MCS");
+        b->activation += n_act;
         ++b->mcs;
         ++b->mcs_run;
     }
-    for (int32_t i = 0; i < b->n && b->mirror; ++i) {
-        const SweepArgs &a = b->args[i];
-        if ((e = cpm::launch_from_mirror(b->mirror_cells[i], a.lat, (size_t)a.L[0] * a.L[1] * a.L[2], st)) != hipSuccess)
-            return device_fail(e, "from int16 working copy");
-    }
+    if (b->mirror && (e = cpm::launch_batch_mirror(b->d_args, b->n, b->max_sites, false, st)) != hipSuccess)
+        return device_fail(e, "from int16 working copy");
+    return CPM_OK;
+}
+
+int cpm_batch_use_graph(cpm_batch *b, int32_t enabled)
+{
+    if (!b) return fail(CPM_EINVAL, "batch is NULL");
+    b->use_graph = enabled != 0;
     return CPM_OK;
 }
 
@@ -784,21 +879,10 @@ int cpm_batch_counters(cpm_batch *b, int32_t *d_volume, int32_t *d_surface, void
 int cpm_batch_cell_stats(cpm_batch *b, int32_t *d_volume, int32_t *d_surface, int64_t *d_centroid_sum, void *stream)
 {
     if (!b || !d_volume || !d_surface) return fail(CPM_EINVAL, "NULL argument");
-    hipStream_t st = as_stream(stream);
-    hipError_t e;
-    for (int32_t i = 0; i < b->n; ++i) {
-        const SweepArgs &a = b->args[i];
-        const size_t nl = (size_t)b->n_cells[i] + 1;
-        int32_t *v = d_volume + b->label_off[i], *s = d_surface + b->label_off[i];
-        if ((e = cpm::launch_fill_i32(v, 0, nl, st)) != hipSuccess) return device_fail(e, "clear volume");
-        if ((e = cpm::launch_fill_i32(s, 0, nl, st)) != hipSuccess) return device_fail(e, "clear surface");
-        if ((e = cpm::launch_count(a, b->ndim, v, s, 1, st)) != hipSuccess) return device_fail(e, "count");
-        if (d_centroid_sum &&
-            (e = cpm::launch_centroids(a, b->ndim, b->n_cells[i], b->ref[i],
-                                       d_centroid_sum + b->label_off[i] * (size_t)b->ndim, st)) != hipSuccess)
-            return device_fail(e, "centroids");
-    }
-    return CPM_OK;
+    const hipError_t e = cpm::launch_batch_cell_stats(b->d_args, b->stats_tables.label_off, b->n, b->ndim,
+                                                      b->max_sites, (size_t)b->stats_tables.total_labels, d_volume,
+                                                      d_surface, b->scratch_ref, d_centroid_sum, as_stream(stream));
+    return e == hipSuccess ? CPM_OK : device_fail(e, "cell stats");
 }
 
 int cpm_batch_attempt_stats(cpm_batch *b, uint64_t *out, void *stream)

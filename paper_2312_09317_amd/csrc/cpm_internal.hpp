@@ -108,12 +108,20 @@ struct StatsTables {
 
 // Launchers.  All asynchronous on `stream`.
 hipError_t launch_fill_i32(int32_t *p, int32_t value, size_t n, hipStream_t stream);
+// Volume, surface and (cent != NULL) centroid sums of every lattice of a
+// batch, packed per label; ref is scratch of total_labels entries.
+hipError_t launch_batch_cell_stats(const SweepArgs *d_args, const int64_t *d_label_off, int n_lattices, int ndim,
+                                   size_t max_sites, size_t total_labels, int32_t *v_out, int32_t *s_out,
+                                   int32_t *ref, int64_t *cent, hipStream_t stream);
 hipError_t launch_count(const SweepArgs &a, int ndim, int32_t *v_out, int32_t *s_out, int stride,
                         hipStream_t stream);
 hipError_t launch_activation(const SweepArgs &a, int ndim, bool act, bool mirror, uint32_t mcs,
                              uint32_t alpha, int parity, hipStream_t stream);
 hipError_t launch_to_mirror(const int32_t *lat, int16_t *mirror, size_t n, hipStream_t stream);
 hipError_t launch_from_mirror(const int16_t *mirror, int32_t *lat, size_t n, hipStream_t stream);
+// Every lattice of a batch (args[i].lat <-> args[i].cells) in one launch.
+hipError_t launch_batch_mirror(const SweepArgs *d_args, int n_lattices, size_t max_sites, bool to_mirror,
+                               hipStream_t stream);
 hipError_t launch_act_decay(uint8_t *act, size_t n, hipStream_t stream);
 hipError_t launch_centroids(const SweepArgs &a, int ndim, int32_t n_cells, int32_t *ref,
                             int64_t *out, hipStream_t stream);

@@ -33,9 +33,11 @@ __device__ __forceinline__ int map_slot(LabelMap &m, int label)
     return -1;
 }
 
+// One workgroup's share (kSitesPerBlock sites from `block`) of a reduction
+// over lattice a.
 template <int D, int MODE>
-__global__ void __launch_bounds__(kBlock) reduce_kernel(SweepArgs a, int32_t *v_out, int32_t *s_out, int stride,
-                                                        int32_t *ref, int64_t *cent)
+__device__ __forceinline__ void reduce_block(const SweepArgs &a, int64_t block, int32_t *v_out, int32_t *s_out,
+                                             int stride, int32_t *ref, int64_t *cent)
 {
     __shared__ LabelMap m;
     const int tid = threadIdx.x;
@@ -48,7 +50,7 @@ __global__ void __launch_bounds__(kBlock) reduce_kernel(SweepArgs a, int32_t *v_
     __syncthreads();
     const int L0 = a.L[0], L1 = a.L[1], L2 = a.L[2];
     const int64_t n_sites = (int64_t)L0 * L1 * L2;
-    const int64_t base = (int64_t)blockIdx.x * kSitesPerBlock;
+    const int64_t base = block * kSitesPerBlock;
     constexpr int NNB = D == 2 ? 8 : 26;
     for (int j = 0; j < kSitesPerThread; ++j) {
         const int64_t i = base + tid + (int64_t)j * kBlock;
@@ -106,6 +108,28 @@ __global__ void __launch_bounds__(kBlock) reduce_kernel(SweepArgs a, int32_t *v_
                 atomicAdd(reinterpret_cast<unsigned long long *>(&cent[(size_t)c * D + d]), m.c[h][d]);
         }
     }
+}
+
+template <int D, int MODE>
+__global__ void __launch_bounds__(kBlock) reduce_kernel(SweepArgs a, int32_t *v_out, int32_t *s_out, int stride,
+                                                        int32_t *ref, int64_t *cent)
+{
+    reduce_block<D, MODE>(a, blockIdx.x, v_out, s_out, stride, ref, cent);
+}
+
+// Every lattice of a batch in one launch: blockIdx.y is the lattice, outputs
+// are packed per label (label_off) as in the batch's per-cell arrays.
+template <int D, int MODE>
+__global__ void __launch_bounds__(kBlock) batch_reduce_kernel(const SweepArgs *args, const int64_t *label_off,
+                                                              int32_t *v_out, int32_t *s_out, int32_t *ref,
+                                                              int64_t *cent)
+{
+    const SweepArgs &a = args[blockIdx.y];
+    const int64_t n_sites = (int64_t)a.L[0] * a.L[1] * a.L[2];
+    if ((int64_t)blockIdx.x * kSitesPerBlock >= n_sites) return;
+    const int64_t o = label_off[blockIdx.y];
+    reduce_block<D, MODE>(a, blockIdx.x, v_out ? v_out + o : nullptr, s_out ? s_out + o : nullptr, 1,
+                          ref ? ref + o : nullptr, cent ? cent + o * D : nullptr);
 }
 
 __global__ void fill_i32_kernel(int32_t *p, int32_t value, size_t n)
@@ -190,6 +214,30 @@ hipError_t launch_centroids(const SweepArgs &a, int ndim, int32_t n_cells, int32
     } else {
         reduce_kernel<3, kRef><<<grid, kBlock, 0, stream>>>(a, nullptr, nullptr, 0, ref, nullptr);
         reduce_kernel<3, kCentroid><<<grid, kBlock, 0, stream>>>(a, nullptr, nullptr, 0, ref, out);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_cell_stats(const SweepArgs *d_args, const int64_t *d_label_off, int n_lattices, int ndim,
+                                   size_t max_sites, size_t total_labels, int32_t *v_out, int32_t *s_out,
+                                   int32_t *ref, int64_t *cent, hipStream_t stream)
+{
+    const dim3 grid((unsigned)((max_sites + kSitesPerBlock - 1) / kSitesPerBlock), (unsigned)n_lattices);
+    hipError_t e;
+    if ((e = launch_fill_i32(v_out, 0, total_labels, stream)) != hipSuccess) return e;
+    if ((e = launch_fill_i32(s_out, 0, total_labels, stream)) != hipSuccess) return e;
+    if (ndim == 2) batch_reduce_kernel<2, kCount><<<grid, kBlock, 0, stream>>>(d_args, d_label_off, v_out, s_out, nullptr, nullptr);
+    else batch_reduce_kernel<3, kCount><<<grid, kBlock, 0, stream>>>(d_args, d_label_off, v_out, s_out, nullptr, nullptr);
+    if ((e = hipGetLastError()) != hipSuccess || !cent) return e;
+    if ((e = launch_fill_i32(ref, INT32_MAX, total_labels, stream)) != hipSuccess) return e;
+    if ((e = launch_fill_i32(reinterpret_cast<int32_t *>(cent), 0, total_labels * ndim * 2, stream)) != hipSuccess)
+        return e;
+    if (ndim == 2) {
+        batch_reduce_kernel<2, kRef><<<grid, kBlock, 0, stream>>>(d_args, d_label_off, nullptr, nullptr, ref, nullptr);
+        batch_reduce_kernel<2, kCentroid><<<grid, kBlock, 0, stream>>>(d_args, d_label_off, nullptr, nullptr, ref, cent);
+    } else {
+        batch_reduce_kernel<3, kRef><<<grid, kBlock, 0, stream>>>(d_args, d_label_off, nullptr, nullptr, ref, nullptr);
+        batch_reduce_kernel<3, kCentroid><<<grid, kBlock, 0, stream>>>(d_args, d_label_off, nullptr, nullptr, ref, cent);
     }
     return hipGetLastError();
 }

@@ -28,6 +28,8 @@
 // exact state at its start) and adds its own deltas plus those of activation
 // g-1 (kept per tile in `dlist`) into buffer (g+1)&1, which so becomes the
 // exact state at the start of g+1.
+#include <algorithm>
+
 #include "cpm_device.hpp"
 
 namespace cpm {
@@ -541,6 +543,38 @@ __global__ void from_mirror_kernel(const int16_t *__restrict__ mir, int32_t *__r
     }
 }
 
+// All lattices of a batch to / from their int16 working copies in one
+// launch: blockIdx.y is the lattice, x blocks stride over its sites in
+// groups of 4 (lattice sizes are multiples of (2s)^d, bases 16-byte aligned).
+template <bool TO>
+__global__ void batch_mirror_kernel(const SweepArgs *__restrict__ args)
+{
+    const SweepArgs &a = args[blockIdx.y];
+    const size_t n = (size_t)a.L[0] * a.L[1] * a.L[2];
+    int16_t *mir = static_cast<int16_t *>(a.cells);
+    for (size_t i = ((size_t)blockIdx.x * kBlock + threadIdx.x) * 4; i < n; i += (size_t)gridDim.x * kBlock * 4) {
+        if (i + 4 <= n) {
+            if (TO) {
+                const int4 v = *reinterpret_cast<const int4 *>(a.lat + i);
+                short4 w;
+                w.x = (short)v.x;
+                w.y = (short)v.y;
+                w.z = (short)v.z;
+                w.w = (short)v.w;
+                *reinterpret_cast<short4 *>(mir + i) = w;
+            } else {
+                const short4 w = *reinterpret_cast<const short4 *>(mir + i);
+                *reinterpret_cast<int4 *>(a.lat + i) = make_int4(w.x, w.y, w.z, w.w);
+            }
+        } else {
+            for (size_t j = i; j < n; ++j) {
+                if (TO) mir[j] = (int16_t)a.lat[j];
+                else a.lat[j] = mir[j];
+            }
+        }
+    }
+}
+
 }  // namespace
 
 size_t sweep_lds_bytes(int ndim, bool act, bool mirror, int box_sites)
@@ -605,6 +639,16 @@ hipError_t launch_from_mirror(const int16_t *mirror, int32_t *lat, size_t n, hip
 {
     const size_t threads = (n + 3) / 4;
     from_mirror_kernel<<<(unsigned)((threads + kBlock - 1) / kBlock), kBlock, 0, stream>>>(mirror, lat, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_mirror(const SweepArgs *d_args, int n_lattices, size_t max_sites, bool to_mirror,
+                               hipStream_t stream)
+{
+    const size_t groups = (max_sites + 4 * kBlock - 1) / (4 * kBlock);
+    const dim3 grid((unsigned)std::min<size_t>(groups, 64), (unsigned)n_lattices);
+    if (to_mirror) batch_mirror_kernel<true><<<grid, kBlock, 0, stream>>>(d_args);
+    else batch_mirror_kernel<false><<<grid, kBlock, 0, stream>>>(d_args);
     return hipGetLastError();
 }
 

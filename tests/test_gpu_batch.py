@@ -122,3 +122,24 @@ def test_batch_summary_statistics(torch_cuda):
             Ps.append(summary.centroids(V, C, w.dims))
         ref = summary.summary(np.array(Vs), np.array(Ss), np.array(Ps), w.dims, float(interval))
         np.testing.assert_allclose(out[i], ref, rtol=1e-9, atol=1e-9)
+
+
+def test_batch_graph_replays_match_eager_and_oracle(torch_cuda):
+    # the MCS graph is replayed with eager work (counters, cell stats) between
+    # replays; every replay must leave the state the eager launches leave
+    ws = inputs.config3(n_lattices=6, L_min=24, L_max=64, seed=8, n_mcs=6)
+    _say("graph replays vs eager vs oracle")
+    mk = lambda: cpm.Batch([cpm.Params.from_workload(w) for w in ws], [w.lattice for w in ws],
+                           [w.cell_type for w in ws])
+    g, e = mk(), mk()
+    e.use_graph(False)
+    for step in range(6):
+        g.sweep(1)
+        e.sweep(1)
+        vg, sg, cg = g.cell_stats()
+        ve, se, ce = e.cell_stats()
+        torch_cuda.cuda.synchronize()
+        assert torch_cuda.equal(g.lattices, e.lattices), step
+        assert torch_cuda.equal(g.act, e.act), step
+        assert torch_cuda.equal(vg, ve) and torch_cuda.equal(sg, se) and torch_cuda.equal(cg, ce), step
+    _check(torch_cuda, ws, g, 6)
