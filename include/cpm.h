@@ -132,13 +132,6 @@ int cpm_init(const cpm_params *params, int32_t *d_lattice, const int32_t *d_cell
  * counter with it.  Asynchronous on `stream`. */
 int cpm_sweep(cpm_handle *h, int32_t n_mcs, void *stream);
 
-/* cpm_sweep for benchmarks (n_mcs >= 1): the same launches and results, with
- * a HIP event pair recorded on `stream` around every activation launch.
- * Waits for the stream after each MCS and stores in *mean_us the mean
- * elapsed time of the pairs, the activation kernel's average duration in
- * microseconds. */
-int cpm_sweep_profiled(cpm_handle *h, int32_t n_mcs, void *stream, double *mean_us);
-
 /*
  * Recounts, from the lattice alone, every label's volume V and surface S
  * (d_volume, d_surface: int32[n_cells + 1] device; entry 0 is the medium's)

@@ -50,7 +50,7 @@ class cpm_params(ctypes.Structure):
     ]
 
 
-EXPORTS = ("cpm_validate", "cpm_workspace_bytes", "cpm_init", "cpm_sweep", "cpm_sweep_profiled", "cpm_cell_stats",
+EXPORTS = ("cpm_validate", "cpm_workspace_bytes", "cpm_init", "cpm_sweep", "cpm_cell_stats",
            "cpm_counters", "cpm_attempt_stats", "cpm_set_mcs", "cpm_get_mcs", "cpm_destroy",
            "cpm_batch_workspace_bytes", "cpm_batch_init", "cpm_batch_sweep", "cpm_batch_use_graph", "cpm_batch_counters",
            "cpm_batch_cell_stats", "cpm_batch_attempt_stats", "cpm_batch_sample", "cpm_batch_summary",
@@ -79,7 +79,6 @@ def load(path: str = LIB_PATH):
     l.cpm_workspace_bytes.argtypes = [pp, I32, ctypes.POINTER(SZ)]
     l.cpm_init.argtypes = [pp, P, P, I32, P, P, SZ, P, ctypes.POINTER(P)]
     l.cpm_sweep.argtypes = [P, I32, P]
-    l.cpm_sweep_profiled.argtypes = [P, I32, P, ctypes.POINTER(ctypes.c_double)]
     l.cpm_cell_stats.argtypes = [P, P, P, P, P]
     l.cpm_counters.argtypes = [P, P, P, P]
     l.cpm_attempt_stats.argtypes = [P, P, P]
@@ -192,12 +191,6 @@ def cpm_sweep(h: int, n_mcs: int, stream: int) -> None:
     _check(load().cpm_sweep(h, n_mcs, stream), "cpm_sweep")
 
 
-def cpm_sweep_profiled(h: int, n_mcs: int, stream: int) -> float:
-    v = ctypes.c_double(0.0)
-    _check(load().cpm_sweep_profiled(h, n_mcs, stream, ctypes.byref(v)), "cpm_sweep_profiled")
-    return v.value
-
-
 def cpm_cell_stats(h: int, d_volume, d_surface, d_centroid_sum, stream: int) -> None:
     _check(load().cpm_cell_stats(h, _ptr(d_volume), _ptr(d_surface), _ptr(d_centroid_sum), stream),
            "cpm_cell_stats")
@@ -260,10 +253,6 @@ class Simulation:
 
     def sweep(self, n_mcs: int) -> None:
         cpm_sweep(self.handle, n_mcs, self.stream)
-
-    def sweep_profiled(self, n_mcs: int) -> float:
-        """sweep(n_mcs), returning the activation kernel's mean duration (us)."""
-        return cpm_sweep_profiled(self.handle, n_mcs, self.stream)
 
     def counters(self):
         v = self.torch.empty(self.n_cells + 1, dtype=self.torch.int32, device=self.device)

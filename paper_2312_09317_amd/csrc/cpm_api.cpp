@@ -452,10 +452,8 @@ int cpm_init(const cpm_params *params, int32_t *d_lattice, const int32_t *d_cell
 
 namespace {
 
-// n_mcs MCS of a single lattice.  With `ev` (2 * activations-per-MCS events)
-// every activation launch is bracketed by an event pair; the stream is then
-// waited for after each MCS and the pairs' elapsed times added to *kernel_ms.
-int sweep_impl(cpm_handle *h, int32_t n_mcs, hipStream_t st, hipEvent_t *ev, double *kernel_ms)
+// n_mcs MCS of a single lattice.
+int sweep_impl(cpm_handle *h, int32_t n_mcs, hipStream_t st)
 {
     int64_t sd = 1;
     for (int d = 0; d < h->ndim; ++d) sd *= h->s;
@@ -467,25 +465,14 @@ int sweep_impl(cpm_handle *h, int32_t n_mcs, hipStream_t st, hipEvent_t *ev, dou
     for (int32_t i = 0; i < n_mcs; ++i) {
         const uint32_t mcs = (uint32_t)h->mcs;
         for (uint32_t alpha = 0; alpha < n_act; ++alpha) {
-            if (ev && (e = hipEventRecord(ev[2 * alpha], st)) != hipSuccess) return device_fail(e, "event");
             e = cpm::launch_activation(h->args, h->ndim, h->act, h->mirror, mcs, alpha, (int)(h->activation & 1), st);
             if (e != hipSuccess) return device_fail(e, "activation");
-            if (ev && (e = hipEventRecord(ev[2 * alpha + 1], st)) != hipSuccess) return device_fail(e, "event");
             ++h->activation;
         }
         if (h->act && (e = cpm::launch_act_decay(h->args.act, n_sites, st)) != hipSuccess)
             return device_fail(e, "act decay");
         ++h->mcs;
         h->attempts_run += (uint64_t)n_sites;
-        if (ev) {
-            if ((e = hipStreamSynchronize(st)) != hipSuccess) return device_fail(e, "synchronize");
-            for (uint32_t alpha = 0; alpha < n_act; ++alpha) {
-                float ms = 0.f;
-                if ((e = hipEventElapsedTime(&ms, ev[2 * alpha], ev[2 * alpha + 1])) != hipSuccess)
-                    return device_fail(e, "event time");
-                *kernel_ms += ms;
-            }
-        }
     }
     if (h->mirror && (e = cpm::launch_from_mirror(h->mirror_cells, h->args.lat, n_sites, st)) != hipSuccess)
         return device_fail(e, "from int16 working copy");
@@ -501,26 +488,7 @@ int cpm_sweep(cpm_handle *h, int32_t n_mcs, void *stream)
     if (!h) return fail(CPM_EINVAL, "handle is NULL");
     if (n_mcs < 0) return fail(CPM_EINVAL, "n_mcs must be >= 0");
     if (n_mcs == 0) return CPM_OK;
-    return sweep_impl(h, n_mcs, as_stream(stream), nullptr, nullptr);
-}
-
-int cpm_sweep_profiled(cpm_handle *h, int32_t n_mcs, void *stream, double *mean_us)
-{
-    if (!h || !mean_us) return fail(CPM_EINVAL, "NULL argument");
-    if (n_mcs < 1) return fail(CPM_EINVAL, "n_mcs must be >= 1");
-    int64_t sd = 1;
-    for (int d = 0; d < h->ndim; ++d) sd *= h->s;
-    const uint32_t n_act = (uint32_t)(((int64_t)1 << h->ndim) * sd / h->k);
-    std::vector<hipEvent_t> ev(2 * (size_t)n_act, nullptr);
-    hipError_t e = hipSuccess;
-    for (size_t i = 0; i < ev.size() && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
-    int rc = e == hipSuccess ? CPM_OK : device_fail(e, "create events");
-    double ms = 0.0;
-    if (rc == CPM_OK) rc = sweep_impl(h, n_mcs, as_stream(stream), ev.data(), &ms);
-    for (hipEvent_t x : ev)
-        if (x) (void)hipEventDestroy(x);
-    if (rc == CPM_OK) *mean_us = ms * 1e3 / ((double)n_mcs * n_act);
-    return rc;
+    return sweep_impl(h, n_mcs, as_stream(stream));
 }
 
 int cpm_attempt_stats(cpm_handle *h, uint64_t *out, void *stream)

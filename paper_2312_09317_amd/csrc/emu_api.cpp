@@ -399,6 +399,8 @@ int emu_adam(emu_handle *h, const float *d_grad, float lr, void *stream)
     a.lr = lr;
     a.beta1 = 0.9f;
     a.beta2 = 0.999f;
+    a.one_minus_beta1 = 0.1f;
+    a.one_minus_beta2 = 0.001f;
     a.eps = 1e-8f;
     const int64_t t = h->steps + 1;
     a.c1 = (float)(1.0 - std::pow(0.9, (double)t));

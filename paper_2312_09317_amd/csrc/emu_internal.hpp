@@ -66,7 +66,8 @@ struct AdamArgs {
     float *param, *m, *v;
     const float *grad;
     int64_t n;
-    float lr, beta1, beta2, eps, c1, c2;  // c1, c2: bias corrections 1 - beta^t
+    // 1 - beta is passed separately: 1 - 0.999f in fp32 is 1.3e-5 off 0.001
+    float lr, beta1, beta2, one_minus_beta1, one_minus_beta2, eps, c1, c2;  // c1, c2: bias corrections 1 - beta^t
     AdamSeg seg[2 * kLayers];
 };
 

@@ -208,8 +208,8 @@ __global__ void adam_kernel(AdamArgs a)
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
     const float g = a.grad[i];
-    const float m = a.beta1 * a.m[i] + (1.f - a.beta1) * g;
-    const float v = a.beta2 * a.v[i] + (1.f - a.beta2) * g * g;
+    const float m = a.beta1 * a.m[i] + a.one_minus_beta1 * g;
+    const float v = a.beta2 * a.v[i] + a.one_minus_beta2 * g * g;
     a.m[i] = m;
     a.v[i] = v;
     const float p = a.param[i] - a.lr * (m / a.c1) / (sqrtf(v / a.c2) + a.eps);
