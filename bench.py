@@ -72,6 +72,13 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--cpu-mcs", type=int, default=4, help="MCS of the oracle sample (0 to skip)")
+    ap.add_argument("--workload", choices=("sweep", "batch", "emulator"), default="sweep",
+                    help="sweep: the 3D 256^3 benchmark (default); batch: 512 uneven 2D lattices; "
+                         "emulator: train the emulator on batched runs and judge it against fresh ones")
+    ap.add_argument("--emu-train", type=int, default=8192, help="emulator workload: training runs")
+    ap.add_argument("--emu-test", type=int, default=256, help="emulator workload: held-out points")
+    ap.add_argument("--emu-reps", type=int, default=8, help="emulator workload: replicates per held-out point")
+    ap.add_argument("--emu-epochs", type=int, default=300)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device copy of this many bytes, 5 times (calibrates "
                          "the HBM byte counters of a profiler against a known traffic)")
@@ -91,6 +98,10 @@ def main():
         log("bench.py needs a GPU")
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.workload == "batch":
+        return bench_batch(args)
+    if args.workload == "emulator":
+        return bench_emulator(args)
     w = inputs.config1(n_mcs=args.steps)
     log(f"workload {w.name}: {w.n_sites} sites, {w.n_cells} cells")
     sim = cpm.Simulation(cpm.Params.from_workload(w), w.lattice, w.cell_type, device="cuda:0")
@@ -159,6 +170,61 @@ def main():
     }
     print(json.dumps(out), flush=True)
     sim.close()
+
+
+def bench_batch(args):
+    """512 independent 2D lattices of uneven sizes (64..512, 30% cells, Act
+    term, per-lattice parameters), advanced together: one launch per
+    activation, each MCS one replay of a captured HIP graph.  Step = 1 MCS
+    of every lattice."""
+    import torch
+    from paper_2312_09317_amd import cpm, inputs
+    ws = inputs.config3(n_lattices=512, seed=1, n_mcs=args.steps)
+    sites = sum(w.n_sites for w in ws)
+    log(f"batch of {len(ws)} lattices, {sites} sites")
+    b = cpm.Batch([cpm.Params.from_workload(w) for w in ws], [w.lattice for w in ws], [w.cell_type for w in ws])
+    b.sweep(args.warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    b.sweep(args.steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    n_act = (2 * ws[0].s) ** 2 // ws[0].k
+    stats = b.attempt_stats()
+    acc = float(sum(int(r[2]) for r in stats)) / max(1, sum(int(r[0]) for r in stats))
+    avg_launch_s = ms / 1e3 / (args.steps * n_act)
+    per_launch_bytes = bytes_per_attempt(2, ws[0].s, ws[0].k, acc) * (sites // n_act)
+    achieved = per_launch_bytes / avg_launch_s / 1e9
+    print(json.dumps({
+        "metric": "site copy-attempts/s, 512 batched uneven 2D lattices", "value": sites * args.steps / (ms / 1e3),
+        "unit": "attempts/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "2d-batch-512-L64..512", "n_lattices": len(ws), "sites": sites, "sub": ws[0].s,
+                   "attempts_per_activation": ws[0].k, "act": True, "graph": True},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "batch_sweep_kernel",
+                     "avg_launch_us": avg_launch_s * 1e6},
+        "cpu_baseline": None}), flush=True)
+    b.close()
+
+
+def bench_emulator(args):
+    """The emulator study: batched CPM runs of the 512-lattice parameter
+    space as training data, training on the GPU, and the held-out error
+    against fresh CPM replicates, with the cost per parameter point of each."""
+    from paper_2312_09317_amd import emulator
+    r = emulator.study(n_train=args.emu_train, n_test=args.emu_test, reps=args.emu_reps, epochs=args.emu_epochs,
+                       log=log)
+    print(json.dumps({
+        "metric": "emulator vs CPM cost per parameter point", "value": r["cost_ratio"], "unit": "x",
+        "n_gpus": 1, "steps": args.emu_epochs, "warmup": 0, "ms_per_step": None, "higher_is_better": True,
+        "scaling": "strong", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "emulator-6-256-256-256-8", **{k: r[k] for k in ("n_train", "n_test", "replicates",
+                                                                               "plan", "L_range", "epochs")}},
+        "emulator": r, "roofline": None, "cpu_baseline": None}), flush=True)
 
 
 if __name__ == "__main__":

@@ -14,8 +14,10 @@
  * ln J(cell,cell), ln J(cell,medium), ln T, ln lambda_act and L / 512; its
  * eight outputs are, in order, mean and variance of volume, of surface, of
  * speed and of persistence time.  Inputs and targets are z-scored with a
- * stored normalisation (emu_fit_norm / emu_set_norm); emu_forward returns
- * de-normalised outputs.
+ * stored normalisation (emu_fit_norm / emu_set_norm); a target column with a
+ * positive offset `off` is learnt as log(t + off) (for quantities that span
+ * decades and may be 0).  emu_forward returns outputs in the targets' own
+ * units.
  *
  * Arithmetic: matrix products on the matrix cores with bf16 operands
  * (weights, activations, gradients of pre-activations, rounded to nearest
@@ -28,8 +30,9 @@
  * W4 (8 x 256), b4 (8); W is (out x in), row-major, and a layer computes
  * z = x W^T + b.
  *
- * Normalisation vector (28 fp32): input means (6), input standard
- * deviations (6), target means (8), target standard deviations (8).
+ * Normalisation vector (36 fp32): input means (6), input standard
+ * deviations (6), target means (8) and standard deviations (8) after the
+ * transform, target offsets (8; 0 = no transform).
  *
  * Training loss: mean over the n x 8 normalised outputs of the squared
  * error.  Adam with beta1 = 0.9, beta2 = 0.999, eps = 1e-8 and bias
@@ -60,7 +63,7 @@ extern "C" {
 
 #define EMU_IN 6
 #define EMU_OUT 8
-#define EMU_NORM 28
+#define EMU_NORM 36
 
 typedef struct emu_handle emu_handle;
 
@@ -85,10 +88,14 @@ int emu_get_params(emu_handle *h, float *d_params, void *stream);
 /* Set the normalisation from a device vector of EMU_NORM values (standard
  * deviations must be positive; not checked on the device), or fit it to a
  * data set: column means and population standard deviations of x (n x 6) and
- * targets (n x 8), in fp64 sums; a column with no spread gets 1. */
+ * targets (n x 8), in fp64 sums; a column with no spread gets 1.  Target
+ * columns j with bit j of log_mask set get off_j = (column mean) / 100 (1 if
+ * the mean is not positive) and are fitted as log(t + off_j); targets must
+ * then exceed -off_j. */
 int emu_set_norm(emu_handle *h, const float *d_norm, void *stream);
 int emu_get_norm(emu_handle *h, float *d_norm, void *stream);
-int emu_fit_norm(emu_handle *h, const float *d_x, const float *d_targets, int32_t n, void *stream);
+int emu_fit_norm(emu_handle *h, const float *d_x, const float *d_targets, int32_t n, int32_t log_mask,
+                 void *stream);
 
 /* Outputs d_y (n x 8, de-normalised) for inputs d_x (n x 6),
  * 1 <= n <= max_batch. */

@@ -289,9 +289,11 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
         return rec;
     };
 
-    // k = 1: draw the attempt and read the two labels and their counters from
-    // global memory while the staging loads are in flight (no other attempt
-    // of this activation writes this sub-area or reads it)
+    // k = 1: the attempt of this thread's area, its two labels (from LDS) and,
+    // when nontrivial, their counters as the activation began.  Drawing while
+    // the staging loads are in flight, or reading the labels from global
+    // memory then, measured slower on gfx950 (the wait for the labels also
+    // waits for every staging load issued before them).
     int d_ttx = 0, d_tty = 0, d_ttz = 0, d_ssx = 0, d_ssy = 0, d_ssz = 0, d_lt = 0, d_ls = 0;
     uint32_t d_u2 = 0;
     bool d_nontrivial = false;
@@ -300,8 +302,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
         if (!K1 || tid >= areas) return;
         uint32_t area_id;
         draw(tid, 0, d_ttx, d_tty, d_ttz, d_ssx, d_ssy, d_ssz, d_u2, area_id);
-        d_lt = cells[global_index(d_ttx, d_tty, d_ttz)];
-        d_ls = cells[global_index(d_ssx, d_ssy, d_ssz)];
+        d_lt = lab[map.at(d_ttx, d_tty, d_ttz)];
+        d_ls = lab[map.at(d_ssx, d_ssy, d_ssz)];
         d_nontrivial = d_lt != d_ls && d_lt >= 0 && d_ls >= 0;
         if (d_nontrivial) {
             d_ct = seen_counters(rd, d_lt, nullptr, 0);
@@ -315,7 +317,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
         // whole rows in the widest chunks (16, 8 or 4 bytes) that tile a row,
         // eight loads in flight per thread
         const FastDiv by_b1((uint32_t)b1);
-        auto copy_rows = [&](auto chunk, const void *src_v, void *dst_v, int row_bytes, auto &&in_flight) {
+        auto copy_rows = [&](auto chunk, const void *src_v, void *dst_v, int row_bytes) {
             using Chunk = decltype(chunk);
             const Chunk *src = reinterpret_cast<const Chunk *>(src_v);
             Chunk *dst = reinterpret_cast<Chunk *>(dst_v);
@@ -330,7 +332,6 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
             };
             const int total = rows * per_row;
             int c0 = tid;
-            bool pending = true;
             for (; c0 + 7 * kBlock < total; c0 += 8 * kBlock) {
                 // eight independent loads before the first LDS store
                 const Chunk v0 = src[row_chunk(c0)];
@@ -341,10 +342,6 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
                 const Chunk v5 = src[row_chunk(c0 + 5 * kBlock)];
                 const Chunk v6 = src[row_chunk(c0 + 6 * kBlock)];
                 const Chunk v7 = src[row_chunk(c0 + 7 * kBlock)];
-                if (pending) {
-                    in_flight();
-                    pending = false;
-                }
                 dst[c0] = v0;
                 dst[c0 + kBlock] = v1;
                 dst[c0 + 2 * kBlock] = v2;
@@ -354,18 +351,16 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
                 dst[c0 + 6 * kBlock] = v6;
                 dst[c0 + 7 * kBlock] = v7;
             }
-            if (pending) in_flight();
             for (; c0 < total; c0 += kBlock) dst[c0] = src[row_chunk(c0)];
         };
-        auto copy_any = [&](int chunk, const void *src, void *dst, int row_bytes, auto &&in_flight) {
-            if (chunk == 16) copy_rows(uint4{}, src, dst, row_bytes, in_flight);
-            else if (chunk == 8) copy_rows(uint2{}, src, dst, row_bytes, in_flight);
-            else copy_rows(uint32_t{}, src, dst, row_bytes, in_flight);
+        auto copy_any = [&](int chunk, const void *src, void *dst, int row_bytes) {
+            if (chunk == 16) copy_rows(uint4{}, src, dst, row_bytes);
+            else if (chunk == 8) copy_rows(uint2{}, src, dst, row_bytes);
+            else copy_rows(uint32_t{}, src, dst, row_bytes);
         };
-        copy_any(tg.row_chunk, cells, lab, L0 * (int)sizeof(Cell), draw_k1);
-        if (ACT) copy_any(tg.act_chunk, a.act, lact, L0, [] {});
+        copy_any(tg.row_chunk, cells, lab, L0 * (int)sizeof(Cell));
+        if (ACT) copy_any(tg.act_chunk, a.act, lact, L0);
     } else {
-        draw_k1();
         const int wave = tid >> 6, lane = tid & 63;
         const FastDiv by_b1((uint32_t)b1);
         for (int r = wave; r < rows; r += kBlock / 64) {
@@ -391,6 +386,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
                    J[tc], J[0], J[to]};
     }
     if (K1) {
+        draw_k1();
         // phase 1: queue the nontrivial attempts with their counters
         if (d_nontrivial) {
             const int slot = atomicAdd(&queue_n, 1);

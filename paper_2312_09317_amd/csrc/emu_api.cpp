@@ -352,11 +352,12 @@ int emu_get_norm(emu_handle *h, float *d_norm, void *stream)
     return e == hipSuccess ? CPM_OK : device_fail(e, "emu_get_norm");
 }
 
-int emu_fit_norm(emu_handle *h, const float *d_x, const float *d_targets, int32_t n, void *stream)
+int emu_fit_norm(emu_handle *h, const float *d_x, const float *d_targets, int32_t n, int32_t log_mask, void *stream)
 {
     if (!h || !d_x || !d_targets) return fail(CPM_EINVAL, "null pointer");
     if (n < 1) return fail(CPM_EINVAL, "empty data set");
-    hipError_t e = launch_fit_norm(d_x, d_targets, n, h->norm(), as_stream(stream));
+    if (log_mask < 0 || log_mask > 0xFF) return fail(CPM_EINVAL, "log_mask has bits beyond the 8 outputs");
+    hipError_t e = launch_fit_norm(d_x, d_targets, n, log_mask, h->norm(), as_stream(stream));
     return e == hipSuccess ? CPM_OK : device_fail(e, "emu_fit_norm");
 }
 

@@ -83,7 +83,7 @@ hipError_t launch_loss(const float *y, const float *t, int n, int n_pad, const f
 hipError_t launch_loss_sum(const float *loss_rows, int n, float *out, hipStream_t st);
 hipError_t launch_adam(const AdamArgs &a, hipStream_t st);
 hipError_t launch_cast(const AdamSeg &s, const float *param, hipStream_t st);
-hipError_t launch_fit_norm(const float *x, const float *t, int n, float *norm, hipStream_t st);
+hipError_t launch_fit_norm(const float *x, const float *t, int n, int log_mask, float *norm, hipStream_t st);
 hipError_t launch_fill_u16(uint16_t *p, uint16_t v, int64_t n, hipStream_t st);
 hipError_t launch_fill_f32(float *p, float v, int64_t n, hipStream_t st);
 

@@ -144,13 +144,18 @@ __global__ void input_kernel(const float *x, int n, int n_pad, const float *norm
     }
 }
 
+// Target transform of output c: log(t + off) when its offset is positive.
+__device__ __forceinline__ float to_target_space(float t, float off) { return off > 0.f ? logf(t + off) : t; }
+__device__ __forceinline__ float from_target_space(float u, float off) { return off > 0.f ? expf(u) - off : u; }
+
 // Normalised outputs (pitch kOut) -> raw outputs.
 __global__ void output_kernel(const float *y, int n, const float *norm, float *out)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const float *mean = norm + 2 * kIn, *sd = norm + 2 * kIn + kOut;
-    for (int c = 0; c < kOut; ++c) out[(size_t)i * kOut + c] = y[(size_t)i * kOut + c] * sd[c] + mean[c];
+    const float *mean = norm + 2 * kIn, *sd = mean + kOut, *off = sd + kOut;
+    for (int c = 0; c < kOut; ++c)
+        out[(size_t)i * kOut + c] = from_target_space(y[(size_t)i * kOut + c] * sd[c] + mean[c], off[c]);
 }
 
 // Mean squared error over the n x 8 normalised outputs: dL/dy = 2 (y - t) / (8 n)
@@ -161,13 +166,13 @@ __global__ void loss_kernel(const float *y, const float *t_raw, int n, int n_pad
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_pad) return;
-    const float *mean = norm + 2 * kIn, *sd = norm + 2 * kIn + kOut;
+    const float *mean = norm + 2 * kIn, *sd = mean + kOut, *off = sd + kOut;
     const float scale = 2.0f / (float)((int64_t)n * kOut);
     float l = 0.f;
     for (int c = 0; c < kOutPad; ++c) {
         float d = 0.f;
         if (i < n && c < kOut) {
-            const float t = (t_raw[(size_t)i * kOut + c] - mean[c]) / sd[c];
+            const float t = (to_target_space(t_raw[(size_t)i * kOut + c], off[c]) - mean[c]) / sd[c];
             const float e = y[(size_t)i * kOut + c] - t;
             l += e * e;
             d = scale * e;
@@ -226,22 +231,8 @@ __global__ void cast_kernel(AdamSeg s, const float *param)
     write_copies(s, j, param[s.begin + j]);
 }
 
-// Column means and population standard deviations (FP64 sums) of the inputs
-// (6 columns) and targets (8 columns): norm = [mean_x, sd_x, mean_t, sd_t].
-// A column with zero spread gets sd = 1.
-__global__ void __launch_bounds__(256) fit_norm_kernel(const float *x, const float *t, int n, float *norm)
+__device__ void block_sums(double &s1, double &s2, double *r1, double *r2)
 {
-    __shared__ double r1[256], r2[256];
-    const int col = blockIdx.x;  // 0..13
-    const float *src = col < kIn ? x : t;
-    const int c = col < kIn ? col : col - kIn;
-    const int w = col < kIn ? kIn : kOut;
-    double s1 = 0.0, s2 = 0.0;
-    for (int i = threadIdx.x; i < n; i += 256) {
-        const double v = (double)src[(size_t)i * w + c];
-        s1 += v;
-        s2 += v * v;
-    }
     r1[threadIdx.x] = s1;
     r2[threadIdx.x] = s2;
     __syncthreads();
@@ -252,13 +243,50 @@ __global__ void __launch_bounds__(256) fit_norm_kernel(const float *x, const flo
         }
         __syncthreads();
     }
+    s1 = r1[0];
+    s2 = r2[0];
+    __syncthreads();
+}
+
+// Column means and population standard deviations (FP64 sums) of the inputs
+// (6 columns) and the targets (8 columns), the targets of the columns set in
+// log_mask first mapped to log(t + off) with off = (column mean of t) / 100
+// (1 if that is not positive): norm = [mean_x, sd_x, mean_t, sd_t, off_t].
+// A column with zero spread gets sd = 1.
+__global__ void __launch_bounds__(256) fit_norm_kernel(const float *x, const float *t, int n, int log_mask,
+                                                       float *norm)
+{
+    __shared__ double r1[256], r2[256];
+    const int col = blockIdx.x;  // 0..13
+    const bool is_x = col < kIn;
+    const float *src = is_x ? x : t;
+    const int c = is_x ? col : col - kIn;
+    const int w = is_x ? kIn : kOut;
+    const bool logt = !is_x && ((log_mask >> c) & 1);
+    float off = 0.f;
+    if (logt) {
+        double s1 = 0.0, s2 = 0.0;
+        for (int i = threadIdx.x; i < n; i += 256) s1 += (double)src[(size_t)i * w + c];
+        block_sums(s1, s2, r1, r2);
+        const double m = s1 / n;
+        off = m > 0.0 ? (float)(m / 100.0) : 1.f;
+    }
+    double s1 = 0.0, s2 = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) {
+        const float raw = src[(size_t)i * w + c];
+        const double v = (double)(logt ? to_target_space(raw, off) : raw);
+        s1 += v;
+        s2 += v * v;
+    }
+    block_sums(s1, s2, r1, r2);
     if (threadIdx.x == 0) {
-        const double mean = r1[0] / n;
-        const double var = fmax(r2[0] / n - mean * mean, 0.0);
+        const double mean = s1 / n;
+        const double var = fmax(s2 / n - mean * mean, 0.0);
         const double sd = var > 0.0 ? sqrt(var) : 1.0;
-        const int base = col < kIn ? 0 : 2 * kIn;
+        const int base = is_x ? 0 : 2 * kIn;
         norm[base + c] = (float)mean;
         norm[base + w + c] = (float)sd;
+        if (!is_x) norm[2 * kIn + 2 * kOut + c] = off;
     }
 }
 
@@ -343,9 +371,9 @@ hipError_t launch_cast(const AdamSeg &s, const float *param, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_fit_norm(const float *x, const float *t, int n, float *norm, hipStream_t st)
+hipError_t launch_fit_norm(const float *x, const float *t, int n, int log_mask, float *norm, hipStream_t st)
 {
-    fit_norm_kernel<<<kIn + kOut, 256, 0, st>>>(x, t, n, norm);
+    fit_norm_kernel<<<kIn + kOut, 256, 0, st>>>(x, t, n, log_mask, norm);
     return hipGetLastError();
 }
 

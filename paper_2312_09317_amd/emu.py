@@ -14,7 +14,7 @@ EXPORTS = ("emu_param_count", "emu_workspace_bytes", "emu_init", "emu_set_params
            "emu_set_norm", "emu_get_norm", "emu_fit_norm", "emu_forward", "emu_grads", "emu_adam",
            "emu_train_step", "emu_step_count", "emu_destroy")
 
-N_IN, N_OUT, N_NORM = 6, 8, 28
+N_IN, N_OUT, N_NORM = 6, 8, 36
 SIZES = (6, 256, 256, 256, 8)
 
 _bound = False
@@ -34,7 +34,7 @@ def lib():
     l.emu_get_params.argtypes = [P, P, P]
     l.emu_set_norm.argtypes = [P, P, P]
     l.emu_get_norm.argtypes = [P, P, P]
-    l.emu_fit_norm.argtypes = [P, P, P, I32, P]
+    l.emu_fit_norm.argtypes = [P, P, P, I32, I32, P]
     l.emu_forward.argtypes = [P, P, I32, P, P]
     l.emu_grads.argtypes = [P, P, P, I32, P, P, P]
     l.emu_adam.argtypes = [P, P, F32, P]
@@ -92,8 +92,8 @@ def emu_get_norm(h, d_norm, stream):
     _check(lib().emu_get_norm(h, _ptr(d_norm), stream), "emu_get_norm")
 
 
-def emu_fit_norm(h, d_x, d_t, n, stream):
-    _check(lib().emu_fit_norm(h, _ptr(d_x), _ptr(d_t), n, stream), "emu_fit_norm")
+def emu_fit_norm(h, d_x, d_t, n, log_mask, stream):
+    _check(lib().emu_fit_norm(h, _ptr(d_x), _ptr(d_t), n, log_mask, stream), "emu_fit_norm")
 
 
 def emu_forward(h, d_x, n, d_y, stream):
@@ -145,8 +145,9 @@ def unpack(p):
     return W, b
 
 
-def norm_vector(x_mean, x_std, t_mean, t_std) -> np.ndarray:
-    return np.concatenate([x_mean, x_std, t_mean, t_std]).astype(np.float32)
+def norm_vector(x_mean, x_std, t_mean, t_std, t_off=None) -> np.ndarray:
+    t_off = np.zeros(N_OUT) if t_off is None else t_off
+    return np.concatenate([x_mean, x_std, t_mean, t_std, t_off]).astype(np.float32)
 
 
 # ---------------------------------------------------------------- convenience wrapper
@@ -190,9 +191,9 @@ class Emulator:
         emu_get_norm(self.handle, out, self.stream)
         return out
 
-    def fit_norm(self, x, t) -> None:
+    def fit_norm(self, x, t, log_mask: int = 0) -> None:
         x, t = self._dev(x, N_IN), self._dev(t, N_OUT)
-        emu_fit_norm(self.handle, x, t, x.shape[0], self.stream)
+        emu_fit_norm(self.handle, x, t, x.shape[0], log_mask, self.stream)
 
     def forward(self, x):
         x = self._dev(x, N_IN)

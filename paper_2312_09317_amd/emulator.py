@@ -96,13 +96,17 @@ class Surrogate:
         self.lo = None
         self.hi = None
 
-    def train(self, x, t, epochs=200, batch=512, lr=2e-3, lr_final=5e-5, seed=0):
+    # every statistic but the mean volume (which stays near its target) is
+    # learnt in log space: they span decades and may be 0
+    LOG_MASK = 0b11111110
+
+    def train(self, x, t, epochs=200, batch=512, lr=2e-3, lr_final=5e-5, seed=0, log_mask=LOG_MASK):
         """Fit the network to inputs x (n x 6) and statistics t (n x 8) from
         fresh weights; returns the per-epoch mean losses."""
         x = np.asarray(x, dtype=np.float64)
         W, b = inputs.mlp_weights(seed)
         self.net.set_params(emu.pack(W, b))
-        self.net.fit_norm(x, t)
+        self.net.fit_norm(x, t, log_mask)
         self.lo, self.hi = x.min(axis=0), x.max(axis=0)
         return self.net.fit(x, t, epochs=epochs, batch=batch, lr=lr, seed=seed, lr_final=lr_final)
 
@@ -140,3 +144,68 @@ def linear_baseline(x_train, t_train, x_test):
 def relative_error(pred, ref):
     """Per point and statistic |pred - ref| / |ref|."""
     return np.abs(pred - ref) / np.maximum(np.abs(ref), 1e-300)
+
+
+STAT_NAMES = ("mean_volume", "var_volume", "mean_surface", "var_surface", "mean_speed", "var_speed",
+              "mean_persistence", "var_persistence")
+
+
+def inference_seconds_per_point(sur, x, n_points=65536, repeats=20):
+    """Device time of emu_forward on n_points inputs (tiled from x), per point."""
+    import torch
+    xx = np.resize(np.asarray(x, dtype=np.float64), (n_points, emu.N_IN))
+    xd = torch.as_tensor(xx, dtype=torch.float32, device=sur.net.device)
+    for _ in range(3):
+        sur.net.forward(xd)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(repeats):
+        sur.net.forward(xd)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / repeats / n_points
+
+
+def study(n_train=8192, n_test=256, reps=8, plan=RunPlan(), L_min=64, L_max=512, epochs=300, batch=512,
+          lr=2e-3, lr_final=5e-5, seed=1, log=None):
+    """Train the emulator on n_train single CPM runs and judge it on n_test
+    fresh parameter points against the mean of `reps` fresh CPM replicates
+    each (new Philox seeds).  Returns per-statistic median relative errors
+    of the emulator, of a linear fit and of one fresh CPM run, the
+    replicate noise floor (standard error / |mean|), and the cost per point
+    of the CPM (batched, GPU seconds) and of the emulator (inference)."""
+    say = log or (lambda m: None)
+    train_pts = points(n_train, seed, L_min, L_max)
+    test_pts = points(n_test, seed + 1000, L_min, L_max)
+    t_train, cpm_s = simulate(train_pts, plan, log=say)
+    cpm_per_point = cpm_s / n_train
+    say(f"training set: {n_train} runs, {cpm_s:.2f} s GPU")
+    rep = np.stack([simulate(reseed(test_pts, seed + 2000 + r), plan)[0] for r in range(reps)])
+    say(f"test set: {n_test} points x {reps} replicates")
+    ref = rep.mean(axis=0)
+    x_train, x_test = features(train_pts), features(test_pts)
+    sur = Surrogate(max_batch=max(65536, n_test))
+    losses = sur.train(x_train, t_train, epochs=epochs, batch=batch, lr=lr, lr_final=lr_final, seed=seed)
+    say(f"trained {epochs} epochs: loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+    pred, outside = sur.predict(x_test, test_pts, plan)
+    emu_per_point = inference_seconds_per_point(sur, x_test)
+    sur.close()
+    with np.errstate(divide="ignore", invalid="ignore"):
+        noise = rep.std(axis=0, ddof=1) / np.sqrt(reps) / np.abs(ref)
+    med = lambda e: {k: float(v) for k, v in zip(STAT_NAMES, np.nanmedian(e, axis=0))}
+    return {
+        "n_train": n_train, "n_test": n_test, "replicates": reps,
+        "plan": {"burn_in": plan.burn_in, "n_samples": plan.n_samples, "interval": plan.interval},
+        "L_range": [L_min, L_max], "epochs": epochs, "final_loss": float(losses[-1]),
+        "outside_domain": int(outside.sum()),
+        "median_rel_err": {
+            "emulator": med(relative_error(pred, ref)),
+            "linear": med(relative_error(linear_baseline(x_train, t_train, x_test), ref)),
+            "one_cpm_run": med(relative_error(rep[0], ref)),
+            "noise_floor": med(noise),
+        },
+        "cpm_s_per_point": cpm_per_point,
+        "emulator_s_per_point": emu_per_point,
+        "cost_ratio": cpm_per_point / emu_per_point,
+    }

@@ -73,7 +73,7 @@ def test_fit_norm_and_denormalised_forward(torch):
     x = rng.normal(size=(500, 6)) * [1, 2, 3, 4, 5, 0.1] + [10, -3, 0, 2, 7, 0.5]
     t = rng.normal(size=(500, 8)) * np.arange(1, 9) + np.arange(8)
     x32, t32 = x.astype(np.float32).astype(np.float64), t.astype(np.float32).astype(np.float64)
-    ref_norm = np.concatenate([x32.mean(0), x32.std(0), t32.mean(0), t32.std(0)])
+    ref_norm = np.concatenate([x32.mean(0), x32.std(0), t32.mean(0), t32.std(0), np.zeros(8)])
     e.fit_norm(x, t)
     norm = e.norm().cpu().numpy().astype(np.float64)
     np.testing.assert_allclose(norm, ref_norm, rtol=1e-6, atol=1e-6)
@@ -83,7 +83,7 @@ def test_fit_norm_and_denormalised_forward(torch):
     y = e.forward(x).cpu().numpy().astype(np.float64)
     W32, b32 = emu.unpack(emu.pack(W, b))
     xn = mlp.normalise(x32, n32[:6], n32[6:12])
-    ref = mlp.denormalise(mlp.forward(W32, b32, xn, rnd=mlp.bf16), n32[12:20], n32[20:])
+    ref = mlp.denormalise(mlp.forward(W32, b32, xn, rnd=mlp.bf16), n32[12:20], n32[20:28])
     assert _rel(y - n32[12:20], ref - n32[12:20]) < 2e-3
 
 
@@ -202,4 +202,41 @@ def test_errors(torch):
     # a valid call still works after the rejected ones
     e.forward(x[:100])
     torch.cuda.synchronize()
+    e.close()
+
+
+def test_log_targets(torch):
+    # targets spanning decades, some zero: columns in the mask are learnt as
+    # log(t + off), off = column mean / 100
+    emu, e = _emu(torch)
+    W, b = mlp.init(seed=17)
+    e.set_params(emu.pack(W, b))
+    rng = np.random.default_rng(9)
+    x = rng.normal(size=(700, 6))
+    t = np.exp(rng.normal(size=(700, 8)) * 2.0) * np.arange(1, 9)
+    t[::7, 3] = 0.0
+    mask = 0b11111010
+    e.fit_norm(x, t, log_mask=mask)
+    norm = e.norm().cpu().numpy().astype(np.float64)
+    x32, t32 = x.astype(np.float32).astype(np.float64), t.astype(np.float32).astype(np.float64)
+    off = np.where([(mask >> j) & 1 for j in range(8)], t32.mean(0) / 100.0, 0.0)
+    u = np.where(off > 0, np.log(t32 + np.where(off > 0, off, 1.0)), t32)
+    np.testing.assert_allclose(norm[:12], np.concatenate([x32.mean(0), x32.std(0)]), rtol=1e-6, atol=1e-6)
+    np.testing.assert_allclose(norm[28:], off, rtol=1e-6)
+    np.testing.assert_allclose(norm[12:20], u.mean(0), rtol=1e-5, atol=1e-5)
+    np.testing.assert_allclose(norm[20:28], u.std(0), rtol=1e-5)
+    # outputs come back through exp(.) - off
+    n32 = np.concatenate([x32.mean(0), x32.std(0), u.mean(0), u.std(0), off]).astype(np.float32).astype(np.float64)
+    e.set_norm(n32)
+    y = e.forward(x).cpu().numpy().astype(np.float64)
+    W32, b32 = emu.unpack(emu.pack(W, b))
+    z = mlp.denormalise(mlp.forward(W32, b32, mlp.normalise(x32, n32[:6], n32[6:12]), rnd=mlp.bf16),
+                        n32[12:20], n32[20:28])
+    ref = np.where(n32[28:] > 0, np.exp(z) - n32[28:], z)
+    assert _rel(np.log(np.abs(y) + 1.0), np.log(np.abs(ref) + 1.0)) < 2e-3
+    # the loss is taken on the transformed, z-scored targets
+    _, loss = e.grads(x, t)
+    tn = mlp.normalise(u, n32[12:20], n32[20:28])
+    ref_loss = mlp.loss(W32, b32, mlp.normalise(x32, n32[:6], n32[6:12]), tn, rnd=mlp.bf16)
+    assert abs(float(loss.item()) - ref_loss) <= 5e-3 * ref_loss
     e.close()
