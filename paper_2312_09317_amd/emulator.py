@@ -35,51 +35,66 @@ class RunPlan:
         return self.burn_in + (self.n_samples - 1) * self.interval
 
 
-def features(workloads) -> np.ndarray:
-    """Emulator inputs of a list of batched-workload lattices."""
-    out = np.empty((len(workloads), emu.N_IN))
-    for i, w in enumerate(workloads):
-        p = w.extra["params"]
+@dataclass
+class Point:
+    """One parameter point: the batched workload's draws for lattice `index`
+    of the stream `stream_seed`, run with Philox seed `seed`.  Its lattice is
+    built only when it is simulated."""
+    params: dict
+    index: int
+    stream_seed: int
+    seed: int
+
+    def workload(self, max_act=30):
+        w = inputs.config3_workload(self.params, self.index, self.stream_seed, n_mcs=0, max_act=max_act)
+        w.seed = self.seed
+        return w
+
+
+def features(pts) -> np.ndarray:
+    """Emulator inputs of parameter points (or of workloads built from them)."""
+    out = np.empty((len(pts), emu.N_IN))
+    for i, q in enumerate(pts):
+        p = q.params if isinstance(q, Point) else q.extra["params"]
         out[i] = [np.log(p["lambda_V"]), np.log(p["J_cc"]), np.log(p["J_cm"]), np.log(p["T"]),
                   np.log(p["lambda_act"]), p["L"] / 512.0]
     return out
 
 
-def points(n, seed, L_min=64, L_max=512, max_act=30):
-    """n parameter points (the batched workload's lattices) from seed."""
-    return inputs.config3(n_lattices=n, L_min=L_min, L_max=L_max, seed=seed, n_mcs=0, max_act=max_act)
+def points(n, seed, L_min=64, L_max=512):
+    """n parameter points of the batched workload drawn from stream `seed`."""
+    return [Point(p, i, seed, seed) for i, p in enumerate(inputs.config3_points(n, L_min, L_max, seed))]
 
 
-def reseed(workloads, seed):
+def reseed(pts, seed):
     """The same parameter points with another Philox seed (fresh replicates)."""
-    out = []
-    for w in workloads:
-        c = inputs.Workload(**{**w.__dict__, "seed": seed, "extra": dict(w.extra)})
-        out.append(c)
-    return out
+    return [Point(q.params, q.index, q.stream_seed, seed) for q in pts]
 
 
-def simulate(workloads, plan: RunPlan, batch: int = 512, device="cuda", log=None):
-    """Summary statistics (n x 8, float64 on the host) of one run per
-    workload, batch lattices per launch.  Returns (stats, gpu_seconds)."""
+def simulate(pts, plan: RunPlan, batch: int = 512, device="cuda", log=None):
+    """Summary statistics (n x 8, float64 on the host) of one run per point,
+    `batch` lattices per launch.  Returns (stats, gpu_seconds): the device
+    time of the sweeps, sampling and summary kernels."""
     import torch
-    stats = np.empty((len(workloads), 8))
+    stats = np.empty((len(pts), 8))
     seconds = 0.0
-    for s in range(0, len(workloads), batch):
-        part = workloads[s:s + batch]
+    for s in range(0, len(pts), batch):
+        part = [q.workload() if isinstance(q, Point) else q for q in pts[s:s + batch]]
         params = [cpm.Params.from_workload(w) for w in part]
         b = cpm.Batch(params, [w.lattice for w in part], [w.cell_type for w in part], device=device)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
         samples = b.run_with_samples(plan.burn_in, plan.n_samples, plan.interval)
         out = b.summary(samples, plan.n_samples, float(plan.interval))
+        e1.record()
         torch.cuda.synchronize()
-        seconds += time.perf_counter() - t0
+        seconds += e0.elapsed_time(e1) / 1e3
         stats[s:s + len(part)] = out.cpu().numpy()
         b.close()
         del samples
         if log:
-            log(f"simulated {s + len(part)}/{len(workloads)} points, {seconds:.2f} s GPU")
+            log(f"simulated {s + len(part)}/{len(pts)} points, {seconds:.2f} s GPU")
     return stats, seconds
 
 
@@ -114,19 +129,19 @@ class Surrogate:
         x = np.asarray(x, dtype=np.float64)
         return np.all((x >= self.lo) & (x <= self.hi), axis=1)
 
-    def predict(self, x, workloads=None, plan: RunPlan = None):
+    def predict(self, x, pts=None, plan: RunPlan = None):
         """Statistics for inputs x; rows outside the training domain come
-        from CPM runs of the matching workloads (required then)."""
+        from CPM runs of the matching points (required then)."""
         x = np.asarray(x, dtype=np.float64)
         y = np.empty((len(x), 8))
         for s in range(0, len(x), self.net.max_batch):
             y[s:s + self.net.max_batch] = self.net.forward(x[s:s + self.net.max_batch]).cpu().numpy()
         out = ~self.inside(x)
         if out.any():
-            if workloads is None or plan is None:
-                raise ValueError("points outside the training domain need their workloads and a run plan")
+            if pts is None or plan is None:
+                raise ValueError("points outside the training domain need their parameter points and a run plan")
             idx = np.nonzero(out)[0]
-            y[idx], _ = simulate([workloads[i] for i in idx], plan, device=self.device)
+            y[idx], _ = simulate([pts[i] for i in idx], plan, device=self.device)
         return y, out
 
     def close(self):
@@ -185,9 +200,14 @@ def study(n_train=8192, n_test=256, reps=8, plan=RunPlan(), L_min=64, L_max=512,
     say(f"test set: {n_test} points x {reps} replicates")
     ref = rep.mean(axis=0)
     x_train, x_test = features(train_pts), features(test_pts)
+    import torch
     sur = Surrogate(max_batch=max(65536, n_test))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     losses = sur.train(x_train, t_train, epochs=epochs, batch=batch, lr=lr, lr_final=lr_final, seed=seed)
-    say(f"trained {epochs} epochs: loss {losses[0]:.4f} -> {losses[-1]:.4f}")
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    say(f"trained {epochs} epochs in {train_s:.1f} s: loss {losses[0]:.4f} -> {losses[-1]:.4f}")
     pred, outside = sur.predict(x_test, test_pts, plan)
     emu_per_point = inference_seconds_per_point(sur, x_test)
     sur.close()
@@ -197,7 +217,7 @@ def study(n_train=8192, n_test=256, reps=8, plan=RunPlan(), L_min=64, L_max=512,
     return {
         "n_train": n_train, "n_test": n_test, "replicates": reps,
         "plan": {"burn_in": plan.burn_in, "n_samples": plan.n_samples, "interval": plan.interval},
-        "L_range": [L_min, L_max], "epochs": epochs, "final_loss": float(losses[-1]),
+        "L_range": [L_min, L_max], "epochs": epochs, "final_loss": float(losses[-1]), "train_s": train_s,
         "outside_domain": int(outside.sum()),
         "median_rel_err": {
             "emulator": med(relative_error(pred, ref)),

@@ -186,6 +186,36 @@ def squares_jittered_2d(L, density=0.3, side=10, seed=1):
     return lat.reshape(1, L, L), cid
 
 
+def config3_points(n_lattices=512, L_min=64, L_max=512, seed=1):
+    """The per-lattice draws of config3, without building lattices: side L
+    uniform over the multiples of 4 in [L_min, L_max], then lambda_V, J_cc,
+    J_cm, T and lambda_act log-uniform within a factor 4 of 50, 20, 10, 20,
+    300, one lattice after another from one PCG64 stream."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sides = np.arange(L_min, L_max + 1, 4)
+    out = []
+    for _ in range(n_lattices):
+        L = int(rng.choice(sides))
+        f = np.exp(rng.uniform(np.log(0.25), np.log(4.0), size=5))
+        out.append(dict(lambda_V=50.0 * f[0], J_cc=20.0 * f[1], J_cm=10.0 * f[2], T=20.0 * f[3],
+                        lambda_act=300.0 * f[4], L=L))
+    return out
+
+
+def config3_workload(p, i, seed=1, n_mcs=500, max_act=30):
+    """Lattice i of config3 from its draws p: cells seeded at 30% density as
+    10x10 squares (V_target = 100), Max_act = 30, s = 2, k = 1,
+    lattice_id = i."""
+    L = p["L"]
+    lat, n = squares_jittered_2d(L, 0.3, 10, seed=seed * 100003 + i)
+    J, lv, vt, ls, st = _two_type(p["J_cc"], p["J_cm"], p["lambda_V"], 100)
+    w = Workload(f"2d-{L}x{L}-batch{i}", 2, (L, L, 1), lat, np.array([0] + [1] * n, dtype=np.int32),
+                 J, lv, vt, ls, st, T=float(p["T"]), n_mcs=n_mcs, seed=seed, lattice_id=i,
+                 lambda_act=np.array([0.0, p["lambda_act"]]), max_act=np.array([0, max_act], dtype=np.int32))
+    w.extra["params"] = dict(p)
+    return w
+
+
 def config3(n_lattices=512, L_min=64, L_max=512, seed=1, n_mcs=500, max_act=30):
     """Batched 2D CPM: n_lattices independent lattices with side lengths drawn
     uniformly from the multiples of 4 in [L_min, L_max], cells seeded at 30%
@@ -193,21 +223,8 @@ def config3(n_lattices=512, L_min=64, L_max=512, seed=1, n_mcs=500, max_act=30):
     J_cm, T and lambda_act drawn log-uniformly within a factor 4 of the 2D
     base values (lambda_V 50, J_cc 20, J_cm 10, T 20, lambda_act 300);
     Max_act = 30, s = 2, k = 1.  Lattice i has lattice_id i."""
-    rng = np.random.Generator(np.random.PCG64(seed))
-    sides = np.arange(L_min, L_max + 1, 4)
-    out = []
-    for i in range(n_lattices):
-        L = int(rng.choice(sides))
-        f = np.exp(rng.uniform(np.log(0.25), np.log(4.0), size=5))
-        lam_v, j_cc, j_cm, T, lam_act = 50.0 * f[0], 20.0 * f[1], 10.0 * f[2], 20.0 * f[3], 300.0 * f[4]
-        lat, n = squares_jittered_2d(L, 0.3, 10, seed=seed * 100003 + i)
-        J, lv, vt, ls, st = _two_type(j_cc, j_cm, lam_v, 100)
-        w = Workload(f"2d-{L}x{L}-batch{i}", 2, (L, L, 1), lat, np.array([0] + [1] * n, dtype=np.int32),
-                     J, lv, vt, ls, st, T=float(T), n_mcs=n_mcs, seed=seed, lattice_id=i,
-                     lambda_act=np.array([0.0, lam_act]), max_act=np.array([0, max_act], dtype=np.int32))
-        w.extra["params"] = dict(lambda_V=lam_v, J_cc=j_cc, J_cm=j_cm, T=float(T), lambda_act=lam_act, L=L)
-        out.append(w)
-    return out
+    return [config3_workload(p, i, seed, n_mcs, max_act)
+            for i, p in enumerate(config3_points(n_lattices, L_min, L_max, seed))]
 
 
 def mlp_weights(seed=0, sizes=(6, 256, 256, 256, 8)):
