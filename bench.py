@@ -53,12 +53,16 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def bytes_per_attempt(ndim, s, k, p_acc):
+def bytes_per_attempt(ndim, s, k, p_acc, act=False):
     # per activation each thread area stages the halo box of its active
     # sub-area, (s+2)^d int32 sites, which at s = 2 is the whole (2s)^d area,
-    # and writes back its accepted copy
+    # and writes back its accepted copy; with the Act term the uint8 activity
+    # of the same sites as well
     f = min(1.0, (s + 2.0) / (2.0 * s)) ** ndim
-    return 4.0 * f * (2 * s) ** ndim / k + 4.0 * p_acc
+    b = 4.0 * f * (2 * s) ** ndim / k + 4.0 * p_acc
+    if act:
+        b += 1.0 * f * (2 * s) ** ndim / k + 1.0 * p_acc
+    return b
 
 
 def cpu_baseline(w, n_mcs):
@@ -93,9 +97,10 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--cpu-mcs", type=int, default=4, help="MCS of the oracle sample (0 to skip)")
-    ap.add_argument("--workload", choices=("sweep", "batch", "emulator"), default="sweep",
-                    help="sweep: the 3D 256^3 benchmark (default); batch: 512 uneven 2D lattices; "
-                         "emulator: train the emulator on batched runs and judge it against fresh ones")
+    ap.add_argument("--workload", choices=("sweep", "tissue", "batch", "emulator"), default="sweep",
+                    help="sweep: the 3D 256^3 benchmark (default); tissue: 3D 1024^3 with obstacles and the "
+                         "Act term; batch: 512 uneven 2D lattices; emulator: train the emulator on batched "
+                         "runs and judge it against fresh ones")
     ap.add_argument("--emu-train", type=int, default=8192, help="emulator workload: training runs")
     ap.add_argument("--emu-test", type=int, default=256, help="emulator workload: held-out points")
     ap.add_argument("--emu-reps", type=int, default=8, help="emulator workload: replicates per held-out point")
@@ -121,6 +126,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload == "tissue":
+        return bench_tissue(args)
     if args.workload == "emulator":
         return bench_emulator(args)
     w = inputs.config1(n_mcs=args.steps)
@@ -193,6 +200,55 @@ def main():
     sim.close()
 
 
+def bench_tissue(args):
+    """1024^3 lattice (4 GiB of int32 labels, too many cells for the int16
+    copy) with Gaussian-random-field obstacles, ~820k cells of V_target
+    1000, half of them motile with the Act term.  Step = 1 MCS = 64
+    activations; nothing of it fits in the caches."""
+    import torch
+    from paper_2312_09317_amd import cpm, inputs
+    t0 = time.perf_counter()
+    w = inputs.config2(n_mcs=args.steps)
+    log(f"workload {w.name}: {w.n_sites} sites, {w.n_cells} cells, built in {time.perf_counter() - t0:.1f} s")
+    sim = cpm.Simulation(cpm.Params.from_workload(w), w.lattice, w.cell_type, w.act, device="cuda:0")
+    del w.lattice, w.act
+    sim.sweep(args.warmup)
+    torch.cuda.synchronize()
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    e0.record()
+    sim.sweep(args.steps)
+    e1.record()
+    v, s, _ = sim.cell_stats(centroids=False)
+    e2.record()
+    torch.cuda.synchronize()
+    sweep_ms, total_ms = e0.elapsed_time(e1), e0.elapsed_time(e2)
+    tv, ts = sim.counters()
+    torch.cuda.synchronize()
+    if not (torch.equal(tv[1:], v[1:]) and torch.equal(ts[1:], s[1:])):
+        log("ERROR: tracked counters differ from the lattice recount")
+        sys.exit(3)
+    n_act = (2 * w.s) ** w.ndim // w.k
+    att = sim.attempt_stats()
+    p_acc = att[2] / max(1, att[0])
+    avg_launch_s = sweep_ms / 1e3 / (args.steps * n_act)
+    per_launch_bytes = bytes_per_attempt(3, w.s, w.k, p_acc, act=True) * (w.n_sites // n_act)
+    achieved = per_launch_bytes / avg_launch_s / 1e9
+    print(json.dumps({
+        "metric": "site copy-attempts/s on 3D 1024³ tissue (HBM % peak)",
+        "value": w.n_sites * args.steps / (total_ms / 1e3), "unit": "attempts/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": total_ms / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": w.name, "lattice": list(w.dims), "n_cells": w.n_cells,
+                   "obstacle_voxels": w.extra["obstacle_voxels"], "sub": w.s, "attempts_per_activation": w.k,
+                   "act": True},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "tile_sweep_kernel",
+                     "avg_launch_us": avg_launch_s * 1e6,
+                     "bytes_per_attempt": bytes_per_attempt(3, w.s, w.k, p_acc, act=True)},
+        "cpu_baseline": None}), flush=True)
+    sim.close()
+
+
 def bench_batch(args):
     """512 independent 2D lattices of uneven sizes (64..512, 30% cells, Act
     term, per-lattice parameters), advanced together: one launch per
@@ -216,7 +272,7 @@ def bench_batch(args):
     stats = b.attempt_stats()
     acc = float(sum(int(r[2]) for r in stats)) / max(1, sum(int(r[0]) for r in stats))
     avg_launch_s = ms / 1e3 / (args.steps * n_act)
-    per_launch_bytes = bytes_per_attempt(2, ws[0].s, ws[0].k, acc) * (sites // n_act)
+    per_launch_bytes = bytes_per_attempt(2, ws[0].s, ws[0].k, acc, act=True) * (sites // n_act)
     achieved = per_launch_bytes / avg_launch_s / 1e9
     print(json.dumps({
         "metric": "site copy-attempts/s, 512 batched uneven 2D lattices", "value": sites * args.steps / (ms / 1e3),

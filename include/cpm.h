@@ -111,6 +111,13 @@ int cpm_validate(const cpm_params *params, int32_t n_cells);
 /* Device workspace size (bytes) cpm_init needs for this model; host only. */
 int cpm_workspace_bytes(const cpm_params *params, int32_t n_cells, size_t *bytes);
 
+/* How cpm_init will tile this model (host only, for reports and tests):
+ * out[0..2] thread areas per workgroup tile along x, y, z; out[3] 1 if tiles
+ * span whole lattice rows (full-row LDS layout), 0 for halo boxes; out[4] LDS
+ * bytes per workgroup; out[5] tiles per activation; out[6] 1 if sweeps run on
+ * an int16 copy of the labels.  Results never depend on the tiling. */
+int cpm_tile_shape(const cpm_params *params, int32_t n_cells, int32_t *out);
+
 /*
  * Binds a lattice to a new handle and counts every cell's volume and surface
  * from the lattice (the counters the sweep then keeps exact).

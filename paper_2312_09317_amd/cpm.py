@@ -50,7 +50,7 @@ class cpm_params(ctypes.Structure):
     ]
 
 
-EXPORTS = ("cpm_validate", "cpm_workspace_bytes", "cpm_init", "cpm_sweep", "cpm_cell_stats",
+EXPORTS = ("cpm_validate", "cpm_workspace_bytes", "cpm_tile_shape", "cpm_init", "cpm_sweep", "cpm_cell_stats",
            "cpm_counters", "cpm_attempt_stats", "cpm_set_mcs", "cpm_get_mcs", "cpm_destroy",
            "cpm_batch_workspace_bytes", "cpm_batch_init", "cpm_batch_sweep", "cpm_batch_use_graph", "cpm_batch_counters",
            "cpm_batch_cell_stats", "cpm_batch_attempt_stats", "cpm_batch_sample", "cpm_batch_summary",
@@ -77,6 +77,7 @@ def load(path: str = LIB_PATH):
     pp = ctypes.POINTER(cpm_params)
     l.cpm_validate.argtypes = [pp, I32]
     l.cpm_workspace_bytes.argtypes = [pp, I32, ctypes.POINTER(SZ)]
+    l.cpm_tile_shape.argtypes = [pp, I32, P]
     l.cpm_init.argtypes = [pp, P, P, I32, P, P, SZ, P, ctypes.POINTER(P)]
     l.cpm_sweep.argtypes = [P, I32, P]
     l.cpm_cell_stats.argtypes = [P, P, P, P, P]
@@ -177,6 +178,13 @@ def cpm_workspace_bytes(params: Params, n_cells: int) -> int:
     b = ctypes.c_size_t(0)
     _check(load().cpm_workspace_bytes(ctypes.byref(params.c), n_cells, ctypes.byref(b)), "cpm_workspace_bytes")
     return b.value
+
+
+def cpm_tile_shape(params: Params, n_cells: int) -> dict:
+    out = (ctypes.c_int32 * 7)()
+    _check(load().cpm_tile_shape(ctypes.byref(params.c), n_cells, out), "cpm_tile_shape")
+    return {"areas": (out[0], out[1], out[2]), "full_rows": bool(out[3]), "lds_bytes": out[4],
+            "tiles": out[5], "int16": bool(out[6])}
 
 
 def cpm_init(params: Params, d_lattice, d_cell_type, n_cells: int, d_act, d_workspace, workspace_bytes: int,

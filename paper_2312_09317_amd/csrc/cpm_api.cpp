@@ -150,22 +150,36 @@ cpm::TileGeometry choose_tiles(const cpm_params *p, bool mirror, bool force_box 
         }
     }
     if (!full) {
-        T[0] = std::min(na[0], cpm::kBlock);
-        T[1] = std::min(na[1], cpm::kBlock / T[0]);
-        T[2] = p->ndim == 3 ? std::min(na[2], cpm::kBlock / (T[0] * T[1])) : 1;
-        for (;;) {
-            int box = 1;
-            for (int d = 0; d < p->ndim; ++d) box *= extent(T[d]);
-            const size_t bytes = cpm::sweep_lds_bytes(p->ndim, act, mirror, box);
-            if (bytes <= budget || (T[0] == 1 && T[1] == 1 && T[2] == 1)) {
-                g.box_sites = box;
-                g.lds_bytes = (int32_t)bytes;
-                break;
-            }
-            if (T[2] > 1) T[2] = (T[2] + 1) / 2;
-            else if (T[1] > 1) T[1] = (T[1] + 1) / 2;
-            else T[0] = (T[0] + 1) / 2;
-        }
+        // Box tiles: of all tiles of at most kBlock areas whose box fits the
+        // budget, the one that moves the fewest bytes per activation over the
+        // whole lattice, counting every staged row in 128-byte cache lines (halo
+        // overlap, ragged edge tiles and short rows all cost); ties go to
+        // larger tiles.
+        const int t2max = p->ndim == 3 ? std::min(na[2], cpm::kBlock) : 1;
+        double best = -1.0;
+        int best_areas = 0;
+        for (int t0 = 1; t0 <= std::min(na[0], cpm::kBlock); ++t0)
+            for (int t1 = 1; t1 <= std::min(na[1], cpm::kBlock / t0); ++t1)
+                for (int t2 = 1; t2 <= std::min(t2max, cpm::kBlock / (t0 * t1)); ++t2) {
+                    const int e0 = extent(t0), e1 = extent(t1), e2 = p->ndim == 3 ? extent(t2) : 1;
+                    const int box = e0 * e1 * e2;
+                    const size_t bytes = cpm::sweep_lds_bytes(p->ndim, act, mirror, box);
+                    if (bytes > budget && !(t0 == 1 && t1 == 1 && t2 == 1)) continue;
+                    const double tiles = (double)((na[0] + t0 - 1) / t0) * ((na[1] + t1 - 1) / t1) *
+                                         ((na[2] + t2 - 1) / t2);
+                    const double seg = 128.0;
+                    double row = std::ceil(e0 * (double)cell / seg) * seg;
+                    if (act) row += std::ceil(e0 / seg) * seg;
+                    const double cost = tiles * row * e1 * e2;
+                    const int areas = t0 * t1 * t2;
+                    if (best < 0 || cost < best * 0.999 || (cost <= best * 1.001 && areas > best_areas)) {
+                        best = cost;
+                        best_areas = areas;
+                        T[0] = t0, T[1] = t1, T[2] = t2;
+                        g.box_sites = box;
+                        g.lds_bytes = (int32_t)bytes;
+                    }
+                }
     }
     g.full_rows = full ? 1 : 0;
     g.n_tiles = 1;
@@ -401,6 +415,20 @@ int cpm_workspace_bytes(const cpm_params *params, int32_t n_cells, size_t *bytes
     if (rc != CPM_OK) return rc;
     if (!bytes) return fail(CPM_EINVAL, "bytes is NULL");
     *bytes = layout_of(params, n_cells).total;
+    return CPM_OK;
+}
+
+int cpm_tile_shape(const cpm_params *params, int32_t n_cells, int32_t *out)
+{
+    const int rc = validate(params, n_cells);
+    if (rc != CPM_OK) return rc;
+    if (!out) return fail(CPM_EINVAL, "out is NULL");
+    const Layout l = layout_of(params, n_cells);
+    for (int d = 0; d < 3; ++d) out[d] = l.tg.T[d];
+    out[3] = l.tg.full_rows;
+    out[4] = l.tg.lds_bytes;
+    out[5] = l.tg.n_tiles;
+    out[6] = l.mirror_on ? 1 : 0;
     return CPM_OK;
 }
 

@@ -65,13 +65,14 @@ struct LdsMap {
 // Geometric mean of the activity over the site at (x,y,z) (label `cell`) and
 // its Moore neighbours of the same cell (eq. 8), 2^16 fixed point.
 template <typename Cell, int D, bool FULLROW>
-__device__ __forceinline__ int64_t gm_lds(const DeviceModel *m, const Cell *lab, const uint8_t *lact,
-                                          const LdsMap<FULLROW> &map, int x, int y, int z, int cell, bool motile)
+__device__ __forceinline__ int64_t gm_lds(const DeviceModel *m, const int64_t *lg, const Cell *lab,
+                                          const uint8_t *lact, const LdsMap<FULLROW> &map, int x, int y, int z,
+                                          int cell, bool motile)
 {
     if (cell <= 0 || !motile) return 0;
     const int c = map.at(x, y, z);
     const uint32_t a0 = lact[c];
-    uint64_t sum = (uint64_t)m->LG[a0];
+    uint64_t sum = (uint64_t)lg[a0];
     uint32_t cnt = 1;
     bool zero = a0 == 0;
     constexpr int NNB = D == 2 ? 8 : 26;
@@ -81,7 +82,7 @@ __device__ __forceinline__ int64_t gm_lds(const DeviceModel *m, const Cell *lab,
         if ((int)lab[u] == cell) {
             const uint32_t au = lact[u];
             zero |= au == 0;
-            sum += (uint64_t)m->LG[au];
+            sum += (uint64_t)lg[au];
             ++cnt;
         }
     }
@@ -118,8 +119,16 @@ struct JRows {
 // ls into the target (x,y,z) (eq. 1, eq. 3, eq. 7) and the Metropolis test
 // (eq. 2).  cnt_t / cnt_s are the (V, S) counters of the two cells as the
 // attempt sees them.  Returns acceptance; dso / dsn are the surface deltas.
+// Per-workgroup LDS copies of the model tables the energy change reads per
+// neighbour: J (multi-type models) and the Act log table.
+struct SharedTables {
+    const int64_t *J;
+    const int64_t *lg;
+};
+
 template <typename Cell, int D, bool ACT, bool SINGLE, bool FULLROW>
-__device__ __forceinline__ bool evaluate(const SweepArgs &a, const ThrTables &tb, const JRows &jr, Cell *lab,
+__device__ __forceinline__ bool evaluate(const SweepArgs &a, const ThrTables &tb, const JRows &jr,
+                                         const SharedTables &st, Cell *lab,
                                          uint8_t *lact, const LdsMap<FULLROW> &map, int tx_, int ty_, int tz_,
                                          int sx_, int sy_, int sz_, int lt, int ls, int2 cnt_t, int2 cnt_s,
                                          uint32_t u2, int64_t &dso_out, int64_t &dsn_out)
@@ -146,8 +155,8 @@ __device__ __forceinline__ bool evaluate(const SweepArgs &a, const ThrTables &tb
             n_obs += lu < 0;
         } else {
             const int tu = lu < 0 ? to : a.cell_type[lu];
-            if (lu != ls) adh += m->J[ts * kMaxTypes + tu];
-            if (lu != lt) adh -= m->J[tt * kMaxTypes + tu];
+            if (lu != ls) adh += st.J[ts * kMaxTypes + tu];
+            if (lu != lt) adh -= st.J[tt * kMaxTypes + tu];
         }
     }
     if (SINGLE) {
@@ -169,8 +178,10 @@ __device__ __forceinline__ bool evaluate(const SweepArgs &a, const ThrTables &tb
         q += m->lam_s[ts] * (2 * dsn * ((int64_t)cnt_s.y - m->s_target[ts]) + dsn * dsn);
     }
     if (ACT) {
-        const int64_t gt = gm_lds<Cell, D, FULLROW>(m, lab, lact, map, tx_, ty_, tz_, lt, lt > 0 && m->max_act[tt] > 0);
-        const int64_t gs = gm_lds<Cell, D, FULLROW>(m, lab, lact, map, sx_, sy_, sz_, ls, ls > 0 && m->max_act[ts] > 0);
+        const int64_t gt = gm_lds<Cell, D, FULLROW>(m, st.lg, lab, lact, map, tx_, ty_, tz_, lt,
+                                                    lt > 0 && m->max_act[tt] > 0);
+        const int64_t gs = gm_lds<Cell, D, FULLROW>(m, st.lg, lab, lact, map, sx_, sy_, sz_, ls,
+                                                    ls > 0 && m->max_act[ts] > 0);
         const int64_t rt = lt >= 1 ? m->r_act[tt] : 0;
         const int64_t rs = ls >= 1 ? m->r_act[ts] : 0;
         q += (rt * gt - rs * gs) >> 16;
@@ -205,6 +216,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
     // counters (V, S) of both cells fetched while drawing
     __shared__ int4 queue[K1 ? kQueue : 1];
     __shared__ int4 queue_cnt[K1 ? kQueue : 1];
+    __shared__ int64_t j_lds[SINGLE ? 1 : kMaxTypes * kMaxTypes];
+    __shared__ int64_t lg_lds[ACT ? 256 : 1];
     constexpr int R = ACT ? 2 : 1;           // read radius: the Act term reads neighbours of the source
     constexpr int NNB = D == 2 ? 8 : 26;
 
@@ -239,6 +252,13 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
         n_nontrivial = 0;
         n_accepted = 0;
     }
+    // model tables read per neighbour, copied to LDS (visible after the
+    // staging barrier)
+    if (!SINGLE)
+        for (int i = tid; i < kMaxTypes * kMaxTypes; i += kBlock) j_lds[i] = a.model->J[i];
+    if (ACT)
+        for (int i = tid; i < 256; i += kBlock) lg_lds[i] = a.model->LG[i];
+    const SharedTables sht{j_lds, lg_lds};
     // deltas of the previous activation go into the write buffer as well
     const int prev_n = a.dcount[tile];
     for (int i = tid; i < prev_n; i += kBlock) add_deltas(wr, dl[i]);
@@ -361,18 +381,47 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
         copy_any(tg.row_chunk, cells, lab, L0 * (int)sizeof(Cell));
         if (ACT) copy_any(tg.act_chunk, a.act, lact, L0);
     } else {
-        const int wave = tid >> 6, lane = tid & 63;
-        const FastDiv by_b1((uint32_t)b1);
-        for (int r = wave; r < rows; r += kBlock / 64) {
+        // the box x fastest, site c of the box at LDS index c: consecutive
+        // threads read consecutive sites of a row, eight loads (and eight
+        // activity loads) in flight per thread before the LDS stores
+        const int total = b0 * rows;
+        const FastDiv by_b0((uint32_t)b0), by_b1((uint32_t)b1);
+        auto src = [&](int c) {
+            const int r = (int)by_b0.div((uint32_t)c), x = c - r * b0;
             const int rz = (int)by_b1.div((uint32_t)r), ry = r - rz * b1;
+            const int gx = wrap_once(o0 + x, L0);
             const int gy = wrap_once(o1 + ry, L1);
             const int gz = D == 3 ? wrap_once(o2 + rz, L2) : 0;
-            const size_t base = ((size_t)gz * L1 + gy) * L0;
-            for (int x = lane; x < b0; x += 64) {
-                const int gx = wrap_once(o0 + x, L0);
-                lab[r * b0 + x] = cells[base + gx];
-                if (ACT) lact[r * b0 + x] = a.act[base + gx];
+            return (int)(((size_t)gz * L1 + gy) * L0 + gx);
+        };
+        // kBatch sites per thread per round: all their loads are issued
+        // before the first LDS store (the arrays are indexed by unrolled
+        // constants only, so they stay in registers)
+        constexpr int kBatch = 8;
+        int c0 = tid;
+        for (; c0 + (kBatch - 1) * kBlock < total; c0 += kBatch * kBlock) {
+            int idx[kBatch];
+            Cell v[kBatch];
+            uint8_t w[kBatch];
+#pragma unroll
+            for (int q = 0; q < kBatch; ++q) idx[q] = src(c0 + q * kBlock);
+#pragma unroll
+            for (int q = 0; q < kBatch; ++q) v[q] = cells[idx[q]];
+            if (ACT) {
+#pragma unroll
+                for (int q = 0; q < kBatch; ++q) w[q] = a.act[idx[q]];
             }
+#pragma unroll
+            for (int q = 0; q < kBatch; ++q) lab[c0 + q * kBlock] = v[q];
+            if (ACT) {
+#pragma unroll
+                for (int q = 0; q < kBatch; ++q) lact[c0 + q * kBlock] = w[q];
+            }
+        }
+        for (; c0 < total; c0 += kBlock) {
+            const int i = src(c0);
+            lab[c0] = cells[i];
+            if (ACT) lact[c0] = a.act[i];
         }
     }
     __syncthreads();
@@ -397,7 +446,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
             } else {
                 // queue full: evaluate here (no other attempt reads this sub-area)
                 int64_t dso, dsn;
-                if (evaluate<Cell, D, ACT, SINGLE, FULLROW>(a, tb, jr, lab, lact, map, d_ttx, d_tty, d_ttz, d_ssx,
+                if (evaluate<Cell, D, ACT, SINGLE, FULLROW>(a, tb, jr, sht, lab, lact, map, d_ttx, d_tty, d_ttz, d_ssx,
                                                             d_ssy, d_ssz, d_lt, d_ls, d_ct, d_cs, d_u2, dso, dsn)) {
                     ++my_accepted;
                     commit(map.at(d_ttx, d_tty, d_ttz), global_index(d_ttx, d_tty, d_ttz), d_lt, d_ls, dso, dsn);
@@ -415,7 +464,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
             const int t = map.at(ttx, tty, ttz);
             const int lt = lab[t], ls = lab[map.at(ssx, ssy, ssz)];
             int64_t dso, dsn;
-            if (evaluate<Cell, D, ACT, SINGLE, FULLROW>(a, tb, jr, lab, lact, map, ttx, tty, ttz, ssx, ssy, ssz, lt,
+            if (evaluate<Cell, D, ACT, SINGLE, FULLROW>(a, tb, jr, sht, lab, lact, map, ttx, tty, ttz, ssx, ssy, ssz, lt,
                                                         ls, make_int2(c.x, c.y), make_int2(c.z, c.w), (uint32_t)e.w,
                                                         dso, dsn)) {
                 ++my_accepted;
@@ -437,7 +486,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
                 if (lt != ls && lt >= 0 && ls >= 0) {
                     ++my_nontrivial;
                     int64_t dso, dsn;
-                    if (evaluate<Cell, D, ACT, SINGLE, FULLROW>(a, tb, jr, lab, lact, map, ttx, tty, ttz, ssx, ssy,
+                    if (evaluate<Cell, D, ACT, SINGLE, FULLROW>(a, tb, jr, sht, lab, lact, map, ttx, tty, ttz, ssx, ssy,
                                                                 ssz, lt, ls, seen_counters(rd, lt, own, j),
                                                                 seen_counters(rd, ls, own, j), u2, dso, dsn)) {
                         ++my_accepted;

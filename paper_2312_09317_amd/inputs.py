@@ -19,6 +19,9 @@ import numpy as np
 # 515 voxels; the tie is broken towards the smaller ball).  Checked by a test
 # against the oracle's recount.
 S_TARGET_BALL_V500 = 2690
+# The same count for x^2+y^2+z^2 <= 38 (1021 voxels), the ball nearest to
+# V = 1000.
+S_TARGET_BALL_V1000 = 4490
 
 
 @dataclass
@@ -128,6 +131,87 @@ def config1(L=256, grid=27, seed=1, n_mcs=1000):
     return Workload(f"3d-{L}^3-{n}cells", 3, (L, L, L), lat,
                     np.array([0] + [1] * n, dtype=np.int32), J, lv, vt, ls, st,
                     T=20.0, n_mcs=n_mcs, seed=seed)
+
+
+def gaussian_field(L, corr=12.0, seed=1, workers=None):
+    """Periodic Gaussian random field on an L^3 lattice (float32): seeded
+    white noise convolved with a Gaussian kernel of standard deviation
+    corr / sqrt(2), so that the field's covariance is a Gaussian of standard
+    deviation `corr` voxels.  Done in Fourier space with scipy's float32
+    FFT."""
+    import os
+    import scipy.fft
+    rng = np.random.Generator(np.random.PCG64(seed))
+    noise = rng.standard_normal((L, L, L), dtype=np.float32)
+    w = workers or min(16, os.cpu_count() or 1)
+    spec = scipy.fft.rfftn(noise, workers=w)
+    del noise
+    sk = corr / np.sqrt(2.0)
+    k = np.fft.fftfreq(L).astype(np.float32)
+    kr = np.fft.rfftfreq(L).astype(np.float32)
+    c = np.float32(-2.0 * np.pi ** 2 * sk ** 2)
+    gz = np.exp(c * k * k)[:, None, None]
+    gy = np.exp(c * k * k)[None, :, None]
+    gx = np.exp(c * kr * kr)[None, None, :]
+    spec *= gz
+    spec *= gy
+    spec *= gx
+    return scipy.fft.irfftn(spec, s=(L, L, L), workers=w).astype(np.float32, copy=False)
+
+
+def config2(L=1024, grid=100, seed=1, n_mcs=200, edge=8, corr=12.0, obstacle_frac=0.3, min_voxels=64,
+            motile_frac=0.5):
+    """3D tissue-scale CPM: an L^3 periodic lattice whose static obstacle
+    (label -1, type 3) is the top `obstacle_frac` of a Gaussian random field
+    of correlation length `corr`; cells seeded as grid^3 jittered cubes of
+    `edge` (as in config1), clipped to the free voxels, cells left with fewer
+    than `min_voxels` voxels dropped and the rest relabelled 1..C in seeding
+    order; each cell motile (type 1, Act term lambda_act 300, Max_act 30) or
+    not (type 2) by a seeded draw with probability `motile_frac`.  Energies
+    as config1 (J_cc 40, J_cm 20, lambda_V 25, lambda_S 0.5) with V_target
+    1000 and S_target 4490; J(cell, obstacle) = J(cell, medium), J(medium,
+    obstacle) = 0; T = 20.  L = 1024, grid = 100 is the full-size workload."""
+    field = gaussian_field(L, corr, seed)
+    flat = field.reshape(-1)
+    cut = np.partition(flat, int((1.0 - obstacle_frac) * flat.size))[int((1.0 - obstacle_frac) * flat.size)]
+    obstacle = field > cut
+    del field, flat
+    rng = np.random.Generator(np.random.PCG64(seed + 1))
+    starts = np.array([(i * L) // grid for i in range(grid)] + [L])
+    widths = np.diff(starts)
+    if widths.min() < edge:
+        raise ValueError("cubes do not fit their grid boxes")
+    iz, iy, ix = np.meshgrid(np.arange(grid), np.arange(grid), np.arange(grid), indexing="ij")
+    iz, iy, ix = iz.reshape(-1), iy.reshape(-1), ix.reshape(-1)
+    jit = rng.integers(0, np.stack([widths[ix], widths[iy], widths[iz]], axis=1) - edge + 1)
+    x0, y0, z0 = starts[ix] + jit[:, 0], starts[iy] + jit[:, 1], starts[iz] + jit[:, 2]
+    lat = np.zeros((L, L, L), dtype=np.int32)
+    ids = np.arange(1, grid ** 3 + 1, dtype=np.int32)
+    for dz in range(edge):
+        for dy in range(edge):
+            lat[(z0 + dz)[:, None], (y0 + dy)[:, None], x0[:, None] + np.arange(edge)[None, :]] = ids[:, None]
+    lat[obstacle] = -1
+    del obstacle
+    vol = np.bincount(lat.reshape(-1)[lat.reshape(-1) > 0], minlength=grid ** 3 + 1)
+    keep = vol >= min_voxels
+    keep[0] = False
+    remap = np.zeros(grid ** 3 + 2, dtype=np.int32)  # index 0 (medium) -> 0; -1 indexes the last entry
+    remap[-1] = -1
+    remap[np.nonzero(keep)[0]] = np.arange(1, int(keep.sum()) + 1, dtype=np.int32)
+    lat = remap[lat]
+    n = int(keep.sum())
+    motile = rng.random(n) < motile_frac
+    cell_type = np.concatenate([[0], np.where(motile, 1, 2)]).astype(np.int32)
+    J = np.array([[0.0, 20.0, 20.0, 0.0], [20.0, 40.0, 40.0, 20.0], [20.0, 40.0, 40.0, 20.0], [0.0, 20.0, 20.0, 0.0]])
+    w = Workload(f"3d-{L}^3-tissue-{n}cells", 3, (L, L, L), lat, cell_type, J,
+                 np.array([0.0, 25.0, 25.0, 0.0]), np.array([0, 1000, 1000, 0], dtype=np.int32),
+                 np.array([0.0, 0.5, 0.5, 0.0]), np.array([0, S_TARGET_BALL_V1000, S_TARGET_BALL_V1000, 0],
+                                                          dtype=np.int32),
+                 T=20.0, n_mcs=n_mcs, seed=seed, obstacle_type=3,
+                 lambda_act=np.array([0.0, 300.0, 0.0, 0.0]), max_act=np.array([0, 30, 0, 0], dtype=np.int32),
+                 act=np.zeros((L, L, L), dtype=np.uint8))
+    w.extra["obstacle_voxels"] = int((lat < 0).sum())
+    return w
 
 
 def random_labels(dims, n_labels, seed, p_obstacle=0.0):

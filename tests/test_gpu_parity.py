@@ -174,3 +174,38 @@ def test_config1_full_size(torch_cuda):
     w = inputs.config1(n_mcs=2)
     st, sim = run_both(torch_cuda, w, 2)
     assert_same(st, sim, torch_cuda)
+
+
+def test_tissue_crop(torch_cuda):
+    # the tissue-scale workload's recipe (Gaussian-random-field obstacles,
+    # motile and non-motile cells, Act term, int32 labels when cells exceed
+    # the int16 range are covered elsewhere) at 128^3, every site compared
+    w = inputs.config2(L=128, grid=12, n_mcs=2)
+    st, sim = run_both(torch_cuda, w, 2)
+    assert_same(st, sim, torch_cuda)
+
+
+def test_tissue_full_size_properties(torch_cuda):
+    # 1024^3 (4 GiB of int32 labels, ~820k cells, so the int32 path) in the
+    # benchmark's launch configuration: the tracked counters equal a recount
+    # of the lattice, obstacles stay put, activity stays within [0, Max_act]
+    # and is zero off motile cells
+    w = inputs.config2(n_mcs=2)
+    _say(f"case {w.name}: {w.n_cells} cells, {w.extra['obstacle_voxels']} obstacle voxels")
+    obst = torch_cuda.as_tensor(w.lattice < 0).cuda()
+    sim = cpm.Simulation(cpm.Params.from_workload(w), w.lattice, w.cell_type, w.act)
+    del w.lattice
+    sim.sweep(2)
+    v, s, _ = sim.cell_stats(centroids=False)
+    tv, ts = sim.counters()
+    torch_cuda.cuda.synchronize()
+    assert torch_cuda.equal(v[1:], tv[1:]) and torch_cuda.equal(s[1:], ts[1:])
+    assert torch_cuda.equal(sim.lattice < 0, obst)
+    act = sim.act
+    assert int(act.max()) <= 30
+    motile = torch_cuda.as_tensor(w.cell_type == 1).cuda()
+    lab = sim.lattice.long()
+    on_motile = motile[lab.clamp(min=0)] & (lab > 0)
+    assert int(act[~on_motile].max()) == 0
+    assert int((act > 0).sum()) > 0
+    assert int(v[1:].sum()) + int((sim.lattice == 0).sum()) + int(obst.sum()) == sim.lattice.numel()

@@ -141,6 +141,21 @@ def test_ball_surface_target():
     assert S[1] == inputs.S_TARGET_BALL_V500
 
 
+def test_ball_surface_target_v1000():
+    # r^2 <= 38 (1021 voxels) is the digitised ball nearest to V = 1000
+    # (r^2 <= 37 has 949)
+    g = np.arange(-8, 9)
+    Z, Y, X = np.meshgrid(g, g, g, indexing="ij")
+    r2 = X * X + Y * Y + Z * Z
+    assert (r2 <= 37).sum() == 949 and (r2 <= 38).sum() == 1021
+    lat = np.zeros((24, 24, 24), dtype=np.int32)
+    lat[4:21, 4:21, 4:21] = (r2 <= 38).astype(np.int32)
+    m = oracle.Model(3, (24, 24, 24), np.zeros((2, 2)), [0, 0], [0, 0])
+    V, S = oracle.recount(m, lat, 1)
+    assert V[1] == 1021
+    assert S[1] == inputs.S_TARGET_BALL_V1000
+
+
 @pytest.mark.parametrize("ndim,dims", [(2, (12, 8, 1)), (3, (6, 4, 8))])
 def test_recount_matches_definition(ndim, dims):
     lat = inputs.random_labels(dims, 5, seed=3, p_obstacle=0.1)
