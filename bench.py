@@ -101,6 +101,8 @@ def main():
                     help="sweep: the 3D 256^3 benchmark (default); tissue: 3D 1024^3 with obstacles and the "
                          "Act term; batch: 512 uneven 2D lattices; emulator: train the emulator on batched "
                          "runs and judge it against fresh ones")
+    ap.add_argument("--layout", default="tune", choices=("tune", "auto", "box", "full_rows", "in_place"),
+                    help="sweep layout: tune = time the candidates first and take the fastest (default)")
     ap.add_argument("--emu-train", type=int, default=8192, help="emulator workload: training runs")
     ap.add_argument("--emu-test", type=int, default=256, help="emulator workload: held-out points")
     ap.add_argument("--emu-reps", type=int, default=8, help="emulator workload: replicates per held-out point")
@@ -132,7 +134,8 @@ def main():
         return bench_emulator(args)
     w = inputs.config1(n_mcs=args.steps)
     log(f"workload {w.name}: {w.n_sites} sites, {w.n_cells} cells")
-    sim = cpm.Simulation(cpm.Params.from_workload(w), w.lattice, w.cell_type, device="cuda:0")
+    params, tuning = choose_layout(args, cpm, cpm.Params.from_workload(w), w)
+    sim = cpm.Simulation(params, w.lattice, w.cell_type, device="cuda:0")
     torch.cuda.synchronize()
     sim.sweep(args.warmup)
     torch.cuda.synchronize()
@@ -189,7 +192,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "lattice": list(w.dims), "n_cells": w.n_cells, "sub": w.s,
                    "attempts_per_activation": w.k, "mcs_per_step": 1, "activations_per_mcs": n_act,
-                   "temperature": w.T, "seed": w.seed},
+                   "temperature": w.T, "seed": w.seed, "tiling": cpm.cpm_tile_shape(params, w.n_cells),
+                   "tuning_ms_per_mcs": tuning},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic_bytes(),
                      "kernel": "tile_sweep_kernel", "avg_launch_us": avg_launch_s * 1e6,
@@ -198,6 +202,16 @@ def main():
     }
     print(json.dumps(out), flush=True)
     sim.close()
+
+
+def choose_layout(args, cpm, params, w):
+    """The sweep layout: timed candidates (--layout tune) or the one named."""
+    if args.layout != "tune":
+        return params.replace(layout=args.layout), None
+    r = cpm.autotune(params, w.lattice, w.cell_type, w.act, trial_mcs=2)
+    log("autotune (ms per MCS): " + ", ".join(f"{k[0]}{list(k[1])}: {v:.3f}" for k, v in sorted(r["times"].items(), key=lambda kv: kv[1])))
+    lay, tile = r["best"]
+    return params.replace(layout=lay, tile=tile), {f"{k[0]}{list(k[1])}": round(v, 4) for k, v in r["times"].items()}
 
 
 def bench_tissue(args):
@@ -210,7 +224,8 @@ def bench_tissue(args):
     t0 = time.perf_counter()
     w = inputs.config2(n_mcs=args.steps)
     log(f"workload {w.name}: {w.n_sites} sites, {w.n_cells} cells, built in {time.perf_counter() - t0:.1f} s")
-    sim = cpm.Simulation(cpm.Params.from_workload(w), w.lattice, w.cell_type, w.act, device="cuda:0")
+    params, tuning = choose_layout(args, cpm, cpm.Params.from_workload(w), w)
+    sim = cpm.Simulation(params, w.lattice, w.cell_type, w.act, device="cuda:0")
     del w.lattice, w.act
     sim.sweep(args.warmup)
     torch.cuda.synchronize()
@@ -240,7 +255,7 @@ def bench_tissue(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
         "config": {"workload": w.name, "lattice": list(w.dims), "n_cells": w.n_cells,
                    "obstacle_voxels": w.extra["obstacle_voxels"], "sub": w.s, "attempts_per_activation": w.k,
-                   "act": True},
+                   "act": True, "tiling": cpm.cpm_tile_shape(params, w.n_cells), "tuning_ms_per_mcs": tuning},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "tile_sweep_kernel",
                      "avg_launch_us": avg_launch_s * 1e6,

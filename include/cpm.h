@@ -99,6 +99,14 @@ typedef struct cpm_params {
     const int32_t *surface_target;/* n_types (may be NULL when lambda_surface is NULL) */
     const double *lambda_act;     /* n_types (read when act_enabled) */
     const int32_t *max_act;       /* n_types, 0..255; a type is motile iff max_act > 0 */
+    /* How the sweep is laid out on the GPU (results never depend on it; an
+     * autotuner picks it by timing): 0 = the library's choice, 1 = halo boxes
+     * staged in LDS, 2 = whole lattice rows staged in LDS (k = 1), 3 = the
+     * lattice read in place (k = 1).  A layout that cannot run this model
+     * gives CPM_ENOTSUP. */
+    int32_t layout;
+    int32_t tile[3];              /* thread areas per workgroup tile (product <= 256); 0 = the library's choice.
+                                     With layout 2 tile[0] must be 0 or the whole row of areas. */
 } cpm_params;
 
 typedef struct cpm_handle cpm_handle;
@@ -112,10 +120,12 @@ int cpm_validate(const cpm_params *params, int32_t n_cells);
 int cpm_workspace_bytes(const cpm_params *params, int32_t n_cells, size_t *bytes);
 
 /* How cpm_init will tile this model (host only, for reports and tests):
- * out[0..2] thread areas per workgroup tile along x, y, z; out[3] 1 if tiles
- * span whole lattice rows (full-row LDS layout), 0 for halo boxes; out[4] LDS
- * bytes per workgroup; out[5] tiles per activation; out[6] 1 if sweeps run on
- * an int16 copy of the labels.  Results never depend on the tiling. */
+ * out[0..2] thread areas per workgroup tile along x, y, z; out[3] the layout:
+ * 0 = each tile stages its active sub-areas with their halo in LDS, 1 = tiles
+ * span whole lattice rows staged in LDS, 2 = attempts read the lattice in
+ * place (k = 1); out[4] staged LDS bytes per workgroup; out[5] tiles per
+ * activation; out[6] 1 if sweeps run on an int16 copy of the labels.  Results
+ * never depend on the tiling or layout. */
 int cpm_tile_shape(const cpm_params *params, int32_t n_cells, int32_t *out);
 
 /*

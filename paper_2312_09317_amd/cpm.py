@@ -47,7 +47,11 @@ class cpm_params(ctypes.Structure):
         ("surface_target", ctypes.POINTER(ctypes.c_int32)),
         ("lambda_act", ctypes.POINTER(ctypes.c_double)),
         ("max_act", ctypes.POINTER(ctypes.c_int32)),
+        ("layout", ctypes.c_int32),
+        ("tile", ctypes.c_int32 * 3),
     ]
+
+LAYOUTS = {"auto": 0, "box": 1, "full_rows": 2, "in_place": 3}
 
 
 EXPORTS = ("cpm_validate", "cpm_workspace_bytes", "cpm_tile_shape", "cpm_init", "cpm_sweep", "cpm_cell_stats",
@@ -119,7 +123,7 @@ class Params:
     def __init__(self, ndim: int, dims: Sequence[int], J, lambda_volume, volume_target,
                  lambda_surface=None, surface_target=None, lambda_act=None, max_act=None,
                  temperature: float = 20.0, seed: int = 1, lattice_id: int = 0, sub: int = 2,
-                 attempts: int = 1, obstacle_type: int = -1):
+                 attempts: int = 1, obstacle_type: int = -1, layout="auto", tile=(0, 0, 0)):
         n = len(lambda_volume)
         self._J = np.ascontiguousarray(np.asarray(J, dtype=np.float64).reshape(n, n))
         self._lv = np.ascontiguousarray(lambda_volume, dtype=np.float64)
@@ -148,7 +152,19 @@ class Params:
         c.surface_target = self._st.ctypes.data_as(ip) if self._st is not None else None
         c.lambda_act = self._la.ctypes.data_as(dp) if self._la is not None else None
         c.max_act = self._ma.ctypes.data_as(ip) if self._ma is not None else None
+        c.layout = LAYOUTS[layout] if isinstance(layout, str) else int(layout)
+        c.tile = (ctypes.c_int32 * 3)(*[int(t) for t in tile])
         self.c = c
+        self._kw = dict(ndim=ndim, dims=dims, J=J, lambda_volume=lambda_volume, volume_target=volume_target,
+                        lambda_surface=lambda_surface, surface_target=surface_target, lambda_act=lambda_act,
+                        max_act=max_act, temperature=temperature, seed=seed, lattice_id=lattice_id, sub=sub,
+                        attempts=attempts, obstacle_type=obstacle_type, layout=layout, tile=tile)
+
+    def replace(self, **over) -> "Params":
+        """A copy with some fields changed (e.g. layout, tile)."""
+        kw = dict(self._kw)
+        kw.update(over)
+        return Params(**kw)
 
     @property
     def act_enabled(self) -> bool:
@@ -183,7 +199,7 @@ def cpm_workspace_bytes(params: Params, n_cells: int) -> int:
 def cpm_tile_shape(params: Params, n_cells: int) -> dict:
     out = (ctypes.c_int32 * 7)()
     _check(load().cpm_tile_shape(ctypes.byref(params.c), n_cells, out), "cpm_tile_shape")
-    return {"areas": (out[0], out[1], out[2]), "full_rows": bool(out[3]), "lds_bytes": out[4],
+    return {"areas": (out[0], out[1], out[2]), "layout": ("box", "full_rows", "in_place")[out[3]], "lds_bytes": out[4],
             "tiles": out[5], "int16": bool(out[6])}
 
 
@@ -483,3 +499,59 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------- autotuner
+
+def tuning_candidates(params: Params, n_cells: int):
+    """(layout, tile) pairs worth timing for this model: the library's
+    choice of each layout that fits, and in-place tiles of other shapes."""
+    c = params.c
+    na = [c.dims[d] // (2 * c.sub) if d < c.ndim else 1 for d in range(3)]
+    out = []
+    layouts = ["box"] if c.attempts != 1 else ["in_place", "full_rows", "box"]
+    for lay in layouts:
+        if cpm_validate(params.replace(layout=lay, tile=(0, 0, 0)), n_cells) == CPM_OK:
+            out.append((lay, (0, 0, 0)))
+    if c.attempts == 1:
+        for t0 in (16, 32, 64, 128, 256):
+            t0 = min(t0, na[0])
+            rest = 256 // t0
+            t1 = min(na[1], rest if c.ndim == 2 else max(1, int(round(rest ** 0.5))))
+            t2 = min(na[2], max(1, rest // t1)) if c.ndim == 3 else 1
+            cand = ("in_place", (t0, t1, t2))
+            if cand not in out and cpm_validate(params.replace(layout="in_place", tile=cand[1]), n_cells) == CPM_OK:
+                out.append(cand)
+    return out
+
+
+def autotune(params: Params, lattice, cell_type, act=None, trial_mcs: int = 2, candidates=None, device="cuda"):
+    """Time each candidate (layout, tile) on a copy of the lattice for
+    trial_mcs MCS after one warm-up MCS and return the fastest.  Every
+    candidate must leave the same lattice (results never depend on the
+    layout); a disagreement raises.  Returns {"best": (layout, tile),
+    "times": {(layout, tile): ms per MCS}}."""
+    import hashlib
+    import torch
+    n_cells = len(cell_type) - 1
+    cands = candidates or tuning_candidates(params, n_cells)
+    times, digest = {}, None
+    for lay, tile in cands:
+        p = params.replace(layout=lay, tile=tile)
+        sim = Simulation(p, lattice, cell_type, act, device=device)
+        sim.sweep(1)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        sim.sweep(trial_mcs)
+        e1.record()
+        torch.cuda.synchronize()
+        times[(lay, tuple(tile))] = e0.elapsed_time(e1) / trial_mcs
+        h = hashlib.sha256(sim.lattice.cpu().numpy().tobytes()).hexdigest()
+        if digest is None:
+            digest = h
+        elif h != digest:
+            raise RuntimeError(f"layout {lay} tile {tile} changed the result of the sweep")
+        sim.close()
+    best = min(times, key=times.get)
+    return {"best": best, "times": times}

@@ -35,7 +35,8 @@ struct cpm_handle {
 struct cpm_batch {
     int32_t n = 0;
     int32_t ndim = 0, s = 0, k = 0;
-    bool act = false, mirror = false, single = false, full_rows = false;
+    bool act = false, mirror = false, single = false;
+    int layout = 0;
     std::vector<SweepArgs> args;                     // host copies, one per lattice
     std::vector<int32_t> n_cells;
     std::vector<size_t> site_off, label_off;         // packed offsets of lattices / cell-type arrays
@@ -115,9 +116,17 @@ int32_t chunk_for(const void *base, size_t row_bytes)
 // (full-row LDS layout: every staged row is one aligned lattice row, no row
 // staged twice), growing along y then z up to kBlock areas while the staged
 // rows fit 64 KiB of LDS.  Otherwise a box tile, shrunk until it fits.
-cpm::TileGeometry choose_tiles(const cpm_params *p, bool mirror, bool force_box = false)
+// k = 1 sweeps read the lattice in place (no LDS staging) unless the
+// parameters ask for another layout.
+constexpr bool kDirectForK1 = true;
+constexpr size_t kLdsLimit = 160 * 1024;  // LDS per workgroup on gfx950
+
+// Tile geometry for layout L (0 = halo boxes, 1 = full rows, 2 = in place;
+// -1 = choose), honouring the requested tile (p->tile, 0 = choose).  Returns
+// false when the layout cannot run this model.
+bool tile_geometry(const cpm_params *p, bool mirror, int force_layout, cpm::TileGeometry &g)
 {
-    cpm::TileGeometry g{};
+    g = cpm::TileGeometry{};
     const int s = p->sub, R = p->act_enabled ? 2 : 1;
     const bool act = p->act_enabled != 0;
     const int cell = mirror ? 2 : 4;
@@ -127,77 +136,117 @@ cpm::TileGeometry choose_tiles(const cpm_params *p, bool mirror, bool force_box 
     const size_t budget = 65536;
     int T[3] = {1, 1, 1};
     const int L0 = p->dims[0];
+    const int *want = p->tile;
+    auto finish = [&](int layout) {
+        g.layout = layout;
+        g.n_tiles = 1;
+        for (int d = 0; d < 3; ++d) {
+            g.T[d] = T[d];
+            g.nt[d] = (na[d] + T[d] - 1) / T[d];
+            g.n_tiles *= g.nt[d];
+        }
+        g.tiles_per_xcd = (g.n_tiles + cpm::kXcds - 1) / cpm::kXcds;
+        g.grid = g.tiles_per_xcd * cpm::kXcds;
+        return true;
+    };
+    const bool k1 = p->attempts == 1;
+    if (force_layout < 0) force_layout = k1 && kDirectForK1 ? 2 : -1;
+    if (force_layout == 2) {
+        if (!k1) return false;
+        // in place: tiles of up to kBlock areas, whole rows of areas first
+        T[0] = want[0] ? want[0] : std::min(na[0], cpm::kBlock);
+        T[1] = want[1] ? want[1] : std::min(na[1], cpm::kBlock / T[0]);
+        T[2] = p->ndim == 3 ? (want[2] ? want[2] : std::min(na[2], cpm::kBlock / (T[0] * T[1]))) : 1;
+        g.box_sites = 0;
+        g.lds_bytes = 0;
+        return finish(2);
+    }
     // rows are staged in 16-, 8- or 4-byte chunks: int16 rows are even-length
     // (L0 is a multiple of 2s), activity rows a multiple of 4 bytes (s >= 2)
-    bool full = !force_box && p->attempts == 1 && na[0] <= cpm::kBlock && (L0 * cell) % 4 == 0 &&
-                (!act || L0 % 4 == 0);
-    if (full) {
+    const bool can_rows = k1 && na[0] <= cpm::kBlock && (L0 * cell) % 4 == 0 && (!act || L0 % 4 == 0) &&
+                          (want[0] == 0 || want[0] == na[0]);
+    if (force_layout == 1 || force_layout < 0) {
         auto lds_for = [&](int t1, int t2) {
             const int rows = extent(t1) * (p->ndim == 3 ? extent(t2) : 1);
             return cpm::sweep_lds_bytes(p->ndim, act, mirror, rows * L0);
         };
         T[0] = na[0];
-        if (lds_for(1, 1) > budget) {
-            full = false;
-        } else {
-            while (T[1] < na[1] && T[0] * (T[1] + 1) <= cpm::kBlock && lds_for(T[1] + 1, 1) <= budget) ++T[1];
-            if (p->ndim == 3)
-                while (T[2] < na[2] && T[0] * T[1] * (T[2] + 1) <= cpm::kBlock && lds_for(T[1], T[2] + 1) <= budget)
-                    ++T[2];
+        bool ok = can_rows;
+        if (ok && (want[1] || want[2])) {
+            T[1] = want[1] ? want[1] : 1;
+            T[2] = p->ndim == 3 && want[2] ? want[2] : 1;
+            ok = lds_for(T[1], T[2]) <= kLdsLimit && T[0] * T[1] * T[2] <= cpm::kBlock;
+        } else if (ok) {
+            ok = lds_for(1, 1) <= budget;
+            if (ok) {
+                while (T[1] < na[1] && T[0] * (T[1] + 1) <= cpm::kBlock && lds_for(T[1] + 1, 1) <= budget) ++T[1];
+                if (p->ndim == 3)
+                    while (T[2] < na[2] && T[0] * T[1] * (T[2] + 1) <= cpm::kBlock &&
+                           lds_for(T[1], T[2] + 1) <= budget)
+                        ++T[2];
+            }
+        }
+        if (ok) {
             const int rows = extent(T[1]) * (p->ndim == 3 ? extent(T[2]) : 1);
             g.box_sites = rows * L0;
             g.lds_bytes = (int32_t)lds_for(T[1], T[2]);
+            return finish(1);
         }
+        if (force_layout == 1) return false;
+        T[0] = T[1] = T[2] = 1;
     }
-    if (!full) {
-        // Box tiles: of all tiles of at most kBlock areas whose box fits the
-        // budget, the one that moves the fewest bytes per activation over the
-        // whole lattice, counting every staged row in 128-byte cache lines (halo
-        // overlap, ragged edge tiles and short rows all cost); ties go to
-        // larger tiles.
-        const int t2max = p->ndim == 3 ? std::min(na[2], cpm::kBlock) : 1;
-        double best = -1.0;
-        int best_areas = 0;
-        for (int t0 = 1; t0 <= std::min(na[0], cpm::kBlock); ++t0)
-            for (int t1 = 1; t1 <= std::min(na[1], cpm::kBlock / t0); ++t1)
-                for (int t2 = 1; t2 <= std::min(t2max, cpm::kBlock / (t0 * t1)); ++t2) {
-                    const int e0 = extent(t0), e1 = extent(t1), e2 = p->ndim == 3 ? extent(t2) : 1;
-                    const int box = e0 * e1 * e2;
-                    const size_t bytes = cpm::sweep_lds_bytes(p->ndim, act, mirror, box);
-                    if (bytes > budget && !(t0 == 1 && t1 == 1 && t2 == 1)) continue;
-                    const double tiles = (double)((na[0] + t0 - 1) / t0) * ((na[1] + t1 - 1) / t1) *
-                                         ((na[2] + t2 - 1) / t2);
-                    const double seg = 128.0;
-                    double row = std::ceil(e0 * (double)cell / seg) * seg;
-                    if (act) row += std::ceil(e0 / seg) * seg;
-                    const double cost = tiles * row * e1 * e2;
-                    const int areas = t0 * t1 * t2;
-                    if (best < 0 || cost < best * 0.999 || (cost <= best * 1.001 && areas > best_areas)) {
-                        best = cost;
-                        best_areas = areas;
-                        T[0] = t0, T[1] = t1, T[2] = t2;
-                        g.box_sites = box;
-                        g.lds_bytes = (int32_t)bytes;
-                    }
+    // Box tiles: the requested tile, or of all tiles of at most kBlock areas
+    // whose box fits the budget, the one that moves the fewest bytes per
+    // activation over the whole lattice, counting every staged row in
+    // 128-byte cache lines (halo overlap, ragged edge tiles and short rows all
+    // cost); ties go to larger tiles.
+    if (want[0] || want[1] || want[2]) {
+        T[0] = want[0] ? want[0] : 1;
+        T[1] = want[1] ? want[1] : 1;
+        T[2] = p->ndim == 3 && want[2] ? want[2] : 1;
+        const int box = extent(T[0]) * extent(T[1]) * (p->ndim == 3 ? extent(T[2]) : 1);
+        const size_t bytes = cpm::sweep_lds_bytes(p->ndim, act, mirror, box);
+        if (bytes > kLdsLimit) return false;
+        g.box_sites = box;
+        g.lds_bytes = (int32_t)bytes;
+        return finish(0);
+    }
+    const int t2max = p->ndim == 3 ? std::min(na[2], cpm::kBlock) : 1;
+    double best = -1.0;
+    int best_areas = 0;
+    for (int t0 = 1; t0 <= std::min(na[0], cpm::kBlock); ++t0)
+        for (int t1 = 1; t1 <= std::min(na[1], cpm::kBlock / t0); ++t1)
+            for (int t2 = 1; t2 <= std::min(t2max, cpm::kBlock / (t0 * t1)); ++t2) {
+                const int e0 = extent(t0), e1 = extent(t1), e2 = p->ndim == 3 ? extent(t2) : 1;
+                const int box = e0 * e1 * e2;
+                const size_t bytes = cpm::sweep_lds_bytes(p->ndim, act, mirror, box);
+                if (bytes > budget && !(t0 == 1 && t1 == 1 && t2 == 1)) continue;
+                const double tiles =
+                    (double)((na[0] + t0 - 1) / t0) * ((na[1] + t1 - 1) / t1) * ((na[2] + t2 - 1) / t2);
+                const double seg = 128.0;
+                double row = std::ceil(e0 * (double)cell / seg) * seg;
+                if (act) row += std::ceil(e0 / seg) * seg;
+                const double cost = tiles * row * e1 * e2;
+                const int areas = t0 * t1 * t2;
+                if (best < 0 || cost < best * 0.999 || (cost <= best * 1.001 && areas > best_areas)) {
+                    best = cost;
+                    best_areas = areas;
+                    T[0] = t0, T[1] = t1, T[2] = t2;
+                    g.box_sites = box;
+                    g.lds_bytes = (int32_t)bytes;
                 }
-    }
-    g.full_rows = full ? 1 : 0;
-    g.n_tiles = 1;
-    for (int d = 0; d < 3; ++d) {
-        g.T[d] = T[d];
-        g.nt[d] = (na[d] + T[d] - 1) / T[d];
-        g.n_tiles *= g.nt[d];
-    }
-    g.tiles_per_xcd = (g.n_tiles + cpm::kXcds - 1) / cpm::kXcds;
-    g.grid = g.tiles_per_xcd * cpm::kXcds;
-    return g;
+            }
+    return finish(0);
 }
 
-Layout layout_of(const cpm_params *p, int32_t n_cells, int mirror = -1, bool force_box = false)
+// The layout the parameters ask for (0 in cpm_params = the library's choice).
+int requested_layout(const cpm_params *p) { return p->layout >= 1 && p->layout <= 3 ? p->layout - 1 : -1; }
+
+Layout layout_of(const cpm_params *p, int32_t n_cells, int mirror = -1, int force_layout = -1)
 {
     Layout l{};
     l.mirror_on = mirror < 0 ? use_mirror(n_cells) : mirror != 0;
-    l.tg = choose_tiles(p, l.mirror_on, force_box);
+    tile_geometry(p, l.mirror_on, force_layout >= 0 ? force_layout : requested_layout(p), l.tg);
     l.dlist_cap = l.tg.T[0] * l.tg.T[1] * l.tg.T[2] * p->attempts;
     int64_t n_sites = (int64_t)p->dims[0] * p->dims[1] * p->dims[2];
     size_t off = 0;
@@ -259,6 +308,21 @@ int validate(const cpm_params *p, int32_t n_cells)
     if (p->act_enabled) {
         if (!p->lambda_act || !p->max_act) return fail(CPM_EINVAL, "lambda_act / max_act NULL with act enabled");
         if (p->sub < 2) return fail(CPM_EINVAL, "the Act term reads two sites out: sub must be >= 2");
+    }
+    if (p->layout < 0 || p->layout > 3) return fail(CPM_EINVAL, "layout must be 0..3");
+    {
+        int areas = 1;
+        for (int d = 0; d < 3; ++d) {
+            const int na = d < p->ndim ? p->dims[d] / (2 * p->sub) : 1;
+            if (p->tile[d] < 0 || p->tile[d] > na) return fail(CPM_EINVAL, "tile exceeds the thread areas per axis");
+            areas *= p->tile[d] ? p->tile[d] : 1;
+        }
+        if (areas > cpm::kBlock) return fail(CPM_EINVAL, "a tile holds at most 256 thread areas");
+        if (p->ndim == 2 && p->tile[2] > 1) return fail(CPM_EINVAL, "tile[2] must be 0 or 1 in 2D");
+        if (p->layout >= 2 && p->attempts != 1) return fail(CPM_ENOTSUP, "layouts 2 and 3 need attempts == 1");
+        cpm::TileGeometry g;
+        if (!tile_geometry(p, use_mirror(n_cells), requested_layout(p), g))
+            return fail(CPM_ENOTSUP, "the requested layout / tile does not fit this model");
     }
     const int n = p->n_types;
     const int nnb = n_neighbours(p->ndim);
@@ -425,7 +489,7 @@ int cpm_tile_shape(const cpm_params *params, int32_t n_cells, int32_t *out)
     if (!out) return fail(CPM_EINVAL, "out is NULL");
     const Layout l = layout_of(params, n_cells);
     for (int d = 0; d < 3; ++d) out[d] = l.tg.T[d];
-    out[3] = l.tg.full_rows;
+    out[3] = l.tg.layout;
     out[4] = l.tg.lds_bytes;
     out[5] = l.tg.n_tiles;
     out[6] = l.mirror_on ? 1 : 0;
@@ -611,7 +675,8 @@ struct BatchLayout {
     size_t args, work, mcs, label_off, dims, scratch_v, scratch_s, scratch_c, scratch_ref, total;
     size_t total_labels;
     int grid;
-    bool mirror, full_rows;
+    bool mirror, feasible;
+    int layout;
 };
 
 int validate_batch(const cpm_params *p, int32_t n, const int32_t *n_cells)
@@ -621,8 +686,8 @@ int validate_batch(const cpm_params *p, int32_t n, const int32_t *n_cells)
         const int rc = validate(&p[i], n_cells[i]);
         if (rc != CPM_OK) return rc;
         if (p[i].ndim != p[0].ndim || p[i].sub != p[0].sub || p[i].attempts != p[0].attempts ||
-            (p[i].act_enabled != 0) != (p[0].act_enabled != 0))
-            return fail(CPM_EINVAL, "lattices of a batch must share ndim, sub, attempts and act_enabled");
+            (p[i].act_enabled != 0) != (p[0].act_enabled != 0) || p[i].layout != p[0].layout)
+            return fail(CPM_EINVAL, "lattices of a batch must share ndim, sub, attempts, act_enabled and layout");
     }
     return CPM_OK;
 }
@@ -632,13 +697,19 @@ BatchLayout batch_layout_of(const cpm_params *p, int32_t n, const int32_t *n_cel
     BatchLayout b{};
     b.mirror = true;
     for (int32_t i = 0; i < n; ++i) b.mirror = b.mirror && use_mirror(n_cells[i]);
-    b.full_rows = true;
+    // one kernel variant for the whole batch: the layout every lattice
+    // chooses, else halo boxes (valid for all)
+    b.feasible = true;
+    for (int32_t i = 0; i < n; ++i) b.lat.push_back(layout_of(&p[i], n_cells[i], b.mirror ? 1 : 0));
+    b.layout = b.lat[0].tg.layout;
+    for (int32_t i = 1; i < n; ++i)
+        if (b.lat[i].tg.layout != b.layout) b.layout = 0;
+    if (b.layout == 0)
+        for (int32_t i = 0; i < n; ++i) b.lat[i] = layout_of(&p[i], n_cells[i], b.mirror ? 1 : 0, 0);
     for (int32_t i = 0; i < n; ++i) {
-        b.lat.push_back(layout_of(&p[i], n_cells[i], b.mirror ? 1 : 0));
-        b.full_rows = b.full_rows && b.lat.back().tg.full_rows;
+        cpm::TileGeometry g;
+        b.feasible = b.feasible && tile_geometry(&p[i], b.mirror, b.layout, g);
     }
-    if (!b.full_rows)  // one kernel variant for the whole batch
-        for (int32_t i = 0; i < n; ++i) b.lat[i] = layout_of(&p[i], n_cells[i], b.mirror ? 1 : 0, true);
     b.grid = 0;
     for (const Layout &l : b.lat) b.grid += l.tg.n_tiles;
     size_t off = 0;
@@ -679,7 +750,9 @@ int cpm_batch_workspace_bytes(const cpm_params *params, int32_t n, const int32_t
     const int rc = validate_batch(params, n, n_cells);
     if (rc != CPM_OK) return rc;
     if (!bytes) return fail(CPM_EINVAL, "bytes is NULL");
-    *bytes = batch_layout_of(params, n, n_cells).total;
+    const BatchLayout bl = batch_layout_of(params, n, n_cells);
+    if (!bl.feasible) return fail(CPM_ENOTSUP, "the requested layout / tile does not fit every lattice of the batch");
+    *bytes = bl.total;
     return CPM_OK;
 }
 
@@ -695,6 +768,7 @@ int cpm_batch_init(const cpm_params *params, int32_t n, const int32_t *n_cells, 
     if (params[0].act_enabled && !d_act) return fail(CPM_EINVAL, "act enabled but d_act is NULL");
     if (reinterpret_cast<uintptr_t>(d_workspace) % 256 != 0) return fail(CPM_EINVAL, "workspace not 256-byte aligned");
     const BatchLayout bl = batch_layout_of(params, n, n_cells);
+    if (!bl.feasible) return fail(CPM_ENOTSUP, "the requested layout / tile does not fit every lattice of the batch");
     if (workspace_bytes < bl.total) return fail(CPM_ENOMEM, "workspace smaller than cpm_batch_workspace_bytes()");
 
     std::unique_ptr<cpm_batch> b(new (std::nothrow) cpm_batch());
@@ -705,7 +779,7 @@ int cpm_batch_init(const cpm_params *params, int32_t n, const int32_t *n_cells, 
     b->k = params[0].attempts;
     b->act = params[0].act_enabled != 0;
     b->mirror = bl.mirror;
-    b->full_rows = bl.full_rows;
+    b->layout = bl.layout;
     b->lattices = d_lattices;
     b->act_field = d_act;
     size_t sites = 0, labels = 0;
@@ -782,7 +856,7 @@ int cpm_batch_init(const cpm_params *params, int32_t n, const int32_t *n_cells, 
     L.mirror = b->mirror;
     L.single = b->single;
     L.k1 = b->k == 1;
-    L.full_rows = b->full_rows;
+    L.layout = b->layout;
     *out = b.release();
     return CPM_OK;
 }

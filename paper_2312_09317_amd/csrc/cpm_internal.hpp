@@ -57,7 +57,7 @@ struct TileGeometry {
     int32_t grid;          // workgroups launched: kXcds * tiles_per_xcd
     int32_t box_sites;     // LDS sites of the largest staged box
     int32_t lds_bytes;
-    int32_t full_rows;     // 1: tiles span whole rows along x (full-row LDS layout)
+    int32_t layout;        // 0: halo boxes in LDS; 1: whole rows along x in LDS; 2: no staging (in place)
     int32_t row_chunk;     // bytes per load when staging label rows (16, 8 or 4)
     int32_t act_chunk;     // bytes per load when staging activity rows
 };
@@ -94,7 +94,8 @@ struct BatchLaunch {
     int grid;
     size_t lds;
     int ndim;
-    bool act, mirror, single, k1, full_rows;
+    bool act, mirror, single, k1;
+    int layout;
 };
 
 // Per-lattice tables for the summary statistics of a batch (device arrays).

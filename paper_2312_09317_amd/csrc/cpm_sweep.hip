@@ -51,22 +51,30 @@ __host__ __device__ constexpr int align16(int v) { return (v + 15) & ~15; }
 
 constexpr int kQueue = 128;  // queued attempts per workgroup; the rest are evaluated where drawn
 
-// Where a lattice site lives in LDS.  Full-row layout: x is the global
-// coordinate and wraps; box layout: x is box-local.  y, z are box-local.
-template <bool FULLROW>
+// Where the sites an attempt reads live.  kBox: an LDS box, coordinates
+// box-local; kFullRow: LDS rows spanning the lattice along x, x global and
+// wrapping, y, z box-local; kDirect: the lattice itself in global memory,
+// every coordinate global and wrapping.
+enum Layout { kBox = 0, kFullRow = 1, kDirect = 2 };
+
+template <int LAYOUT>
 struct LdsMap {
-    int pitch;  // sites per LDS row
-    int rows;   // LDS rows per z plane
-    int L0;
-    __device__ __forceinline__ int x(int v) const { return FULLROW ? wrap_once(v, L0) : v; }
-    __device__ __forceinline__ int at(int vx, int vy, int vz) const { return x(vx) + pitch * (vy + rows * vz); }
+    int pitch;  // sites per row
+    int rows;   // rows per z plane
+    int L0, L1, L2;
+    __device__ __forceinline__ int x(int v) const { return LAYOUT == kBox ? v : wrap_once(v, L0); }
+    __device__ __forceinline__ int row(int vy, int vz) const
+    {
+        return LAYOUT == kDirect ? L0 * (wrap_once(vy, L1) + L1 * wrap_once(vz, L2)) : pitch * (vy + rows * vz);
+    }
+    __device__ __forceinline__ int at(int vx, int vy, int vz) const { return x(vx) + row(vy, vz); }
 };
 
 // Geometric mean of the activity over the site at (x,y,z) (label `cell`) and
 // its Moore neighbours of the same cell (eq. 8), 2^16 fixed point.
-template <typename Cell, int D, bool FULLROW>
+template <typename Cell, int D, int LAYOUT>
 __device__ __forceinline__ int64_t gm_lds(const DeviceModel *m, const int64_t *lg, const Cell *lab,
-                                          const uint8_t *lact, const LdsMap<FULLROW> &map, int x, int y, int z,
+                                          const uint8_t *lact, const LdsMap<LAYOUT> &map, int x, int y, int z,
                                           int cell, bool motile)
 {
     if (cell <= 0 || !motile) return 0;
@@ -126,10 +134,10 @@ struct SharedTables {
     const int64_t *lg;
 };
 
-template <typename Cell, int D, bool ACT, bool SINGLE, bool FULLROW>
+template <typename Cell, int D, bool ACT, bool SINGLE, int LAYOUT>
 __device__ __forceinline__ bool evaluate(const SweepArgs &a, const ThrTables &tb, const JRows &jr,
                                          const SharedTables &st, Cell *lab,
-                                         uint8_t *lact, const LdsMap<FULLROW> &map, int tx_, int ty_, int tz_,
+                                         uint8_t *lact, const LdsMap<LAYOUT> &map, int tx_, int ty_, int tz_,
                                          int sx_, int sy_, int sz_, int lt, int ls, int2 cnt_t, int2 cnt_s,
                                          uint32_t u2, int64_t &dso_out, int64_t &dsn_out)
 {
@@ -146,7 +154,7 @@ __device__ __forceinline__ bool evaluate(const SweepArgs &a, const ThrTables &tb
     for (int n = 0; n < NNB; ++n) {
         const int dx = nb_dx<D>(n);
         const int xx = dx < 0 ? xm : (dx > 0 ? xp : x0);
-        const int lu = lab[xx + map.pitch * (ty_ + nb_dy<D>(n) + map.rows * (tz_ + nb_dz<D>(n)))];
+        const int lu = lab[xx + map.row(ty_ + nb_dy<D>(n), tz_ + nb_dz<D>(n))];
         k_old += lu == lt;
         k_new += lu == ls;
         if (SINGLE) {
@@ -178,9 +186,9 @@ __device__ __forceinline__ bool evaluate(const SweepArgs &a, const ThrTables &tb
         q += m->lam_s[ts] * (2 * dsn * ((int64_t)cnt_s.y - m->s_target[ts]) + dsn * dsn);
     }
     if (ACT) {
-        const int64_t gt = gm_lds<Cell, D, FULLROW>(m, st.lg, lab, lact, map, tx_, ty_, tz_, lt,
+        const int64_t gt = gm_lds<Cell, D, LAYOUT>(m, st.lg, lab, lact, map, tx_, ty_, tz_, lt,
                                                     lt > 0 && m->max_act[tt] > 0);
-        const int64_t gs = gm_lds<Cell, D, FULLROW>(m, st.lg, lab, lact, map, sx_, sy_, sz_, ls,
+        const int64_t gs = gm_lds<Cell, D, LAYOUT>(m, st.lg, lab, lact, map, sx_, sy_, sz_, ls,
                                                     ls > 0 && m->max_act[ts] > 0);
         const int64_t rt = lt >= 1 ? m->r_act[tt] : 0;
         const int64_t rs = ls >= 1 ? m->r_act[ts] : 0;
@@ -206,7 +214,7 @@ __device__ __forceinline__ int2 seen_counters(const int32_t *rd, int c, const in
 }
 
 // One workgroup's share of one activation: tile `tile` of the lattice `a`.
-template <typename Cell, int D, bool ACT, bool SINGLE, bool K1, bool FULLROW>
+template <typename Cell, int D, bool ACT, bool SINGLE, bool K1, int LAYOUT>
 __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_t mcs, uint32_t alpha, int parity)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -231,17 +239,19 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
     const int A0 = tx * tg.T[0], A1 = ty * tg.T[1], A2 = tz * tg.T[2];
     const int n0 = min(tg.T[0], a.na[0] - A0), n1 = min(tg.T[1], a.na[1] - A1);
     const int n2 = D == 3 ? min(tg.T[2], a.na[2] - A2) : 1;
-    // staged box: sub-areas of the active colour plus the read halo
+    constexpr bool FULLROW = LAYOUT == kFullRow, DIRECT = LAYOUT == kDirect;
+    // staged box: sub-areas of the active colour plus the read halo (none
+    // for the direct layout, which reads the lattice in place)
     const int b0 = FULLROW ? L0 : 2 * s * (n0 - 1) + s + 2 * R;
     const int b1 = 2 * s * (n1 - 1) + s + 2 * R;
     const int b2 = D == 3 ? 2 * s * (n2 - 1) + s + 2 * R : 1;
-    const int o0 = FULLROW ? 0 : 2 * s * A0 + s * cx - R;
-    const int o1 = 2 * s * A1 + s * cy - R;
-    const int o2 = D == 3 ? 2 * s * A2 + s * cz - R : 0;
-    const LdsMap<FULLROW> map{b0, b1, L0};
-    Cell *lab = reinterpret_cast<Cell *>(smem);
-    uint8_t *lact = smem + align16(tg.box_sites * (int)sizeof(Cell));
+    const int o0 = FULLROW || DIRECT ? 0 : 2 * s * A0 + s * cx - R;
+    const int o1 = DIRECT ? 0 : 2 * s * A1 + s * cy - R;
+    const int o2 = D == 3 && !DIRECT ? 2 * s * A2 + s * cz - R : 0;
+    const LdsMap<LAYOUT> map{DIRECT ? L0 : b0, DIRECT ? L1 : b1, L0, L1, L2};
     Cell *cells = reinterpret_cast<Cell *>(a.cells);
+    Cell *lab = DIRECT ? cells : reinterpret_cast<Cell *>(smem);
+    uint8_t *lact = DIRECT ? a.act : smem + align16(tg.box_sites * (int)sizeof(Cell));
     const int32_t *rd = a.counters[parity];
     int32_t *wr = a.counters[parity ^ 1];
     int4 *dl = a.dlist + (size_t)tile * a.dlist_cap;
@@ -278,9 +288,9 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
         const uint32_t o = (uint32_t)(((uint64_t)u.x * sd) >> 32);
         const int q1 = (int)by_s.div(o), ox = (int)o - q1 * s;
         const int oz = D == 3 ? (int)by_s.div((uint32_t)q1) : 0, oy = q1 - oz * s;
-        ttx = FULLROW ? 2 * s * ax + s * cx + ox : 2 * s * ax + R + ox;
-        tty = 2 * s * ay + R + oy;
-        ttz = D == 3 ? 2 * s * az + R + oz : 0;
+        ttx = DIRECT ? 2 * s * (A0 + ax) + s * cx + ox : (FULLROW ? 2 * s * ax + s * cx + ox : 2 * s * ax + R + ox);
+        tty = DIRECT ? 2 * s * (A1 + ay) + s * cy + oy : 2 * s * ay + R + oy;
+        ttz = D == 3 ? (DIRECT ? 2 * s * (A2 + az) + s * cz + oz : 2 * s * az + R + oz) : 0;
         const int nsel = (int)(((uint64_t)u.y * (uint32_t)NNB) >> 32);
         const int msel = nsel < NNB / 2 ? nsel : nsel + 1;
         ssx = ttx + msel % 3 - 1;
@@ -289,18 +299,19 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
         u2 = u.z;
     };
     auto global_index = [&](int vx, int vy, int vz) {
+        if (DIRECT) return map.at(vx, vy, vz);
         const int gx = FULLROW ? wrap_once(vx, L0) : wrap_once(o0 + vx, L0);
         const int gy = wrap_once(o1 + vy, L1);
         const int gz = D == 3 ? wrap_once(o2 + vz, L2) : 0;
         return (int)(((size_t)gz * L1 + gy) * L0 + gx);
     };
     auto commit = [&](int t, int gi, int lt, int ls, int64_t dso, int64_t dsn) {
-        lab[t] = (Cell)ls;
+        if (!DIRECT) lab[t] = (Cell)ls;
         cells[gi] = (Cell)ls;
         if (ACT) {
             const int ts = ls == 0 ? 0 : (a.single_type >= 0 ? a.single_type : a.cell_type[ls]);
             const uint8_t na = (ls >= 1 && a.model->max_act[ts] > 0) ? (uint8_t)a.model->max_act[ts] : (uint8_t)0;
-            lact[t] = na;
+            if (!DIRECT) lact[t] = na;
             a.act[gi] = na;
         }
         const int4 rec = make_int4(lt, ls, (int)dso, (int)dsn);
@@ -333,7 +344,10 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
 
     // stage the box (labels, and activity for the Act term)
     const int rows = b1 * b2;
-    if (FULLROW) {
+    if (DIRECT) {
+        // nothing to stage: attempts read the lattice in place (no other
+        // attempt of this activation writes a site that one reads)
+    } else if (FULLROW) {
         // whole rows in the widest chunks (16, 8 or 4 bytes) that tile a row,
         // eight loads in flight per thread
         const FastDiv by_b1((uint32_t)b1);
@@ -446,7 +460,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
             } else {
                 // queue full: evaluate here (no other attempt reads this sub-area)
                 int64_t dso, dsn;
-                if (evaluate<Cell, D, ACT, SINGLE, FULLROW>(a, tb, jr, sht, lab, lact, map, d_ttx, d_tty, d_ttz, d_ssx,
+                if (evaluate<Cell, D, ACT, SINGLE, LAYOUT>(a, tb, jr, sht, lab, lact, map, d_ttx, d_tty, d_ttz, d_ssx,
                                                             d_ssy, d_ssz, d_lt, d_ls, d_ct, d_cs, d_u2, dso, dsn)) {
                     ++my_accepted;
                     commit(map.at(d_ttx, d_tty, d_ttz), global_index(d_ttx, d_tty, d_ttz), d_lt, d_ls, dso, dsn);
@@ -464,7 +478,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
             const int t = map.at(ttx, tty, ttz);
             const int lt = lab[t], ls = lab[map.at(ssx, ssy, ssz)];
             int64_t dso, dsn;
-            if (evaluate<Cell, D, ACT, SINGLE, FULLROW>(a, tb, jr, sht, lab, lact, map, ttx, tty, ttz, ssx, ssy, ssz, lt,
+            if (evaluate<Cell, D, ACT, SINGLE, LAYOUT>(a, tb, jr, sht, lab, lact, map, ttx, tty, ttz, ssx, ssy, ssz, lt,
                                                         ls, make_int2(c.x, c.y), make_int2(c.z, c.w), (uint32_t)e.w,
                                                         dso, dsn)) {
                 ++my_accepted;
@@ -486,7 +500,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
                 if (lt != ls && lt >= 0 && ls >= 0) {
                     ++my_nontrivial;
                     int64_t dso, dsn;
-                    if (evaluate<Cell, D, ACT, SINGLE, FULLROW>(a, tb, jr, sht, lab, lact, map, ttx, tty, ttz, ssx, ssy,
+                    if (evaluate<Cell, D, ACT, SINGLE, LAYOUT>(a, tb, jr, sht, lab, lact, map, ttx, tty, ttz, ssx, ssy,
                                                                 ssz, lt, ls, seen_counters(rd, lt, own, j),
                                                                 seen_counters(rd, ls, own, j), u2, dso, dsn)) {
                         ++my_accepted;
@@ -511,43 +525,46 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
 
 // One lattice: workgroup b takes tile (b mod 8) * tiles_per_xcd + b div 8, so
 // each XCD sweeps one contiguous slab of tiles in every activation.
-template <typename Cell, int D, bool ACT, bool SINGLE, bool K1, bool FULLROW>
+template <typename Cell, int D, bool ACT, bool SINGLE, bool K1, int LAYOUT>
 __global__ void __launch_bounds__(kBlock) tile_sweep_kernel(SweepArgs a, uint32_t mcs, uint32_t alpha, int parity)
 {
     const int tile = (int)(blockIdx.x % kXcds) * a.tg.tiles_per_xcd + (int)(blockIdx.x / kXcds);
     if (tile >= a.tg.n_tiles) return;  // uniform over the block
-    sweep_tile<Cell, D, ACT, SINGLE, K1, FULLROW>(a, tile, mcs, alpha, parity);
+    sweep_tile<Cell, D, ACT, SINGLE, K1, LAYOUT>(a, tile, mcs, alpha, parity);
 }
 
 // Many lattices advanced together: work[b] = (lattice, tile) of workgroup b;
 // all lattices share the MCS counter at *mcs.
-template <typename Cell, int D, bool ACT, bool SINGLE, bool K1, bool FULLROW>
+template <typename Cell, int D, bool ACT, bool SINGLE, bool K1, int LAYOUT>
 __global__ void __launch_bounds__(kBlock) batch_sweep_kernel(const SweepArgs *args, const int2 *work,
                                                              const uint32_t *mcs, uint32_t alpha, int parity)
 {
     const int2 w = work[blockIdx.x];
-    sweep_tile<Cell, D, ACT, SINGLE, K1, FULLROW>(args[w.x], w.y, *mcs, alpha, parity);
+    sweep_tile<Cell, D, ACT, SINGLE, K1, LAYOUT>(args[w.x], w.y, *mcs, alpha, parity);
 }
 
 template <typename Cell, int D, bool ACT, bool SINGLE>
-hipError_t launch_k(const SweepArgs &a, bool k1, bool fullrow, uint32_t mcs, uint32_t alpha, int parity, size_t lds,
+hipError_t launch_k(const SweepArgs &a, bool k1, int layout, uint32_t mcs, uint32_t alpha, int parity, size_t lds,
                     hipStream_t st)
 {
-    if (k1 && fullrow)
-        tile_sweep_kernel<Cell, D, ACT, SINGLE, true, true><<<a.tg.grid, kBlock, lds, st>>>(a, mcs, alpha, parity);
+    if (k1 && layout == kDirect)
+        tile_sweep_kernel<Cell, D, ACT, SINGLE, true, kDirect><<<a.tg.grid, kBlock, lds, st>>>(a, mcs, alpha, parity);
+    else if (k1 && layout == kFullRow)
+        tile_sweep_kernel<Cell, D, ACT, SINGLE, true, kFullRow><<<a.tg.grid, kBlock, lds, st>>>(a, mcs, alpha, parity);
     else if (k1)
-        tile_sweep_kernel<Cell, D, ACT, SINGLE, true, false><<<a.tg.grid, kBlock, lds, st>>>(a, mcs, alpha, parity);
+        tile_sweep_kernel<Cell, D, ACT, SINGLE, true, kBox><<<a.tg.grid, kBlock, lds, st>>>(a, mcs, alpha, parity);
     else
-        tile_sweep_kernel<Cell, D, ACT, SINGLE, false, false><<<a.tg.grid, kBlock, lds, st>>>(a, mcs, alpha, parity);
+        tile_sweep_kernel<Cell, D, ACT, SINGLE, false, kBox><<<a.tg.grid, kBlock, lds, st>>>(a, mcs, alpha, parity);
     return hipGetLastError();
 }
 
 template <typename Cell, int D, bool ACT>
 hipError_t launch_s(const SweepArgs &a, uint32_t mcs, uint32_t alpha, int parity, size_t lds, hipStream_t st)
 {
-    const bool k1 = a.k == 1, fr = a.tg.full_rows != 0;
-    return a.single_type >= 0 ? launch_k<Cell, D, ACT, true>(a, k1, fr, mcs, alpha, parity, lds, st)
-                              : launch_k<Cell, D, ACT, false>(a, k1, fr, mcs, alpha, parity, lds, st);
+    const bool k1 = a.k == 1;
+    const int layout = a.tg.layout;
+    return a.single_type >= 0 ? launch_k<Cell, D, ACT, true>(a, k1, layout, mcs, alpha, parity, lds, st)
+                              : launch_k<Cell, D, ACT, false>(a, k1, layout, mcs, alpha, parity, lds, st);
 }
 
 template <typename Cell>
@@ -642,12 +659,14 @@ namespace {
 template <typename Cell, int D, bool ACT, bool SINGLE>
 hipError_t launch_batch_k(const BatchLaunch &b, uint32_t alpha, int parity, hipStream_t st)
 {
-    if (b.k1 && b.full_rows)
-        batch_sweep_kernel<Cell, D, ACT, SINGLE, true, true><<<b.grid, kBlock, b.lds, st>>>(b.args, b.work, b.mcs, alpha, parity);
+    if (b.k1 && b.layout == kDirect)
+        batch_sweep_kernel<Cell, D, ACT, SINGLE, true, kDirect><<<b.grid, kBlock, b.lds, st>>>(b.args, b.work, b.mcs, alpha, parity);
+    else if (b.k1 && b.layout == kFullRow)
+        batch_sweep_kernel<Cell, D, ACT, SINGLE, true, kFullRow><<<b.grid, kBlock, b.lds, st>>>(b.args, b.work, b.mcs, alpha, parity);
     else if (b.k1)
-        batch_sweep_kernel<Cell, D, ACT, SINGLE, true, false><<<b.grid, kBlock, b.lds, st>>>(b.args, b.work, b.mcs, alpha, parity);
+        batch_sweep_kernel<Cell, D, ACT, SINGLE, true, kBox><<<b.grid, kBlock, b.lds, st>>>(b.args, b.work, b.mcs, alpha, parity);
     else
-        batch_sweep_kernel<Cell, D, ACT, SINGLE, false, false><<<b.grid, kBlock, b.lds, st>>>(b.args, b.work, b.mcs, alpha, parity);
+        batch_sweep_kernel<Cell, D, ACT, SINGLE, false, kBox><<<b.grid, kBlock, b.lds, st>>>(b.args, b.work, b.mcs, alpha, parity);
     return hipGetLastError();
 }
 

@@ -209,3 +209,41 @@ def test_tissue_full_size_properties(torch_cuda):
     assert int(act[~on_motile].max()) == 0
     assert int((act > 0).sum()) > 0
     assert int(v[1:].sum()) + int((sim.lattice == 0).sum()) + int(obst.sum()) == sim.lattice.numel()
+
+
+def _layout_cases():
+    w3 = inputs.config1(L=48, grid=5, n_mcs=2)
+    wa2 = _multi((32, 24, 1), 2, 41, act=True)
+    wa3 = _multi((16, 12, 12), 3, 42, act=True)
+    wm3 = _multi((16, 16, 8), 3, 43)
+    return [("config1-48", w3), ("act-2d", wa2), ("act-3d", wa3), ("multi-3d", wm3)]
+
+
+@pytest.mark.parametrize("layout,tile", [("box", (0, 0, 0)), ("full_rows", (0, 0, 0)), ("in_place", (0, 0, 0)),
+                                         ("in_place", (3, 2, 1)), ("box", (2, 3, 1))])
+def test_every_layout_matches_oracle(torch_cuda, layout, tile):
+    # the layout and tile shape change how a sweep is staged, never its result
+    for name, w in _layout_cases():
+        t = tile if w.ndim == 3 or tile[2] <= 1 else (tile[0], tile[1], 1)
+        p = cpm.Params.from_workload(w, layout=layout, tile=t)
+        if cpm.cpm_validate(p, w.n_cells) != cpm.CPM_OK:
+            _say(f"{name}: layout {layout} tile {t} does not fit; skipped")
+            continue
+        _say(f"{name}: layout {layout} tile {t} -> {cpm.cpm_tile_shape(p, w.n_cells)}")
+        st = oracle.State(oracle_model(w), w.lattice, w.cell_type, w.act)
+        st.sweep(2)
+        sim = cpm.Simulation(p, w.lattice, w.cell_type, w.act)
+        sim.sweep(2)
+        torch_cuda.cuda.synchronize()
+        assert_same(st, sim, torch_cuda)
+        sim.close()
+
+
+def test_autotune_agrees_and_picks(torch_cuda):
+    w = inputs.config1(L=48, grid=5, n_mcs=2)
+    r = cpm.autotune(cpm.Params.from_workload(w), w.lattice, w.cell_type, trial_mcs=2)
+    _say(f"autotune: {r}")
+    assert len(r["times"]) >= 2
+    assert r["best"] in r["times"]
+    p = cpm.Params.from_workload(w, layout=r["best"][0], tile=r["best"][1])
+    assert cpm.cpm_validate(p, w.n_cells) == cpm.CPM_OK
