@@ -103,6 +103,7 @@ def main():
                          "runs and judge it against fresh ones")
     ap.add_argument("--layout", default="tune", choices=("tune", "auto", "box", "full_rows", "in_place"),
                     help="sweep layout: tune = time the candidates first and take the fastest (default)")
+    ap.add_argument("--tune-mcs", type=int, default=6, help="MCS timed per candidate layout when tuning")
     ap.add_argument("--emu-train", type=int, default=8192, help="emulator workload: training runs")
     ap.add_argument("--emu-test", type=int, default=256, help="emulator workload: held-out points")
     ap.add_argument("--emu-reps", type=int, default=8, help="emulator workload: replicates per held-out point")
@@ -208,7 +209,7 @@ def choose_layout(args, cpm, params, w):
     """The sweep layout: timed candidates (--layout tune) or the one named."""
     if args.layout != "tune":
         return params.replace(layout=args.layout), None
-    r = cpm.autotune(params, w.lattice, w.cell_type, w.act, trial_mcs=2)
+    r = cpm.autotune(params, w.lattice, w.cell_type, w.act, trial_mcs=args.tune_mcs)
     log("autotune (ms per MCS): " + ", ".join(f"{k[0]}{list(k[1])}: {v:.3f}" for k, v in sorted(r["times"].items(), key=lambda kv: kv[1])))
     lay, tile = r["best"]
     return params.replace(layout=lay, tile=tile), {f"{k[0]}{list(k[1])}": round(v, 4) for k, v in r["times"].items()}

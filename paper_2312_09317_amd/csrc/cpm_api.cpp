@@ -258,8 +258,8 @@ Layout layout_of(const cpm_params *p, int32_t n_cells, int mirror = -1, int forc
     l.model = take(sizeof(DeviceModel));
     l.counters0 = take(sizeof(int32_t) * 2 * ((size_t)n_cells + 1));
     l.counters1 = take(sizeof(int32_t) * 2 * ((size_t)n_cells + 1));
-    l.dlist = take(sizeof(int4) * (size_t)l.tg.n_tiles * (size_t)l.dlist_cap);
-    l.dcount = take(sizeof(int32_t) * (size_t)l.tg.n_tiles);
+    l.dlist = take(2 * sizeof(int4) * (size_t)l.tg.n_tiles * (size_t)l.dlist_cap);
+    l.dcount = take(2 * sizeof(int32_t) * (size_t)l.tg.n_tiles);
     l.stats = take(sizeof(uint64_t) * 2 * (size_t)l.tg.n_tiles);
     l.ref = take(sizeof(int32_t) * ((size_t)n_cells + 1));
     l.mirror = take(l.mirror_on ? sizeof(int16_t) * (size_t)n_sites : 0);
@@ -427,8 +427,10 @@ void fill_args(SweepArgs &a, const cpm_params *p, const Layout &lay, char *ws, i
     a.model = reinterpret_cast<const DeviceModel *>(ws + lay.model);
     a.counters[0] = reinterpret_cast<int32_t *>(ws + lay.counters0);
     a.counters[1] = reinterpret_cast<int32_t *>(ws + lay.counters1);
-    a.dlist = reinterpret_cast<int4 *>(ws + lay.dlist);
-    a.dcount = reinterpret_cast<int32_t *>(ws + lay.dcount);
+    a.dlist[0] = reinterpret_cast<int4 *>(ws + lay.dlist);
+    a.dlist[1] = a.dlist[0] + (size_t)lay.tg.n_tiles * (size_t)lay.dlist_cap;
+    a.dcount[0] = reinterpret_cast<int32_t *>(ws + lay.dcount);
+    a.dcount[1] = a.dcount[0] + lay.tg.n_tiles;
     a.stats = reinterpret_cast<uint64_t *>(ws + lay.stats);
     uint32_t n_areas = 1;
     for (int d = 0; d < 3; ++d) {
@@ -458,7 +460,7 @@ hipError_t start_lattice(const SweepArgs &a, const Layout &lay, char *ws, const 
     if (e != hipSuccess) return e;
     const size_t pairs = 2 * ((size_t)n_cells + 1);
     if ((e = cpm::launch_fill_i32(a.counters[0], 0, pairs, st)) != hipSuccess) return e;
-    if ((e = cpm::launch_fill_i32(a.dcount, 0, (size_t)lay.tg.n_tiles, st)) != hipSuccess) return e;
+    if ((e = cpm::launch_fill_i32(a.dcount[0], 0, 2 * (size_t)lay.tg.n_tiles, st)) != hipSuccess) return e;
     if ((e = cpm::launch_fill_i32(reinterpret_cast<int32_t *>(a.stats), 0, 4 * (size_t)lay.tg.n_tiles, st)) != hipSuccess)
         return e;
     if ((e = cpm::launch_count(a, ndim, a.counters[0], a.counters[0] + 1, 2, st)) != hipSuccess) return e;

@@ -70,8 +70,8 @@ struct SweepArgs {
     uint8_t *act;
     const DeviceModel *model;
     int32_t *counters[2];  // ping-pong (V, S) pairs per label
-    int4 *dlist;           // per tile: accepted copies of the previous activation
-    int32_t *dcount;       // per tile: number of records in dlist
+    int4 *dlist[2];        // per tile: accepted copies of an activation, by activation parity
+    int32_t *dcount[2];    // per tile: number of records in dlist[parity]
     uint64_t *stats;       // per tile: attempts past the early rejection, accepted copies
     int32_t L[3];
     int32_t na[3];         // thread areas per axis
