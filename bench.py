@@ -32,19 +32,19 @@ HBM_PEAK_GBS = 8000.0
 # counters read for a plain 256 MiB copy (FETCH x 2.0, WRITE x 1.0), for the
 # kernel sources whose sha256 prefix is given; reported only while the
 # sources are unchanged.
-MEASURED_TRAFFIC = {"sources_sha256": "30482d7eb7f27103", "fetch_kib": 16699.2, "write_kib": 1144.3,
-                    "fetch_scale": 2.0, "write_scale": 1.0}
+MEASURED_TRAFFIC = {"sources_sha256": "34ad273778b4029f", "layout": "in_place", "fetch_kib": 17141.5,
+                    "write_kib": 1117.0, "fetch_scale": 2.0, "write_scale": 1.0}
 KERNEL_SOURCES = ("cpm_sweep.hip", "cpm_device.hpp", "cpm_internal.hpp")
 
 
-def measured_traffic_bytes():
+def measured_traffic_bytes(layout=None):
     import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2312_09317_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     t = MEASURED_TRAFFIC
-    if h.hexdigest()[:16] != t["sources_sha256"]:
+    if h.hexdigest()[:16] != t["sources_sha256"] or (layout is not None and layout != t["layout"]):
         return None
     return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0
 
@@ -196,7 +196,7 @@ def main():
                    "temperature": w.T, "seed": w.seed, "tiling": cpm.cpm_tile_shape(params, w.n_cells),
                    "tuning_ms_per_mcs": tuning},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic_bytes(),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic_bytes(cpm.cpm_tile_shape(params, w.n_cells)["layout"]),
                      "kernel": "tile_sweep_kernel", "avg_launch_us": avg_launch_s * 1e6,
                      "bytes_per_attempt": bytes_per_attempt(w.ndim, w.s, w.k, p_acc)},
         "cpu_baseline": {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")} if cpu else None,
