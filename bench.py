@@ -107,7 +107,11 @@ def main():
     ap.add_argument("--emu-train", type=int, default=8192, help="emulator workload: training runs")
     ap.add_argument("--emu-test", type=int, default=256, help="emulator workload: held-out points")
     ap.add_argument("--emu-reps", type=int, default=8, help="emulator workload: replicates per held-out point")
-    ap.add_argument("--emu-epochs", type=int, default=300)
+    ap.add_argument("--emu-epochs", type=int, default=2000)
+    ap.add_argument("--emu-data", default=None, help="emulator workload: .npz of the study's CPM runs "
+                    "(written if missing, reused if present)")
+    ap.add_argument("--emu-lr", type=float, default=1e-3)
+    ap.add_argument("--emu-batch", type=int, default=256)
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="only run a plain device copy of this many bytes, 5 times (calibrates "
                          "the HBM byte counters of a profiler against a known traffic)")
@@ -310,7 +314,8 @@ def bench_emulator(args):
     against fresh CPM replicates, with the cost per parameter point of each."""
     from paper_2312_09317_amd import emulator
     r = emulator.study(n_train=args.emu_train, n_test=args.emu_test, reps=args.emu_reps, epochs=args.emu_epochs,
-                       log=log)
+                       batch=args.emu_batch, lr=args.emu_lr, lr_final=args.emu_lr / 40, log=log,
+                       data_path=args.emu_data)
     print(json.dumps({
         "metric": "emulator vs CPM cost per parameter point", "value": r["cost_ratio"], "unit": "x",
         "n_gpus": 1, "steps": args.emu_epochs, "warmup": 0, "ms_per_step": None, "higher_is_better": True,

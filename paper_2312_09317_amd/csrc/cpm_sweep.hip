@@ -84,11 +84,14 @@ __device__ __forceinline__ int64_t gm_lds(const DeviceModel *m, const int64_t *l
     uint32_t cnt = 1;
     bool zero = a0 == 0;
     constexpr int NNB = D == 2 ? 8 : 26;
+    // every label and activity of the neighbourhood is loaded before any is
+    // used, so the in-place layout reads them in one round
 #pragma unroll
     for (int n = 0; n < NNB; ++n) {
         const int u = map.at(x + nb_dx<D>(n), y + nb_dy<D>(n), z + nb_dz<D>(n));
-        if ((int)lab[u] == cell) {
-            const uint32_t au = lact[u];
+        const int lu = (int)lab[u];
+        const uint32_t au = lact[u];
+        if (lu == cell) {
             zero |= au == 0;
             sum += (uint64_t)lg[au];
             ++cnt;

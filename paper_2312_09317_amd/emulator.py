@@ -183,7 +183,7 @@ def inference_seconds_per_point(sur, x, n_points=65536, repeats=20):
 
 
 def study(n_train=8192, n_test=256, reps=8, plan=RunPlan(), L_min=64, L_max=512, epochs=300, batch=512,
-          lr=2e-3, lr_final=5e-5, seed=1, log=None):
+          lr=2e-3, lr_final=5e-5, seed=1, log=None, data_path=None):
     """Train the emulator on n_train single CPM runs and judge it on n_test
     fresh parameter points against the mean of `reps` fresh CPM replicates
     each (new Philox seeds).  Returns per-statistic median relative errors
@@ -193,11 +193,25 @@ def study(n_train=8192, n_test=256, reps=8, plan=RunPlan(), L_min=64, L_max=512,
     say = log or (lambda m: None)
     train_pts = points(n_train, seed, L_min, L_max)
     test_pts = points(n_test, seed + 1000, L_min, L_max)
-    t_train, cpm_s = simulate(train_pts, plan, log=say)
+    import os
+    if data_path and os.path.exists(data_path):
+        # the same study's CPM runs, saved earlier (they depend only on the
+        # points, seeds and plan, which are checked)
+        d = np.load(data_path)
+        key = np.array([n_train, n_test, reps, plan.burn_in, plan.n_samples, plan.interval, L_min, L_max, seed])
+        if not np.array_equal(d["key"], key):
+            raise ValueError(f"{data_path} holds another study's runs")
+        t_train, rep, cpm_s = d["t_train"], d["rep"], float(d["cpm_s"])
+        say(f"loaded {n_train} training runs and {n_test} x {reps} test runs from {data_path}")
+    else:
+        t_train, cpm_s = simulate(train_pts, plan, log=say)
+        say(f"training set: {n_train} runs, {cpm_s:.2f} s GPU")
+        rep = np.stack([simulate(reseed(test_pts, seed + 2000 + r), plan)[0] for r in range(reps)])
+        say(f"test set: {n_test} points x {reps} replicates")
+        if data_path:
+            key = np.array([n_train, n_test, reps, plan.burn_in, plan.n_samples, plan.interval, L_min, L_max, seed])
+            np.savez(data_path, key=key, t_train=t_train, rep=rep, cpm_s=cpm_s)
     cpm_per_point = cpm_s / n_train
-    say(f"training set: {n_train} runs, {cpm_s:.2f} s GPU")
-    rep = np.stack([simulate(reseed(test_pts, seed + 2000 + r), plan)[0] for r in range(reps)])
-    say(f"test set: {n_test} points x {reps} replicates")
     ref = rep.mean(axis=0)
     x_train, x_test = features(train_pts), features(test_pts)
     import torch
