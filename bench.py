@@ -75,7 +75,7 @@ def cpu_baseline(w, n_mcs):
     dt = time.perf_counter() - t0
     attempts = int(st.stats[0])
     return {"value": attempts / dt, "unit": "attempts/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {n_mcs} MCS of the same 256^3 workload ({attempts} attempts, "
+            "sample": f"first {n_mcs} MCS of the same {w.name} workload ({attempts} attempts, "
                       f"{dt:.1f} s, one thread, initial recount excluded)",
             "p_acc": float(st.stats[2]) / max(1, attempts)}
 
@@ -97,7 +97,7 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--cpu-mcs", type=int, default=4, help="MCS of the oracle sample (0 to skip)")
-    ap.add_argument("--workload", choices=("sweep", "tissue", "batch", "emulator"), default="sweep",
+    ap.add_argument("--workload", choices=("sweep", "tissue", "sorting", "batch", "emulator"), default="sweep",
                     help="sweep: the 3D 256^3 benchmark (default); tissue: 3D 1024^3 with obstacles and the "
                          "Act term; batch: 512 uneven 2D lattices; emulator: train the emulator on batched "
                          "runs and judge it against fresh ones")
@@ -135,6 +135,8 @@ def main():
         return bench_batch(args)
     if args.workload == "tissue":
         return bench_tissue(args)
+    if args.workload == "sorting":
+        return bench_sorting(args)
     if args.workload == "emulator":
         return bench_emulator(args)
     w = inputs.config1(n_mcs=args.steps)
@@ -266,6 +268,57 @@ def bench_tissue(args):
                      "avg_launch_us": avg_launch_s * 1e6,
                      "bytes_per_attempt": bytes_per_attempt(3, w.s, w.k, p_acc, act=True)},
         "cpu_baseline": None}), flush=True)
+    sim.close()
+
+
+def bench_sorting(args):
+    """Two-type cell sorting on a 2048^2 lattice (1,600 cells of 50 x 50,
+    differential adhesion), the paper's 2D benchmark workload.  Step = 1 MCS
+    = 16 activations.  Also reports the homotypic share of cell-cell contacts
+    before and after the timed MCS (it grows as the populations sort)."""
+    import numpy as np
+    import torch
+    from paper_2312_09317_amd import cpm, inputs
+    w = inputs.sorting_2d(n_mcs=args.steps)
+    log(f"workload {w.name}: {w.n_sites} sites, {w.n_cells} cells")
+    params, tuning = choose_layout(args, cpm, cpm.Params.from_workload(w), w)
+    sim = cpm.Simulation(params, w.lattice, w.cell_type, device="cuda:0")
+    def homotypic():
+        m = sim.contacts().cpu().numpy()
+        return float(np.trace(m[1:, 1:]) / max(1, m[1:, 1:].sum()))
+    h0 = homotypic()
+    sim.sweep(args.warmup)
+    torch.cuda.synchronize()
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    e0.record()
+    sim.sweep(args.steps)
+    e1.record()
+    v, s, _ = sim.cell_stats(centroids=False)
+    e2.record()
+    torch.cuda.synchronize()
+    sweep_ms, total_ms = e0.elapsed_time(e1), e0.elapsed_time(e2)
+    h1 = homotypic()
+    n_act = (2 * w.s) ** w.ndim // w.k
+    att = sim.attempt_stats()
+    p_acc = att[2] / max(1, att[0])
+    avg_launch_s = sweep_ms / 1e3 / (args.steps * n_act)
+    per_launch_bytes = bytes_per_attempt(2, w.s, w.k, p_acc) * (w.n_sites // n_act)
+    achieved = per_launch_bytes / avg_launch_s / 1e9
+    cpu = cpu_baseline(w, args.cpu_mcs) if args.cpu_mcs > 0 else None
+    print(json.dumps({
+        "metric": "site copy-attempts/s on 2D 2048² cell sorting", "value": w.n_sites * args.steps / (total_ms / 1e3),
+        "unit": "attempts/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": total_ms / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32", "data": "synthetic",
+        "config": {"workload": w.name, "lattice": list(w.dims), "n_cells": w.n_cells, "sub": w.s,
+                   "attempts_per_activation": w.k, "tiling": cpm.cpm_tile_shape(params, w.n_cells),
+                   "tuning_ms_per_mcs": tuning, "homotypic_contacts_before": h0,
+                   "homotypic_contacts_after": h1, "mcs_run": args.warmup + args.steps},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "tile_sweep_kernel",
+                     "avg_launch_us": avg_launch_s * 1e6, "bytes_per_attempt": bytes_per_attempt(2, w.s, w.k, p_acc)},
+        "cpu_baseline": {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")} if cpu else None}),
+        flush=True)
     sim.close()
 
 

@@ -159,6 +159,16 @@ int cpm_sweep(cpm_handle *h, int32_t n_mcs, void *stream);
 int cpm_cell_stats(cpm_handle *h, int32_t *d_volume, int32_t *d_surface, int64_t *d_centroid_sum,
                    void *stream);
 
+/* Contact statistics of the lattice by cell type, the read-out of the cell
+ * sorting experiments (Results, cell sorting; Fig. 4: homotypic and
+ * heterotypic cell borders): d_out[a * n_types + b] (int64, device, n_types^2
+ * entries, overwritten) = the number of ordered pairs (x, y), y a Moore
+ * neighbour of x, with different labels, neither an obstacle, x of type a and
+ * y of type b (the medium is type 0).  The matrix is symmetric; row a summed
+ * over b is the surface (cpm_cell_stats) of the cells of type a, less their
+ * contacts with obstacles.  Asynchronous. */
+int cpm_contacts(cpm_handle *h, int64_t *d_out, void *stream);
+
 /* Copies the volume / surface counters the sweep tracks (int32[n_cells + 1]
  * each, device; entry 0 unused and written as 0).  Asynchronous. */
 int cpm_counters(cpm_handle *h, int32_t *d_volume, int32_t *d_surface, void *stream);

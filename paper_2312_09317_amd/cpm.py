@@ -54,7 +54,7 @@ class cpm_params(ctypes.Structure):
 LAYOUTS = {"auto": 0, "box": 1, "full_rows": 2, "in_place": 3}
 
 
-EXPORTS = ("cpm_validate", "cpm_workspace_bytes", "cpm_tile_shape", "cpm_init", "cpm_sweep", "cpm_cell_stats",
+EXPORTS = ("cpm_validate", "cpm_workspace_bytes", "cpm_tile_shape", "cpm_init", "cpm_sweep", "cpm_cell_stats", "cpm_contacts",
            "cpm_counters", "cpm_attempt_stats", "cpm_set_mcs", "cpm_get_mcs", "cpm_destroy",
            "cpm_batch_workspace_bytes", "cpm_batch_init", "cpm_batch_sweep", "cpm_batch_use_graph", "cpm_batch_counters",
            "cpm_batch_cell_stats", "cpm_batch_attempt_stats", "cpm_batch_sample", "cpm_batch_summary",
@@ -85,6 +85,7 @@ def load(path: str = LIB_PATH):
     l.cpm_init.argtypes = [pp, P, P, I32, P, P, SZ, P, ctypes.POINTER(P)]
     l.cpm_sweep.argtypes = [P, I32, P]
     l.cpm_cell_stats.argtypes = [P, P, P, P, P]
+    l.cpm_contacts.argtypes = [P, P, P]
     l.cpm_counters.argtypes = [P, P, P, P]
     l.cpm_attempt_stats.argtypes = [P, P, P]
     l.cpm_set_mcs.argtypes = [P, U64]
@@ -220,6 +221,10 @@ def cpm_cell_stats(h: int, d_volume, d_surface, d_centroid_sum, stream: int) -> 
            "cpm_cell_stats")
 
 
+def cpm_contacts(h: int, d_out, stream: int) -> None:
+    _check(load().cpm_contacts(h, _ptr(d_out), stream), "cpm_contacts")
+
+
 def cpm_counters(h: int, d_volume, d_surface, stream: int) -> None:
     _check(load().cpm_counters(h, _ptr(d_volume), _ptr(d_surface), stream), "cpm_counters")
 
@@ -292,6 +297,13 @@ class Simulation:
             if centroids else None
         cpm_cell_stats(self.handle, v, s, c, self.stream)
         return v, s, c
+
+    def contacts(self):
+        """n_types x n_types contact counts by cell type (int64 device tensor)."""
+        n = self.params.c.n_types
+        out = self.torch.empty((n, n), dtype=self.torch.int64, device=self.device)
+        cpm_contacts(self.handle, out, self.stream)
+        return out
 
     def attempt_stats(self):
         """(attempts, attempts past the early rejection, accepted copies)."""

@@ -21,6 +21,7 @@ struct cpm_handle {
     int32_t L[3] = {1, 1, 1};
     int32_t s = 0, k = 0;
     int32_t n_cells = 0;
+    int32_t n_types = 0;
     bool act = false;
     bool mirror = false;             // sweeps run on an int16 copy of the lattice
     int16_t *mirror_cells = nullptr;
@@ -531,6 +532,7 @@ int cpm_init(const cpm_params *params, int32_t *d_lattice, const int32_t *d_cell
     h->s = params->sub;
     h->k = params->attempts;
     h->n_cells = n_cells;
+    h->n_types = params->n_types;
     h->act = params->act_enabled != 0;
     h->mirror = lay.mirror_on;
     h->mirror_cells = lay.mirror_on ? reinterpret_cast<int16_t *>(ws + lay.mirror) : nullptr;
@@ -619,6 +621,13 @@ int cpm_cell_stats(cpm_handle *h, int32_t *d_volume, int32_t *d_surface, int64_t
             return device_fail(e, "centroids");
     }
     return CPM_OK;
+}
+
+int cpm_contacts(cpm_handle *h, int64_t *d_out, void *stream)
+{
+    if (!h || !d_out) return fail(CPM_EINVAL, "NULL argument");
+    const hipError_t e = cpm::launch_contacts(h->args, h->ndim, h->n_types, d_out, as_stream(stream));
+    return e == hipSuccess ? CPM_OK : device_fail(e, "contacts");
 }
 
 int cpm_counters(cpm_handle *h, int32_t *d_volume, int32_t *d_surface, void *stream)

@@ -109,6 +109,8 @@ struct StatsTables {
 
 // Launchers.  All asynchronous on `stream`.
 hipError_t launch_fill_i32(int32_t *p, int32_t value, size_t n, hipStream_t stream);
+// n_types x n_types int64 contact counts of a lattice (cleared first).
+hipError_t launch_contacts(const SweepArgs &a, int ndim, int n_types, int64_t *out, hipStream_t stream);
 // Volume, surface and (cent != NULL) centroid sums of every lattice of a
 // batch, packed per label; ref is scratch of total_labels entries.
 hipError_t launch_batch_cell_stats(const SweepArgs *d_args, const int64_t *d_label_off, int n_lattices, int ndim,

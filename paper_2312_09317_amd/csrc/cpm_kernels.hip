@@ -132,6 +132,48 @@ __global__ void __launch_bounds__(kBlock) batch_reduce_kernel(const SweepArgs *a
                           ref ? ref + o : nullptr, cent ? cent + o * D : nullptr);
 }
 
+// Ordered Moore pairs (x, y) of different labels, neither an obstacle, counted
+// by (type of x, type of y); the medium is type 0.  Per-wave LDS histograms,
+// one 64-bit global atomic per bin and workgroup.
+template <int D>
+__global__ void __launch_bounds__(kBlock) contact_kernel(SweepArgs a, unsigned long long *out, int n_types)
+{
+    constexpr int kBins = kMaxTypes * kMaxTypes;
+    __shared__ uint32_t hist[kBlock / 64][kBins];
+    const int tid = threadIdx.x, wave = tid >> 6;
+    for (int i = tid; i < (kBlock / 64) * kBins; i += kBlock) (&hist[0][0])[i] = 0;
+    __syncthreads();
+    const int L0 = a.L[0], L1 = a.L[1], L2 = a.L[2];
+    const int64_t n_sites = (int64_t)L0 * L1 * L2;
+    const int64_t base = (int64_t)blockIdx.x * kSitesPerBlock;
+    constexpr int NNB = D == 2 ? 8 : 26;
+    for (int j = 0; j < kSitesPerThread; ++j) {
+        const int64_t i = base + tid + (int64_t)j * kBlock;
+        if (i >= n_sites) break;
+        const int32_t c = a.lat[i];
+        if (c < 0) continue;
+        const int tc = c == 0 ? 0 : a.cell_type[c];
+        const int x = (int)(i % L0), y = (int)((i / L0) % L1), z = (int)(i / ((int64_t)L0 * L1));
+#pragma unroll
+        for (int n = 0; n < NNB; ++n) {
+            const int u = wrap_once(x + nb_dx<D>(n), L0) +
+                          L0 * (wrap_once(y + nb_dy<D>(n), L1) + L1 * (D == 3 ? wrap_once(z + nb_dz<D>(n), L2) : 0));
+            const int32_t lu = a.lat[u];
+            if (lu == c || lu < 0) continue;
+            const int tu = lu == 0 ? 0 : a.cell_type[lu];
+            atomicAdd(&hist[wave][tc * kMaxTypes + tu], 1u);
+        }
+    }
+    __syncthreads();
+    for (int b = tid; b < kBins; b += kBlock) {
+        const int ta = b / kMaxTypes, tb = b % kMaxTypes;
+        if (ta >= n_types || tb >= n_types) continue;
+        unsigned long long v = 0;
+        for (int w = 0; w < kBlock / 64; ++w) v += hist[w][b];
+        if (v) atomicAdd(&out[ta * n_types + tb], v);
+    }
+}
+
 __global__ void fill_i32_kernel(int32_t *p, int32_t value, size_t n)
 {
     const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
@@ -189,6 +231,18 @@ hipError_t launch_count(const SweepArgs &a, int ndim, int32_t *v_out, int32_t *s
         reduce_kernel<2, kCount><<<grid, kBlock, 0, stream>>>(a, v_out, s_out, stride, nullptr, nullptr);
     else
         reduce_kernel<3, kCount><<<grid, kBlock, 0, stream>>>(a, v_out, s_out, stride, nullptr, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_contacts(const SweepArgs &a, int ndim, int n_types, int64_t *out, hipStream_t stream)
+{
+    hipError_t e = launch_fill_i32(reinterpret_cast<int32_t *>(out), 0, (size_t)n_types * n_types * 2, stream);
+    if (e != hipSuccess) return e;
+    const size_t n = (size_t)a.L[0] * a.L[1] * a.L[2];
+    const unsigned grid = (unsigned)((n + kSitesPerBlock - 1) / kSitesPerBlock);
+    auto *o = reinterpret_cast<unsigned long long *>(out);
+    if (ndim == 2) contact_kernel<2><<<grid, kBlock, 0, stream>>>(a, o, n_types);
+    else contact_kernel<3><<<grid, kBlock, 0, stream>>>(a, o, n_types);
     return hipGetLastError();
 }
 

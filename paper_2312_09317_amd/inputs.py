@@ -214,6 +214,24 @@ def config2(L=1024, grid=100, seed=1, n_mcs=200, edge=8, corr=12.0, obstacle_fra
     return w
 
 
+def sorting_2d(L=2048, side=50, seed=1, n_mcs=1000, density=0.95, j_same=5.0, j_diff=15.0, j_medium=10.0):
+    """Two-type cell sorting in 2D: side x side squares on a jittered grid
+    filling about `density` of an L x L lattice (squares_jittered_2d; 40 x 40
+    = 1,600 cells at L = 2048), each cell of type 1 or 2 by a seeded fair
+    draw.  The paper's settings for all its 2D runs: V_target 2500, surface
+    target 600, lambda_surface 2, J(cell, medium) 10, T 10; lambda_V 20;
+    differential adhesion J(1,1) = J(2,2) = j_same < J(1,2) = j_diff (like
+    types adhere more strongly, so the populations sort)."""
+    lat, n = squares_jittered_2d(L, density, side, seed)
+    rng = np.random.Generator(np.random.PCG64(seed + 7))
+    types = np.concatenate([[0], 1 + (rng.random(n) < 0.5)]).astype(np.int32)
+    J = np.array([[0.0, j_medium, j_medium], [j_medium, j_same, j_diff], [j_medium, j_diff, j_same]])
+    return Workload(f"2d-{L}x{L}-sorting-{n}cells", 2, (L, L, 1), lat, types, J,
+                    np.array([0.0, 20.0, 20.0]), np.array([0, 2500, 2500], dtype=np.int32),
+                    np.array([0.0, 2.0, 2.0]), np.array([0, 600, 600], dtype=np.int32),
+                    T=10.0, n_mcs=n_mcs, seed=seed)
+
+
 def random_labels(dims, n_labels, seed, p_obstacle=0.0):
     """Uniform random labels 0..n_labels-1 (and -1 with probability
     p_obstacle): a maximally rough state that exercises every branch."""

@@ -247,3 +247,44 @@ def test_autotune_agrees_and_picks(torch_cuda):
     assert r["best"] in r["times"]
     p = cpm.Params.from_workload(w, layout=r["best"][0], tile=r["best"][1])
     assert cpm.cpm_validate(p, w.n_cells) == cpm.CPM_OK
+
+
+@pytest.mark.parametrize("ndim,dims", [(2, (40, 32, 1)), (3, (16, 12, 12))])
+def test_contacts_match_oracle(torch_cuda, ndim, dims):
+    from oracle import contacts
+    w = _multi(dims, ndim, 51)
+    st, sim = run_both(torch_cuda, w, 2)
+    assert_same(st, sim, torch_cuda)
+    m = sim.contacts().cpu().numpy()
+    lat = st.lattice.reshape(dims[2], dims[1], dims[0])
+    np.testing.assert_array_equal(m, contacts.contact_matrix(lat, w.cell_type, len(w.lambda_V), ndim))
+
+
+def test_sorting_crop(torch_cuda):
+    # the sorting workload's recipe at 256^2 (25 cells of 50 x 50), every site
+    # and the contact matrix compared
+    from oracle import contacts
+    w = inputs.sorting_2d(L=256, n_mcs=3)
+    st, sim = run_both(torch_cuda, w, 3)
+    assert_same(st, sim, torch_cuda)
+    m = sim.contacts().cpu().numpy()
+    np.testing.assert_array_equal(m, contacts.contact_matrix(st.lattice.reshape(1, 256, 256), w.cell_type, 3, 2))
+
+
+def test_sorting_full_size_properties(torch_cuda):
+    # 2048^2, 1,600 cells, in the benchmark's launch configuration: counters
+    # equal the recount; the contact matrix is symmetric and each cell type's
+    # row sums to its cells' summed surfaces (no obstacles)
+    w = inputs.sorting_2d(n_mcs=2)
+    sim = cpm.Simulation(cpm.Params.from_workload(w), w.lattice, w.cell_type)
+    sim.sweep(2)
+    v, s, _ = sim.cell_stats(centroids=False)
+    tv, ts = sim.counters()
+    m = sim.contacts()
+    torch_cuda.cuda.synchronize()
+    assert torch_cuda.equal(v[1:], tv[1:]) and torch_cuda.equal(s[1:], ts[1:])
+    m = m.cpu().numpy()
+    np.testing.assert_array_equal(m, m.T)
+    s = s.cpu().numpy()
+    for t in (1, 2):
+        assert m[t].sum() == s[1:][w.cell_type[1:] == t].sum()

@@ -288,3 +288,52 @@ def test_invalid_inputs_rejected():
     with pytest.raises(ValueError):
         st = oracle.State.__new__(oracle.State)
         oracle.State(m3, bad, w.cell_type)
+
+
+def test_contacts_two_squares_closed_form():
+    # two a x a squares of types 1 and 2 sharing a full edge in medium: each
+    # side sees 3 sites across the edge per row but 2 at the two end rows
+    from oracle import contacts
+    for a in (3, 5, 8):
+        lat = np.zeros((1, 20, 30), dtype=np.int32)
+        lat[0, 4:4 + a, 5:5 + a] = 1
+        lat[0, 4:4 + a, 5 + a:5 + 2 * a] = 2
+        m = contacts.contact_matrix(lat, np.array([0, 1, 2]), 3, 2)
+        assert m[1, 2] == m[2, 1] == 3 * a - 2
+        assert m[1, 1] == m[2, 2] == 0  # one cell per type
+        # row sums are the cells' surfaces (no obstacles here)
+        mo = oracle.Model(2, (30, 20), np.zeros((3, 3)), [0, 0, 0], [0, 0, 0])
+        V, S = oracle.recount(mo, lat[0], 2)
+        assert m[1].sum() == S[1] and m[2].sum() == S[2]
+        assert m[0].sum() == m[:, 0].sum()
+
+
+@pytest.mark.parametrize("ndim,dims", [(2, (24, 18, 1)), (3, (8, 10, 6))])
+def test_contacts_row_sums_equal_recounted_surfaces(ndim, dims):
+    # on random multi-type states with obstacles: symmetric, and each type's
+    # row sum equals the summed surfaces of its cells less obstacle contacts
+    from oracle import contacts
+    lat = inputs.random_blobs(dims, 9, seed=21, fill=0.7, p_obstacle=0.0)
+    types = np.array([0] + [1 + (i % 3) for i in range(9)])
+    m = contacts.contact_matrix(lat, types, 4, ndim)
+    np.testing.assert_array_equal(m, m.T)
+    mo = oracle.Model(ndim, dims[:ndim], np.zeros((4, 4)), [0] * 4, [0] * 4)
+    V, S = oracle.recount(mo, lat if ndim == 3 else lat[0], 9)
+    for t in (1, 2, 3):
+        assert m[t].sum() == sum(S[c] for c in range(1, 10) if types[c] == t)
+    # brute force over every site and neighbour on a tiny lattice
+    small = inputs.random_labels((4, 5, 1) if ndim == 2 else (3, 4, 3), 4, seed=3, p_obstacle=0.2)
+    ts = np.array([0, 1, 2, 1])
+    bf = np.zeros((3, 3), dtype=np.int64)
+    Lz, Ly, Lx = small.shape
+    offs = [(dz, dy, dx) for dz in ((-1, 0, 1) if ndim == 3 else (0,)) for dy in (-1, 0, 1) for dx in (-1, 0, 1)
+            if (dz, dy, dx) != (0, 0, 0)]
+    for z in range(Lz):
+        for y in range(Ly):
+            for x in range(Lx):
+                c = small[z, y, x]
+                for dz, dy, dx in offs:
+                    u = small[(z + dz) % Lz, (y + dy) % Ly, (x + dx) % Lx]
+                    if c != u and c >= 0 and u >= 0:
+                        bf[ts[c] if c > 0 else 0, ts[u] if u > 0 else 0] += 1
+    np.testing.assert_array_equal(contacts.contact_matrix(small, ts, 3, ndim), bf)
