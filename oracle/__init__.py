@@ -40,6 +40,9 @@ class OrcModel(ctypes.Structure):
         ("S_target", ctypes.POINTER(ctypes.c_int32)),
         ("lambda_act", ctypes.POINTER(ctypes.c_double)),
         ("max_act", ctypes.POINTER(ctypes.c_int32)),
+        ("lambda_P", ctypes.POINTER(ctypes.c_double)),
+        ("mu_P", ctypes.POINTER(ctypes.c_double)),
+        ("dt_P", ctypes.c_int32),
     ]
 
 
@@ -53,7 +56,11 @@ def _declare(l):
     l.oracle_recount.argtypes = [ctypes.POINTER(OrcModel), _P, ctypes.c_int32, _P, _P]
     l.oracle_cell_stats.argtypes = [ctypes.POINTER(OrcModel), _P, ctypes.c_int32, _P, _P, _P]
     l.oracle_delta_h.argtypes = [ctypes.POINTER(OrcModel), _P, _P, ctypes.c_int32, _P, _P, _P,
-                                 ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, _P]
+                                 ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, _P, _P]
+    l.oracle_persist_init.argtypes = [ctypes.POINTER(OrcModel), _P, ctypes.c_int32, _P, _P, _P]
+    l.oracle_persist_update.argtypes = [ctypes.POINTER(OrcModel), _P, _P, ctypes.c_int32, _P, _P, _P]
+    l.oracle_sweep_p.argtypes = [ctypes.POINTER(OrcModel), _P, _P, ctypes.c_int32, _P, _P, _P,
+                                 ctypes.c_uint64, ctypes.c_int32, _P, _P, _P, _P]
     l.oracle_gm_act.argtypes = [ctypes.POINTER(OrcModel), _P, _P, ctypes.c_int32, _P,
                                 ctypes.c_int64, _P]
     l.oracle_sweep.argtypes = [ctypes.POINTER(OrcModel), _P, _P, ctypes.c_int32, _P, _P, _P,
@@ -64,7 +71,7 @@ def _declare(l):
                                     ctypes.c_int32, ctypes.c_int32, _P]
     for f in ("oracle_replicates", "oracle_philox", "oracle_tables", "oracle_threshold", "oracle_recount",
               "oracle_cell_stats", "oracle_delta_h", "oracle_gm_act", "oracle_sweep",
-              "oracle_serial_sweep"):
+              "oracle_serial_sweep", "oracle_persist_init", "oracle_sweep_p", "oracle_persist_update"):
         getattr(l, f).restype = ctypes.c_int
 
 
@@ -88,7 +95,7 @@ class Model:
 
     def __init__(self, ndim, dims, J, lambda_V, V_target, lambda_S=None, S_target=None,
                  lambda_act=None, max_act=None, T=20.0, seed=1, lattice_id=0, s=2, k=1,
-                 obstacle_type=-1):
+                 obstacle_type=-1, lambda_P=None, mu_P=None, dt_P=1):
         n = len(lambda_V)
         self.J = np.ascontiguousarray(np.asarray(J, dtype=np.float64).reshape(n, n))
         self.lambda_V = np.ascontiguousarray(lambda_V, dtype=np.float64)
@@ -119,6 +126,12 @@ class Model:
         self.c.S_target = self.S_target.ctypes.data_as(ip)
         self.c.lambda_act = self.lambda_act.ctypes.data_as(dp)
         self.c.max_act = self.max_act.ctypes.data_as(ip)
+        self.persistence = lambda_P is not None
+        self.lambda_P = np.ascontiguousarray(np.zeros(n) if lambda_P is None else lambda_P, dtype=np.float64)
+        self.mu_P = np.ascontiguousarray(np.zeros(n) if mu_P is None else mu_P, dtype=np.float64)
+        self.c.lambda_P = self.lambda_P.ctypes.data_as(dp) if self.persistence else None
+        self.c.mu_P = self.mu_P.ctypes.data_as(dp) if self.persistence else None
+        self.c.dt_P = int(dt_P)
 
     @property
     def dims(self):
@@ -173,16 +186,17 @@ def cell_stats(model, lattice, n_cells):
     return V, S, cs
 
 
-def delta_h(model, lattice, cell_type, V, S, t, src, new_label, act=None):
+def delta_h(model, lattice, cell_type, V, S, t, src, new_label, act=None, P=None):
     lat = np.ascontiguousarray(lattice, dtype=np.int32)
     ct = np.ascontiguousarray(cell_type, dtype=np.int32)
     V = np.ascontiguousarray(V, dtype=np.int64)
     S = np.ascontiguousarray(S, dtype=np.int64)
     a = None if act is None else np.ascontiguousarray(act, dtype=np.uint8)
+    p = None if P is None else np.ascontiguousarray(P, dtype=np.int32)
     out = ctypes.c_int64(0)
     _check(lib().oracle_delta_h(ctypes.byref(model.c), _ptr(lat), _ptr(ct), len(ct) - 1, _ptr(a),
-                                _ptr(V), _ptr(S), int(t), int(src), int(new_label), ctypes.byref(out)),
-           "delta_h")
+                                _ptr(V), _ptr(S), int(t), int(src), int(new_label), ctypes.byref(out),
+                                _ptr(p)), "delta_h")
     return out.value
 
 
@@ -212,11 +226,27 @@ class State:
         self.V, self.S = recount(model, self.lattice, self.n_cells)
         self.mcs = 0
         self.stats = np.zeros(3, dtype=np.int64)
+        self.P = self.hist = None
+        if model.persistence:
+            # per cell: direction (3 x 2^-14) and dt+1 centroids (3 x 2^-16)
+            self.P = np.zeros((self.n_cells + 1) * 3, dtype=np.int32)
+            self.hist = np.zeros((self.n_cells + 1) * (model.c.dt_P + 1) * 3, dtype=np.int64)
+            self.p_t = np.zeros(1, dtype=np.int64)
+            _check(lib().oracle_persist_init(ctypes.byref(model.c), _ptr(self.lattice), self.n_cells,
+                                             _ptr(self.P), _ptr(self.hist), _ptr(self.p_t)), "persist_init")
 
     def sweep(self, n_mcs, target_log=None):
-        rc = lib().oracle_sweep(ctypes.byref(self.model.c), _ptr(self.lattice), _ptr(self.cell_type),
-                                self.n_cells, _ptr(self.act), _ptr(self.V), _ptr(self.S),
-                                self.mcs, n_mcs, _ptr(self.stats), _ptr(target_log))
+        if self.model.persistence:
+            if target_log is not None:
+                raise ValueError("target logs are not kept with persistence")
+            rc = lib().oracle_sweep_p(ctypes.byref(self.model.c), _ptr(self.lattice), _ptr(self.cell_type),
+                                      self.n_cells, _ptr(self.act), _ptr(self.V), _ptr(self.S),
+                                      self.mcs, n_mcs, _ptr(self.stats), _ptr(self.P), _ptr(self.hist),
+                                      _ptr(self.p_t))
+        else:
+            rc = lib().oracle_sweep(ctypes.byref(self.model.c), _ptr(self.lattice), _ptr(self.cell_type),
+                                    self.n_cells, _ptr(self.act), _ptr(self.V), _ptr(self.S),
+                                    self.mcs, n_mcs, _ptr(self.stats), _ptr(target_log))
         _check(rc, "sweep")
         self.mcs += n_mcs
 
@@ -240,3 +270,24 @@ def replicates(model, lattice, cell_type, n_mcs, n_rep, mode="dcs"):
     _check(lib().oracle_replicates(ctypes.byref(model.c), _ptr(lat), _ptr(ct), len(ct) - 1, n_mcs,
                                    n_rep, code, _ptr(out)), "replicates")
     return out
+
+
+class Persistence:
+    """Direction state of the persistence term for one lattice (eq. 5-6)."""
+
+    def __init__(self, model, lattice, n_cells):
+        self.model = model
+        self.n_cells = n_cells
+        self.P = np.zeros((n_cells + 1) * 3, dtype=np.int32)
+        self.hist = np.zeros((n_cells + 1) * (model.c.dt_P + 1) * 3, dtype=np.int64)
+        self.t = np.zeros(1, dtype=np.int64)
+        lat = np.ascontiguousarray(lattice, dtype=np.int32).reshape(-1)
+        _check(lib().oracle_persist_init(ctypes.byref(model.c), _ptr(lat), n_cells, _ptr(self.P),
+                                         _ptr(self.hist), _ptr(self.t)), "persist_init")
+
+    def update(self, lattice, cell_type):
+        lat = np.ascontiguousarray(lattice, dtype=np.int32).reshape(-1)
+        ct = np.ascontiguousarray(cell_type, dtype=np.int32)
+        _check(lib().oracle_persist_update(ctypes.byref(self.model.c), _ptr(lat), _ptr(ct), self.n_cells,
+                                           _ptr(self.P), _ptr(self.hist), _ptr(self.t)), "persist_update")
+        return self.P.reshape(-1, 3)

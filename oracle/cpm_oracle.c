@@ -27,6 +27,12 @@
  *     per-cell counters as they stood when the activation began (the
  *     stale-read tolerance of the same section) plus the attempting thread's
  *     own earlier deltas.
+ *   - Persistence extension (Methods, eq. 5-6): a direction per cell,
+ *     updated after every MCS from the displacement of the cell's centroid
+ *     over the last dt MCS, mixed with the previous direction by mu and
+ *     renormalised; a copy into a site favoured in proportion to how well the
+ *     copy direction (source -> target) aligns with the copying cell's
+ *     direction.  Kept in integer fixed point (see persistence_update).
  *   - Serial CPM (Methods, first paragraph) and a symmetric-proposal variant
  *     used only to pin the Hamiltonian + acceptance against Boltzmann
  *     weights.
@@ -71,6 +77,9 @@ typedef struct orc_model {
     const int32_t *S_target;   /* per type */
     const double *lambda_act;  /* per type (used when act_enabled) */
     const int32_t *max_act;    /* per type; a type is motile iff max_act > 0 */
+    const double *lambda_P;    /* per type, persistence strength (NULL: no persistence term) */
+    const double *mu_P;        /* per type, weight of the previous direction, 0..1 */
+    int32_t dt_P;              /* MCS looked back for the displacement, >= 1 */
 } orc_model;
 
 /* Quantised energy parameters and acceptance tables. */
@@ -86,6 +95,9 @@ typedef struct orc_q {
     uint64_t TM[256], TL[256];
     int64_t LG[256];
     uint64_t EH[2048], EM[256], EL[256];
+    int64_t lP[16];        /* persistence strength, 2^-16 */
+    int64_t muP[16];       /* previous-direction weight, 2^-14 */
+    int32_t U[27][3];      /* unit vector of offset (dx,dy,dz), index (dx+1)+3(dy+1)+9(dz+1), 2^-14 */
 } orc_q;
 
 static int64_t quantise(double x) { return (int64_t)llround(x * 65536.0); }
@@ -167,6 +179,23 @@ static int model_prepare(const orc_model *m, orc_q *q)
                       ? quantise(m->lambda_act[a] / (double)m->max_act[a]) : 0;
     }
     build_neighbours(m->ndim, q);
+    if (m->lambda_P) {
+        if (!m->mu_P || m->dt_P < 1) return ORC_EINVAL;
+        for (int a = 0; a < m->n_types; a++) {
+            if (!(m->mu_P[a] >= 0.0 && m->mu_P[a] <= 1.0)) return ORC_EINVAL;
+            q->lP[a] = quantise(m->lambda_P[a]);
+            q->muP[a] = (int64_t)llround(m->mu_P[a] * 16384.0);
+        }
+    }
+    /* unit vectors of the Moore offsets, rounded to 2^-14 in FP64 */
+    for (int dz = -1; dz <= 1; dz++)
+        for (int dy = -1; dy <= 1; dy++)
+            for (int dx = -1; dx <= 1; dx++) {
+                int i = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
+                double len = sqrt((double)(dx * dx + dy * dy + dz * dz));
+                int o[3] = {dx, dy, dz};
+                for (int d = 0; d < 3; d++) q->U[i][d] = len > 0 ? (int32_t)llround(o[d] / len * 16384.0) : 0;
+            }
     return build_tables(m->T, q);
 }
 
@@ -208,6 +237,7 @@ typedef struct orc_state {
     int32_t C;
     uint8_t *act;        /* may be NULL when act is disabled */
     int64_t *V, *S;      /* per label 0..C, entries for 0 unused */
+    const int32_t *P;    /* per label 0..C, 3 components (2^-14); NULL without persistence */
 } orc_state;
 
 static int wrapc(int v, int L) { v %= L; return v < 0 ? v + L : v; }
@@ -272,7 +302,7 @@ int oracle_gm_act(const orc_model *m, const int32_t *lat, const int32_t *type, i
     orc_q *q = (orc_q *)malloc(sizeof(orc_q));
     if (!q) return ORC_ENOMEM;
     if (model_prepare(m, q) != ORC_OK) { free(q); return ORC_EINVAL; }
-    orc_state st = {m, q, (int32_t *)lat, type, C, (uint8_t *)act, NULL, NULL};
+    orc_state st = {m, q, (int32_t *)lat, type, C, (uint8_t *)act, NULL, NULL, NULL};
     *gm_out = gm_act(&st, site);
     free(q);
     return ORC_OK;
@@ -324,19 +354,37 @@ static int64_t delta_h(const orc_state *st, int64_t t, int64_t src, int32_t nl,
         int64_t rt = ol >= 1 ? q->R[to] : 0, rs = nl >= 1 ? q->R[tn] : 0;
         actterm = (rt * gt - rs * gs) >> 16; /* arithmetic shift: floor */
     }
+    /* persistence (eq. 5): the copying cell nl extends from src into t; the
+     * term is -lambda_P * (unit copy direction . its direction), so copies
+     * along the direction are favoured */
+    int64_t pers = 0;
+    if (m->lambda_P && st->P && nl >= 1 && src >= 0) {
+        int sx, sy, sz;
+        coords_of(m, src, &sx, &sy, &sz);
+        int o[3] = {x - sx, y - sy, z - sz};
+        for (int d = 0; d < 3; d++) {
+            /* undo the periodic wrap: source and target are Moore neighbours */
+            if (o[d] > 1) o[d] -= m->L[d];
+            if (o[d] < -1) o[d] += m->L[d];
+        }
+        const int32_t *u = q->U[(o[0] + 1) + 3 * (o[1] + 1) + 9 * (o[2] + 1)];
+        const int32_t *p = st->P + 3 * (int64_t)nl;
+        int64_t dot = (int64_t)u[0] * p[0] + (int64_t)u[1] * p[1] + (int64_t)u[2] * p[2];
+        pers = -((q->lP[tn] * dot) >> 28); /* arithmetic shift: floor, then negated */
+    }
     *dS_old = dso;
     *dS_new = dsn;
-    return adh + vol + surf + actterm;
+    return adh + vol + surf + actterm + pers;
 }
 
 int oracle_delta_h(const orc_model *m, const int32_t *lat, const int32_t *type, int32_t C,
                    const uint8_t *act, const int64_t *V, const int64_t *S, int64_t t,
-                   int64_t src, int32_t new_label, int64_t *dh_out)
+                   int64_t src, int32_t new_label, int64_t *dh_out, const int32_t *P)
 {
     orc_q *q = (orc_q *)malloc(sizeof(orc_q));
     if (!q) return ORC_ENOMEM;
     if (model_prepare(m, q) != ORC_OK) { free(q); return ORC_EINVAL; }
-    orc_state st = {m, q, (int32_t *)lat, type, C, (uint8_t *)act, NULL, NULL};
+    orc_state st = {m, q, (int32_t *)lat, type, C, (uint8_t *)act, NULL, NULL, P};
     int64_t a, b;
     *dh_out = delta_h(&st, t, src, new_label, V, S, &a, &b);
     free(q);
@@ -462,12 +510,145 @@ static int check_state(const orc_model *m, const int32_t *lat, int32_t C)
     return ORC_OK;
 }
 
+/* Persistence state of a run: per cell the direction P (3 components,
+ * 2^-14), the centroid history hist ((dt+1) slots of 3 components, 2^-16)
+ * and the number t of direction updates done. */
+typedef struct orc_pers {
+    int32_t *P;
+    int64_t *hist;
+    int64_t *t;
+} orc_pers;
+
 static int sweep_dcs(const orc_model *m, const orc_q *qp, int32_t *lat, const int32_t *type, int32_t C,
                      uint8_t *act, int64_t *V, int64_t *S, uint64_t mcs0, int32_t n_mcs,
-                     int64_t *stats, int32_t *target_log);
+                     int64_t *stats, int32_t *target_log, orc_pers *pers);
 static int sweep_serial(const orc_model *m, const orc_q *qp, int32_t *lat, const int32_t *type, int32_t C,
                         uint8_t *act, int64_t *V, int64_t *S, uint64_t mcs0, int32_t n_mcs,
-                        int32_t symmetric, int64_t *stats, int32_t *target_log);
+                        int32_t symmetric, int64_t *stats, int32_t *target_log, orc_pers *pers);
+
+/* floor(sqrt(n)), exact for 0 <= n < 2^62 (the FP64 root is only a first guess) */
+static int64_t isqrt64(int64_t n)
+{
+    if (n <= 0) return 0;
+    int64_t r = (int64_t)sqrt((double)n);
+    while (r > 0 && r * r > n) r--;
+    while ((r + 1) * (r + 1) <= n) r++;
+    return r;
+}
+
+static int64_t floor_div(int64_t a, int64_t b) /* b > 0 */
+{
+    int64_t q = a / b;
+    if (a % b != 0 && a < 0) q--;
+    return q;
+}
+
+/* Centroids of every cell in 2^-16 fixed point: floor(centroid sum * 2^16 / V),
+ * the sum taken as in oracle_cell_stats. */
+static int centroids_fixed(const orc_model *m, const int32_t *lat, int32_t C, int64_t *X, int64_t *V)
+{
+    int64_t *S = (int64_t *)malloc(sizeof(int64_t) * (size_t)(C + 1));
+    int64_t *cs = (int64_t *)malloc(sizeof(int64_t) * (size_t)(C + 1) * 3);
+    if (!S || !cs) { free(S); free(cs); return ORC_ENOMEM; }
+    int rc = oracle_cell_stats(m, lat, C, V, S, cs);
+    for (int32_t c = 0; c <= C && rc == ORC_OK; c++)
+        for (int d = 0; d < 3; d++)
+            X[3 * (int64_t)c + d] = (d < m->ndim && V[c] > 0) ? floor_div(cs[(int64_t)c * m->ndim + d] * 65536, V[c]) : 0;
+    free(S); free(cs);
+    return rc;
+}
+
+/*
+ * Direction update after an MCS (eq. 6), in integers.  For every cell alive:
+ * X = its centroid (2^-16); D = X - X(dt updates ago), each component brought
+ * to the minimum image [-L/2, L/2) * 2^16; u = trunc(D * 2^14 / |D|) (0 if D
+ * is 0), |.| = floor of the Euclidean norm; p = (2^14 - mu) * u + mu * P;
+ * P = trunc(p * 2^14 / |p|) (0 if p is 0).  Dead cells get P = 0.  The
+ * history holds dt + 1 centroids per cell: update t writes slot t mod (dt+1)
+ * and reads slot (t + 1) mod (dt+1), which holds the centroid of update
+ * t - dt, or the initial one.
+ */
+static int persistence_update(const orc_model *m, const orc_q *q, const int32_t *lat, const int32_t *type,
+                              int32_t C, orc_pers *pers)
+{
+    int64_t *X = (int64_t *)malloc(sizeof(int64_t) * (size_t)(C + 1) * 3);
+    int64_t *V = (int64_t *)malloc(sizeof(int64_t) * (size_t)(C + 1));
+    if (!X || !V) { free(X); free(V); return ORC_ENOMEM; }
+    int rc = centroids_fixed(m, lat, C, X, V);
+    const int64_t slots = m->dt_P + 1;
+    const int64_t t = *pers->t + 1;
+    for (int32_t c = 1; c <= C && rc == ORC_OK; c++) {
+        int32_t *P = pers->P + 3 * (int64_t)c;
+        int64_t *h = pers->hist + 3 * slots * (int64_t)c;
+        if (V[c] == 0) { P[0] = P[1] = P[2] = 0; continue; }
+        int64_t D[3];
+        for (int d = 0; d < 3; d++) {
+            D[d] = X[3 * (int64_t)c + d] - h[3 * ((t + 1) % slots) + d];
+            int64_t W = (int64_t)m->L[d] * 65536;
+            int64_t w = D[d] % W;
+            if (w < 0) w += W;
+            if (w >= W / 2) w -= W;
+            D[d] = d < m->ndim ? w : 0;
+        }
+        for (int d = 0; d < 3; d++) h[3 * (t % slots) + d] = X[3 * (int64_t)c + d];
+        int64_t nd = isqrt64(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);
+        int64_t mu = q->muP[type[c]];
+        int64_t pv[3];
+        for (int d = 0; d < 3; d++) {
+            int64_t u = nd > 0 ? (D[d] * 16384) / nd : 0;
+            pv[d] = (16384 - mu) * u + mu * P[d];
+        }
+        int64_t np = isqrt64(pv[0] * pv[0] + pv[1] * pv[1] + pv[2] * pv[2]);
+        for (int d = 0; d < 3; d++) P[d] = np > 0 ? (int32_t)((pv[d] * 16384) / np) : 0;
+    }
+    *pers->t = t;
+    free(X); free(V);
+    return rc;
+}
+
+/* Start of a run with persistence: P = 0 and every history slot = the
+ * current centroid. */
+int oracle_persist_init(const orc_model *m, const int32_t *lat, int32_t C, int32_t *P, int64_t *hist,
+                        int64_t *t)
+{
+    if (!m || m->dt_P < 1) return ORC_EINVAL;
+    int64_t *X = (int64_t *)malloc(sizeof(int64_t) * (size_t)(C + 1) * 3);
+    int64_t *V = (int64_t *)malloc(sizeof(int64_t) * (size_t)(C + 1));
+    if (!X || !V) { free(X); free(V); return ORC_ENOMEM; }
+    int rc = centroids_fixed(m, lat, C, X, V);
+    const int64_t slots = m->dt_P + 1;
+    for (int32_t c = 0; c <= C && rc == ORC_OK; c++) {
+        for (int d = 0; d < 3; d++) P[3 * (int64_t)c + d] = 0;
+        for (int64_t k = 0; k < slots; k++)
+            for (int d = 0; d < 3; d++) hist[3 * (slots * c + k) + d] = X[3 * (int64_t)c + d];
+    }
+    *t = 0;
+    free(X); free(V);
+    return rc;
+}
+
+/* One direction update (for tests): as after an MCS. */
+int oracle_persist_update(const orc_model *m, const int32_t *lat, const int32_t *type, int32_t C, int32_t *P,
+                          int64_t *hist, int64_t *t)
+{
+    if (!m || !m->lambda_P) return ORC_EINVAL;
+    orc_q *q = (orc_q *)malloc(sizeof(orc_q));
+    if (!q) return ORC_ENOMEM;
+    int rc = model_prepare(m, q);
+    orc_pers pers = {P, hist, t};
+    if (rc == ORC_OK) rc = persistence_update(m, q, lat, type, C, &pers);
+    free(q);
+    return rc;
+}
+
+/* The per-MCS end of a sweep: Act decays, then the persistence directions
+ * are updated. */
+static int end_of_mcs(orc_state *st, orc_pers *pers)
+{
+    act_decay(st);
+    if (st->m->lambda_P && pers) return persistence_update(st->m, st->q, st->lat, st->type, st->C, pers);
+    return ORC_OK;
+}
 
 /*
  * The deterministic parallel scheme.  One MCS is (2s)^d / k activations.
@@ -488,14 +669,30 @@ int oracle_sweep(const orc_model *m, int32_t *lat, const int32_t *type, int32_t 
     orc_q *qp = (orc_q *)malloc(sizeof(orc_q));
     if (!qp) return ORC_ENOMEM;
     int rc = model_prepare(m, qp);
-    if (rc == ORC_OK) rc = sweep_dcs(m, qp, lat, type, C, act, V, S, mcs0, n_mcs, stats, target_log);
+    if (rc == ORC_OK) rc = sweep_dcs(m, qp, lat, type, C, act, V, S, mcs0, n_mcs, stats, target_log, NULL);
+    free(qp);
+    return rc;
+}
+
+/* oracle_sweep with the persistence term: P, hist, t as set up by
+ * oracle_persist_init and carried from call to call. */
+int oracle_sweep_p(const orc_model *m, int32_t *lat, const int32_t *type, int32_t C, uint8_t *act,
+                   int64_t *V, int64_t *S, uint64_t mcs0, int32_t n_mcs, int64_t *stats,
+                   int32_t *P, int64_t *hist, int64_t *t)
+{
+    if (!m->lambda_P || !P || !hist || !t) return ORC_EINVAL;
+    orc_q *qp = (orc_q *)malloc(sizeof(orc_q));
+    if (!qp) return ORC_ENOMEM;
+    orc_pers pers = {P, hist, t};
+    int rc = model_prepare(m, qp);
+    if (rc == ORC_OK) rc = sweep_dcs(m, qp, lat, type, C, act, V, S, mcs0, n_mcs, stats, NULL, &pers);
     free(qp);
     return rc;
 }
 
 static int sweep_dcs(const orc_model *m, const orc_q *qp, int32_t *lat, const int32_t *type, int32_t C,
                      uint8_t *act, int64_t *V, int64_t *S, uint64_t mcs0, int32_t n_mcs,
-                     int64_t *stats, int32_t *target_log)
+                     int64_t *stats, int32_t *target_log, orc_pers *pers)
 {
     const orc_q *q = qp;
     int d = m->ndim;
@@ -516,7 +713,7 @@ static int sweep_dcs(const orc_model *m, const orc_q *qp, int32_t *lat, const in
     int n_act = colours * sd / k; /* (2s)^d / k */
     uint32_t key[2] = {(uint32_t)m->seed, (uint32_t)(m->seed >> 32)};
 
-    orc_state st = {m, q, lat, type, C, act, V, S};
+    orc_state st = {m, q, lat, type, C, act, V, S, pers ? pers->P : NULL};
     int64_t *Vr = (int64_t *)malloc(sizeof(int64_t) * (size_t)(C + 1));
     int64_t *Sr = (int64_t *)malloc(sizeof(int64_t) * (size_t)(C + 1));
     int64_t *dV = (int64_t *)calloc((size_t)(C + 1), sizeof(int64_t));
@@ -601,7 +798,10 @@ static int sweep_dcs(const orc_model *m, const orc_q *qp, int32_t *lat, const in
                 dV[c] = 0; dS[c] = 0;
             }
         }
-        act_decay(&st);
+        if (end_of_mcs(&st, pers) != ORC_OK) {
+            free(Vr); free(Sr); free(dV); free(dS); free(own_c); free(own_v); free(own_s);
+            return ORC_ENOMEM;
+        }
     }
     free(Vr); free(Sr); free(dV); free(dS); free(own_c); free(own_v); free(own_s);
     return ORC_OK;
@@ -624,14 +824,14 @@ int oracle_serial_sweep(const orc_model *m, int32_t *lat, const int32_t *type, i
     if (!qp) return ORC_ENOMEM;
     int rc = model_prepare(m, qp);
     if (rc == ORC_OK)
-        rc = sweep_serial(m, qp, lat, type, C, act, V, S, mcs0, n_mcs, symmetric, stats, target_log);
+        rc = sweep_serial(m, qp, lat, type, C, act, V, S, mcs0, n_mcs, symmetric, stats, target_log, NULL);
     free(qp);
     return rc;
 }
 
 static int sweep_serial(const orc_model *m, const orc_q *qp, int32_t *lat, const int32_t *type, int32_t C,
                         uint8_t *act, int64_t *V, int64_t *S, uint64_t mcs0, int32_t n_mcs,
-                        int32_t symmetric, int64_t *stats, int32_t *target_log)
+                        int32_t symmetric, int64_t *stats, int32_t *target_log, orc_pers *pers)
 {
     const orc_q *q = qp;
     if (m->act_enabled && !act) return ORC_EINVAL;
@@ -640,7 +840,7 @@ static int sweep_serial(const orc_model *m, const orc_q *qp, int32_t *lat, const
     int64_t N = (int64_t)m->L[0] * m->L[1] * m->L[2];
     if (N >= ((int64_t)1 << 32)) return ORC_EINVAL;
     uint32_t key[2] = {(uint32_t)m->seed, (uint32_t)(m->seed >> 32)};
-    orc_state st = {m, q, lat, type, C, act, V, S};
+    orc_state st = {m, q, lat, type, C, act, V, S, pers ? pers->P : NULL};
     int64_t log_pos = 0;
     for (int32_t mi = 0; mi < n_mcs; mi++) {
         uint32_t mcs = (uint32_t)(mcs0 + (uint64_t)mi);
@@ -675,7 +875,7 @@ static int sweep_serial(const orc_model *m, const orc_q *qp, int32_t *lat, const
             if (lt >= 1) { V[lt] -= 1; S[lt] += dso; }
             if (ls >= 1) { V[ls] += 1; S[ls] += dsn; }
         }
-        act_decay(&st);
+        if (end_of_mcs(&st, pers) != ORC_OK) return ORC_ENOMEM;
     }
     return ORC_OK;
 }
@@ -704,9 +904,9 @@ int oracle_replicates(const orc_model *m, const int32_t *lat0, const int32_t *ty
         if (rc != ORC_OK) break;
         mr.lattice_id = m->lattice_id + (uint32_t)r;
         if (mode == 0)
-            rc = sweep_dcs(&mr, qp, lat, type, C, NULL, V, S, 0, n_mcs, NULL, NULL);
+            rc = sweep_dcs(&mr, qp, lat, type, C, NULL, V, S, 0, n_mcs, NULL, NULL, NULL);
         else
-            rc = sweep_serial(&mr, qp, lat, type, C, NULL, V, S, 0, n_mcs, mode == 2, NULL, NULL);
+            rc = sweep_serial(&mr, qp, lat, type, C, NULL, V, S, 0, n_mcs, mode == 2, NULL, NULL, NULL);
     }
     free(qp); free(V); free(S);
     return rc;
