@@ -68,7 +68,7 @@ def bytes_per_attempt(ndim, s, k, p_acc, act=False):
 def cpu_baseline(w, n_mcs):
     import oracle
     m = oracle.Model(w.ndim, w.dims[:w.ndim], w.J, w.lambda_V, w.V_target, w.lambda_S, w.S_target,
-                     T=w.T, seed=w.seed, s=w.s, k=w.k)
+                     T=w.T, seed=w.seed, s=w.s, k=w.k, lambda_P=w.lambda_P, mu_P=w.mu_P, dt_P=w.dt_P)
     st = oracle.State(m, w.lattice, w.cell_type)
     t0 = time.perf_counter()
     st.sweep(n_mcs)
@@ -97,10 +97,12 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--cpu-mcs", type=int, default=4, help="MCS of the oracle sample (0 to skip)")
-    ap.add_argument("--workload", choices=("sweep", "tissue", "sorting", "batch", "emulator"), default="sweep",
+    ap.add_argument("--workload", choices=("sweep", "tissue", "sorting", "collective", "batch", "emulator"),
+                    default="sweep",
                     help="sweep: the 3D 256^3 benchmark (default); tissue: 3D 1024^3 with obstacles and the "
-                         "Act term; batch: 512 uneven 2D lattices; emulator: train the emulator on batched "
-                         "runs and judge it against fresh ones")
+                         "Act term; sorting: 2D 2048^2 two-type cell sorting; collective: 3D 256^3 packed "
+                         "collective with the persistence term; batch: 512 uneven 2D lattices; emulator: "
+                         "train the emulator on batched runs and judge it against fresh ones")
     ap.add_argument("--layout", default="tune", choices=("tune", "auto", "box", "full_rows", "in_place"),
                     help="sweep layout: tune = time the candidates first and take the fastest (default)")
     ap.add_argument("--tune-mcs", type=int, default=6, help="MCS timed per candidate layout when tuning")
@@ -137,6 +139,8 @@ def main():
         return bench_tissue(args)
     if args.workload == "sorting":
         return bench_sorting(args)
+    if args.workload == "collective":
+        return bench_collective(args)
     if args.workload == "emulator":
         return bench_emulator(args)
     w = inputs.config1(n_mcs=args.steps)
@@ -317,6 +321,69 @@ def bench_sorting(args):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "tile_sweep_kernel",
                      "avg_launch_us": avg_launch_s * 1e6, "bytes_per_attempt": bytes_per_attempt(2, w.s, w.k, p_acc)},
+        "cpu_baseline": {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")} if cpu else None}),
+        flush=True)
+    sim.close()
+
+
+def bench_collective(args):
+    """A packed 3D collective of persistently moving cells on a 256^3
+    lattice (54,872 cells of V_target 150 at density 0.49: int32 labels),
+    the paper's 3D collective settings (mu 0.95, dt 15, lambda_persistence
+    40).  Step = 1 MCS = 64 activations plus the direction update (centroid
+    sums of every cell, then one thread per cell).  Also reports the polar
+    order of the cells' directions, |sum of unit directions| / cells."""
+    import numpy as np
+    import torch
+    from paper_2312_09317_amd import cpm, inputs
+    w = inputs.collective_3d(n_mcs=args.steps)
+    log(f"workload {w.name}: {w.n_sites} sites, {w.n_cells} cells, density {w.extra['density']:.3f}")
+    params, tuning = choose_layout(args, cpm, cpm.Params.from_workload(w), w)
+    sim = cpm.Simulation(params, w.lattice, w.cell_type, device="cuda:0")
+
+    def order():
+        P = sim.persistence().cpu().numpy()[1:].astype(np.float64)
+        alive = np.any(P != 0, axis=1)
+        return float(np.linalg.norm(P[alive].sum(axis=0)) / (16384.0 * max(1, alive.sum())))
+    sim.sweep(args.warmup)
+    torch.cuda.synchronize()
+    o0 = order()
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    e0.record()
+    sim.sweep(args.steps)
+    e1.record()
+    v, s, _ = sim.cell_stats(centroids=False)
+    e2.record()
+    torch.cuda.synchronize()
+    sweep_ms, total_ms = e0.elapsed_time(e1), e0.elapsed_time(e2)
+    o1 = order()
+    tv, ts = sim.counters()
+    torch.cuda.synchronize()
+    if not (torch.equal(tv[1:], v[1:]) and torch.equal(ts[1:], s[1:])):
+        log("ERROR: tracked counters differ from the lattice recount")
+        sys.exit(3)
+    n_act = (2 * w.s) ** w.ndim // w.k
+    att = sim.attempt_stats()
+    p_acc = att[2] / max(1, att[0])
+    # the timed region also holds one direction update per MCS, so this
+    # average is an upper bound on the activation kernel's duration
+    avg_launch_s = sweep_ms / 1e3 / (args.steps * n_act)
+    per_launch_bytes = bytes_per_attempt(3, w.s, w.k, p_acc) * (w.n_sites // n_act)
+    achieved = per_launch_bytes / avg_launch_s / 1e9
+    cpu = cpu_baseline(w, args.cpu_mcs) if args.cpu_mcs > 0 else None
+    print(json.dumps({
+        "metric": "site copy-attempts/s on a 3D 256³ persistent cell collective",
+        "value": w.n_sites * args.steps / (total_ms / 1e3), "unit": "attempts/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": total_ms / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": w.name, "lattice": list(w.dims), "n_cells": w.n_cells,
+                   "density": w.extra["density"], "sub": w.s, "attempts_per_activation": w.k,
+                   "persistence": {"lambda": float(w.lambda_P[1]), "mu": float(w.mu_P[1]), "dt": w.dt_P},
+                   "tiling": cpm.cpm_tile_shape(params, w.n_cells), "tuning_ms_per_mcs": tuning,
+                   "order_before": o0, "order_after": o1, "mcs_run": args.warmup + args.steps},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "tile_sweep_kernel",
+                     "avg_launch_us": avg_launch_s * 1e6, "bytes_per_attempt": bytes_per_attempt(3, w.s, w.k, p_acc)},
         "cpu_baseline": {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")} if cpu else None}),
         flush=True)
     sim.close()

@@ -107,6 +107,22 @@ typedef struct cpm_params {
     int32_t layout;
     int32_t tile[3];              /* thread areas per workgroup tile (product <= 256); 0 = the library's choice.
                                      With layout 2 tile[0] must be 0 or the whole row of areas. */
+    /* Persistence (Methods, eq. 5-6; NULL lambda_persistence = off; not for
+     * batches).  Every cell has a direction P, updated after each MCS from the
+     * displacement D of its centroid over the last persistence_dt MCS, in
+     * integers: centroids X = floor(centroid sum * 2^16 / V) (sums as in
+     * cpm_cell_stats); D = X - X(dt MCS ago) per axis at its minimum image;
+     * u = trunc(D * 2^14 / |D|); p = (2^14 - mu) u + mu P with
+     * mu = round(persistence_mu * 2^14); P = trunc(p * 2^14 / |p|); |.| the
+     * floor of the Euclidean norm, 0 / 0 = 0, dead cells P = 0.  A copy
+     * from source s into target t by cell c of type tc adds
+     * -floor(lambda * (U(t - s) . P_c) / 2^28) (2^-16 units) to the energy
+     * change, U the offset's unit vector rounded to 2^-14: copies along a
+     * cell's direction are favoured (the paper's sign convention is read
+     * this way; its formula alone would penalise them). */
+    const double *lambda_persistence; /* n_types (2^-16 quantised like J) */
+    const double *persistence_mu;     /* n_types, 0..1 */
+    int32_t persistence_dt;           /* >= 1 */
 } cpm_params;
 
 typedef struct cpm_handle cpm_handle;
@@ -168,6 +184,12 @@ int cpm_cell_stats(cpm_handle *h, int32_t *d_volume, int32_t *d_surface, int64_t
  * over b is the surface (cpm_cell_stats) of the cells of type a, less their
  * contacts with obstacles.  Asynchronous. */
 int cpm_contacts(cpm_handle *h, int64_t *d_out, void *stream);
+
+/* Persistence directions P of every label (int32, device, (n_cells + 1) x 3:
+ * x, y, z in 2^-14 units; label 0 and dead cells 0), as the parameters'
+ * persistence fields define them.  CPM_EINVAL when persistence is off.
+ * Asynchronous. */
+int cpm_persistence(cpm_handle *h, int32_t *d_dir, void *stream);
 
 /* Copies the volume / surface counters the sweep tracks (int32[n_cells + 1]
  * each, device; entry 0 unused and written as 0).  Asynchronous. */

@@ -49,13 +49,16 @@ class cpm_params(ctypes.Structure):
         ("max_act", ctypes.POINTER(ctypes.c_int32)),
         ("layout", ctypes.c_int32),
         ("tile", ctypes.c_int32 * 3),
+        ("lambda_persistence", ctypes.POINTER(ctypes.c_double)),
+        ("persistence_mu", ctypes.POINTER(ctypes.c_double)),
+        ("persistence_dt", ctypes.c_int32),
     ]
 
 LAYOUTS = {"auto": 0, "box": 1, "full_rows": 2, "in_place": 3}
 
 
 EXPORTS = ("cpm_validate", "cpm_workspace_bytes", "cpm_tile_shape", "cpm_init", "cpm_sweep", "cpm_cell_stats", "cpm_contacts",
-           "cpm_counters", "cpm_attempt_stats", "cpm_set_mcs", "cpm_get_mcs", "cpm_destroy",
+           "cpm_persistence", "cpm_counters", "cpm_attempt_stats", "cpm_set_mcs", "cpm_get_mcs", "cpm_destroy",
            "cpm_batch_workspace_bytes", "cpm_batch_init", "cpm_batch_sweep", "cpm_batch_use_graph", "cpm_batch_counters",
            "cpm_batch_cell_stats", "cpm_batch_attempt_stats", "cpm_batch_sample", "cpm_batch_summary",
            "cpm_batch_set_mcs", "cpm_batch_get_mcs",
@@ -86,6 +89,7 @@ def load(path: str = LIB_PATH):
     l.cpm_sweep.argtypes = [P, I32, P]
     l.cpm_cell_stats.argtypes = [P, P, P, P, P]
     l.cpm_contacts.argtypes = [P, P, P]
+    l.cpm_persistence.argtypes = [P, P, P]
     l.cpm_counters.argtypes = [P, P, P, P]
     l.cpm_attempt_stats.argtypes = [P, P, P]
     l.cpm_set_mcs.argtypes = [P, U64]
@@ -124,7 +128,8 @@ class Params:
     def __init__(self, ndim: int, dims: Sequence[int], J, lambda_volume, volume_target,
                  lambda_surface=None, surface_target=None, lambda_act=None, max_act=None,
                  temperature: float = 20.0, seed: int = 1, lattice_id: int = 0, sub: int = 2,
-                 attempts: int = 1, obstacle_type: int = -1, layout="auto", tile=(0, 0, 0)):
+                 attempts: int = 1, obstacle_type: int = -1, layout="auto", tile=(0, 0, 0),
+                 lambda_persistence=None, persistence_mu=None, persistence_dt: int = 1):
         n = len(lambda_volume)
         self._J = np.ascontiguousarray(np.asarray(J, dtype=np.float64).reshape(n, n))
         self._lv = np.ascontiguousarray(lambda_volume, dtype=np.float64)
@@ -133,6 +138,8 @@ class Params:
         self._st = None if surface_target is None else np.ascontiguousarray(surface_target, dtype=np.int32)
         self._la = None if lambda_act is None else np.ascontiguousarray(lambda_act, dtype=np.float64)
         self._ma = None if max_act is None else np.ascontiguousarray(max_act, dtype=np.int32)
+        self._lp = None if lambda_persistence is None else np.ascontiguousarray(lambda_persistence, dtype=np.float64)
+        self._mp = None if persistence_mu is None else np.ascontiguousarray(persistence_mu, dtype=np.float64)
         d = list(dims) + [1] * (3 - len(dims))
         c = cpm_params()
         c.ndim = ndim
@@ -155,11 +162,16 @@ class Params:
         c.max_act = self._ma.ctypes.data_as(ip) if self._ma is not None else None
         c.layout = LAYOUTS[layout] if isinstance(layout, str) else int(layout)
         c.tile = (ctypes.c_int32 * 3)(*[int(t) for t in tile])
+        c.lambda_persistence = self._lp.ctypes.data_as(dp) if self._lp is not None else None
+        c.persistence_mu = self._mp.ctypes.data_as(dp) if self._mp is not None else None
+        c.persistence_dt = int(persistence_dt)
         self.c = c
         self._kw = dict(ndim=ndim, dims=dims, J=J, lambda_volume=lambda_volume, volume_target=volume_target,
                         lambda_surface=lambda_surface, surface_target=surface_target, lambda_act=lambda_act,
                         max_act=max_act, temperature=temperature, seed=seed, lattice_id=lattice_id, sub=sub,
-                        attempts=attempts, obstacle_type=obstacle_type, layout=layout, tile=tile)
+                        attempts=attempts, obstacle_type=obstacle_type, layout=layout, tile=tile,
+                        lambda_persistence=lambda_persistence, persistence_mu=persistence_mu,
+                        persistence_dt=persistence_dt)
 
     def replace(self, **over) -> "Params":
         """A copy with some fields changed (e.g. layout, tile)."""
@@ -176,7 +188,9 @@ class Params:
         kw = dict(ndim=w.ndim, dims=w.dims, J=w.J, lambda_volume=w.lambda_V, volume_target=w.V_target,
                   lambda_surface=w.lambda_S, surface_target=w.S_target, lambda_act=w.lambda_act,
                   max_act=w.max_act, temperature=w.T, seed=w.seed, lattice_id=w.lattice_id, sub=w.s,
-                  attempts=w.k, obstacle_type=w.obstacle_type)
+                  attempts=w.k, obstacle_type=w.obstacle_type,
+                  lambda_persistence=getattr(w, "lambda_P", None), persistence_mu=getattr(w, "mu_P", None),
+                  persistence_dt=getattr(w, "dt_P", 1))
         kw.update(over)
         return cls(**kw)
 
@@ -223,6 +237,10 @@ def cpm_cell_stats(h: int, d_volume, d_surface, d_centroid_sum, stream: int) -> 
 
 def cpm_contacts(h: int, d_out, stream: int) -> None:
     _check(load().cpm_contacts(h, _ptr(d_out), stream), "cpm_contacts")
+
+
+def cpm_persistence(h: int, d_dir, stream: int) -> None:
+    _check(load().cpm_persistence(h, _ptr(d_dir), stream), "cpm_persistence")
 
 
 def cpm_counters(h: int, d_volume, d_surface, stream: int) -> None:
@@ -303,6 +321,12 @@ class Simulation:
         n = self.params.c.n_types
         out = self.torch.empty((n, n), dtype=self.torch.int64, device=self.device)
         cpm_contacts(self.handle, out, self.stream)
+        return out
+
+    def persistence(self):
+        """Persistence directions, (n_cells + 1) x 3 int32 in 2^-14 units."""
+        out = self.torch.empty((self.n_cells + 1, 3), dtype=self.torch.int32, device=self.device)
+        cpm_persistence(self.handle, out, self.stream)
         return out
 
     def attempt_stats(self):

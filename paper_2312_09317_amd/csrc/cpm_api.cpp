@@ -27,6 +27,12 @@ struct cpm_handle {
     int16_t *mirror_cells = nullptr;
     SweepArgs args{};
     int32_t *ref = nullptr;          // centroid reference sites, n_cells + 1
+    // persistence (NULL pdir = off): directions, centroid history, centroid sums
+    int4 *pdir = nullptr;
+    int64_t *hist = nullptr;
+    int64_t *csum = nullptr;
+    int32_t persist_slots = 0;
+    int64_t persist_t = 0;           // direction updates done
     uint64_t mcs = 0;                // next MCS index
     uint64_t activation = 0;         // activations run so far (buffer parity)
     uint64_t attempts_run = 0;       // copy attempts run since init
@@ -97,7 +103,7 @@ int64_t to_fixed(double x) { return (int64_t)std::llround(x * 65536.0); }
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t model, counters0, counters1, dlist, dcount, stats, ref, mirror, total;
+    size_t model, counters0, counters1, dlist, dcount, stats, ref, mirror, pdir, hist, csum, total;
     cpm::TileGeometry tg;
     bool mirror_on;
     int32_t dlist_cap;
@@ -264,6 +270,11 @@ Layout layout_of(const cpm_params *p, int32_t n_cells, int mirror = -1, int forc
     l.stats = take(sizeof(uint64_t) * 2 * (size_t)l.tg.n_tiles);
     l.ref = take(sizeof(int32_t) * ((size_t)n_cells + 1));
     l.mirror = take(l.mirror_on ? sizeof(int16_t) * (size_t)n_sites : 0);
+    const bool pers = p->lambda_persistence != nullptr;
+    const size_t labels = (size_t)n_cells + 1;
+    l.pdir = take(pers ? sizeof(int4) * labels : 0);
+    l.hist = take(pers ? sizeof(int64_t) * 3 * labels * (size_t)(p->persistence_dt + 1) : 0);
+    l.csum = take(pers ? sizeof(int64_t) * (size_t)p->ndim * labels : 0);
     l.total = off;
     return l;
 }
@@ -359,6 +370,22 @@ int validate(const cpm_params *p, int32_t n_cells)
                                     2.0 * lsmax * (2.0 * nnb * (nnb * N + stmax) + nnb * nnb) +
                                     2.0 * ramax * 256.0);
     if (bound >= 4.0e18) return fail(CPM_ERANGE, "fixed-point energy change could overflow int64");
+    if (p->lambda_persistence) {
+        if (!p->persistence_mu) return fail(CPM_EINVAL, "persistence_mu NULL with persistence enabled");
+        if (p->persistence_dt < 1 || p->persistence_dt > 4096) return fail(CPM_EINVAL, "persistence_dt must be in 1..4096");
+        for (int d = 0; d < p->ndim; ++d)
+            if (p->dims[d] < 4 || p->dims[d] > 32768)
+                return fail(CPM_EINVAL, "persistence needs every dim in 4..32768");
+        double lpmax = 0;
+        for (int a = 0; a < n; ++a) {
+            const double lp = p->lambda_persistence[a], mu = p->persistence_mu[a];
+            if (!std::isfinite(lp) || std::fabs(lp) >= lim) return fail(CPM_ERANGE, "lambda_persistence out of range");
+            if (!(mu >= 0.0 && mu <= 1.0)) return fail(CPM_EINVAL, "persistence_mu must be in 0..1");
+            lpmax = std::fmax(lpmax, std::fabs(lp));
+        }
+        // |U . P| <= 3 * 2^28: the term adds at most 3 * 2^16 * lambda
+        if (bound + 65536.0 * 3.0 * lpmax >= 4.0e18) return fail(CPM_ERANGE, "fixed-point energy change could overflow int64");
+    }
     if (table_length(p->temperature) > cpm::kMaxTI) return fail(CPM_ENOTSUP, "temperature too high for the threshold table");
     if (p->attempts > cpm::kMaxAttempts) return fail(CPM_ENOTSUP, "this build runs at most 8 attempts per activation");
     return CPM_OK;
@@ -378,6 +405,16 @@ void build_model(const cpm_params *p, DeviceModel *m)
             m->max_act[a] = p->max_act[a];
             m->r_act[a] = to_fixed(p->lambda_act[a] / (double)p->max_act[a]);
         }
+        if (p->lambda_persistence) {
+            m->lam_p[a] = to_fixed(p->lambda_persistence[a]);
+            m->mu_p[a] = (int64_t)std::llround(p->persistence_mu[a] * 16384.0);
+        }
+    }
+    // unit vectors of the Moore offsets, 2^-14 (eq. 5)
+    for (int i = 0; i < 27; ++i) {
+        const int o[3] = {i % 3 - 1, (i / 3) % 3 - 1, i / 9 - 1};
+        const double len = std::sqrt((double)(o[0] * o[0] + o[1] * o[1] + o[2] * o[2]));
+        for (int d = 0; d < 3; ++d) m->unit[i][d] = len > 0 ? (int32_t)std::llround(o[d] / len * 16384.0) : 0;
     }
     // Acceptance: TI[h] = floor(2^32 e^{-h/T}) while nonzero, TM, TL finer steps.
     const double T = p->temperature;
@@ -470,6 +507,26 @@ hipError_t start_lattice(const SweepArgs &a, const Layout &lay, char *ws, const 
 
 hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
+// Persistence directions after update t (t = 0: initialisation) from the
+// current lattice: centroid sums, then one thread per cell.
+hipError_t persist_step(cpm_handle *h, int64_t t, bool from_mirror, hipStream_t st)
+{
+    hipError_t e = cpm::launch_centroids(h->args, h->ndim, h->n_cells, h->ref, h->csum, st, from_mirror);
+    if (e != hipSuccess) return e;
+    cpm::PersistArgs p{};
+    p.pdir = h->pdir;
+    p.hist = h->hist;
+    p.csum = h->csum;
+    p.pairs = h->args.counters[h->activation & 1];
+    p.cell_type = h->args.cell_type;
+    p.model = h->args.model;
+    p.n_labels = h->n_cells + 1;
+    p.ndim = h->ndim;
+    p.slots = h->persist_slots;
+    for (int d = 0; d < 3; ++d) p.L[d] = h->L[d];
+    return cpm::launch_persist(p, t, st);
+}
+
 }  // namespace
 
 extern "C" {
@@ -538,8 +595,16 @@ int cpm_init(const cpm_params *params, int32_t *d_lattice, const int32_t *d_cell
     h->mirror_cells = lay.mirror_on ? reinterpret_cast<int16_t *>(ws + lay.mirror) : nullptr;
     h->ref = reinterpret_cast<int32_t *>(ws + lay.ref);
     fill_args(h->args, params, lay, ws, d_lattice, d_cell_type, d_act, single);
+    if (params->lambda_persistence) {
+        h->pdir = reinterpret_cast<int4 *>(ws + lay.pdir);
+        h->hist = reinterpret_cast<int64_t *>(ws + lay.hist);
+        h->csum = reinterpret_cast<int64_t *>(ws + lay.csum);
+        h->persist_slots = params->persistence_dt + 1;
+        h->args.pdir = h->pdir;
+    }
     if ((e = start_lattice(h->args, lay, ws, h->host_model.get(), params->ndim, n_cells, st)) != hipSuccess)
         return device_fail(e, "init");
+    if (h->pdir && (e = persist_step(h.get(), 0, false, st)) != hipSuccess) return device_fail(e, "persistence init");
     *out = h.release();
     return CPM_OK;
 }
@@ -567,6 +632,8 @@ int sweep_impl(cpm_handle *h, int32_t n_mcs, hipStream_t st)
         }
         if (h->act && (e = cpm::launch_act_decay(h->args.act, n_sites, st)) != hipSuccess)
             return device_fail(e, "act decay");
+        if (h->pdir && (e = persist_step(h, ++h->persist_t, h->mirror, st)) != hipSuccess)
+            return device_fail(e, "persistence update");
         ++h->mcs;
         h->attempts_run += (uint64_t)n_sites;
     }
@@ -628,6 +695,14 @@ int cpm_contacts(cpm_handle *h, int64_t *d_out, void *stream)
     if (!h || !d_out) return fail(CPM_EINVAL, "NULL argument");
     const hipError_t e = cpm::launch_contacts(h->args, h->ndim, h->n_types, d_out, as_stream(stream));
     return e == hipSuccess ? CPM_OK : device_fail(e, "contacts");
+}
+
+int cpm_persistence(cpm_handle *h, int32_t *d_dir, void *stream)
+{
+    if (!h || !d_dir) return fail(CPM_EINVAL, "NULL argument");
+    if (!h->pdir) return fail(CPM_EINVAL, "persistence is off for this lattice");
+    const hipError_t e = cpm::launch_copy_dirs(h->pdir, h->n_cells + 1, d_dir, as_stream(stream));
+    return e == hipSuccess ? CPM_OK : device_fail(e, "copy directions");
 }
 
 int cpm_counters(cpm_handle *h, int32_t *d_volume, int32_t *d_surface, void *stream)
@@ -696,6 +771,7 @@ int validate_batch(const cpm_params *p, int32_t n, const int32_t *n_cells)
     for (int32_t i = 0; i < n; ++i) {
         const int rc = validate(&p[i], n_cells[i]);
         if (rc != CPM_OK) return rc;
+        if (p[i].lambda_persistence) return fail(CPM_ENOTSUP, "persistence is not available in batches");
         if (p[i].ndim != p[0].ndim || p[i].sub != p[0].sub || p[i].attempts != p[0].attempts ||
             (p[i].act_enabled != 0) != (p[0].act_enabled != 0) || p[i].layout != p[0].layout)
             return fail(CPM_EINVAL, "lattices of a batch must share ndim, sub, attempts, act_enabled and layout");

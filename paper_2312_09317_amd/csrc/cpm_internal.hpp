@@ -43,6 +43,11 @@ struct DeviceModel {
     uint64_t EH[2048];
     uint64_t EM[256];
     uint64_t EL[256];
+    // persistence: strength (2^-16), previous-direction weight (2^-14), and
+    // the unit vectors of the Moore offsets, index (dx+1) + 3(dy+1) + 9(dz+1) (2^-14)
+    int64_t lam_p[kMaxTypes];
+    int64_t mu_p[kMaxTypes];
+    int32_t unit[27][3];
 };
 
 // How thread areas are grouped into workgroup tiles.  Tiles are numbered x
@@ -68,6 +73,7 @@ struct SweepArgs {
     int32_t *lat;          // the caller's int32 lattice
     const int32_t *cell_type;
     uint8_t *act;
+    const int4 *pdir;      // persistence direction per label (x, y, z, unused), 2^-14; NULL when off
     const DeviceModel *model;
     int32_t *counters[2];  // ping-pong (V, S) pairs per label
     int4 *dlist[2];        // per tile: accepted copies of an activation, by activation parity
@@ -109,6 +115,20 @@ struct StatsTables {
 
 // Launchers.  All asynchronous on `stream`.
 hipError_t launch_fill_i32(int32_t *p, int32_t value, size_t n, hipStream_t stream);
+// Persistence directions: init (P = 0, every history slot = the current
+// centroid) or one update (update index t >= 1), from centroid sums (ndim per
+// label) and volumes (the V of (V, S) counter pairs).
+struct PersistArgs {
+    int4 *pdir;
+    int64_t *hist;         // per label: slots x 3 centroids, 2^-16
+    const int64_t *csum;
+    const int32_t *pairs;
+    const int32_t *cell_type;
+    const DeviceModel *model;
+    int32_t n_labels, ndim, slots;
+    int32_t L[3];
+};
+hipError_t launch_persist(const PersistArgs &p, int64_t t, hipStream_t stream);
 // n_types x n_types int64 contact counts of a lattice (cleared first).
 hipError_t launch_contacts(const SweepArgs &a, int ndim, int n_types, int64_t *out, hipStream_t stream);
 // Volume, surface and (cent != NULL) centroid sums of every lattice of a
@@ -127,7 +147,9 @@ hipError_t launch_batch_mirror(const SweepArgs *d_args, int n_lattices, size_t m
                                hipStream_t stream);
 hipError_t launch_act_decay(uint8_t *act, size_t n, hipStream_t stream);
 hipError_t launch_centroids(const SweepArgs &a, int ndim, int32_t n_cells, int32_t *ref,
-                            int64_t *out, hipStream_t stream);
+                            int64_t *out, hipStream_t stream, bool from_mirror = false);
+// Persistence directions (x, y, z of each int4) into out, 3 x n_labels int32.
+hipError_t launch_copy_dirs(const int4 *pdir, int32_t n_labels, int32_t *out, hipStream_t stream);
 hipError_t launch_copy_counters(const int32_t *pairs, int32_t n_labels, int32_t *v_out,
                                 int32_t *s_out, hipStream_t stream);
 hipError_t launch_batch_activation(const BatchLaunch &b, uint32_t alpha, int parity, hipStream_t stream);

@@ -34,8 +34,8 @@ __device__ __forceinline__ int map_slot(LabelMap &m, int label)
 }
 
 // One workgroup's share (kSitesPerBlock sites from `block`) of a reduction
-// over lattice a.
-template <int D, int MODE>
+// over lattice a, read from its int32 labels or (M16) its int16 working copy.
+template <int D, int MODE, bool M16 = false>
 __device__ __forceinline__ void reduce_block(const SweepArgs &a, int64_t block, int32_t *v_out, int32_t *s_out,
                                              int stride, int32_t *ref, int64_t *cent)
 {
@@ -55,7 +55,7 @@ __device__ __forceinline__ void reduce_block(const SweepArgs &a, int64_t block, 
     for (int j = 0; j < kSitesPerThread; ++j) {
         const int64_t i = base + tid + (int64_t)j * kBlock;
         if (i >= n_sites) break;
-        const int32_t c = a.lat[i];
+        const int32_t c = M16 ? (int32_t) reinterpret_cast<const int16_t *>(a.cells)[i] : a.lat[i];
         if (c <= 0) continue;
         const int x = (int)(i % L0), y = (int)((i / L0) % L1), z = (int)(i / ((int64_t)L0 * L1));
         const int slot = map_slot(m, c);
@@ -110,11 +110,12 @@ __device__ __forceinline__ void reduce_block(const SweepArgs &a, int64_t block, 
     }
 }
 
-template <int D, int MODE>
+template <int D, int MODE, bool M16 = false>
 __global__ void __launch_bounds__(kBlock) reduce_kernel(SweepArgs a, int32_t *v_out, int32_t *s_out, int stride,
                                                         int32_t *ref, int64_t *cent)
 {
-    reduce_block<D, MODE>(a, blockIdx.x, v_out, s_out, stride, ref, cent);
+    static_assert(!M16 || MODE != kCount, "counts read the int32 labels");
+    reduce_block<D, MODE, M16>(a, blockIdx.x, v_out, s_out, stride, ref, cent);
 }
 
 // Every lattice of a batch in one launch: blockIdx.y is the lattice, outputs
@@ -172,6 +173,70 @@ __global__ void __launch_bounds__(kBlock) contact_kernel(SweepArgs a, unsigned l
         for (int w = 0; w < kBlock / 64; ++w) v += hist[w][b];
         if (v) atomicAdd(&out[ta * n_types + tb], v);
     }
+}
+
+// floor(sqrt(n)) for 0 <= n < 2^62; the FP64 root is only a first guess
+__device__ __forceinline__ int64_t isqrt_floor(int64_t n)
+{
+    if (n <= 0) return 0;
+    int64_t r = (int64_t)sqrt((double)n);
+    while (r > 0 && r * r > n) --r;
+    while ((r + 1) * (r + 1) <= n) ++r;
+    return r;
+}
+
+__device__ __forceinline__ int64_t div_floor(int64_t a, int64_t b)  // b > 0
+{
+    const int64_t q = a / b;
+    return (a % b != 0 && a < 0) ? q - 1 : q;
+}
+
+// One thread per label (label 0 untouched).  t == 0: initialise; t >= 1:
+// update number t, writing history slot t mod slots and reading slot
+// (t + 1) mod slots (the centroid of update t - dt, or the initial one).
+__global__ void persist_kernel(PersistArgs p, int64_t t)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < 1 || c >= p.n_labels) return;
+    const int64_t v = p.pairs[2 * c];
+    int64_t X[3] = {0, 0, 0};
+    for (int d = 0; d < p.ndim; ++d)
+        if (v > 0) X[d] = div_floor(p.csum[(int64_t)c * p.ndim + d] * 65536, v);
+    int64_t *h = p.hist + (int64_t)c * p.slots * 3;
+    if (t == 0) {
+        for (int k = 0; k < p.slots; ++k)
+            for (int d = 0; d < 3; ++d) h[3 * k + d] = X[d];
+        p.pdir[c] = make_int4(0, 0, 0, 0);
+        return;
+    }
+    if (v == 0) {
+        p.pdir[c] = make_int4(0, 0, 0, 0);
+        return;
+    }
+    const int64_t *old = h + 3 * ((t + 1) % p.slots);
+    int64_t D[3];
+    for (int d = 0; d < 3; ++d) {
+        const int64_t W = (int64_t)p.L[d] * 65536;
+        int64_t w = (X[d] - old[d]) % W;
+        if (w < 0) w += W;
+        if (w >= W / 2) w -= W;
+        D[d] = d < p.ndim ? w : 0;
+    }
+    int64_t *slot = h + 3 * (t % p.slots);
+    for (int d = 0; d < 3; ++d) slot[d] = X[d];
+    const int64_t nd = isqrt_floor(D[0] * D[0] + D[1] * D[1] + D[2] * D[2]);
+    const int4 prev = p.pdir[c];
+    const int64_t pp[3] = {prev.x, prev.y, prev.z};
+    const int64_t mu = p.model->mu_p[p.cell_type[c]];
+    int64_t q[3];
+    for (int d = 0; d < 3; ++d) {
+        const int64_t u = nd > 0 ? (D[d] * 16384) / nd : 0;
+        q[d] = (16384 - mu) * u + mu * pp[d];
+    }
+    const int64_t np = isqrt_floor(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+    p.pdir[c] = np > 0 ? make_int4((int)((q[0] * 16384) / np), (int)((q[1] * 16384) / np),
+                                   (int)((q[2] * 16384) / np), 0)
+                       : make_int4(0, 0, 0, 0);
 }
 
 __global__ void fill_i32_kernel(int32_t *p, int32_t value, size_t n)
@@ -246,6 +311,12 @@ hipError_t launch_contacts(const SweepArgs &a, int ndim, int n_types, int64_t *o
     return hipGetLastError();
 }
 
+hipError_t launch_persist(const PersistArgs &p, int64_t t, hipStream_t stream)
+{
+    persist_kernel<<<blocks_for((size_t)p.n_labels), kBlock, 0, stream>>>(p, t);
+    return hipGetLastError();
+}
+
 hipError_t launch_act_decay(uint8_t *act, size_t n, hipStream_t stream)
 {
     const size_t threads = (n + 15) / 16;
@@ -254,7 +325,7 @@ hipError_t launch_act_decay(uint8_t *act, size_t n, hipStream_t stream)
 }
 
 hipError_t launch_centroids(const SweepArgs &a, int ndim, int32_t n_cells, int32_t *ref, int64_t *out,
-                            hipStream_t stream)
+                            hipStream_t stream, bool from_mirror)
 {
     const size_t n = (size_t)a.L[0] * a.L[1] * a.L[2];
     const unsigned grid = (unsigned)((n + kSitesPerBlock - 1) / kSitesPerBlock);
@@ -262,13 +333,37 @@ hipError_t launch_centroids(const SweepArgs &a, int ndim, int32_t n_cells, int32
     if (e != hipSuccess) return e;
     e = launch_fill_i32(reinterpret_cast<int32_t *>(out), 0, ((size_t)n_cells + 1) * ndim * 2, stream);
     if (e != hipSuccess) return e;
-    if (ndim == 2) {
+    if (ndim == 2 && from_mirror) {
+        reduce_kernel<2, kRef, true><<<grid, kBlock, 0, stream>>>(a, nullptr, nullptr, 0, ref, nullptr);
+        reduce_kernel<2, kCentroid, true><<<grid, kBlock, 0, stream>>>(a, nullptr, nullptr, 0, ref, out);
+    } else if (ndim == 2) {
         reduce_kernel<2, kRef><<<grid, kBlock, 0, stream>>>(a, nullptr, nullptr, 0, ref, nullptr);
         reduce_kernel<2, kCentroid><<<grid, kBlock, 0, stream>>>(a, nullptr, nullptr, 0, ref, out);
+    } else if (from_mirror) {
+        reduce_kernel<3, kRef, true><<<grid, kBlock, 0, stream>>>(a, nullptr, nullptr, 0, ref, nullptr);
+        reduce_kernel<3, kCentroid, true><<<grid, kBlock, 0, stream>>>(a, nullptr, nullptr, 0, ref, out);
     } else {
         reduce_kernel<3, kRef><<<grid, kBlock, 0, stream>>>(a, nullptr, nullptr, 0, ref, nullptr);
         reduce_kernel<3, kCentroid><<<grid, kBlock, 0, stream>>>(a, nullptr, nullptr, 0, ref, out);
     }
+    return hipGetLastError();
+}
+
+namespace {
+__global__ void copy_dirs_kernel(const int4 *pdir, int32_t n_labels, int32_t *out)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n_labels) return;
+    const int4 v = i == 0 ? make_int4(0, 0, 0, 0) : pdir[i];
+    out[3 * i] = v.x;
+    out[3 * i + 1] = v.y;
+    out[3 * i + 2] = v.z;
+}
+}  // namespace
+
+hipError_t launch_copy_dirs(const int4 *pdir, int32_t n_labels, int32_t *out, hipStream_t stream)
+{
+    copy_dirs_kernel<<<blocks_for((size_t)n_labels), kBlock, 0, stream>>>(pdir, n_labels, out);
     return hipGetLastError();
 }
 

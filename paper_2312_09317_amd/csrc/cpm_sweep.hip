@@ -195,6 +195,15 @@ __device__ __forceinline__ bool evaluate_nb(const SweepArgs &a, const ThrTables 
         const int64_t rs = ls >= 1 ? m->r_act[ts] : 0;
         q += (rt * gt - rs * gs) >> 16;
     }
+    if (a.pdir && ls >= 1) {
+        // persistence: the copying cell ls extends from the source into the
+        // target; copies along its direction are favoured
+        const int o = (tx_ - sx_ + 1) + 3 * (ty_ - sy_ + 1) + 9 * (tz_ - sz_ + 1);
+        const int4 pd = a.pdir[ls];
+        const int64_t dot = (int64_t)m->unit[o][0] * pd.x + (int64_t)m->unit[o][1] * pd.y +
+                            (int64_t)m->unit[o][2] * pd.z;
+        q -= (m->lam_p[ts] * dot) >> 28;
+    }
     dso_out = dso;
     dsn_out = dsn;
     return metropolis32(tb, q, u2);

@@ -47,6 +47,9 @@ class Workload:
     lambda_act: Optional[np.ndarray] = None
     max_act: Optional[np.ndarray] = None
     act: Optional[np.ndarray] = None   # uint8, same shape as lattice
+    lambda_P: Optional[np.ndarray] = None   # persistence strength per type (None: off)
+    mu_P: Optional[np.ndarray] = None       # weight of the previous direction per type
+    dt_P: int = 1                           # MCS looked back for the displacement
     extra: dict = field(default_factory=dict)
 
     @property
@@ -211,6 +214,28 @@ def config2(L=1024, grid=100, seed=1, n_mcs=200, edge=8, corr=12.0, obstacle_fra
                  lambda_act=np.array([0.0, 300.0, 0.0, 0.0]), max_act=np.array([0, 30, 0, 0], dtype=np.int32),
                  act=np.zeros((L, L, L), dtype=np.uint8))
     w.extra["obstacle_voxels"] = int((lat < 0).sum())
+    return w
+
+
+def collective_3d(L=256, density=0.5, seed=1, n_mcs=200, lambda_p=40.0, mu=0.95, dt=15):
+    """A packed 3D collective of persistently moving cells: cubes of edge 5
+    on a jittered grid of an L^3 periodic lattice, as many as put cells of
+    the target volume 150 at `density` of the lattice (grid^3 cells, grid =
+    round((density L^3 / 150)^(1/3)); 38^3 = 54,872 at L = 256, density
+    0.5).  The paper's 3D settings: V_target 150, lambda_V 25, surface
+    target 1500, lambda_surface 0.2, J(cell, cell) 10, T 20; for the
+    collective J(cell, medium) 0, mu 0.95, dt 15 MCS, lambda_persistence 40."""
+    grid = max(1, int(round((density * L ** 3 / 150.0) ** (1.0 / 3.0))))
+    lat = jittered_cubes(L, grid, 5, seed)
+    n = grid ** 3
+    J, lv, vt, ls, st = _two_type(10.0, 0.0, 25.0, 150, 0.2, 1500)
+    w = Workload(f"3d-{L}^3-collective-{n}cells", 3, (L, L, L), lat,
+                 np.array([0] + [1] * n, dtype=np.int32), J, lv, vt, ls, st,
+                 T=20.0, n_mcs=n_mcs, seed=seed)
+    w.lambda_P = np.array([0.0, lambda_p])
+    w.mu_P = np.array([0.0, mu])
+    w.dt_P = int(dt)
+    w.extra["density"] = n * 150.0 / float(L) ** 3
     return w
 
 

@@ -73,6 +73,12 @@ def test_validate_accepts_workloads():
     (dict(lambda_act=[0, 1.0], max_act=[0, 5], sub=1), cpm.CPM_EINVAL),
     (dict(lambda_act=[0, 1.0], max_act=[0, 300]), cpm.CPM_EINVAL),
     (dict(lambda_act=[0, 1.0], max_act=[3, 5]), cpm.CPM_EINVAL),
+    (dict(lambda_persistence=[0, 40.0], persistence_mu=[0, 0.9], persistence_dt=0), cpm.CPM_EINVAL),
+    (dict(lambda_persistence=[0, 40.0], persistence_mu=[0, 1.5], persistence_dt=5), cpm.CPM_EINVAL),
+    (dict(lambda_persistence=[0, 40.0], persistence_mu=None, persistence_dt=5), cpm.CPM_EINVAL),
+    (dict(lambda_persistence=[0, 1e6], persistence_mu=[0, 0.5], persistence_dt=5), cpm.CPM_ERANGE),
+    (dict(lambda_persistence=[0, 40.0], persistence_mu=[0, 0.5], persistence_dt=5, dims=(2, 32, 32), sub=1),
+     cpm.CPM_EINVAL),                          # an axis of 2 sites makes Moore offsets ambiguous
 ])
 def test_validate_rejects(change, code):
     p, w = _params(**change)
@@ -81,6 +87,21 @@ def test_validate_rejects(change, code):
         cpm.cpm_workspace_bytes(p, w.n_cells)
     assert e.value.code == code
     assert cpm.load().cpm_last_error()  # a message is set
+
+
+def test_persistence_workspace_and_batches():
+    p, w = _params()
+    q, _ = _params(lambda_persistence=[0, 40.0], persistence_mu=[0, 0.95], persistence_dt=15)
+    assert cpm.cpm_validate(q, w.n_cells) == cpm.CPM_OK
+    # directions (int4) + 16 history centroids (3 x int64) + centroid sums per label
+    extra = cpm.cpm_workspace_bytes(q, w.n_cells) - cpm.cpm_workspace_bytes(p, w.n_cells)
+    labels = w.n_cells + 1
+    assert extra >= labels * (16 + 16 * 24 + 3 * 8)
+    with pytest.raises(cpm.CpmError) as e:
+        cpm.cpm_batch_workspace_bytes([q], [w.n_cells])
+    assert e.value.code == cpm.CPM_ENOTSUP
+    wc = inputs.collective_3d(L=32, n_mcs=1)
+    assert cpm.cpm_validate(cpm.Params.from_workload(wc), wc.n_cells) == cpm.CPM_OK
 
 
 def test_validate_rejects_bad_cell_count_and_null():
