@@ -183,7 +183,7 @@ def main():
     launches = args.steps * n_act
     # the activation kernels run back to back on one stream: the timed
     # region's time per launch is their average duration (the MCS loop
-    # launches nothing else in this workload, and the two int16 copy passes
+    # launches nothing else in this workload, and the two 16-bit copy passes
     # per call are under 0.05% of the region at 1000 MCS)
     avg_launch_s = (sweep_ms / 1e3) / launches
     per_launch_bytes = bytes_per_attempt(w.ndim, w.s, w.k, p_acc) * (w.n_sites // n_act)
@@ -226,7 +226,7 @@ def choose_layout(args, cpm, params, w):
 
 
 def bench_tissue(args):
-    """1024^3 lattice (4 GiB of int32 labels, too many cells for the int16
+    """1024^3 lattice (4 GiB of int32 labels, too many cells for the 16-bit
     copy) with Gaussian-random-field obstacles, ~820k cells of V_target
     1000, half of them motile with the Act term.  Step = 1 MCS = 64
     activations; nothing of it fits in the caches."""
@@ -328,7 +328,7 @@ def bench_sorting(args):
 
 def bench_collective(args):
     """A packed 3D collective of persistently moving cells on a 256^3
-    lattice (54,872 cells of V_target 150 at density 0.49: int32 labels),
+    lattice (54,872 cells of V_target 150 at density 0.49; 16-bit labels),
     the paper's 3D collective settings (mu 0.95, dt 15, lambda_persistence
     40).  Step = 1 MCS = 64 activations plus the direction update (centroid
     sums of every cell, then one thread per cell).  Also reports the polar

@@ -140,7 +140,8 @@ int cpm_workspace_bytes(const cpm_params *params, int32_t n_cells, size_t *bytes
  * 0 = each tile stages its active sub-areas with their halo in LDS, 1 = tiles
  * span whole lattice rows staged in LDS, 2 = attempts read the lattice in
  * place (k = 1); out[4] staged LDS bytes per workgroup; out[5] tiles per
- * activation; out[6] 1 if sweeps run on an int16 copy of the labels.  Results
+ * activation; out[6] 1 if sweeps run on a 16-bit copy of the labels (up to
+ * 65,534 cells).  Results
  * never depend on the tiling or layout. */
 int cpm_tile_shape(const cpm_params *params, int32_t n_cells, int32_t *out);
 

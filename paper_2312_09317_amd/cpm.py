@@ -215,7 +215,7 @@ def cpm_tile_shape(params: Params, n_cells: int) -> dict:
     out = (ctypes.c_int32 * 7)()
     _check(load().cpm_tile_shape(ctypes.byref(params.c), n_cells, out), "cpm_tile_shape")
     return {"areas": (out[0], out[1], out[2]), "layout": ("box", "full_rows", "in_place")[out[3]], "lds_bytes": out[4],
-            "tiles": out[5], "int16": bool(out[6])}
+            "tiles": out[5], "labels16": bool(out[6])}
 
 
 def cpm_init(params: Params, d_lattice, d_cell_type, n_cells: int, d_act, d_workspace, workspace_bytes: int,

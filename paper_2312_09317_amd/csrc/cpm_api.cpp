@@ -23,8 +23,8 @@ struct cpm_handle {
     int32_t n_cells = 0;
     int32_t n_types = 0;
     bool act = false;
-    bool mirror = false;             // sweeps run on an int16 copy of the lattice
-    int16_t *mirror_cells = nullptr;
+    bool mirror = false;             // sweeps run on a 16-bit copy of the lattice
+    uint16_t *mirror_cells = nullptr;
     SweepArgs args{};
     int32_t *ref = nullptr;          // centroid reference sites, n_cells + 1
     // persistence (NULL pdir = off): directions, centroid history, centroid sums
@@ -48,7 +48,7 @@ struct cpm_batch {
     std::vector<int32_t> n_cells;
     std::vector<size_t> site_off, label_off;         // packed offsets of lattices / cell-type arrays
     std::vector<int32_t *> ref;
-    std::vector<int16_t *> mirror_cells;
+    std::vector<uint16_t *> mirror_cells;
     std::vector<std::unique_ptr<DeviceModel>> models;
     std::vector<int2> work;
     SweepArgs *d_args = nullptr;
@@ -68,6 +68,7 @@ struct cpm_batch {
     uint64_t activation = 0;
     uint64_t mcs_run = 0;
     size_t max_sites = 0;
+    int64_t max_bricks = 0;          // largest centroid-reduction grid of the lattices
     bool use_graph = true;
     hipGraphExec_t mcs_graph = nullptr;  // one MCS: every activation, act decay, MCS counter
     ~cpm_batch()
@@ -109,8 +110,9 @@ struct Layout {
     int32_t dlist_cap;
 };
 
-// Labels fit the int16 working copy: cells 1..32767, medium 0, obstacle -1.
-bool use_mirror(int32_t n_cells) { return n_cells <= 32767; }
+// Labels fit the 16-bit working copy (label + 1): cells 1..65534, medium 0,
+// obstacle -1.
+bool use_mirror(int32_t n_cells) { return n_cells <= 65534; }
 
 // Widest load (16, 8 or 4 bytes) that divides both a row and the base address.
 int32_t chunk_for(const void *base, size_t row_bytes)
@@ -168,7 +170,7 @@ bool tile_geometry(const cpm_params *p, bool mirror, int force_layout, cpm::Tile
         g.lds_bytes = 0;
         return finish(2);
     }
-    // rows are staged in 16-, 8- or 4-byte chunks: int16 rows are even-length
+    // rows are staged in 16-, 8- or 4-byte chunks: 16-bit rows are even-length
     // (L0 is a multiple of 2s), activity rows a multiple of 4 bytes (s >= 2)
     const bool can_rows = k1 && na[0] <= cpm::kBlock && (L0 * cell) % 4 == 0 && (!act || L0 % 4 == 0) &&
                           (want[0] == 0 || want[0] == na[0]);
@@ -269,7 +271,7 @@ Layout layout_of(const cpm_params *p, int32_t n_cells, int mirror = -1, int forc
     l.dcount = take(2 * sizeof(int32_t) * (size_t)l.tg.n_tiles);
     l.stats = take(sizeof(uint64_t) * 2 * (size_t)l.tg.n_tiles);
     l.ref = take(sizeof(int32_t) * ((size_t)n_cells + 1));
-    l.mirror = take(l.mirror_on ? sizeof(int16_t) * (size_t)n_sites : 0);
+    l.mirror = take(l.mirror_on ? sizeof(uint16_t) * (size_t)n_sites : 0);
     const bool pers = p->lambda_persistence != nullptr;
     const size_t labels = (size_t)n_cells + 1;
     l.pdir = take(pers ? sizeof(int4) * labels : 0);
@@ -592,7 +594,7 @@ int cpm_init(const cpm_params *params, int32_t *d_lattice, const int32_t *d_cell
     h->n_types = params->n_types;
     h->act = params->act_enabled != 0;
     h->mirror = lay.mirror_on;
-    h->mirror_cells = lay.mirror_on ? reinterpret_cast<int16_t *>(ws + lay.mirror) : nullptr;
+    h->mirror_cells = lay.mirror_on ? reinterpret_cast<uint16_t *>(ws + lay.mirror) : nullptr;
     h->ref = reinterpret_cast<int32_t *>(ws + lay.ref);
     fill_args(h->args, params, lay, ws, d_lattice, d_cell_type, d_act, single);
     if (params->lambda_persistence) {
@@ -622,7 +624,7 @@ int sweep_impl(cpm_handle *h, int32_t n_mcs, hipStream_t st)
     const size_t n_sites = (size_t)h->L[0] * h->L[1] * h->L[2];
     hipError_t e;
     if (h->mirror && (e = cpm::launch_to_mirror(h->args.lat, h->mirror_cells, n_sites, st)) != hipSuccess)
-        return device_fail(e, "to int16 working copy");
+        return device_fail(e, "to 16-bit working copy");
     for (int32_t i = 0; i < n_mcs; ++i) {
         const uint32_t mcs = (uint32_t)h->mcs;
         for (uint32_t alpha = 0; alpha < n_act; ++alpha) {
@@ -638,7 +640,7 @@ int sweep_impl(cpm_handle *h, int32_t n_mcs, hipStream_t st)
         h->attempts_run += (uint64_t)n_sites;
     }
     if (h->mirror && (e = cpm::launch_from_mirror(h->mirror_cells, h->args.lat, n_sites, st)) != hipSuccess)
-        return device_fail(e, "from int16 working copy");
+        return device_fail(e, "from 16-bit working copy");
     return CPM_OK;
 }
 
@@ -878,8 +880,10 @@ int cpm_batch_init(const cpm_params *params, int32_t n, const int32_t *n_cells, 
         b->n_cells.push_back(n_cells[i]);
     }
     b->total_sites = sites;
-    for (int32_t i = 0; i < n; ++i)
+    for (int32_t i = 0; i < n; ++i) {
         b->max_sites = std::max(b->max_sites, (size_t)params[i].dims[0] * params[i].dims[1] * params[i].dims[2]);
+        b->max_bricks = std::max(b->max_bricks, cpm::reduce_brick_count(params[i].dims, params[i].ndim));
+    }
 
     std::vector<int32_t> types(labels);
     hipStream_t st = as_stream(stream);
@@ -901,7 +905,7 @@ int cpm_batch_init(const cpm_params *params, int32_t n, const int32_t *n_cells, 
                   b->act ? d_act + b->site_off[i] : nullptr, single);
         b->args.push_back(a);
         b->ref.push_back(reinterpret_cast<int32_t *>(lws + lay.ref));
-        b->mirror_cells.push_back(lay.mirror_on ? reinterpret_cast<int16_t *>(lws + lay.mirror) : nullptr);
+        b->mirror_cells.push_back(lay.mirror_on ? reinterpret_cast<uint16_t *>(lws + lay.mirror) : nullptr);
         b->models.emplace_back(new (std::nothrow) DeviceModel);
         if (!b->models.back()) return fail(CPM_EINVAL, "host allocation failed");
         build_model(&params[i], b->models.back().get());
@@ -1000,7 +1004,7 @@ int cpm_batch_sweep(cpm_batch *b, int32_t n_mcs, void *stream)
     if (b->use_graph && !b->mcs_graph && (e = capture_mcs(b, n_act)) != hipSuccess)
         return device_fail(e, "capture MCS graph");
     if (b->mirror && (e = cpm::launch_batch_mirror(b->d_args, b->n, b->max_sites, true, st)) != hipSuccess)
-        return device_fail(e, "to int16 working copy");
+        return device_fail(e, "to 16-bit working copy");
     if ((e = cpm::launch_set_u32(b->d_mcs, (uint32_t)b->mcs, st)) != hipSuccess) return device_fail(e, "set mcs");
     for (int32_t m = 0; m < n_mcs; ++m) {
         e = b->use_graph ? hipGraphLaunch(b->mcs_graph, st) : enqueue_mcs(b, n_act, st);
@@ -1010,7 +1014,7 @@ int cpm_batch_sweep(cpm_batch *b, int32_t n_mcs, void *stream)
         ++b->mcs_run;
     }
     if (b->mirror && (e = cpm::launch_batch_mirror(b->d_args, b->n, b->max_sites, false, st)) != hipSuccess)
-        return device_fail(e, "from int16 working copy");
+        return device_fail(e, "from 16-bit working copy");
     return CPM_OK;
 }
 
@@ -1037,7 +1041,7 @@ int cpm_batch_cell_stats(cpm_batch *b, int32_t *d_volume, int32_t *d_surface, in
 {
     if (!b || !d_volume || !d_surface) return fail(CPM_EINVAL, "NULL argument");
     const hipError_t e = cpm::launch_batch_cell_stats(b->d_args, b->stats_tables.label_off, b->n, b->ndim,
-                                                      b->max_sites, (size_t)b->stats_tables.total_labels, d_volume,
+                                                      b->max_sites, b->max_bricks, (size_t)b->stats_tables.total_labels, d_volume,
                                                       d_surface, b->scratch_ref, d_centroid_sum, as_stream(stream));
     return e == hipSuccess ? CPM_OK : device_fail(e, "cell stats");
 }

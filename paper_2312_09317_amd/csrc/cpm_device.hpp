@@ -23,6 +23,16 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
 
 __device__ __forceinline__ int wrap_once(int v, int L) { return v < 0 ? v + L : (v >= L ? v - L : v); }
 
+// Labels as stored.  int32: the label itself.  The 16-bit working copy holds
+// label + 1 (obstacle -1 -> 0, medium 0 -> 1, cells 1..65534 -> 2..65535),
+// so lattices of up to 65,534 cells sweep on half the bytes.
+__device__ __forceinline__ int label_of(int32_t v) { return v; }
+__device__ __forceinline__ int label_of(uint16_t v) { return (int)v - 1; }
+template <typename Cell>
+__device__ __forceinline__ Cell stored_label(int label) { return (Cell)label; }
+template <>
+__device__ __forceinline__ uint16_t stored_label<uint16_t>(int label) { return (uint16_t)(label + 1); }
+
 // Division by a divisor fixed for a whole workgroup: q = floor(n / d) as one
 // multiply-high, exact whenever n * d < 2^32 (m = floor((2^32 - 1) / d) + 1
 // overshoots 2^32 / d by less than 1, so the error n / 2^32 stays below the

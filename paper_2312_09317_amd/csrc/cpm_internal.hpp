@@ -69,7 +69,7 @@ struct TileGeometry {
 
 // Everything a sweep kernel needs, passed by value.
 struct SweepArgs {
-    void *cells;           // lattice the sweep works on: the caller's int32 one or the int16 mirror
+    void *cells;           // lattice the sweep works on: the caller's int32 one or the 16-bit mirror (label + 1)
     int32_t *lat;          // the caller's int32 lattice
     const int32_t *cell_type;
     uint8_t *act;
@@ -133,15 +133,18 @@ hipError_t launch_persist(const PersistArgs &p, int64_t t, hipStream_t stream);
 hipError_t launch_contacts(const SweepArgs &a, int ndim, int n_types, int64_t *out, hipStream_t stream);
 // Volume, surface and (cent != NULL) centroid sums of every lattice of a
 // batch, packed per label; ref is scratch of total_labels entries.
+// max_bricks: the largest reduce_brick_count of the batch's lattices.
 hipError_t launch_batch_cell_stats(const SweepArgs *d_args, const int64_t *d_label_off, int n_lattices, int ndim,
-                                   size_t max_sites, size_t total_labels, int32_t *v_out, int32_t *s_out,
-                                   int32_t *ref, int64_t *cent, hipStream_t stream);
+                                   size_t max_sites, int64_t max_bricks, size_t total_labels, int32_t *v_out,
+                                   int32_t *s_out, int32_t *ref, int64_t *cent, hipStream_t stream);
+// Workgroups of the centroid reductions over a lattice of dims L.
+int64_t reduce_brick_count(const int *L, int ndim);
 hipError_t launch_count(const SweepArgs &a, int ndim, int32_t *v_out, int32_t *s_out, int stride,
                         hipStream_t stream);
 hipError_t launch_activation(const SweepArgs &a, int ndim, bool act, bool mirror, uint32_t mcs,
                              uint32_t alpha, int parity, hipStream_t stream);
-hipError_t launch_to_mirror(const int32_t *lat, int16_t *mirror, size_t n, hipStream_t stream);
-hipError_t launch_from_mirror(const int16_t *mirror, int32_t *lat, size_t n, hipStream_t stream);
+hipError_t launch_to_mirror(const int32_t *lat, uint16_t *mirror, size_t n, hipStream_t stream);
+hipError_t launch_from_mirror(const uint16_t *mirror, int32_t *lat, size_t n, hipStream_t stream);
 // Every lattice of a batch (args[i].lat <-> args[i].cells) in one launch.
 hipError_t launch_batch_mirror(const SweepArgs *d_args, int n_lattices, size_t max_sites, bool to_mirror,
                                hipStream_t stream);

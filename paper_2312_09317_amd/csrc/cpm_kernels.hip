@@ -13,6 +13,24 @@ constexpr int kProbe = 32;
 constexpr int kSitesPerThread = 16;
 constexpr int kSitesPerBlock = kBlock * kSitesPerThread;
 
+// Brick of the run-based reductions: kTX threads of kSitesPerThread sites
+// along x, kY rows, kZ planes (kTX * kY * kZ = kBlock).
+template <int D>
+struct ReduceBrick {
+    static constexpr int kTX = D == 3 ? 1 : 4;
+    static constexpr int kY = D == 3 ? 16 : 64;
+    static constexpr int kZ = D == 3 ? 16 : 1;
+    static constexpr int kX = kTX * kSitesPerThread;
+    static_assert(kTX * kY * kZ == kBlock, "one thread per brick row segment");
+};
+
+template <int D>
+__host__ __device__ inline int64_t reduce_bricks(const int *L)
+{
+    using B = ReduceBrick<D>;
+    return (int64_t)((L[0] + B::kX - 1) / B::kX) * ((L[1] + B::kY - 1) / B::kY) * ((L[2] + B::kZ - 1) / B::kZ);
+}
+
 enum ReduceMode { kCount = 0, kRef = 1, kCentroid = 2 };
 
 struct LabelMap {
@@ -33,8 +51,53 @@ __device__ __forceinline__ int map_slot(LabelMap &m, int label)
     return -1;
 }
 
-// One workgroup's share (kSitesPerBlock sites from `block`) of a reduction
-// over lattice a, read from its int32 labels or (M16) its int16 working copy.
+// The kSitesPerThread consecutive labels from site i0 (n of them valid),
+// vector loads where the row of them is whole and 16-byte aligned.
+template <bool M16>
+__device__ __forceinline__ void load_run_labels(const SweepArgs &a, int64_t i0, int n, int (&lab)[kSitesPerThread])
+{
+    static_assert(kSitesPerThread == 16, "vector loads below assume 16 sites per thread");
+    if (M16) {
+        const uint16_t *src = reinterpret_cast<const uint16_t *>(a.cells) + i0;
+        if (n == kSitesPerThread && (reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+            const uint4 v[2] = {reinterpret_cast<const uint4 *>(src)[0], reinterpret_cast<const uint4 *>(src)[1]};
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const uint32_t w = (&v[k >> 2].x)[k & 3];
+                lab[2 * k] = label_of((uint16_t)(w & 0xFFFFu));
+                lab[2 * k + 1] = label_of((uint16_t)(w >> 16));
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < kSitesPerThread; ++k) lab[k] = k < n ? label_of(src[k]) : 0;
+        }
+    } else {
+        const int32_t *src = a.lat + i0;
+        if (n == kSitesPerThread && (reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int4 v = reinterpret_cast<const int4 *>(src)[k];
+                lab[4 * k] = v.x;
+                lab[4 * k + 1] = v.y;
+                lab[4 * k + 2] = v.z;
+                lab[4 * k + 3] = v.w;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < kSitesPerThread; ++k) lab[k] = k < n ? src[k] : 0;
+        }
+    }
+}
+
+// One workgroup's share of a reduction over lattice a, read from its int32
+// labels or (M16) its 16-bit working copy.  kCount: kSitesPerBlock sites
+// from `block`, thread t taking sites t, t + kBlock, ... (its neighbours'
+// reads coalesce).  kRef, kCentroid: brick `block` (ReduceBrick), thread t
+// taking kSitesPerThread consecutive sites of one row and touching the label
+// map once per run of one label: at the run's first site (the smallest index
+// of the run) for kRef, with the run's summed coordinates for kCentroid.
+// Bricks rather than row strips keep the workgroups that see one cell, and
+// so the global atomics per cell, few.
 template <int D, int MODE, bool M16 = false>
 __device__ __forceinline__ void reduce_block(const SweepArgs &a, int64_t block, int32_t *v_out, int32_t *s_out,
                                              int stride, int32_t *ref, int64_t *cent)
@@ -52,14 +115,14 @@ __device__ __forceinline__ void reduce_block(const SweepArgs &a, int64_t block, 
     const int64_t n_sites = (int64_t)L0 * L1 * L2;
     const int64_t base = block * kSitesPerBlock;
     constexpr int NNB = D == 2 ? 8 : 26;
-    for (int j = 0; j < kSitesPerThread; ++j) {
-        const int64_t i = base + tid + (int64_t)j * kBlock;
-        if (i >= n_sites) break;
-        const int32_t c = M16 ? (int32_t) reinterpret_cast<const int16_t *>(a.cells)[i] : a.lat[i];
-        if (c <= 0) continue;
-        const int x = (int)(i % L0), y = (int)((i / L0) % L1), z = (int)(i / ((int64_t)L0 * L1));
-        const int slot = map_slot(m, c);
-        if (MODE == kCount) {
+    if (MODE == kCount) {
+        for (int j = 0; j < kSitesPerThread; ++j) {
+            const int64_t i = base + tid + (int64_t)j * kBlock;
+            if (i >= n_sites) break;
+            const int32_t c = a.lat[i];
+            if (c <= 0) continue;
+            const int x = (int)(i % L0), y = (int)((i / L0) % L1), z = (int)(i / ((int64_t)L0 * L1));
+            const int slot = map_slot(m, c);
             int unlike = 0;
 #pragma unroll
             for (int n = 0; n < NNB; ++n) {
@@ -74,23 +137,65 @@ __device__ __forceinline__ void reduce_block(const SweepArgs &a, int64_t block, 
                 atomicAdd(&v_out[(size_t)c * stride], 1);
                 atomicAdd(&s_out[(size_t)c * stride], unlike);
             }
-        } else if (MODE == kRef) {
-            if (slot >= 0) atomicMin(&m.a[slot], (int32_t)i);
-            else atomicMin(&ref[c], (int32_t)i);
-        } else {
-            const int p[3] = {x, y, z};
-            const int L[3] = {L0, L1, L2};
-            const int r0 = ref[c];
-            const int r[3] = {r0 % L0, (r0 / L0) % L1, r0 / (L0 * L1)};
+        }
+    } else {
+        using B = ReduceBrick<D>;
+        const int nbx = (L0 + B::kX - 1) / B::kX, nby = (L1 + B::kY - 1) / B::kY;
+        const int bx = (int)(block % nbx), by = (int)((block / nbx) % nby), bz = (int)(block / ((int64_t)nbx * nby));
+        const int tx = tid % B::kTX, ty = (tid / B::kTX) % B::kY, tz = tid / (B::kTX * B::kY);
+        int x = bx * B::kX + tx * kSitesPerThread;
+        const int y = by * B::kY + ty, z = bz * B::kZ + tz;
+        if (x < L0 && y < L1 && z < L2) {
+            const int n = min(kSitesPerThread, L0 - x);
+            const int first = (z * L1 + y) * L0 + x;  // lattices hold fewer than 2^31 sites
+            int lab[kSitesPerThread];
+            load_run_labels<M16>(a, first, n, lab);
+            int cur = INT32_MIN;  // label of the open run
+            int r[3] = {0, 0, 0};
+            int64_t acc[3] = {0, 0, 0};
+            auto flush = [&]() {
+                const int slot = map_slot(m, cur);
 #pragma unroll
-            for (int d = 0; d < D; ++d) {
-                int diff = p[d] - r[d];
-                if (diff > L[d] / 2) diff -= L[d];
-                if (diff < -(L[d] - 1) / 2) diff += L[d];
-                const unsigned long long v = (unsigned long long)(int64_t)(r[d] + diff);
-                if (slot >= 0) atomicAdd(&m.c[slot][d], v);
-                else atomicAdd(reinterpret_cast<unsigned long long *>(&cent[(size_t)c * D + d]), v);
+                for (int d = 0; d < D; ++d) {
+                    if (slot >= 0) atomicAdd(&m.c[slot][d], (unsigned long long)acc[d]);
+                    else atomicAdd(reinterpret_cast<unsigned long long *>(&cent[(size_t)cur * D + d]),
+                                   (unsigned long long)acc[d]);
+                }
+            };
+            const int L[3] = {L0, L1, L2};
+#pragma unroll
+            for (int j = 0; j < kSitesPerThread; ++j) {
+                if (j < n) {
+                    const int c = lab[j];
+                    if (c != cur) {
+                        if (MODE == kCentroid && cur > 0) flush();
+                        cur = c;
+                        if (c > 0 && MODE == kRef) {
+                            const int slot = map_slot(m, c);
+                            if (slot >= 0) atomicMin(&m.a[slot], first + j);
+                            else atomicMin(&ref[c], first + j);
+                        } else if (c > 0) {
+                            const int r0 = ref[c];
+                            r[0] = r0 % L0;
+                            r[1] = (r0 / L0) % L1;
+                            r[2] = r0 / (L0 * L1);
+                            acc[0] = acc[1] = acc[2] = 0;
+                        }
+                    }
+                    if (MODE == kCentroid && c > 0) {
+                        const int p[3] = {x, y, z};
+#pragma unroll
+                        for (int d = 0; d < D; ++d) {
+                            int diff = p[d] - r[d];
+                            if (diff > L[d] / 2) diff -= L[d];
+                            if (diff < -(L[d] - 1) / 2) diff += L[d];
+                            acc[d] += r[d] + diff;
+                        }
+                    }
+                    ++x;
+                }
             }
+            if (MODE == kCentroid && cur > 0) flush();
         }
     }
     __syncthreads();
@@ -127,7 +232,8 @@ __global__ void __launch_bounds__(kBlock) batch_reduce_kernel(const SweepArgs *a
 {
     const SweepArgs &a = args[blockIdx.y];
     const int64_t n_sites = (int64_t)a.L[0] * a.L[1] * a.L[2];
-    if ((int64_t)blockIdx.x * kSitesPerBlock >= n_sites) return;
+    if (MODE == kCount ? (int64_t)blockIdx.x * kSitesPerBlock >= n_sites : blockIdx.x >= reduce_bricks<D>(a.L))
+        return;  // uniform over the block
     const int64_t o = label_off[blockIdx.y];
     reduce_block<D, MODE>(a, blockIdx.x, v_out ? v_out + o : nullptr, s_out ? s_out + o : nullptr, 1,
                           ref ? ref + o : nullptr, cent ? cent + o * D : nullptr);
@@ -327,8 +433,7 @@ hipError_t launch_act_decay(uint8_t *act, size_t n, hipStream_t stream)
 hipError_t launch_centroids(const SweepArgs &a, int ndim, int32_t n_cells, int32_t *ref, int64_t *out,
                             hipStream_t stream, bool from_mirror)
 {
-    const size_t n = (size_t)a.L[0] * a.L[1] * a.L[2];
-    const unsigned grid = (unsigned)((n + kSitesPerBlock - 1) / kSitesPerBlock);
+    const unsigned grid = (unsigned)(ndim == 2 ? reduce_bricks<2>(a.L) : reduce_bricks<3>(a.L));
     hipError_t e = launch_fill_i32(ref, INT32_MAX, (size_t)n_cells + 1, stream);
     if (e != hipSuccess) return e;
     e = launch_fill_i32(reinterpret_cast<int32_t *>(out), 0, ((size_t)n_cells + 1) * ndim * 2, stream);
@@ -361,6 +466,8 @@ __global__ void copy_dirs_kernel(const int4 *pdir, int32_t n_labels, int32_t *ou
 }
 }  // namespace
 
+int64_t reduce_brick_count(const int *L, int ndim) { return ndim == 2 ? reduce_bricks<2>(L) : reduce_bricks<3>(L); }
+
 hipError_t launch_copy_dirs(const int4 *pdir, int32_t n_labels, int32_t *out, hipStream_t stream)
 {
     copy_dirs_kernel<<<blocks_for((size_t)n_labels), kBlock, 0, stream>>>(pdir, n_labels, out);
@@ -368,10 +475,11 @@ hipError_t launch_copy_dirs(const int4 *pdir, int32_t n_labels, int32_t *out, hi
 }
 
 hipError_t launch_batch_cell_stats(const SweepArgs *d_args, const int64_t *d_label_off, int n_lattices, int ndim,
-                                   size_t max_sites, size_t total_labels, int32_t *v_out, int32_t *s_out,
-                                   int32_t *ref, int64_t *cent, hipStream_t stream)
+                                   size_t max_sites, int64_t max_bricks, size_t total_labels, int32_t *v_out,
+                                   int32_t *s_out, int32_t *ref, int64_t *cent, hipStream_t stream)
 {
     const dim3 grid((unsigned)((max_sites + kSitesPerBlock - 1) / kSitesPerBlock), (unsigned)n_lattices);
+    const dim3 grid_b((unsigned)max_bricks, (unsigned)n_lattices);
     hipError_t e;
     if ((e = launch_fill_i32(v_out, 0, total_labels, stream)) != hipSuccess) return e;
     if ((e = launch_fill_i32(s_out, 0, total_labels, stream)) != hipSuccess) return e;
@@ -382,11 +490,11 @@ hipError_t launch_batch_cell_stats(const SweepArgs *d_args, const int64_t *d_lab
     if ((e = launch_fill_i32(reinterpret_cast<int32_t *>(cent), 0, total_labels * ndim * 2, stream)) != hipSuccess)
         return e;
     if (ndim == 2) {
-        batch_reduce_kernel<2, kRef><<<grid, kBlock, 0, stream>>>(d_args, d_label_off, nullptr, nullptr, ref, nullptr);
-        batch_reduce_kernel<2, kCentroid><<<grid, kBlock, 0, stream>>>(d_args, d_label_off, nullptr, nullptr, ref, cent);
+        batch_reduce_kernel<2, kRef><<<grid_b, kBlock, 0, stream>>>(d_args, d_label_off, nullptr, nullptr, ref, nullptr);
+        batch_reduce_kernel<2, kCentroid><<<grid_b, kBlock, 0, stream>>>(d_args, d_label_off, nullptr, nullptr, ref, cent);
     } else {
-        batch_reduce_kernel<3, kRef><<<grid, kBlock, 0, stream>>>(d_args, d_label_off, nullptr, nullptr, ref, nullptr);
-        batch_reduce_kernel<3, kCentroid><<<grid, kBlock, 0, stream>>>(d_args, d_label_off, nullptr, nullptr, ref, cent);
+        batch_reduce_kernel<3, kRef><<<grid_b, kBlock, 0, stream>>>(d_args, d_label_off, nullptr, nullptr, ref, nullptr);
+        batch_reduce_kernel<3, kCentroid><<<grid_b, kBlock, 0, stream>>>(d_args, d_label_off, nullptr, nullptr, ref, cent);
     }
     return hipGetLastError();
 }

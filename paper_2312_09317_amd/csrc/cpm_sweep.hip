@@ -89,7 +89,7 @@ __device__ __forceinline__ int64_t gm_lds(const DeviceModel *m, const int64_t *l
 #pragma unroll
     for (int n = 0; n < NNB; ++n) {
         const int u = map.at(x + nb_dx<D>(n), y + nb_dy<D>(n), z + nb_dz<D>(n));
-        const int lu = (int)lab[u];
+        const int lu = label_of(lab[u]);
         const uint32_t au = lact[u];
         if (lu == cell) {
             zero |= au == 0;
@@ -221,7 +221,7 @@ __device__ __forceinline__ bool evaluate(const SweepArgs &a, const ThrTables &tb
     auto nbl = [&](int n) {
         const int dx = nb_dx<D>(n);
         const int xx = dx < 0 ? xm : (dx > 0 ? xp : x0);
-        return (int)lab[xx + map.row(ty_ + nb_dy<D>(n), tz_ + nb_dz<D>(n))];
+        return label_of(lab[xx + map.row(ty_ + nb_dy<D>(n), tz_ + nb_dz<D>(n))]);
     };
     return evaluate_nb<Cell, D, ACT, SINGLE, LAYOUT>(a, tb, jr, st, nbl, lab, lact, map, tx_, ty_, tz_, sx_, sy_,
                                                      sz_, lt, ls, cnt_t, cnt_s, u2, dso_out, dsn_out);
@@ -344,8 +344,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
         return (int)(((size_t)gz * L1 + gy) * L0 + gx);
     };
     auto commit = [&](int t, int gi, int lt, int ls, int64_t dso, int64_t dsn) {
-        if (!DIRECT) lab[t] = (Cell)ls;
-        cells[gi] = (Cell)ls;
+        if (!DIRECT) lab[t] = stored_label<Cell>(ls);
+        cells[gi] = stored_label<Cell>(ls);
         if (ACT) {
             const int ts = ls == 0 ? 0 : (a.single_type >= 0 ? a.single_type : a.cell_type[ls]);
             const uint8_t na = (ls >= 1 && a.model->max_act[ts] > 0) ? (uint8_t)a.model->max_act[ts] : (uint8_t)0;
@@ -370,8 +370,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
         const bool mine = tid < areas;
         if (mine) {
             draw(tid, 0, ttx, tty, ttz, ssx, ssy, ssz, u2, area_id);
-            lt = lab[map.at(ttx, tty, ttz)];
-            ls = lab[map.at(ssx, ssy, ssz)];
+            lt = label_of(lab[map.at(ttx, tty, ttz)]);
+            ls = label_of(lab[map.at(ssx, ssy, ssz)]);
         }
         __syncthreads();  // LDS counters and tables initialised
         if (tid < prev_n) add_deltas(wr, prev_rec);
@@ -417,8 +417,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
         if (!K1 || tid >= areas) return;
         uint32_t area_id;
         draw(tid, 0, d_ttx, d_tty, d_ttz, d_ssx, d_ssy, d_ssz, d_u2, area_id);
-        d_lt = lab[map.at(d_ttx, d_tty, d_ttz)];
-        d_ls = lab[map.at(d_ssx, d_ssy, d_ssz)];
+        d_lt = label_of(lab[map.at(d_ttx, d_tty, d_ttz)]);
+        d_ls = label_of(lab[map.at(d_ssx, d_ssy, d_ssz)]);
         d_nontrivial = d_lt != d_ls && d_lt >= 0 && d_ls >= 0;
         if (d_nontrivial) {
             d_ct = seen_counters(rd, d_lt, nullptr, 0);
@@ -560,7 +560,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
             const int ttx = e.x & 0xFFFF, tty = e.x >> 16, ttz = e.y & 0xFFFF;
             const int ssz = e.y >> 16, ssx = (int)(int16_t)(e.z & 0xFFFF), ssy = e.z >> 16;
             const int t = map.at(ttx, tty, ttz);
-            const int lt = lab[t], ls = lab[map.at(ssx, ssy, ssz)];
+            const int lt = label_of(lab[t]), ls = label_of(lab[map.at(ssx, ssy, ssz)]);
             int64_t dso, dsn;
             if (evaluate<Cell, D, ACT, SINGLE, LAYOUT>(a, tb, jr, sht, lab, lact, map, ttx, tty, ttz, ssx, ssy, ssz, lt,
                                                         ls, make_int2(c.x, c.y), make_int2(c.z, c.w), (uint32_t)e.w,
@@ -579,7 +579,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
                 uint32_t u2, area_id;
                 draw(tid, j, ttx, tty, ttz, ssx, ssy, ssz, u2, area_id);
                 const int t = map.at(ttx, tty, ttz);
-                const int lt = lab[t], ls = lab[map.at(ssx, ssy, ssz)];
+                const int lt = label_of(lab[t]), ls = label_of(lab[map.at(ssx, ssy, ssz)]);
                 int4 rec = make_int4(0, 0, 0, 0);
                 if (lt != ls && lt >= 0 && ls >= 0) {
                     ++my_nontrivial;
@@ -662,34 +662,42 @@ hipError_t launch_c(const SweepArgs &a, int ndim, bool act, uint32_t mcs, uint32
                : launch_s<Cell, 3, false>(a, mcs, alpha, parity, lds, st);
 }
 
-__global__ void to_mirror_kernel(const int32_t *__restrict__ lat, int16_t *__restrict__ mir, size_t n)
+__device__ __forceinline__ ushort4 encode4(int4 v)
+{
+    ushort4 w;
+    w.x = stored_label<uint16_t>(v.x);
+    w.y = stored_label<uint16_t>(v.y);
+    w.z = stored_label<uint16_t>(v.z);
+    w.w = stored_label<uint16_t>(v.w);
+    return w;
+}
+
+__device__ __forceinline__ int4 decode4(ushort4 w)
+{
+    return make_int4(label_of(w.x), label_of(w.y), label_of(w.z), label_of(w.w));
+}
+
+__global__ void to_mirror_kernel(const int32_t *__restrict__ lat, uint16_t *__restrict__ mir, size_t n)
 {
     const size_t i = ((size_t)blockIdx.x * kBlock + threadIdx.x) * 4;
     if (i + 4 <= n) {
-        const int4 v = *reinterpret_cast<const int4 *>(lat + i);
-        short4 w;
-        w.x = (short)v.x;
-        w.y = (short)v.y;
-        w.z = (short)v.z;
-        w.w = (short)v.w;
-        *reinterpret_cast<short4 *>(mir + i) = w;
+        *reinterpret_cast<ushort4 *>(mir + i) = encode4(*reinterpret_cast<const int4 *>(lat + i));
     } else {
-        for (size_t j = i; j < n; ++j) mir[j] = (int16_t)lat[j];
+        for (size_t j = i; j < n; ++j) mir[j] = stored_label<uint16_t>(lat[j]);
     }
 }
 
-__global__ void from_mirror_kernel(const int16_t *__restrict__ mir, int32_t *__restrict__ lat, size_t n)
+__global__ void from_mirror_kernel(const uint16_t *__restrict__ mir, int32_t *__restrict__ lat, size_t n)
 {
     const size_t i = ((size_t)blockIdx.x * kBlock + threadIdx.x) * 4;
     if (i + 4 <= n) {
-        const short4 w = *reinterpret_cast<const short4 *>(mir + i);
-        *reinterpret_cast<int4 *>(lat + i) = make_int4(w.x, w.y, w.z, w.w);
+        *reinterpret_cast<int4 *>(lat + i) = decode4(*reinterpret_cast<const ushort4 *>(mir + i));
     } else {
-        for (size_t j = i; j < n; ++j) lat[j] = mir[j];
+        for (size_t j = i; j < n; ++j) lat[j] = label_of(mir[j]);
     }
 }
 
-// All lattices of a batch to / from their int16 working copies in one
+// All lattices of a batch to / from their 16-bit working copies in one
 // launch: blockIdx.y is the lattice, x blocks stride over its sites in
 // groups of 4 (lattice sizes are multiples of (2s)^d, bases 16-byte aligned).
 template <bool TO>
@@ -697,25 +705,15 @@ __global__ void batch_mirror_kernel(const SweepArgs *__restrict__ args)
 {
     const SweepArgs &a = args[blockIdx.y];
     const size_t n = (size_t)a.L[0] * a.L[1] * a.L[2];
-    int16_t *mir = static_cast<int16_t *>(a.cells);
+    uint16_t *mir = static_cast<uint16_t *>(a.cells);
     for (size_t i = ((size_t)blockIdx.x * kBlock + threadIdx.x) * 4; i < n; i += (size_t)gridDim.x * kBlock * 4) {
         if (i + 4 <= n) {
-            if (TO) {
-                const int4 v = *reinterpret_cast<const int4 *>(a.lat + i);
-                short4 w;
-                w.x = (short)v.x;
-                w.y = (short)v.y;
-                w.z = (short)v.z;
-                w.w = (short)v.w;
-                *reinterpret_cast<short4 *>(mir + i) = w;
-            } else {
-                const short4 w = *reinterpret_cast<const short4 *>(mir + i);
-                *reinterpret_cast<int4 *>(a.lat + i) = make_int4(w.x, w.y, w.z, w.w);
-            }
+            if (TO) *reinterpret_cast<ushort4 *>(mir + i) = encode4(*reinterpret_cast<const int4 *>(a.lat + i));
+            else *reinterpret_cast<int4 *>(a.lat + i) = decode4(*reinterpret_cast<const ushort4 *>(mir + i));
         } else {
             for (size_t j = i; j < n; ++j) {
-                if (TO) mir[j] = (int16_t)a.lat[j];
-                else a.lat[j] = mir[j];
+                if (TO) mir[j] = stored_label<uint16_t>(a.lat[j]);
+                else a.lat[j] = label_of(mir[j]);
             }
         }
     }
@@ -734,7 +732,7 @@ hipError_t launch_activation(const SweepArgs &a, int ndim, bool act, bool mirror
                              int parity, hipStream_t stream)
 {
     const size_t lds = (size_t)a.tg.lds_bytes;
-    return mirror ? launch_c<int16_t>(a, ndim, act, mcs, alpha, parity, lds, stream)
+    return mirror ? launch_c<uint16_t>(a, ndim, act, mcs, alpha, parity, lds, stream)
                   : launch_c<int32_t>(a, ndim, act, mcs, alpha, parity, lds, stream);
 }
 
@@ -773,17 +771,17 @@ hipError_t launch_batch_c(const BatchLaunch &b, uint32_t alpha, int parity, hipS
 
 hipError_t launch_batch_activation(const BatchLaunch &b, uint32_t alpha, int parity, hipStream_t stream)
 {
-    return b.mirror ? launch_batch_c<int16_t>(b, alpha, parity, stream) : launch_batch_c<int32_t>(b, alpha, parity, stream);
+    return b.mirror ? launch_batch_c<uint16_t>(b, alpha, parity, stream) : launch_batch_c<int32_t>(b, alpha, parity, stream);
 }
 
-hipError_t launch_to_mirror(const int32_t *lat, int16_t *mirror, size_t n, hipStream_t stream)
+hipError_t launch_to_mirror(const int32_t *lat, uint16_t *mirror, size_t n, hipStream_t stream)
 {
     const size_t threads = (n + 3) / 4;
     to_mirror_kernel<<<(unsigned)((threads + kBlock - 1) / kBlock), kBlock, 0, stream>>>(lat, mirror, n);
     return hipGetLastError();
 }
 
-hipError_t launch_from_mirror(const int16_t *mirror, int32_t *lat, size_t n, hipStream_t stream)
+hipError_t launch_from_mirror(const uint16_t *mirror, int32_t *lat, size_t n, hipStream_t stream)
 {
     const size_t threads = (n + 3) / 4;
     from_mirror_kernel<<<(unsigned)((threads + kBlock - 1) / kBlock), kBlock, 0, stream>>>(mirror, lat, n);

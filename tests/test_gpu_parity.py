@@ -124,14 +124,15 @@ def test_resume_and_chunking(torch_cuda):
 
 
 @pytest.mark.parametrize("single", [True, False])
-def test_wide_labels_int32_path(torch_cuda, single):
-    # more than 32767 cell labels: the sweep works on the int32 lattice itself
-    dims = (32, 32, 32)
-    n_cells = 40000
+@pytest.mark.parametrize("dims,n_cells,labels16", [((32, 32, 32), 40000, True), ((48, 48, 48), 70000, False)])
+def test_wide_labels(torch_cuda, single, dims, n_cells, labels16):
+    # labels past 32767 still fit the 16-bit working copy (label + 1, up to
+    # 65,534 cells); past that the sweep works on the int32 lattice itself
     w = _multi(dims, 3, seed=12, n_cells=n_cells, obstacles=0.02)
     if single:
         w.cell_type = np.array([0] + [2] * n_cells, dtype=np.int32)
-    assert w.lattice.max() > 32767
+    assert w.lattice.max() > (32767 if labels16 else 65534)
+    assert cpm.cpm_tile_shape(cpm.Params.from_workload(w), w.n_cells)["labels16"] == labels16
     st, sim = run_both(torch_cuda, w, 4)
     assert_same(st, sim, torch_cuda)
 
@@ -180,7 +181,7 @@ def test_config1_full_size(torch_cuda):
 def test_tissue_crop(torch_cuda):
     # the tissue-scale workload's recipe (Gaussian-random-field obstacles,
     # motile and non-motile cells, Act term, int32 labels when cells exceed
-    # the int16 range are covered elsewhere) at 128^3, every site compared
+    # the 16-bit range are covered elsewhere) at 128^3, every site compared
     w = inputs.config2(L=128, grid=12, n_mcs=2)
     st, sim = run_both(torch_cuda, w, 2)
     assert_same(st, sim, torch_cuda)

@@ -90,13 +90,13 @@ def test_mixing_weight_extremes(torch_cuda, mu):
         np.testing.assert_array_equal(sim0.lattice.cpu().numpy(), sim.lattice.cpu().numpy())
 
 
-def test_dying_cells_and_wide_labels(torch_cuda):
-    # more than 32767 labels (the int32 path), most cells one or a few sites,
-    # so many die during the run (their direction is reset to zero)
-    dims = (32, 32, 32)
-    w = _multi(dims, 3, seed=23, n_cells=40000, obstacles=0.02)
+@pytest.mark.parametrize("dims,n_cells", [((32, 32, 32), 40000), ((48, 48, 48), 70000)])
+def test_dying_cells_and_wide_labels(torch_cuda, dims, n_cells):
+    # labels past 32767 (16-bit copy) and past 65534 (int32 path), most cells
+    # one or a few sites, so many die during the run (direction reset to zero)
+    w = _multi(dims, 3, seed=23, n_cells=n_cells, obstacles=0.02)
     w = _with_persistence(w, dt=2)
-    assert w.lattice.max() > 32767
+    assert w.lattice.max() > (32767 if n_cells < 65535 else 65534)
     st, sim = run_pers(torch_cuda, w, 4)
     assert_same(st, sim, torch_cuda)
     assert_dirs(st, sim, torch_cuda)
@@ -113,7 +113,7 @@ def test_collective_crop(torch_cuda):
 
 
 def test_collective_full_size(torch_cuda):
-    # 256^3, 54,872 cells (int32 labels) in the benchmark's launch
+    # 256^3, 54,872 cells (16-bit labels) in the benchmark's launch
     # configuration: every site, counter and direction after 3 MCS
     w = inputs.collective_3d(n_mcs=3)
     st, sim = run_pers(torch_cuda, w, 3)
