@@ -43,6 +43,8 @@ class OrcModel(ctypes.Structure):
         ("lambda_P", ctypes.POINTER(ctypes.c_double)),
         ("mu_P", ctypes.POINTER(ctypes.c_double)),
         ("dt_P", ctypes.c_int32),
+        ("lambda_C", ctypes.POINTER(ctypes.c_double)),
+        ("C_field", ctypes.POINTER(ctypes.c_int16)),
     ]
 
 
@@ -95,7 +97,7 @@ class Model:
 
     def __init__(self, ndim, dims, J, lambda_V, V_target, lambda_S=None, S_target=None,
                  lambda_act=None, max_act=None, T=20.0, seed=1, lattice_id=0, s=2, k=1,
-                 obstacle_type=-1, lambda_P=None, mu_P=None, dt_P=1):
+                 obstacle_type=-1, lambda_P=None, mu_P=None, dt_P=1, lambda_C=None, C_field=None):
         n = len(lambda_V)
         self.J = np.ascontiguousarray(np.asarray(J, dtype=np.float64).reshape(n, n))
         self.lambda_V = np.ascontiguousarray(lambda_V, dtype=np.float64)
@@ -132,6 +134,14 @@ class Model:
         self.c.lambda_P = self.lambda_P.ctypes.data_as(dp) if self.persistence else None
         self.c.mu_P = self.mu_P.ctypes.data_as(dp) if self.persistence else None
         self.c.dt_P = int(dt_P)
+        # chemotaxis (eq. 4): per-type strength and the field C, int16 in
+        # units of 2^-14, ndim components per site in lattice order
+        self.chemotaxis = lambda_C is not None
+        self.lambda_C = np.ascontiguousarray(np.zeros(n) if lambda_C is None else lambda_C, dtype=np.float64)
+        self.C_field = None if C_field is None else np.ascontiguousarray(C_field, dtype=np.int16).reshape(-1)
+        self.c.lambda_C = self.lambda_C.ctypes.data_as(dp) if self.chemotaxis else None
+        self.c.C_field = self.C_field.ctypes.data_as(ctypes.POINTER(ctypes.c_int16)) \
+            if self.C_field is not None else None
 
     @property
     def dims(self):

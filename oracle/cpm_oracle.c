@@ -33,6 +33,10 @@
  *     renormalised; a copy into a site favoured in proportion to how well the
  *     copy direction (source -> target) aligns with the copying cell's
  *     direction.  Kept in integer fixed point (see persistence_update).
+ *   - Chemotaxis extension (Methods, eq. 4): a fixed vector field C; a copy
+ *     from source i into a target is favoured in proportion to how well its
+ *     direction aligns with C at i (same sign reading and fixed point as the
+ *     persistence term).
  *   - Serial CPM (Methods, first paragraph) and a symmetric-proposal variant
  *     used only to pin the Hamiltonian + acceptance against Boltzmann
  *     weights.
@@ -80,6 +84,9 @@ typedef struct orc_model {
     const double *lambda_P;    /* per type, persistence strength (NULL: no persistence term) */
     const double *mu_P;        /* per type, weight of the previous direction, 0..1 */
     int32_t dt_P;              /* MCS looked back for the displacement, >= 1 */
+    const double *lambda_C;    /* per type, chemotaxis strength (NULL: no chemotaxis term) */
+    const int16_t *C_field;    /* the vector field C: components x, y (, z) of each site, sites in
+                                * lattice order, in units of 2^-14 */
 } orc_model;
 
 /* Quantised energy parameters and acceptance tables. */
@@ -97,6 +104,7 @@ typedef struct orc_q {
     uint64_t EH[2048], EM[256], EL[256];
     int64_t lP[16];        /* persistence strength, 2^-16 */
     int64_t muP[16];       /* previous-direction weight, 2^-14 */
+    int64_t lC[16];        /* chemotaxis strength, 2^-16 */
     int32_t U[27][3];      /* unit vector of offset (dx,dy,dz), index (dx+1)+3(dy+1)+9(dz+1), 2^-14 */
 } orc_q;
 
@@ -186,6 +194,10 @@ static int model_prepare(const orc_model *m, orc_q *q)
             q->lP[a] = quantise(m->lambda_P[a]);
             q->muP[a] = (int64_t)llround(m->mu_P[a] * 16384.0);
         }
+    }
+    if (m->lambda_C) {
+        if (!m->C_field) return ORC_EINVAL;
+        for (int a = 0; a < m->n_types; a++) q->lC[a] = quantise(m->lambda_C[a]);
     }
     /* unit vectors of the Moore offsets, rounded to 2^-14 in FP64 */
     for (int dz = -1; dz <= 1; dz++)
@@ -372,9 +384,27 @@ static int64_t delta_h(const orc_state *st, int64_t t, int64_t src, int32_t nl,
         int64_t dot = (int64_t)u[0] * p[0] + (int64_t)u[1] * p[1] + (int64_t)u[2] * p[2];
         pers = -((q->lP[tn] * dot) >> 28); /* arithmetic shift: floor, then negated */
     }
+    /* chemotaxis (eq. 4): the field at the source i, dotted with the unit
+     * vector of the copy from i into the target; read like persistence, the
+     * copying cell nl is favoured when it extends along the field */
+    int64_t chem = 0;
+    if (m->lambda_C && nl >= 1 && src >= 0) {
+        int sx, sy, sz;
+        coords_of(m, src, &sx, &sy, &sz);
+        int o[3] = {x - sx, y - sy, z - sz};
+        for (int d = 0; d < 3; d++) {
+            if (o[d] > 1) o[d] -= m->L[d];
+            if (o[d] < -1) o[d] += m->L[d];
+        }
+        const int32_t *u = q->U[(o[0] + 1) + 3 * (o[1] + 1) + 9 * (o[2] + 1)];
+        const int16_t *c = m->C_field + (int64_t)m->ndim * src;
+        int64_t dot = 0;
+        for (int d = 0; d < m->ndim; d++) dot += (int64_t)u[d] * c[d];
+        chem = -((q->lC[tn] * dot) >> 28);
+    }
     *dS_old = dso;
     *dS_new = dsn;
-    return adh + vol + surf + actterm + pers;
+    return adh + vol + surf + actterm + pers + chem;
 }
 
 int oracle_delta_h(const orc_model *m, const int32_t *lat, const int32_t *type, int32_t C,
