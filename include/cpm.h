@@ -123,6 +123,17 @@ typedef struct cpm_params {
     const double *lambda_persistence; /* n_types (2^-16 quantised like J) */
     const double *persistence_mu;     /* n_types, 0..1 */
     int32_t persistence_dt;           /* >= 1 */
+    /* Chemotaxis (Methods, eq. 4; NULL lambda_chemotaxis = off).  A fixed
+     * vector field C: d_chemotaxis_field is device memory, int16, ndim
+     * components (x, y[, z]) per site in lattice order, in units of 2^-14
+     * (|C| <= 1 in the paper), 4-byte aligned, owned by the caller and read
+     * until the handle is destroyed.  A copy from source s into target t by
+     * cell c of type tc adds -floor(lambda * (U(t - s) . C(s)) / 2^28) (2^-16
+     * units) to the energy change, U as for persistence: copies along the
+     * field at their source are favoured (the sign read as for persistence).
+     * Medium copies get no term. */
+    const double *lambda_chemotaxis;  /* n_types (2^-16 quantised like J) */
+    const int16_t *d_chemotaxis_field;
 } cpm_params;
 
 typedef struct cpm_handle cpm_handle;
@@ -242,6 +253,22 @@ int cpm_batch_sweep(cpm_batch *b, int32_t n_mcs, void *stream);
 /* enabled = 0: cpm_batch_sweep launches the same kernels one by one instead
  * of the graph (same results).  Pure host. */
 int cpm_batch_use_graph(cpm_batch *b, int32_t enabled);
+/* Runs n_mcs MCS of the serial CPM on every lattice (Methods, first
+ * paragraph; the reference of Fig. 5 and Fig. 6E): per MCS, N = sites copy
+ * attempts, attempt i at target floor(u0 * N / 2^32) with the Philox counter
+ * (i, MCS, 0xFFFFFF00, lattice_id), a Moore neighbour as source from u1 and
+ * the acceptance draw u2; every attempt sees the lattice, the activity and
+ * the per-cell counters as the attempt before it left them; Act decays at
+ * the end of each MCS.  Energies as for cpm_batch_sweep (adhesion, volume,
+ * surface, Act, chemotaxis).  One wave per lattice: this is the slow
+ * reference, not a fast path.  Shares the MCS counter and the attempt
+ * statistics with cpm_batch_sweep, and may be mixed with it. */
+int cpm_batch_sweep_serial(cpm_batch *b, int32_t n_mcs, void *stream);
+/* Per site, the number of lattices of the batch that hold a cell (label
+ * >= 1) there: d_counts int32, one entry per site of one lattice (device,
+ * overwritten).  Every lattice must have the same dims.  The per-pixel
+ * occupancy of an ensemble (Fig. 5A, Fig. 6E). */
+int cpm_batch_occupancy(cpm_batch *b, int32_t *d_counts, void *stream);
 int cpm_batch_counters(cpm_batch *b, int32_t *d_volume, int32_t *d_surface, void *stream);
 int cpm_batch_cell_stats(cpm_batch *b, int32_t *d_volume, int32_t *d_surface, int64_t *d_centroid_sum,
                          void *stream);

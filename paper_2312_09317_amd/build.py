@@ -10,7 +10,7 @@ OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libcpm.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
-SOURCES = ["cpm_sweep.hip", "cpm_kernels.hip", "cpm_stats.hip", "emu_kernels.hip", "cpm_api.cpp", "emu_api.cpp"]
+SOURCES = ["cpm_sweep.hip", "cpm_serial.hip", "cpm_kernels.hip", "cpm_stats.hip", "emu_kernels.hip", "cpm_api.cpp", "emu_api.cpp"]
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
     # keep the compiler from emitting packed FP32 instructions

@@ -52,6 +52,8 @@ class cpm_params(ctypes.Structure):
         ("lambda_persistence", ctypes.POINTER(ctypes.c_double)),
         ("persistence_mu", ctypes.POINTER(ctypes.c_double)),
         ("persistence_dt", ctypes.c_int32),
+        ("lambda_chemotaxis", ctypes.POINTER(ctypes.c_double)),
+        ("d_chemotaxis_field", ctypes.c_void_p),
     ]
 
 LAYOUTS = {"auto": 0, "box": 1, "full_rows": 2, "in_place": 3}
@@ -59,7 +61,7 @@ LAYOUTS = {"auto": 0, "box": 1, "full_rows": 2, "in_place": 3}
 
 EXPORTS = ("cpm_validate", "cpm_workspace_bytes", "cpm_tile_shape", "cpm_init", "cpm_sweep", "cpm_cell_stats", "cpm_contacts",
            "cpm_persistence", "cpm_counters", "cpm_attempt_stats", "cpm_set_mcs", "cpm_get_mcs", "cpm_destroy",
-           "cpm_batch_workspace_bytes", "cpm_batch_init", "cpm_batch_sweep", "cpm_batch_use_graph", "cpm_batch_counters",
+           "cpm_batch_workspace_bytes", "cpm_batch_init", "cpm_batch_sweep", "cpm_batch_sweep_serial", "cpm_batch_occupancy", "cpm_batch_use_graph", "cpm_batch_counters",
            "cpm_batch_cell_stats", "cpm_batch_attempt_stats", "cpm_batch_sample", "cpm_batch_summary",
            "cpm_batch_set_mcs", "cpm_batch_get_mcs",
            "cpm_batch_destroy", "cpm_strerror", "cpm_last_error")
@@ -99,6 +101,8 @@ def load(path: str = LIB_PATH):
     l.cpm_batch_init.argtypes = [pp, I32, P, P, P, P, P, SZ, P, ctypes.POINTER(P)]
     l.cpm_batch_sweep.argtypes = [P, I32, P]
     l.cpm_batch_use_graph.argtypes = [P, I32]
+    l.cpm_batch_sweep_serial.argtypes = [P, I32, P]
+    l.cpm_batch_occupancy.argtypes = [P, P, P]
     l.cpm_batch_counters.argtypes = [P, P, P, P]
     l.cpm_batch_cell_stats.argtypes = [P, P, P, P, P]
     l.cpm_batch_attempt_stats.argtypes = [P, P, P]
@@ -129,7 +133,8 @@ class Params:
                  lambda_surface=None, surface_target=None, lambda_act=None, max_act=None,
                  temperature: float = 20.0, seed: int = 1, lattice_id: int = 0, sub: int = 2,
                  attempts: int = 1, obstacle_type: int = -1, layout="auto", tile=(0, 0, 0),
-                 lambda_persistence=None, persistence_mu=None, persistence_dt: int = 1):
+                 lambda_persistence=None, persistence_mu=None, persistence_dt: int = 1,
+                 lambda_chemotaxis=None, chemotaxis_field=None):
         n = len(lambda_volume)
         self._J = np.ascontiguousarray(np.asarray(J, dtype=np.float64).reshape(n, n))
         self._lv = np.ascontiguousarray(lambda_volume, dtype=np.float64)
@@ -140,6 +145,9 @@ class Params:
         self._ma = None if max_act is None else np.ascontiguousarray(max_act, dtype=np.int32)
         self._lp = None if lambda_persistence is None else np.ascontiguousarray(lambda_persistence, dtype=np.float64)
         self._mp = None if persistence_mu is None else np.ascontiguousarray(persistence_mu, dtype=np.float64)
+        self._lc = None if lambda_chemotaxis is None else np.ascontiguousarray(lambda_chemotaxis, dtype=np.float64)
+        # the field: a device tensor (int16, ndim per site) the caller keeps alive
+        self._field = chemotaxis_field
         d = list(dims) + [1] * (3 - len(dims))
         c = cpm_params()
         c.ndim = ndim
@@ -165,13 +173,16 @@ class Params:
         c.lambda_persistence = self._lp.ctypes.data_as(dp) if self._lp is not None else None
         c.persistence_mu = self._mp.ctypes.data_as(dp) if self._mp is not None else None
         c.persistence_dt = int(persistence_dt)
+        c.lambda_chemotaxis = self._lc.ctypes.data_as(dp) if self._lc is not None else None
+        c.d_chemotaxis_field = chemotaxis_field.data_ptr() if hasattr(chemotaxis_field, "data_ptr") else None
         self.c = c
         self._kw = dict(ndim=ndim, dims=dims, J=J, lambda_volume=lambda_volume, volume_target=volume_target,
                         lambda_surface=lambda_surface, surface_target=surface_target, lambda_act=lambda_act,
                         max_act=max_act, temperature=temperature, seed=seed, lattice_id=lattice_id, sub=sub,
                         attempts=attempts, obstacle_type=obstacle_type, layout=layout, tile=tile,
                         lambda_persistence=lambda_persistence, persistence_mu=persistence_mu,
-                        persistence_dt=persistence_dt)
+                        persistence_dt=persistence_dt, lambda_chemotaxis=lambda_chemotaxis,
+                        chemotaxis_field=chemotaxis_field)
 
     def replace(self, **over) -> "Params":
         """A copy with some fields changed (e.g. layout, tile)."""
@@ -183,6 +194,16 @@ class Params:
     def act_enabled(self) -> bool:
         return bool(self.c.act_enabled)
 
+    def on_device(self, device):
+        """These parameters with a host (numpy) chemotaxis field copied to
+        `device` (the copy is kept alive by the returned Params)."""
+        f = self._field
+        if f is None or hasattr(f, "data_ptr"):
+            return self
+        import torch
+        dev = torch.as_tensor(np.ascontiguousarray(f, dtype=np.int16).reshape(-1)).to(device)
+        return self.replace(chemotaxis_field=dev)
+
     @classmethod
     def from_workload(cls, w, **over):
         kw = dict(ndim=w.ndim, dims=w.dims, J=w.J, lambda_volume=w.lambda_V, volume_target=w.V_target,
@@ -190,7 +211,8 @@ class Params:
                   max_act=w.max_act, temperature=w.T, seed=w.seed, lattice_id=w.lattice_id, sub=w.s,
                   attempts=w.k, obstacle_type=w.obstacle_type,
                   lambda_persistence=getattr(w, "lambda_P", None), persistence_mu=getattr(w, "mu_P", None),
-                  persistence_dt=getattr(w, "dt_P", 1))
+                  persistence_dt=getattr(w, "dt_P", 1), lambda_chemotaxis=getattr(w, "lambda_C", None),
+                  chemotaxis_field=getattr(w, "C_field", None))
         kw.update(over)
         return cls(**kw)
 
@@ -279,8 +301,9 @@ class Simulation:
     def __init__(self, params: Params, lattice, cell_type, act=None, device="cuda"):
         import torch
         self.torch = torch
-        self.params = params
         self.device = torch.device(device)
+        params = params.on_device(self.device)
+        self.params = params
         self.lattice = torch.as_tensor(np.ascontiguousarray(lattice, dtype=np.int32)).to(self.device).contiguous()
         self.cell_type = torch.as_tensor(np.ascontiguousarray(cell_type, dtype=np.int32)).to(self.device)
         self.n_cells = int(self.cell_type.numel()) - 1
@@ -389,6 +412,14 @@ def cpm_batch_sweep(h: int, n_mcs: int, stream: int) -> None:
     _check(load().cpm_batch_sweep(h, n_mcs, stream), "cpm_batch_sweep")
 
 
+def cpm_batch_sweep_serial(h: int, n_mcs: int, stream: int) -> None:
+    _check(load().cpm_batch_sweep_serial(h, n_mcs, stream), "cpm_batch_sweep_serial")
+
+
+def cpm_batch_occupancy(h: int, d_counts, stream: int) -> None:
+    _check(load().cpm_batch_occupancy(h, _ptr(d_counts), stream), "cpm_batch_occupancy")
+
+
 def cpm_batch_use_graph(h: int, enabled: bool) -> None:
     _check(load().cpm_batch_use_graph(h, 1 if enabled else 0), "cpm_batch_use_graph")
 
@@ -441,8 +472,8 @@ class Batch:
     def __init__(self, params, lattices, cell_types, acts=None, device="cuda"):
         import torch
         self.torch = torch
-        self.params = list(params)
         self.device = torch.device(device)
+        self.params = [p.on_device(self.device) for p in params]
         self.n = len(self.params)
         self.sizes = [int(np.asarray(l).size) for l in lattices]
         self.n_cells = [int(len(t)) - 1 for t in cell_types]
@@ -456,7 +487,9 @@ class Batch:
             if acts is None:
                 a = np.zeros(flat.size, np.uint8)
             else:
-                a = np.concatenate([np.ascontiguousarray(x, dtype=np.uint8).reshape(-1) for x in acts])
+                a = np.concatenate([np.zeros(n, np.uint8) if x is None else
+                                    np.ascontiguousarray(x, dtype=np.uint8).reshape(-1)
+                                    for x, n in zip(acts, self.sizes)])
             self.act = torch.as_tensor(a).to(self.device)
         else:
             self.act = None
@@ -471,6 +504,16 @@ class Batch:
 
     def sweep(self, n_mcs: int) -> None:
         cpm_batch_sweep(self.handle, n_mcs, self.stream)
+
+    def sweep_serial(self, n_mcs: int) -> None:
+        """n_mcs MCS of the serial CPM on every lattice (the reference)."""
+        cpm_batch_sweep_serial(self.handle, n_mcs, self.stream)
+
+    def occupancy(self):
+        """Per site, how many lattices hold a cell there (int32 device tensor)."""
+        out = self.torch.empty(self.sizes[0], dtype=self.torch.int32, device=self.device)
+        cpm_batch_occupancy(self.handle, out, self.stream)
+        return out
 
     def use_graph(self, enabled: bool) -> None:
         cpm_batch_use_graph(self.handle, enabled)

@@ -388,6 +388,21 @@ int validate(const cpm_params *p, int32_t n_cells)
         // |U . P| <= 3 * 2^28: the term adds at most 3 * 2^16 * lambda
         if (bound + 65536.0 * 3.0 * lpmax >= 4.0e18) return fail(CPM_ERANGE, "fixed-point energy change could overflow int64");
     }
+    if (p->lambda_chemotaxis) {
+        if (!p->d_chemotaxis_field) return fail(CPM_EINVAL, "d_chemotaxis_field NULL with chemotaxis enabled");
+        if (reinterpret_cast<uintptr_t>(p->d_chemotaxis_field) % 4 != 0)
+            return fail(CPM_EINVAL, "d_chemotaxis_field must be 4-byte aligned");
+        for (int d = 0; d < p->ndim; ++d)
+            if (p->dims[d] < 4) return fail(CPM_EINVAL, "chemotaxis needs every dim >= 4");
+        double lcmax = 0;
+        for (int a = 0; a < n; ++a) {
+            const double lc = p->lambda_chemotaxis[a];
+            if (!std::isfinite(lc) || std::fabs(lc) >= lim) return fail(CPM_ERANGE, "lambda_chemotaxis out of range");
+            lcmax = std::fmax(lcmax, std::fabs(lc));
+        }
+        // |U . C| < 3 * 2^14 * 2^15: the term adds at most 6 * 2^16 * lambda
+        if (bound + 65536.0 * 6.0 * lcmax >= 4.0e18) return fail(CPM_ERANGE, "fixed-point energy change could overflow int64");
+    }
     if (table_length(p->temperature) > cpm::kMaxTI) return fail(CPM_ENOTSUP, "temperature too high for the threshold table");
     if (p->attempts > cpm::kMaxAttempts) return fail(CPM_ENOTSUP, "this build runs at most 8 attempts per activation");
     return CPM_OK;
@@ -407,6 +422,7 @@ void build_model(const cpm_params *p, DeviceModel *m)
             m->max_act[a] = p->max_act[a];
             m->r_act[a] = to_fixed(p->lambda_act[a] / (double)p->max_act[a]);
         }
+        if (p->lambda_chemotaxis) m->lam_c[a] = to_fixed(p->lambda_chemotaxis[a]);
         if (p->lambda_persistence) {
             m->lam_p[a] = to_fixed(p->lambda_persistence[a]);
             m->mu_p[a] = (int64_t)std::llround(p->persistence_mu[a] * 16384.0);
@@ -464,6 +480,7 @@ void fill_args(SweepArgs &a, const cpm_params *p, const Layout &lay, char *ws, i
     a.cells = lay.mirror_on ? static_cast<void *>(ws + lay.mirror) : static_cast<void *>(d_lattice);
     a.cell_type = d_cell_type;
     a.act = p->act_enabled ? d_act : nullptr;
+    a.chem = p->lambda_chemotaxis ? p->d_chemotaxis_field : nullptr;
     a.model = reinterpret_cast<const DeviceModel *>(ws + lay.model);
     a.counters[0] = reinterpret_cast<int32_t *>(ws + lay.counters0);
     a.counters[1] = reinterpret_cast<int32_t *>(ws + lay.counters1);
@@ -1016,6 +1033,48 @@ int cpm_batch_sweep(cpm_batch *b, int32_t n_mcs, void *stream)
     if (b->mirror && (e = cpm::launch_batch_mirror(b->d_args, b->n, b->max_sites, false, st)) != hipSuccess)
         return device_fail(e, "from 16-bit working copy");
     return CPM_OK;
+}
+
+int cpm_batch_sweep_serial(cpm_batch *b, int32_t n_mcs, void *stream)
+{
+    if (!b) return fail(CPM_EINVAL, "batch is NULL");
+    if (n_mcs < 0) return fail(CPM_EINVAL, "n_mcs must be >= 0");
+    if (n_mcs == 0) return CPM_OK;
+    hipStream_t st = as_stream(stream);
+    const int parity = (int)(b->activation & 1);
+    hipError_t e;
+    if (b->mirror && (e = cpm::launch_batch_mirror(b->d_args, b->n, b->max_sites, true, st)) != hipSuccess)
+        return device_fail(e, "to 16-bit working copy");
+    for (int32_t m = 0; m < n_mcs; ++m) {
+        e = cpm::launch_serial_mcs(b->d_args, b->n, b->ndim, b->act, b->mirror, (uint32_t)b->mcs, parity, st);
+        if (e != hipSuccess) return device_fail(e, "serial MCS");
+        ++b->mcs;
+        ++b->mcs_run;
+    }
+    // the other counter buffer and the pending delta lists as the next
+    // parallel activation expects them: exact counters, no deltas to re-add
+    for (int32_t i = 0; i < b->n; ++i) {
+        const SweepArgs &a = b->args[i];
+        e = hipMemcpyAsync(a.counters[parity ^ 1], a.counters[parity], sizeof(int32_t) * 2 * ((size_t)b->n_cells[i] + 1),
+                           hipMemcpyDeviceToDevice, st);
+        if (e == hipSuccess) e = cpm::launch_fill_i32(a.dcount[parity ^ 1], 0, (size_t)a.tg.n_tiles, st);
+        if (e != hipSuccess) return device_fail(e, "counters after serial MCS");
+    }
+    if (b->mirror && (e = cpm::launch_batch_mirror(b->d_args, b->n, b->max_sites, false, st)) != hipSuccess)
+        return device_fail(e, "from 16-bit working copy");
+    return CPM_OK;
+}
+
+int cpm_batch_occupancy(cpm_batch *b, int32_t *d_counts, void *stream)
+{
+    if (!b || !d_counts) return fail(CPM_EINVAL, "NULL argument");
+    const size_t n_sites = (size_t)b->args[0].L[0] * b->args[0].L[1] * b->args[0].L[2];
+    for (int32_t i = 1; i < b->n; ++i)
+        if ((size_t)b->args[i].L[0] * b->args[i].L[1] * b->args[i].L[2] != n_sites ||
+            b->args[i].L[0] != b->args[0].L[0] || b->args[i].L[1] != b->args[0].L[1])
+            return fail(CPM_EINVAL, "occupancy needs lattices of one shape");
+    const hipError_t e = cpm::launch_occupancy(b->lattices, b->n, n_sites, d_counts, as_stream(stream));
+    return e == hipSuccess ? CPM_OK : device_fail(e, "occupancy");
 }
 
 int cpm_batch_use_graph(cpm_batch *b, int32_t enabled)

@@ -51,6 +51,27 @@ __device__ __forceinline__ constexpr int nb_dy(int n) { return (D == 2 ? (n < 4 
 template <int D>
 __device__ __forceinline__ constexpr int nb_dz(int n) { return D == 2 ? 0 : (n < 13 ? n : n + 1) / 9 - 1; }
 
+// Threshold tables as 32-bit words; entry 0 of each stands for 2^32 and is
+// never read.
+struct ThrTables {
+    const uint32_t *tm, *tl, *ti;
+    int n_ti;
+};
+
+// Accept iff q <= 0 or u < floor(TI[h] TM[m] TL[l] / 2^64), q = h*2^16 + m*2^8 + l.
+__device__ __forceinline__ bool metropolis32(const ThrTables &tb, int64_t q, uint32_t u)
+{
+    if (q <= 0) return true;
+    const uint64_t h = (uint64_t)q >> 16;
+    if (h >= (uint64_t)tb.n_ti) return false;
+    const uint64_t two32 = (uint64_t)1 << 32;
+    const uint64_t ti = h == 0 ? two32 : (uint64_t)tb.ti[h];
+    if ((q & 0xFFFF) == 0) return (uint64_t)u < ti;
+    const int mm = (int)((q >> 8) & 255), ll = (int)(q & 255);
+    const uint64_t tm = mm ? (uint64_t)tb.tm[mm] : two32, tl = ll ? (uint64_t)tb.tl[ll] : two32;
+    return (uint64_t)u < __umul64hi(ti, tm * tl);  // tm * tl < 2^64 since (mm, ll) != (0, 0)
+}
+
 // exp(l * 2^-24) in 2^16 fixed point, floor-composed from the split tables.
 __device__ __forceinline__ int64_t exp_log24(const DeviceModel *m, uint64_t ell)
 {

@@ -47,6 +47,8 @@ struct DeviceModel {
     // the unit vectors of the Moore offsets, index (dx+1) + 3(dy+1) + 9(dz+1) (2^-14)
     int64_t lam_p[kMaxTypes];
     int64_t mu_p[kMaxTypes];
+    // chemotaxis strength (2^-16)
+    int64_t lam_c[kMaxTypes];
     int32_t unit[27][3];
 };
 
@@ -74,6 +76,7 @@ struct SweepArgs {
     const int32_t *cell_type;
     uint8_t *act;
     const int4 *pdir;      // persistence direction per label (x, y, z, unused), 2^-14; NULL when off
+    const int16_t *chem;   // chemotaxis field, ndim components per site, 2^-14; NULL when off
     const DeviceModel *model;
     int32_t *counters[2];  // ping-pong (V, S) pairs per label
     int4 *dlist[2];        // per tile: accepted copies of an activation, by activation parity
@@ -137,6 +140,14 @@ hipError_t launch_contacts(const SweepArgs &a, int ndim, int n_types, int64_t *o
 hipError_t launch_batch_cell_stats(const SweepArgs *d_args, const int64_t *d_label_off, int n_lattices, int ndim,
                                    size_t max_sites, int64_t max_bricks, size_t total_labels, int32_t *v_out,
                                    int32_t *s_out, int32_t *ref, int64_t *cent, hipStream_t stream);
+// One MCS of the serial CPM on every lattice of a batch (one wave each);
+// counters: the exact buffer `parity`.
+hipError_t launch_serial_mcs(const SweepArgs *d_args, int n_lattices, int ndim, bool act, bool mirror, uint32_t mcs,
+                             int parity, hipStream_t st);
+// Per site, how many lattices of a batch hold a cell there (all lattices of
+// one size, n_sites each, packed back to back).
+hipError_t launch_occupancy(const int32_t *lattices, int n_lattices, size_t n_sites, int32_t *counts,
+                            hipStream_t st);
 // Workgroups of the centroid reductions over a lattice of dims L.
 int64_t reduce_brick_count(const int *L, int ndim);
 hipError_t launch_count(const SweepArgs &a, int ndim, int32_t *v_out, int32_t *s_out, int stride,

@@ -466,6 +466,24 @@ __global__ void copy_dirs_kernel(const int4 *pdir, int32_t n_labels, int32_t *ou
 }
 }  // namespace
 
+namespace {
+__global__ void occupancy_kernel(const int32_t *lat, int n_lattices, size_t n_sites, int32_t *counts)
+{
+    const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n_sites) return;
+    int32_t c = 0;
+    for (int l = 0; l < n_lattices; ++l) c += lat[(size_t)l * n_sites + i] > 0;
+    counts[i] = c;
+}
+}  // namespace
+
+hipError_t launch_occupancy(const int32_t *lattices, int n_lattices, size_t n_sites, int32_t *counts,
+                            hipStream_t st)
+{
+    occupancy_kernel<<<blocks_for(n_sites), kBlock, 0, st>>>(lattices, n_lattices, n_sites, counts);
+    return hipGetLastError();
+}
+
 int64_t reduce_brick_count(const int *L, int ndim) { return ndim == 2 ? reduce_bricks<2>(L) : reduce_bricks<3>(L); }
 
 hipError_t launch_copy_dirs(const int4 *pdir, int32_t n_labels, int32_t *out, hipStream_t stream)

@@ -100,27 +100,6 @@ __device__ __forceinline__ int64_t gm_lds(const DeviceModel *m, const int64_t *l
     return zero ? 0 : exp_log24(m, sum / cnt);
 }
 
-// Threshold tables as 32-bit words; entry 0 of each stands for 2^32 and is
-// never read.
-struct ThrTables {
-    const uint32_t *tm, *tl, *ti;
-    int n_ti;
-};
-
-// Accept iff q <= 0 or u < floor(TI[h] TM[m] TL[l] / 2^64), q = h*2^16 + m*2^8 + l.
-__device__ __forceinline__ bool metropolis32(const ThrTables &tb, int64_t q, uint32_t u)
-{
-    if (q <= 0) return true;
-    const uint64_t h = (uint64_t)q >> 16;
-    if (h >= (uint64_t)tb.n_ti) return false;
-    const uint64_t two32 = (uint64_t)1 << 32;
-    const uint64_t ti = h == 0 ? two32 : (uint64_t)tb.ti[h];
-    if ((q & 0xFFFF) == 0) return (uint64_t)u < ti;
-    const int mm = (int)((q >> 8) & 255), ll = (int)(q & 255);
-    const uint64_t tm = mm ? (uint64_t)tb.tm[mm] : two32, tl = ll ? (uint64_t)tb.tl[ll] : two32;
-    return (uint64_t)u < __umul64hi(ti, tm * tl);  // tm * tl < 2^64 since (mm, ll) != (0, 0)
-}
-
 // J rows of the medium type and of the single cell type (when all cells share one type).
 struct JRows {
     int64_t cc, cm, co, mc, mm, mo;
@@ -142,7 +121,7 @@ template <typename Cell, int D, bool ACT, bool SINGLE, int LAYOUT, typename NB>
 __device__ __forceinline__ bool evaluate_nb(const SweepArgs &a, const ThrTables &tb, const JRows &jr,
                                             const SharedTables &st, const NB &nbl, Cell *lab, uint8_t *lact,
                                             const LdsMap<LAYOUT> &map, int tx_, int ty_, int tz_, int sx_, int sy_,
-                                            int sz_, int lt, int ls, int2 cnt_t, int2 cnt_s, uint32_t u2,
+                                            int sz_, int src_gi, int lt, int ls, int2 cnt_t, int2 cnt_s, uint32_t u2,
                                             int64_t &dso_out, int64_t &dsn_out)
 {
     constexpr int NNB = D == 2 ? 8 : 26;
@@ -204,6 +183,19 @@ __device__ __forceinline__ bool evaluate_nb(const SweepArgs &a, const ThrTables 
                             (int64_t)m->unit[o][2] * pd.z;
         q -= (m->lam_p[ts] * dot) >> 28;
     }
+    if (a.chem && ls >= 1) {
+        // chemotaxis: the field at the source, dotted with the copy's direction
+        const int o = (tx_ - sx_ + 1) + 3 * (ty_ - sy_ + 1) + 9 * (tz_ - sz_ + 1);
+        int64_t dot;
+        if (D == 2) {
+            const short2 c = reinterpret_cast<const short2 *>(a.chem)[src_gi];
+            dot = (int64_t)m->unit[o][0] * c.x + (int64_t)m->unit[o][1] * c.y;
+        } else {
+            const int16_t *c = a.chem + 3 * (size_t)src_gi;
+            dot = (int64_t)m->unit[o][0] * c[0] + (int64_t)m->unit[o][1] * c[1] + (int64_t)m->unit[o][2] * c[2];
+        }
+        q -= (m->lam_c[ts] * dot) >> 28;
+    }
     dso_out = dso;
     dsn_out = dsn;
     return metropolis32(tb, q, u2);
@@ -214,7 +206,7 @@ template <typename Cell, int D, bool ACT, bool SINGLE, int LAYOUT>
 __device__ __forceinline__ bool evaluate(const SweepArgs &a, const ThrTables &tb, const JRows &jr,
                                          const SharedTables &st, Cell *lab, uint8_t *lact,
                                          const LdsMap<LAYOUT> &map, int tx_, int ty_, int tz_, int sx_, int sy_,
-                                         int sz_, int lt, int ls, int2 cnt_t, int2 cnt_s, uint32_t u2,
+                                         int sz_, int src_gi, int lt, int ls, int2 cnt_t, int2 cnt_s, uint32_t u2,
                                          int64_t &dso_out, int64_t &dsn_out)
 {
     const int xm = map.x(tx_ - 1), x0 = map.x(tx_), xp = map.x(tx_ + 1);
@@ -224,7 +216,7 @@ __device__ __forceinline__ bool evaluate(const SweepArgs &a, const ThrTables &tb
         return label_of(lab[xx + map.row(ty_ + nb_dy<D>(n), tz_ + nb_dz<D>(n))]);
     };
     return evaluate_nb<Cell, D, ACT, SINGLE, LAYOUT>(a, tb, jr, st, nbl, lab, lact, map, tx_, ty_, tz_, sx_, sy_,
-                                                     sz_, lt, ls, cnt_t, cnt_s, u2, dso_out, dsn_out);
+                                                     sz_, src_gi, lt, ls, cnt_t, cnt_s, u2, dso_out, dsn_out);
 }
 
 // Counters of label c as an attempt of this thread sees them: the read
@@ -386,7 +378,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
             }
             int64_t dso, dsn;
             if (evaluate<Cell, D, ACT, SINGLE, LAYOUT>(a, tb, jr, sht, lab, lact, map, ttx, tty, ttz, ssx, ssy, ssz,
-                                                       lt, ls, seen_counters(rd, lt, nullptr, 0),
+                                                       map.at(ssx, ssy, ssz), lt, ls, seen_counters(rd, lt, nullptr, 0),
                                                        seen_counters(rd, ls, nullptr, 0), u2, dso, dsn)) {
                 accepted = 1;
                 const int gi = map.at(ttx, tty, ttz);
@@ -545,7 +537,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
                 // queue full: evaluate here (no other attempt reads this sub-area)
                 int64_t dso, dsn;
                 if (evaluate<Cell, D, ACT, SINGLE, LAYOUT>(a, tb, jr, sht, lab, lact, map, d_ttx, d_tty, d_ttz, d_ssx,
-                                                            d_ssy, d_ssz, d_lt, d_ls, d_ct, d_cs, d_u2, dso, dsn)) {
+                                                            d_ssy, d_ssz, a.chem ? global_index(d_ssx, d_ssy, d_ssz) : 0,
+                                                            d_lt, d_ls, d_ct, d_cs, d_u2, dso, dsn)) {
                     ++my_accepted;
                     commit(map.at(d_ttx, d_tty, d_ttz), global_index(d_ttx, d_tty, d_ttz), d_lt, d_ls, dso, dsn);
                 }
@@ -562,8 +555,9 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
             const int t = map.at(ttx, tty, ttz);
             const int lt = label_of(lab[t]), ls = label_of(lab[map.at(ssx, ssy, ssz)]);
             int64_t dso, dsn;
-            if (evaluate<Cell, D, ACT, SINGLE, LAYOUT>(a, tb, jr, sht, lab, lact, map, ttx, tty, ttz, ssx, ssy, ssz, lt,
-                                                        ls, make_int2(c.x, c.y), make_int2(c.z, c.w), (uint32_t)e.w,
+            if (evaluate<Cell, D, ACT, SINGLE, LAYOUT>(a, tb, jr, sht, lab, lact, map, ttx, tty, ttz, ssx, ssy, ssz,
+                                                        a.chem ? global_index(ssx, ssy, ssz) : 0, lt, ls,
+                                                        make_int2(c.x, c.y), make_int2(c.z, c.w), (uint32_t)e.w,
                                                         dso, dsn)) {
                 ++my_accepted;
                 commit(t, global_index(ttx, tty, ttz), lt, ls, dso, dsn);
@@ -585,7 +579,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
                     ++my_nontrivial;
                     int64_t dso, dsn;
                     if (evaluate<Cell, D, ACT, SINGLE, LAYOUT>(a, tb, jr, sht, lab, lact, map, ttx, tty, ttz, ssx, ssy,
-                                                                ssz, lt, ls, seen_counters(rd, lt, own, j),
+                                                                ssz, a.chem ? global_index(ssx, ssy, ssz) : 0, lt, ls,
+                                                                seen_counters(rd, lt, own, j),
                                                                 seen_counters(rd, ls, own, j), u2, dso, dsn)) {
                         ++my_accepted;
                         rec = commit(t, global_index(ttx, tty, ttz), lt, ls, dso, dsn);

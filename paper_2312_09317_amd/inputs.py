@@ -50,6 +50,8 @@ class Workload:
     lambda_P: Optional[np.ndarray] = None   # persistence strength per type (None: off)
     mu_P: Optional[np.ndarray] = None       # weight of the previous direction per type
     dt_P: int = 1                           # MCS looked back for the displacement
+    lambda_C: Optional[np.ndarray] = None   # chemotaxis strength per type (None: off)
+    C_field: Optional[np.ndarray] = None    # int16, ndim components per site, units of 2^-14
     extra: dict = field(default_factory=dict)
 
     @property
@@ -236,6 +238,48 @@ def collective_3d(L=256, density=0.5, seed=1, n_mcs=200, lambda_p=40.0, mu=0.95,
     w.mu_P = np.array([0.0, mu])
     w.dt_P = int(dt)
     w.extra["density"] = n * 150.0 / float(L) ** 3
+    return w
+
+
+def circular_field(L):
+    """The paper's circular chemotaxis field on an L x L lattice: at every
+    site the unit vector at 90 degrees (counter-clockwise) to the radial
+    vector from the lattice centre to the site's centre, as int16 in units of
+    2^-14 (x, y per site, sites in lattice order)."""
+    c = L / 2.0
+    y, x = np.mgrid[0:L, 0:L].astype(np.float64)
+    rx, ry = x + 0.5 - c, y + 0.5 - c
+    r = np.hypot(rx, ry)
+    f = np.stack([-ry / r, rx / r], axis=-1)
+    return np.rint(f * 16384.0).astype(np.int16).reshape(-1)
+
+
+def chemotaxis_2d(L=256, n_cells=8, side=50, radius=None, seed=1, n_mcs=200, lambda_chem=10.0):
+    """Cells circling in the circular chemotaxis field (Fig. 5A, Fig. 6A/E):
+    n_cells squares of side `side` centred on a ring of radius `radius`
+    (default 0.35 L) about the lattice centre at equal angles, the first at a
+    seeded random angle.  The paper's 2D settings (V_target 2500, surface
+    target 600, lambda_surface 2, J(cell, medium) 10, T 10) with lambda_V 20
+    and lambda_chemotaxis 10; J(cell, cell) = 20 (not given)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    radius = 0.35 * L if radius is None else radius
+    lat = np.zeros((L, L), dtype=np.int32)
+    phase = rng.random() * 2 * np.pi
+    for i in range(n_cells):
+        ang = phase + 2 * np.pi * i / n_cells
+        cx = int(round(L / 2 + radius * np.cos(ang))) - side // 2
+        cy = int(round(L / 2 + radius * np.sin(ang))) - side // 2
+        ys = (cy + np.arange(side)) % L
+        xs = (cx + np.arange(side)) % L
+        if np.any(lat[np.ix_(ys, xs)] != 0):
+            raise ValueError("cells overlap on the ring")
+        lat[np.ix_(ys, xs)] = i + 1
+    J, lv, vt, ls, st = _two_type(20.0, 10.0, 20.0, 2500, 2.0, 600)
+    w = Workload(f"2d-{L}x{L}-chemotaxis-{n_cells}cells", 2, (L, L, 1), lat.reshape(1, L, L),
+                 np.array([0] + [1] * n_cells, dtype=np.int32), J, lv, vt, ls, st,
+                 T=10.0, n_mcs=n_mcs, seed=seed)
+    w.lambda_C = np.array([0.0, lambda_chem])
+    w.C_field = circular_field(L)
     return w
 
 

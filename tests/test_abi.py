@@ -104,6 +104,30 @@ def test_persistence_workspace_and_batches():
     assert cpm.cpm_validate(cpm.Params.from_workload(wc), wc.n_cells) == cpm.CPM_OK
 
 
+class _FakeDevicePtr:
+    # stands for a device tensor: only its address is read by validation
+    def __init__(self, addr):
+        self.addr = addr
+
+    def data_ptr(self):
+        return self.addr
+
+
+def test_chemotaxis_validation():
+    p, w = _params(lambda_chemotaxis=[0, 10.0])  # no field
+    assert cpm.cpm_validate(p, w.n_cells) == cpm.CPM_EINVAL
+    p, w = _params(lambda_chemotaxis=[0, 10.0], chemotaxis_field=_FakeDevicePtr(1 << 20))
+    assert cpm.cpm_validate(p, w.n_cells) == cpm.CPM_OK
+    p, w = _params(lambda_chemotaxis=[0, 10.0], chemotaxis_field=_FakeDevicePtr((1 << 20) + 2))
+    assert cpm.cpm_validate(p, w.n_cells) == cpm.CPM_EINVAL  # not 4-byte aligned
+    p, w = _params(lambda_chemotaxis=[0, 1e6], chemotaxis_field=_FakeDevicePtr(1 << 20))
+    assert cpm.cpm_validate(p, w.n_cells) == cpm.CPM_ERANGE
+    # the workload generator's field: 2 int16 per site, unit length within rounding
+    wc = inputs.chemotaxis_2d()
+    f = wc.C_field.reshape(-1, 2).astype(np.float64) / 16384
+    assert f.shape[0] == wc.n_sites and np.abs(np.hypot(f[:, 0], f[:, 1]) - 1).max() < 1e-4
+
+
 def test_validate_rejects_bad_cell_count_and_null():
     p, w = _params()
     assert cpm.cpm_validate(p, -1) == cpm.CPM_EINVAL

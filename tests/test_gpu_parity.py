@@ -29,7 +29,7 @@ def oracle_model(w):
     return oracle.Model(w.ndim, w.dims[:w.ndim], w.J, w.lambda_V, w.V_target, w.lambda_S, w.S_target,
                         lambda_act=w.lambda_act, max_act=w.max_act, T=w.T, seed=w.seed,
                         lattice_id=w.lattice_id, s=w.s, k=w.k, obstacle_type=w.obstacle_type,
-                        lambda_P=w.lambda_P, mu_P=w.mu_P, dt_P=w.dt_P)
+                        lambda_P=w.lambda_P, mu_P=w.mu_P, dt_P=w.dt_P, lambda_C=w.lambda_C, C_field=w.C_field)
 
 
 def run_both(torch, w, n_mcs, chunks=None):
