@@ -68,7 +68,8 @@ def bytes_per_attempt(ndim, s, k, p_acc, act=False):
 def cpu_baseline(w, n_mcs):
     import oracle
     m = oracle.Model(w.ndim, w.dims[:w.ndim], w.J, w.lambda_V, w.V_target, w.lambda_S, w.S_target,
-                     T=w.T, seed=w.seed, s=w.s, k=w.k, lambda_P=w.lambda_P, mu_P=w.mu_P, dt_P=w.dt_P)
+                     T=w.T, seed=w.seed, s=w.s, k=w.k, lambda_P=w.lambda_P, mu_P=w.mu_P, dt_P=w.dt_P,
+                     lambda_C=w.lambda_C, C_field=w.C_field)
     st = oracle.State(m, w.lattice, w.cell_type)
     t0 = time.perf_counter()
     st.sweep(n_mcs)
@@ -97,15 +98,19 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--cpu-mcs", type=int, default=4, help="MCS of the oracle sample (0 to skip)")
-    ap.add_argument("--workload", choices=("sweep", "tissue", "sorting", "collective", "batch", "emulator"),
+    ap.add_argument("--workload", choices=("sweep", "tissue", "sorting", "collective", "accuracy", "batch", "emulator"),
                     default="sweep",
                     help="sweep: the 3D 256^3 benchmark (default); tissue: 3D 1024^3 with obstacles and the "
                          "Act term; sorting: 2D 2048^2 two-type cell sorting; collective: 3D 256^3 packed "
-                         "collective with the persistence term; batch: 512 uneven 2D lattices; emulator: "
+                         "collective with the persistence term; accuracy: speed and accuracy of the parallel "
+                         "scheme against the serial CPM (2D circular chemotaxis ensembles); batch: 512 uneven "
+                         "2D lattices; emulator: "
                          "train the emulator on batched runs and judge it against fresh ones")
     ap.add_argument("--layout", default="tune", choices=("tune", "auto", "box", "full_rows", "in_place"),
                     help="sweep layout: tune = time the candidates first and take the fastest (default)")
     ap.add_argument("--tune-mcs", type=int, default=6, help="MCS timed per candidate layout when tuning")
+    ap.add_argument("--acc-runs", type=int, default=250, help="accuracy workload: runs per ensemble")
+    ap.add_argument("--acc-mcs", type=int, default=200, help="accuracy workload: MCS per run")
     ap.add_argument("--emu-train", type=int, default=8192, help="emulator workload: training runs")
     ap.add_argument("--emu-test", type=int, default=256, help="emulator workload: held-out points")
     ap.add_argument("--emu-reps", type=int, default=8, help="emulator workload: replicates per held-out point")
@@ -141,6 +146,8 @@ def main():
         return bench_sorting(args)
     if args.workload == "collective":
         return bench_collective(args)
+    if args.workload == "accuracy":
+        return bench_accuracy(args)
     if args.workload == "emulator":
         return bench_emulator(args)
     w = inputs.config1(n_mcs=args.steps)
@@ -387,6 +394,46 @@ def bench_collective(args):
         "cpu_baseline": {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")} if cpu else None}),
         flush=True)
     sim.close()
+
+
+def bench_accuracy(args):
+    """Speed against accuracy (Fig. 6E): ensembles of the 2D circular
+    chemotaxis workload (256^2, 8 cells of 50^2, lambda_chemotaxis 10), one
+    serial reference ensemble and one parallel ensemble per (s, k), each of
+    --acc-runs runs of --acc-mcs MCS advanced as one batch; accuracy = 1 -
+    mean pixel cross-entropy of the serial occupancy against the parallel
+    one.  value: attempts/s of the parallel ensemble at the default s = 2,
+    k = 1."""
+    from paper_2312_09317_amd import accuracy, inputs
+    w = inputs.chemotaxis_2d(n_mcs=args.acc_mcs)
+    configs = [(1, 1), (2, 1), (2, 4), (4, 1), (4, 8), (8, 1), (8, 8)]
+    log(f"workload {w.name}: {args.acc_runs} runs per ensemble, {args.acc_mcs} MCS, (s, k) in {configs}")
+    out = accuracy.study(w, configs, n_runs=args.acc_runs, n_mcs=args.acc_mcs, log=log)
+    main_row = next(r for r in out["parallel"] if (r["s"], r["k"]) == (2, 1))
+    cpu = None
+    if args.cpu_mcs > 0:
+        # the oracle runs an ensemble sample of the same shape: 32 runs of
+        # the parallel scheme at s = 2, k = 1 over --acc-mcs MCS
+        import oracle
+        m = oracle.Model(w.ndim, w.dims[:w.ndim], w.J, w.lambda_V, w.V_target, w.lambda_S, w.S_target,
+                         T=w.T, seed=w.seed, s=w.s, k=w.k, lambda_C=w.lambda_C, C_field=w.C_field)
+        t0 = time.perf_counter()
+        oracle.replicates(m, w.lattice, w.cell_type, args.acc_mcs, 32, mode="dcs")
+        dt = time.perf_counter() - t0
+        n_att = 32 * args.acc_mcs * w.n_sites
+        cpu = {"value": n_att / dt, "unit": "attempts/s", "cores": 1, "kind": "oracle",
+               "sample": f"32 runs x {args.acc_mcs} MCS of the same workload at s = 2, k = 1 ({n_att} attempts, "
+                         f"{dt:.1f} s, one thread)"}
+    print(json.dumps({
+        "metric": "site copy-attempts/s of a 2D chemotaxis ensemble, with its accuracy against the serial CPM",
+        "value": main_row["attempts_per_s"], "unit": "attempts/s", "n_gpus": 1, "steps": args.acc_mcs,
+        "warmup": 1, "ms_per_step": main_row["ms_per_mcs"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": w.name, "lattice": list(w.dims), "n_cells": w.n_cells, "runs": args.acc_runs,
+                   "study": out},
+        "roofline": None,
+        "cpu_baseline": {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")} if cpu else None}),
+        flush=True)
 
 
 def bench_batch(args):

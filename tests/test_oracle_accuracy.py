@@ -49,3 +49,15 @@ def test_brute_force_tiny_ensembles():
     ce0 = -(2 / 3 * math.log2(0.5) + 1 / 3 * math.log2(0.5))
     ce1 = -(0 * math.log2(0.5) + 1 * math.log2(0.5))
     assert np.isclose(acc.accuracy(ref, par), 1 - (ce0 + ce1) / 2)
+
+
+def test_harness_formula_matches_reference():
+    # the library harness scores occupancy counts with its own code: it must
+    # agree with the reference definition on random ensembles
+    from paper_2312_09317_amd import accuracy as harness
+    rng = np.random.Generator(np.random.PCG64(3))
+    for n_ref, n_par in ((250, 250), (16, 64), (7, 3)):
+        ref = rng.random((n_ref, 300)) < rng.random(300)
+        par = rng.random((n_par, 300)) < rng.random(300)
+        got = 1.0 - harness.cross_entropy_bits(ref.sum(0), n_ref, par.sum(0), n_par)
+        assert np.isclose(got, acc.accuracy(ref.astype(np.int32), par.astype(np.int32)), rtol=0, atol=1e-12)
