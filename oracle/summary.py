@@ -99,3 +99,36 @@ def summary(V, S, pos, dims, interval):
         pe = np.asarray(persist)
         out[6], out[7] = pe.mean(), pe.var()
     return out
+
+
+def autocorrelation(V, pos, dims):
+    """Directional autocorrelation of the cells of one run (Fig. 5B): for
+    every lag tau = 0..K-2 (in sample intervals), the sum over cells c and
+    steps k of u_k(c) . u_{k+tau}(c), the unit minimum-image displacements
+    between consecutive samples (both defined: cell alive at the three or
+    four samples involved and moved), and the number of such pairs.  Entry 0
+    (the medium) is ignored.  Returns (sums, counts), each of length K - 1;
+    their ratio is A(tau), and runs pool by adding sums and counts."""
+    V = np.asarray(V, dtype=np.float64)[:, 1:]
+    pos = np.asarray(pos, dtype=np.float64)[:, 1:, :]
+    K, C = V.shape
+    L = np.asarray(dims[:pos.shape[2]], dtype=np.float64)
+    sums = np.zeros(K - 1)
+    counts = np.zeros(K - 1)
+    for c in range(C):
+        units = []
+        for k in range(K - 1):
+            u = None
+            if V[k, c] > 0 and V[k + 1, c] > 0:
+                d = pos[k + 1, c] - pos[k, c]
+                d = d - L * np.rint(d / L)
+                n = np.sqrt(np.sum(d * d))
+                if n > 0:
+                    u = d / n
+            units.append(u)
+        for tau in range(K - 1):
+            for k in range(K - 1 - tau):
+                if units[k] is not None and units[k + tau] is not None:
+                    sums[tau] += float(np.dot(units[k], units[k + tau]))
+                    counts[tau] += 1
+    return sums, counts

@@ -76,3 +76,51 @@ def test_random_directions_decorrelate_at_first_lag():
     assert np.isclose(out[4], 1.0)
     # A(1) ~ 0, so persistence ~ (1 - 1/e) / (1 - 0) of one lag
     assert abs(out[6] - (1 - np.exp(-1))) < 0.1
+
+
+def _track(steps, L=100.0):
+    # one cell moving by the given 2D steps from (10, 10); V = 50 throughout
+    p = [np.array([10.0, 10.0])]
+    for s_ in steps:
+        p.append(np.mod(p[-1] + np.asarray(s_, dtype=np.float64), L))
+    K = len(p)
+    pos = np.zeros((K, 2, 2))
+    pos[:, 1, :] = np.asarray(p)
+    V = np.zeros((K, 2))
+    V[:, 1] = 50
+    return V, pos
+
+
+def test_autocorrelation_closed_forms():
+    # straight line: A = 1 at every lag; reversals: (-1)^tau; right-angle turns
+    # every step: 1, 0, -1, 0, ...; across the periodic boundary too
+    V, pos = _track([(3, 0)] * 6)
+    s, n = summary.autocorrelation(V, pos, (100, 100))
+    assert np.allclose(s / n, 1.0) and list(n) == [6, 5, 4, 3, 2, 1]
+    V, pos = _track([(2, 0), (-2, 0)] * 3)
+    s, n = summary.autocorrelation(V, pos, (100, 100))
+    assert np.allclose(s / n, [(-1) ** t for t in range(6)])
+    V, pos = _track([(0, 1), (-1, 0), (0, -1), (1, 0)] * 2)
+    s, n = summary.autocorrelation(V, pos, (100, 100))
+    assert np.allclose(s / n, [1, 0, -1, 0, 1, 0, -1, 0][:8])
+    V, pos = _track([(30, 0)] * 5, L=100.0)  # wraps around x twice
+    s, n = summary.autocorrelation(V, pos, (100, 100))
+    assert np.allclose(s / n, 1.0)
+
+
+def test_autocorrelation_skips_dead_and_still_cells():
+    V, pos = _track([(1, 0), (0, 0), (1, 0), (1, 0)])  # step 1 has no direction
+    s, n = summary.autocorrelation(V, pos, (100, 100))
+    assert list(n) == [3, 1, 1, 1] and np.allclose(s / n, 1.0)
+    V[2, 1] = 0  # dead at sample 2: steps 1 and 2 undefined
+    s, n = summary.autocorrelation(V, pos, (100, 100))
+    assert list(n) == [2, 0, 0, 1]
+
+
+def test_autocorrelation_of_a_random_walk_decays():
+    rng = np.random.Generator(np.random.PCG64(4))
+    ang = rng.uniform(0, 2 * np.pi, 1200)
+    V, pos = _track(np.stack([np.cos(ang), np.sin(ang)], 1) * 2.0, L=1e9)
+    s, n = summary.autocorrelation(V, pos, (1e9, 1e9))
+    a = s / n
+    assert a[0] == 1.0 and np.all(np.abs(a[1:20]) < 0.1)
