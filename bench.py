@@ -98,12 +98,14 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--cpu-mcs", type=int, default=4, help="MCS of the oracle sample (0 to skip)")
-    ap.add_argument("--workload", choices=("sweep", "tissue", "sorting", "collective", "accuracy", "batch", "emulator"),
+    ap.add_argument("--workload", choices=("sweep", "tissue", "sorting", "collective", "accuracy", "polarisation",
+                                           "batch", "emulator"),
                     default="sweep",
                     help="sweep: the 3D 256^3 benchmark (default); tissue: 3D 1024^3 with obstacles and the "
                          "Act term; sorting: 2D 2048^2 two-type cell sorting; collective: 3D 256^3 packed "
                          "collective with the persistence term; accuracy: speed and accuracy of the parallel "
-                         "scheme against the serial CPM (2D circular chemotaxis ensembles); batch: 512 uneven "
+                         "scheme against the serial CPM (2D circular chemotaxis ensembles); polarisation: "
+                         "directional autocorrelation of Act cells, serial CPM vs parallel scheme; batch: 512 uneven "
                          "2D lattices; emulator: "
                          "train the emulator on batched runs and judge it against fresh ones")
     ap.add_argument("--layout", default="tune", choices=("tune", "auto", "box", "full_rows", "in_place"),
@@ -148,6 +150,8 @@ def main():
         return bench_collective(args)
     if args.workload == "accuracy":
         return bench_accuracy(args)
+    if args.workload == "polarisation":
+        return bench_polarisation(args)
     if args.workload == "emulator":
         return bench_emulator(args)
     w = inputs.config1(n_mcs=args.steps)
@@ -434,6 +438,35 @@ def bench_accuracy(args):
         "roofline": None,
         "cpu_baseline": {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")} if cpu else None}),
         flush=True)
+
+
+def bench_polarisation(args):
+    """Directional persistence of Act cells (Fig. 5B): single-cell 2D runs
+    (200^2, one 50^2 cell, Max_act 50) at lambda_act 0..800, 50 runs each,
+    750 MCS sampled every 50, under the serial CPM and the parallel scheme
+    at (s, k) = (2, 1) and (2, 4); the directional autocorrelation A(lag) per
+    lambda and mode.  value: attempts/s of the (2, 1) ensemble."""
+    import numpy as np
+    from paper_2312_09317_amd import polarisation
+    lambdas = (0.0, 100.0, 200.0, 400.0, 800.0)
+    out = polarisation.study(lambdas=lambdas, log=log)
+    ser = np.asarray(out["modes"][0]["A"])
+    rows = []
+    for m in out["modes"]:
+        A = np.asarray(m["A"])
+        rows.append({"mode": m["mode"], "A_lag1": A[:, 1].round(4).tolist(), "A_lag3": A[:, 3].round(4).tolist(),
+                     "max_abs_diff_vs_serial": float(np.abs(A - ser)[:, 1:].max()),
+                     "mean_speed": np.round(m["mean_speed"], 4).tolist(), "gpu_s": m["ms"] / 1e3})
+    n_att = len(lambdas) * out["n_runs"] * 200 * 200 * out["n_mcs"]
+    main = out["modes"][1]
+    print(json.dumps({
+        "metric": "site copy-attempts/s of a 2D Act ensemble, with its directional autocorrelation against the serial CPM",
+        "value": n_att / (main["ms"] / 1e3), "unit": "attempts/s", "n_gpus": 1, "steps": out["n_mcs"], "warmup": 0,
+        "ms_per_step": main["ms"] / out["n_mcs"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "2d-200x200-act-single-cell", "lambdas": list(lambdas), "runs": out["n_runs"],
+                   "interval": out["interval"], "modes": rows},
+        "roofline": None, "cpu_baseline": None}), flush=True)
 
 
 def bench_batch(args):

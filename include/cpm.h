@@ -294,6 +294,16 @@ int cpm_batch_attempt_stats(cpm_batch *b, uint64_t *out, void *stream);
 int cpm_batch_sample(cpm_batch *b, double *d_samples, int32_t k, int32_t n_samples, void *stream);
 int cpm_batch_summary(cpm_batch *b, const double *d_samples, int32_t n_samples, double interval, double *d_out,
                       void *stream);
+/* Directional autocorrelation (Fig. 5B) from n_samples >= 2 samples of
+ * cpm_batch_sample: for lattice i and lag tau = 0..n_samples-2 (in sample
+ * intervals), d_out[2 ((n_samples - 1) i + tau)] = the sum over cells c and
+ * steps k of u_k(c) . u_{k+tau}(c), u the unit minimum-image displacement
+ * of the centroid between samples k and k+1 (defined when the cell is alive
+ * at both and moved), over the pairs where both are defined, and
+ * d_out[... + 1] = the number of such pairs (doubles, device).  Their ratio
+ * is A(tau); runs pool by adding sums and counts. */
+int cpm_batch_autocorrelation(cpm_batch *b, const double *d_samples, int32_t n_samples, double *d_out,
+                              void *stream);
 int cpm_batch_set_mcs(cpm_batch *b, uint64_t mcs);
 int cpm_batch_get_mcs(const cpm_batch *b, uint64_t *mcs);
 int cpm_batch_destroy(cpm_batch *b);

@@ -62,7 +62,7 @@ LAYOUTS = {"auto": 0, "box": 1, "full_rows": 2, "in_place": 3}
 EXPORTS = ("cpm_validate", "cpm_workspace_bytes", "cpm_tile_shape", "cpm_init", "cpm_sweep", "cpm_cell_stats", "cpm_contacts",
            "cpm_persistence", "cpm_counters", "cpm_attempt_stats", "cpm_set_mcs", "cpm_get_mcs", "cpm_destroy",
            "cpm_batch_workspace_bytes", "cpm_batch_init", "cpm_batch_sweep", "cpm_batch_sweep_serial", "cpm_batch_occupancy", "cpm_batch_use_graph", "cpm_batch_counters",
-           "cpm_batch_cell_stats", "cpm_batch_attempt_stats", "cpm_batch_sample", "cpm_batch_summary",
+           "cpm_batch_cell_stats", "cpm_batch_attempt_stats", "cpm_batch_sample", "cpm_batch_summary", "cpm_batch_autocorrelation",
            "cpm_batch_set_mcs", "cpm_batch_get_mcs",
            "cpm_batch_destroy", "cpm_strerror", "cpm_last_error")
 
@@ -108,6 +108,7 @@ def load(path: str = LIB_PATH):
     l.cpm_batch_attempt_stats.argtypes = [P, P, P]
     l.cpm_batch_sample.argtypes = [P, P, I32, I32, P]
     l.cpm_batch_summary.argtypes = [P, P, I32, ctypes.c_double, P, P]
+    l.cpm_batch_autocorrelation.argtypes = [P, P, I32, P, P]
     l.cpm_batch_set_mcs.argtypes = [P, U64]
     l.cpm_batch_get_mcs.argtypes = [P, ctypes.POINTER(U64)]
     l.cpm_batch_destroy.argtypes = [P]
@@ -443,6 +444,11 @@ def cpm_batch_sample(h: int, d_samples, k: int, n_samples: int, stream: int) -> 
     _check(load().cpm_batch_sample(h, _ptr(d_samples), k, n_samples, stream), "cpm_batch_sample")
 
 
+def cpm_batch_autocorrelation(h: int, d_samples, n_samples: int, d_out, stream: int) -> None:
+    _check(load().cpm_batch_autocorrelation(h, _ptr(d_samples), n_samples, _ptr(d_out), stream),
+           "cpm_batch_autocorrelation")
+
+
 def cpm_batch_summary(h: int, d_samples, n_samples: int, interval: float, d_out, stream: int) -> None:
     _check(load().cpm_batch_summary(h, _ptr(d_samples), n_samples, interval, _ptr(d_out), stream),
            "cpm_batch_summary")
@@ -542,15 +548,17 @@ class Batch:
     def attempt_stats(self):
         return cpm_batch_attempt_stats(self.handle, self.n, self.stream)
 
-    def run_with_samples(self, burn_in: int, n_samples: int, interval: int):
+    def run_with_samples(self, burn_in: int, n_samples: int, interval: int, serial: bool = False):
         """Sweep burn_in MCS, then take n_samples samples interval MCS apart
-        (the first at the end of the burn-in); returns the sample buffer."""
+        (the first at the end of the burn-in); returns the sample buffer.
+        serial: sweep with the serial CPM instead of the parallel scheme."""
         samples = self.torch.empty(int(self.label_off[-1]) * n_samples * 5, dtype=self.torch.float64,
                                    device=self.device)
-        self.sweep(burn_in)
+        sweep = self.sweep_serial if serial else self.sweep
+        sweep(burn_in)
         for k in range(n_samples):
             if k:
-                self.sweep(interval)
+                sweep(interval)
             cpm_batch_sample(self.handle, samples, k, n_samples, self.stream)
         return samples
 
@@ -559,6 +567,12 @@ class Batch:
         out = self.torch.empty(self.n * 8, dtype=self.torch.float64, device=self.device)
         cpm_batch_summary(self.handle, samples, n_samples, interval, out, self.stream)
         return out.view(self.n, 8)
+
+    def autocorrelation(self, samples, n_samples: int):
+        """Per lattice and lag: (sum of unit-step dot products, pairs), shape (n, n_samples - 1, 2)."""
+        out = self.torch.empty(self.n * (n_samples - 1) * 2, dtype=self.torch.float64, device=self.device)
+        cpm_batch_autocorrelation(self.handle, samples, n_samples, out, self.stream)
+        return out.view(self.n, n_samples - 1, 2)
 
     @property
     def mcs(self) -> int:

@@ -1148,6 +1148,14 @@ int cpm_batch_summary(cpm_batch *b, const double *d_samples, int32_t n_samples, 
     return CPM_OK;
 }
 
+int cpm_batch_autocorrelation(cpm_batch *b, const double *d_samples, int32_t n_samples, double *d_out, void *stream)
+{
+    if (!b || !d_samples || !d_out) return fail(CPM_EINVAL, "NULL argument");
+    if (n_samples < 2) return fail(CPM_EINVAL, "need at least two samples");
+    const hipError_t e = cpm::launch_autocorrelation(b->stats_tables, d_samples, n_samples, d_out, as_stream(stream));
+    return e == hipSuccess ? CPM_OK : device_fail(e, "autocorrelation");
+}
+
 int cpm_batch_set_mcs(cpm_batch *b, uint64_t mcs)
 {
     if (!b) return fail(CPM_EINVAL, "batch is NULL");

@@ -173,6 +173,8 @@ hipError_t launch_sample(const StatsTables &t, const int32_t *vol, const int32_t
                          double *samples, int k, int n_samples, hipStream_t stream);
 hipError_t launch_summary(const StatsTables &t, const double *samples, int n_samples, double interval, double *out,
                           hipStream_t stream);
+hipError_t launch_autocorrelation(const StatsTables &t, const double *samples, int n_samples, double *out,
+                                  hipStream_t stream);
 size_t sweep_lds_bytes(int ndim, bool act, bool mirror, int box_sites);
 
 }  // namespace cpm

@@ -191,7 +191,65 @@ __global__ void __launch_bounds__(256) summary_kernel(const StatsTables t, const
     }
 }
 
+// Unit displacement of cell c over step k (false when undefined: the cell is
+// dead at either sample or did not move).
+__device__ __forceinline__ bool unit_step(const double *base, int64_t labels, int ndim, const double *L, int k,
+                                          int64_t c, double *u)
+{
+    if (!displacement(base, labels, ndim, L, k, c, u)) return false;
+    double n = 0.0;
+    for (int e = 0; e < ndim; ++e) n = n + u[e] * u[e];
+    n = sqrt(n);
+    if (!(n > 0.0)) return false;
+    for (int e = 0; e < ndim; ++e) u[e] = u[e] / n;
+    return true;
+}
+
+// Directional autocorrelation of lattice blockIdx.x: per lag tau, the sum of
+// u_k . u_{k+tau} over cells and steps with both unit steps defined, and the
+// number of such pairs.  One workgroup per lattice, cells strided over its
+// threads; lags one after another.
+__global__ void __launch_bounds__(256) autocorr_kernel(const StatsTables t, const double *samples, int n_samples,
+                                                       double *out)
+{
+    __shared__ double red[256];
+    const int i = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int64_t labels = t.label_off[i + 1] - t.label_off[i];
+    const double *base = samples + t.label_off[i] * n_samples * kRec;
+    const int ndim = t.ndim;
+    double L[3];
+    for (int d = 0; d < 3; ++d) L[d] = (double)t.dims[3 * i + d];
+    const int m = n_samples - 1;  // steps
+    for (int tau = 0; tau < m; ++tau) {
+        double acc = 0.0, cnt = 0.0;
+        for (int64_t c = 1 + tid; c < labels; c += blockDim.x) {
+            for (int k = 0; k + tau < m; ++k) {
+                double u[3] = {0, 0, 0}, w[3] = {0, 0, 0};
+                if (!unit_step(base, labels, ndim, L, k, c, u)) continue;
+                if (!unit_step(base, labels, ndim, L, k + tau, c, w)) continue;
+                double dot = 0.0;
+                for (int e = 0; e < ndim; ++e) dot = dot + u[e] * w[e];
+                acc = acc + dot;
+                cnt = cnt + 1.0;
+            }
+        }
+        const double sa = block_sum(acc, red), sc = block_sum(cnt, red);
+        if (tid == 0) {
+            out[2 * ((int64_t)i * m + tau)] = sa;
+            out[2 * ((int64_t)i * m + tau) + 1] = sc;
+        }
+    }
+}
+
 }  // namespace
+
+hipError_t launch_autocorrelation(const StatsTables &t, const double *samples, int n_samples, double *out,
+                                  hipStream_t stream)
+{
+    autocorr_kernel<<<t.n, 256, 0, stream>>>(t, samples, n_samples, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_sample(const StatsTables &t, const int32_t *vol, const int32_t *surf, const int64_t *csum,
                          double *samples, int k, int n_samples, hipStream_t stream)

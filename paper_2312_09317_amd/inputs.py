@@ -283,6 +283,22 @@ def chemotaxis_2d(L=256, n_cells=8, side=50, radius=None, seed=1, n_mcs=200, lam
     return w
 
 
+def act_2d(L=200, side=50, lambda_act=200.0, max_act=50, seed=1, n_mcs=750):
+    """One cell, a side x side square in the middle of an L x L lattice, with
+    the Act term (Fig. 5B, Fig. 6B): the paper's 2D settings (V_target 2500,
+    surface target 600, lambda_surface 2, J(cell, medium) 10, T 10) with
+    lambda_V 20, Max_act 50 and polarisation strength lambda_act."""
+    lat = np.zeros((L, L), dtype=np.int32)
+    o = (L - side) // 2
+    lat[o:o + side, o:o + side] = 1
+    J, lv, vt, ls, st = _two_type(0.0, 10.0, 20.0, 2500, 2.0, 600)
+    w = Workload(f"2d-{L}x{L}-act-lambda{lambda_act:g}", 2, (L, L, 1), lat.reshape(1, L, L),
+                 np.array([0, 1], dtype=np.int32), J, lv, vt, ls, st, T=10.0, n_mcs=n_mcs, seed=seed)
+    w.lambda_act = np.array([0.0, float(lambda_act)])
+    w.max_act = np.array([0, int(max_act)], dtype=np.int32)
+    return w
+
+
 def sorting_2d(L=2048, side=50, seed=1, n_mcs=1000, density=0.95, j_same=5.0, j_diff=15.0, j_medium=10.0):
     """Two-type cell sorting in 2D: side x side squares on a jittered grid
     filling about `density` of an L x L lattice (squares_jittered_2d; 40 x 40
