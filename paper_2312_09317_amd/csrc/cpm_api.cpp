@@ -964,6 +964,8 @@ int cpm_batch_init(const cpm_params *params, int32_t n, const int32_t *n_cells, 
     L.mirror = b->mirror;
     L.single = b->single;
     L.k1 = b->k == 1;
+    L.ext = false;
+    for (const SweepArgs &a : b->args) L.ext = L.ext || a.chem != nullptr;
     L.layout = b->layout;
     *out = b.release();
     return CPM_OK;

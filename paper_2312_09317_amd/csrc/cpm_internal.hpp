@@ -104,6 +104,7 @@ struct BatchLaunch {
     size_t lds;
     int ndim;
     bool act, mirror, single, k1;
+    bool ext;               // some lattice uses the chemotaxis term
     int layout;
 };
 

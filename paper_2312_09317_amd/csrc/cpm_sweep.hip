@@ -117,7 +117,7 @@ struct SharedTables {
 };
 
 // nbl(n) gives the label of the target's n-th Moore neighbour.
-template <typename Cell, int D, bool ACT, bool SINGLE, int LAYOUT, typename NB>
+template <typename Cell, int D, bool ACT, bool SINGLE, int LAYOUT, bool EXT, typename NB>
 __device__ __forceinline__ bool evaluate_nb(const SweepArgs &a, const ThrTables &tb, const JRows &jr,
                                             const SharedTables &st, const NB &nbl, Cell *lab, uint8_t *lact,
                                             const LdsMap<LAYOUT> &map, int tx_, int ty_, int tz_, int sx_, int sy_,
@@ -174,7 +174,7 @@ __device__ __forceinline__ bool evaluate_nb(const SweepArgs &a, const ThrTables 
         const int64_t rs = ls >= 1 ? m->r_act[ts] : 0;
         q += (rt * gt - rs * gs) >> 16;
     }
-    if (a.pdir && ls >= 1) {
+    if (EXT && a.pdir && ls >= 1) {
         // persistence: the copying cell ls extends from the source into the
         // target; copies along its direction are favoured
         const int o = (tx_ - sx_ + 1) + 3 * (ty_ - sy_ + 1) + 9 * (tz_ - sz_ + 1);
@@ -183,7 +183,7 @@ __device__ __forceinline__ bool evaluate_nb(const SweepArgs &a, const ThrTables 
                             (int64_t)m->unit[o][2] * pd.z;
         q -= (m->lam_p[ts] * dot) >> 28;
     }
-    if (a.chem && ls >= 1) {
+    if (EXT && a.chem && ls >= 1) {
         // chemotaxis: the field at the source, dotted with the copy's direction
         const int o = (tx_ - sx_ + 1) + 3 * (ty_ - sy_ + 1) + 9 * (tz_ - sz_ + 1);
         int64_t dot;
@@ -202,7 +202,7 @@ __device__ __forceinline__ bool evaluate_nb(const SweepArgs &a, const ThrTables 
 }
 
 // evaluate_nb with the neighbour labels read through `map`.
-template <typename Cell, int D, bool ACT, bool SINGLE, int LAYOUT>
+template <typename Cell, int D, bool ACT, bool SINGLE, int LAYOUT, bool EXT>
 __device__ __forceinline__ bool evaluate(const SweepArgs &a, const ThrTables &tb, const JRows &jr,
                                          const SharedTables &st, Cell *lab, uint8_t *lact,
                                          const LdsMap<LAYOUT> &map, int tx_, int ty_, int tz_, int sx_, int sy_,
@@ -215,7 +215,7 @@ __device__ __forceinline__ bool evaluate(const SweepArgs &a, const ThrTables &tb
         const int xx = dx < 0 ? xm : (dx > 0 ? xp : x0);
         return label_of(lab[xx + map.row(ty_ + nb_dy<D>(n), tz_ + nb_dz<D>(n))]);
     };
-    return evaluate_nb<Cell, D, ACT, SINGLE, LAYOUT>(a, tb, jr, st, nbl, lab, lact, map, tx_, ty_, tz_, sx_, sy_,
+    return evaluate_nb<Cell, D, ACT, SINGLE, LAYOUT, EXT>(a, tb, jr, st, nbl, lab, lact, map, tx_, ty_, tz_, sx_, sy_,
                                                      sz_, src_gi, lt, ls, cnt_t, cnt_s, u2, dso_out, dsn_out);
 }
 
@@ -234,7 +234,7 @@ __device__ __forceinline__ int2 seen_counters(const int32_t *rd, int c, const in
 }
 
 // One workgroup's share of one activation: tile `tile` of the lattice `a`.
-template <typename Cell, int D, bool ACT, bool SINGLE, bool K1, int LAYOUT>
+template <typename Cell, int D, bool ACT, bool SINGLE, bool K1, int LAYOUT, bool EXT>
 __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_t mcs, uint32_t alpha, int parity)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -377,7 +377,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
                 jr = JRows{J[tc * kMaxTypes + tc], J[tc * kMaxTypes], J[tc * kMaxTypes + to], J[tc], J[0], J[to]};
             }
             int64_t dso, dsn;
-            if (evaluate<Cell, D, ACT, SINGLE, LAYOUT>(a, tb, jr, sht, lab, lact, map, ttx, tty, ttz, ssx, ssy, ssz,
+            if (evaluate<Cell, D, ACT, SINGLE, LAYOUT, EXT>(a, tb, jr, sht, lab, lact, map, ttx, tty, ttz, ssx, ssy, ssz,
                                                        map.at(ssx, ssy, ssz), lt, ls, seen_counters(rd, lt, nullptr, 0),
                                                        seen_counters(rd, ls, nullptr, 0), u2, dso, dsn)) {
                 accepted = 1;
@@ -536,8 +536,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
             } else {
                 // queue full: evaluate here (no other attempt reads this sub-area)
                 int64_t dso, dsn;
-                if (evaluate<Cell, D, ACT, SINGLE, LAYOUT>(a, tb, jr, sht, lab, lact, map, d_ttx, d_tty, d_ttz, d_ssx,
-                                                            d_ssy, d_ssz, a.chem ? global_index(d_ssx, d_ssy, d_ssz) : 0,
+                if (evaluate<Cell, D, ACT, SINGLE, LAYOUT, EXT>(a, tb, jr, sht, lab, lact, map, d_ttx, d_tty, d_ttz, d_ssx,
+                                                            d_ssy, d_ssz, EXT && a.chem ? global_index(d_ssx, d_ssy, d_ssz) : 0,
                                                             d_lt, d_ls, d_ct, d_cs, d_u2, dso, dsn)) {
                     ++my_accepted;
                     commit(map.at(d_ttx, d_tty, d_ttz), global_index(d_ttx, d_tty, d_ttz), d_lt, d_ls, dso, dsn);
@@ -555,8 +555,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
             const int t = map.at(ttx, tty, ttz);
             const int lt = label_of(lab[t]), ls = label_of(lab[map.at(ssx, ssy, ssz)]);
             int64_t dso, dsn;
-            if (evaluate<Cell, D, ACT, SINGLE, LAYOUT>(a, tb, jr, sht, lab, lact, map, ttx, tty, ttz, ssx, ssy, ssz,
-                                                        a.chem ? global_index(ssx, ssy, ssz) : 0, lt, ls,
+            if (evaluate<Cell, D, ACT, SINGLE, LAYOUT, EXT>(a, tb, jr, sht, lab, lact, map, ttx, tty, ttz, ssx, ssy, ssz,
+                                                        EXT && a.chem ? global_index(ssx, ssy, ssz) : 0, lt, ls,
                                                         make_int2(c.x, c.y), make_int2(c.z, c.w), (uint32_t)e.w,
                                                         dso, dsn)) {
                 ++my_accepted;
@@ -578,8 +578,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
                 if (lt != ls && lt >= 0 && ls >= 0) {
                     ++my_nontrivial;
                     int64_t dso, dsn;
-                    if (evaluate<Cell, D, ACT, SINGLE, LAYOUT>(a, tb, jr, sht, lab, lact, map, ttx, tty, ttz, ssx, ssy,
-                                                                ssz, a.chem ? global_index(ssx, ssy, ssz) : 0, lt, ls,
+                    if (evaluate<Cell, D, ACT, SINGLE, LAYOUT, EXT>(a, tb, jr, sht, lab, lact, map, ttx, tty, ttz, ssx, ssy,
+                                                                ssz, EXT && a.chem ? global_index(ssx, ssy, ssz) : 0, lt, ls,
                                                                 seen_counters(rd, lt, own, j),
                                                                 seen_counters(rd, ls, own, j), u2, dso, dsn)) {
                         ++my_accepted;
@@ -604,36 +604,36 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
 
 // One lattice: workgroup b takes tile (b mod 8) * tiles_per_xcd + b div 8, so
 // each XCD sweeps one contiguous slab of tiles in every activation.
-template <typename Cell, int D, bool ACT, bool SINGLE, bool K1, int LAYOUT>
+template <typename Cell, int D, bool ACT, bool SINGLE, bool K1, int LAYOUT, bool EXT>
 __global__ void __launch_bounds__(kBlock) tile_sweep_kernel(SweepArgs a, uint32_t mcs, uint32_t alpha, int parity)
 {
     const int tile = (int)(blockIdx.x % kXcds) * a.tg.tiles_per_xcd + (int)(blockIdx.x / kXcds);
     if (tile >= a.tg.n_tiles) return;  // uniform over the block
-    sweep_tile<Cell, D, ACT, SINGLE, K1, LAYOUT>(a, tile, mcs, alpha, parity);
+    sweep_tile<Cell, D, ACT, SINGLE, K1, LAYOUT, EXT>(a, tile, mcs, alpha, parity);
 }
 
 // Many lattices advanced together: work[b] = (lattice, tile) of workgroup b;
 // all lattices share the MCS counter at *mcs.
-template <typename Cell, int D, bool ACT, bool SINGLE, bool K1, int LAYOUT>
+template <typename Cell, int D, bool ACT, bool SINGLE, bool K1, int LAYOUT, bool EXT>
 __global__ void __launch_bounds__(kBlock) batch_sweep_kernel(const SweepArgs *args, const int2 *work,
                                                              const uint32_t *mcs, uint32_t alpha, int parity)
 {
     const int2 w = work[blockIdx.x];
-    sweep_tile<Cell, D, ACT, SINGLE, K1, LAYOUT>(args[w.x], w.y, *mcs, alpha, parity);
+    sweep_tile<Cell, D, ACT, SINGLE, K1, LAYOUT, EXT>(args[w.x], w.y, *mcs, alpha, parity);
 }
 
-template <typename Cell, int D, bool ACT, bool SINGLE>
+template <typename Cell, int D, bool ACT, bool SINGLE, bool EXT>
 hipError_t launch_k(const SweepArgs &a, bool k1, int layout, uint32_t mcs, uint32_t alpha, int parity, size_t lds,
                     hipStream_t st)
 {
     if (k1 && layout == kDirect)
-        tile_sweep_kernel<Cell, D, ACT, SINGLE, true, kDirect><<<a.tg.grid, kBlock, lds, st>>>(a, mcs, alpha, parity);
+        tile_sweep_kernel<Cell, D, ACT, SINGLE, true, kDirect, EXT><<<a.tg.grid, kBlock, lds, st>>>(a, mcs, alpha, parity);
     else if (k1 && layout == kFullRow)
-        tile_sweep_kernel<Cell, D, ACT, SINGLE, true, kFullRow><<<a.tg.grid, kBlock, lds, st>>>(a, mcs, alpha, parity);
+        tile_sweep_kernel<Cell, D, ACT, SINGLE, true, kFullRow, EXT><<<a.tg.grid, kBlock, lds, st>>>(a, mcs, alpha, parity);
     else if (k1)
-        tile_sweep_kernel<Cell, D, ACT, SINGLE, true, kBox><<<a.tg.grid, kBlock, lds, st>>>(a, mcs, alpha, parity);
+        tile_sweep_kernel<Cell, D, ACT, SINGLE, true, kBox, EXT><<<a.tg.grid, kBlock, lds, st>>>(a, mcs, alpha, parity);
     else
-        tile_sweep_kernel<Cell, D, ACT, SINGLE, false, kBox><<<a.tg.grid, kBlock, lds, st>>>(a, mcs, alpha, parity);
+        tile_sweep_kernel<Cell, D, ACT, SINGLE, false, kBox, EXT><<<a.tg.grid, kBlock, lds, st>>>(a, mcs, alpha, parity);
     return hipGetLastError();
 }
 
@@ -642,8 +642,13 @@ hipError_t launch_s(const SweepArgs &a, uint32_t mcs, uint32_t alpha, int parity
 {
     const bool k1 = a.k == 1;
     const int layout = a.tg.layout;
-    return a.single_type >= 0 ? launch_k<Cell, D, ACT, true>(a, k1, layout, mcs, alpha, parity, lds, st)
-                              : launch_k<Cell, D, ACT, false>(a, k1, layout, mcs, alpha, parity, lds, st);
+    // the persistence and chemotaxis terms are compiled in only where used
+    const bool ext = a.pdir || a.chem;
+    if (a.single_type >= 0)
+        return ext ? launch_k<Cell, D, ACT, true, true>(a, k1, layout, mcs, alpha, parity, lds, st)
+                   : launch_k<Cell, D, ACT, true, false>(a, k1, layout, mcs, alpha, parity, lds, st);
+    return ext ? launch_k<Cell, D, ACT, false, true>(a, k1, layout, mcs, alpha, parity, lds, st)
+               : launch_k<Cell, D, ACT, false, false>(a, k1, layout, mcs, alpha, parity, lds, st);
 }
 
 template <typename Cell>
@@ -733,25 +738,28 @@ hipError_t launch_activation(const SweepArgs &a, int ndim, bool act, bool mirror
 
 namespace {
 
-template <typename Cell, int D, bool ACT, bool SINGLE>
+template <typename Cell, int D, bool ACT, bool SINGLE, bool EXT>
 hipError_t launch_batch_k(const BatchLaunch &b, uint32_t alpha, int parity, hipStream_t st)
 {
     if (b.k1 && b.layout == kDirect)
-        batch_sweep_kernel<Cell, D, ACT, SINGLE, true, kDirect><<<b.grid, kBlock, b.lds, st>>>(b.args, b.work, b.mcs, alpha, parity);
+        batch_sweep_kernel<Cell, D, ACT, SINGLE, true, kDirect, EXT><<<b.grid, kBlock, b.lds, st>>>(b.args, b.work, b.mcs, alpha, parity);
     else if (b.k1 && b.layout == kFullRow)
-        batch_sweep_kernel<Cell, D, ACT, SINGLE, true, kFullRow><<<b.grid, kBlock, b.lds, st>>>(b.args, b.work, b.mcs, alpha, parity);
+        batch_sweep_kernel<Cell, D, ACT, SINGLE, true, kFullRow, EXT><<<b.grid, kBlock, b.lds, st>>>(b.args, b.work, b.mcs, alpha, parity);
     else if (b.k1)
-        batch_sweep_kernel<Cell, D, ACT, SINGLE, true, kBox><<<b.grid, kBlock, b.lds, st>>>(b.args, b.work, b.mcs, alpha, parity);
+        batch_sweep_kernel<Cell, D, ACT, SINGLE, true, kBox, EXT><<<b.grid, kBlock, b.lds, st>>>(b.args, b.work, b.mcs, alpha, parity);
     else
-        batch_sweep_kernel<Cell, D, ACT, SINGLE, false, kBox><<<b.grid, kBlock, b.lds, st>>>(b.args, b.work, b.mcs, alpha, parity);
+        batch_sweep_kernel<Cell, D, ACT, SINGLE, false, kBox, EXT><<<b.grid, kBlock, b.lds, st>>>(b.args, b.work, b.mcs, alpha, parity);
     return hipGetLastError();
 }
 
 template <typename Cell, int D, bool ACT>
 hipError_t launch_batch_s(const BatchLaunch &b, uint32_t alpha, int parity, hipStream_t st)
 {
-    return b.single ? launch_batch_k<Cell, D, ACT, true>(b, alpha, parity, st)
-                    : launch_batch_k<Cell, D, ACT, false>(b, alpha, parity, st);
+    if (b.single)
+        return b.ext ? launch_batch_k<Cell, D, ACT, true, true>(b, alpha, parity, st)
+                     : launch_batch_k<Cell, D, ACT, true, false>(b, alpha, parity, st);
+    return b.ext ? launch_batch_k<Cell, D, ACT, false, true>(b, alpha, parity, st)
+                 : launch_batch_k<Cell, D, ACT, false, false>(b, alpha, parity, st);
 }
 
 template <typename Cell>
