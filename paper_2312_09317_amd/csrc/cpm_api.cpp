@@ -25,6 +25,7 @@ struct cpm_handle {
     bool act = false;
     bool mirror = false;             // sweeps run on a 16-bit copy of the lattice
     uint16_t *mirror_cells = nullptr;
+    int words = cpm::kWords32;       // what sweeps read: int32 labels, the 16-bit copy or packed words
     SweepArgs args{};
     int32_t *ref = nullptr;          // centroid reference sites, n_cells + 1
     // persistence (NULL pdir = off): directions, centroid history, centroid sums
@@ -113,6 +114,8 @@ struct Layout {
 // Labels fit the 16-bit working copy (label + 1): cells 1..65534, medium 0,
 // obstacle -1.
 bool use_mirror(int32_t n_cells) { return n_cells <= 65534; }
+// Packed words hold label + 1 in 24 bits.
+constexpr int32_t kMaxPackedCells = (1 << 24) - 2;
 
 // Widest load (16, 8 or 4 bytes) that divides both a row and the base address.
 int32_t chunk_for(const void *base, size_t row_bytes)
@@ -528,9 +531,9 @@ hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
 // Persistence directions after update t (t = 0: initialisation) from the
 // current lattice: centroid sums, then one thread per cell.
-hipError_t persist_step(cpm_handle *h, int64_t t, bool from_mirror, hipStream_t st)
+hipError_t persist_step(cpm_handle *h, int64_t t, int words, hipStream_t st)
 {
-    hipError_t e = cpm::launch_centroids(h->args, h->ndim, h->n_cells, h->ref, h->csum, st, from_mirror);
+    hipError_t e = cpm::launch_centroids(h->args, h->ndim, h->n_cells, h->ref, h->csum, st, words);
     if (e != hipSuccess) return e;
     cpm::PersistArgs p{};
     p.pdir = h->pdir;
@@ -623,7 +626,12 @@ int cpm_init(const cpm_params *params, int32_t *d_lattice, const int32_t *d_cell
     }
     if ((e = start_lattice(h->args, lay, ws, h->host_model.get(), params->ndim, n_cells, st)) != hipSuccess)
         return device_fail(e, "init");
-    if (h->pdir && (e = persist_step(h.get(), 0, false, st)) != hipSuccess) return device_fail(e, "persistence init");
+    if (h->pdir && (e = persist_step(h.get(), 0, cpm::kWords32, st)) != hipSuccess)
+        return device_fail(e, "persistence init");
+    // multi-type lattices too large for the 16-bit copy sweep on packed
+    // words (label and type in one word) written over the int32 lattice
+    h->words = h->mirror ? cpm::kWords16
+                         : (single < 0 && n_cells <= kMaxPackedCells ? cpm::kWordsPacked : cpm::kWords32);
     *out = h.release();
     return CPM_OK;
 }
@@ -640,24 +648,29 @@ int sweep_impl(cpm_handle *h, int32_t n_mcs, hipStream_t st)
     const uint32_t n_act = (uint32_t)(((int64_t)1 << h->ndim) * sd / h->k);
     const size_t n_sites = (size_t)h->L[0] * h->L[1] * h->L[2];
     hipError_t e;
+    if (h->words == cpm::kWordsPacked &&
+        (e = cpm::launch_pack(h->args.lat, h->args.cell_type, h->args.obstacle_type, n_sites, st)) != hipSuccess)
+        return device_fail(e, "pack label and type words");
     if (h->mirror && (e = cpm::launch_to_mirror(h->args.lat, h->mirror_cells, n_sites, st)) != hipSuccess)
         return device_fail(e, "to 16-bit working copy");
     for (int32_t i = 0; i < n_mcs; ++i) {
         const uint32_t mcs = (uint32_t)h->mcs;
         for (uint32_t alpha = 0; alpha < n_act; ++alpha) {
-            e = cpm::launch_activation(h->args, h->ndim, h->act, h->mirror, mcs, alpha, (int)(h->activation & 1), st);
+            e = cpm::launch_activation(h->args, h->ndim, h->act, h->words, mcs, alpha, (int)(h->activation & 1), st);
             if (e != hipSuccess) return device_fail(e, "activation");
             ++h->activation;
         }
         if (h->act && (e = cpm::launch_act_decay(h->args.act, n_sites, st)) != hipSuccess)
             return device_fail(e, "act decay");
-        if (h->pdir && (e = persist_step(h, ++h->persist_t, h->mirror, st)) != hipSuccess)
+        if (h->pdir && (e = persist_step(h, ++h->persist_t, h->words, st)) != hipSuccess)
             return device_fail(e, "persistence update");
         ++h->mcs;
         h->attempts_run += (uint64_t)n_sites;
     }
     if (h->mirror && (e = cpm::launch_from_mirror(h->mirror_cells, h->args.lat, n_sites, st)) != hipSuccess)
         return device_fail(e, "from 16-bit working copy");
+    if (h->words == cpm::kWordsPacked && (e = cpm::launch_unpack(h->args.lat, n_sites, st)) != hipSuccess)
+        return device_fail(e, "unpack labels");
     return CPM_OK;
 }
 

@@ -33,6 +33,27 @@ __device__ __forceinline__ Cell stored_label(int label) { return (Cell)label; }
 template <>
 __device__ __forceinline__ uint16_t stored_label<uint16_t>(int label) { return (uint16_t)(label + 1); }
 
+// Packed words (uint32, the caller's int32 lattice rewritten in place for
+// the length of a sweep): label + 1 in bits 0..23, the cell type in bits
+// 24..31 (obstacle: the obstacle type; medium: 0), so a neighbour's type
+// arrives with its label.
+__device__ __forceinline__ int label_of(uint32_t v) { return (int)(v & 0xFFFFFFu) - 1; }
+__device__ __forceinline__ uint32_t packed_word(int label, int type)
+{
+    return (uint32_t)(label + 1) | ((uint32_t)type << 24);
+}
+
+// Cell type of a site from its stored word (`label` = label_of(word)).
+__device__ __forceinline__ int type_of_word(const SweepArgs &a, uint32_t word, int) { return (int)(word >> 24); }
+__device__ __forceinline__ int type_of_word(const SweepArgs &a, int32_t, int label)
+{
+    return label < 0 ? a.obstacle_type : a.cell_type[label];
+}
+__device__ __forceinline__ int type_of_word(const SweepArgs &a, uint16_t, int label)
+{
+    return label < 0 ? a.obstacle_type : a.cell_type[label];
+}
+
 // Division by a divisor fixed for a whole workgroup: q = floor(n / d) as one
 // multiply-high, exact whenever n * d < 2^32 (m = floor((2^32 - 1) / d) + 1
 // overshoots 2^32 / d by less than 1, so the error n / 2^32 stays below the

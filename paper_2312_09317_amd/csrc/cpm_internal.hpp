@@ -153,8 +153,13 @@ hipError_t launch_occupancy(const int32_t *lattices, int n_lattices, size_t n_si
 int64_t reduce_brick_count(const int *L, int ndim);
 hipError_t launch_count(const SweepArgs &a, int ndim, int32_t *v_out, int32_t *s_out, int stride,
                         hipStream_t stream);
-hipError_t launch_activation(const SweepArgs &a, int ndim, bool act, bool mirror, uint32_t mcs,
-                             uint32_t alpha, int parity, hipStream_t stream);
+// Stored words the sweep works on: the caller's int32 labels, the 16-bit
+// working copy, or the int32 lattice rewritten in place as packed words.
+enum Words { kWords32 = 0, kWords16 = 1, kWordsPacked = 2 };
+hipError_t launch_activation(const SweepArgs &a, int ndim, bool act, int words, uint32_t mcs, uint32_t alpha,
+                             int parity, hipStream_t stream);
+hipError_t launch_pack(int32_t *lat, const int32_t *cell_type, int obstacle_type, size_t n, hipStream_t stream);
+hipError_t launch_unpack(int32_t *lat, size_t n, hipStream_t stream);
 hipError_t launch_to_mirror(const int32_t *lat, uint16_t *mirror, size_t n, hipStream_t stream);
 hipError_t launch_from_mirror(const uint16_t *mirror, int32_t *lat, size_t n, hipStream_t stream);
 // Every lattice of a batch (args[i].lat <-> args[i].cells) in one launch.
@@ -162,7 +167,7 @@ hipError_t launch_batch_mirror(const SweepArgs *d_args, int n_lattices, size_t m
                                hipStream_t stream);
 hipError_t launch_act_decay(uint8_t *act, size_t n, hipStream_t stream);
 hipError_t launch_centroids(const SweepArgs &a, int ndim, int32_t n_cells, int32_t *ref,
-                            int64_t *out, hipStream_t stream, bool from_mirror = false);
+                            int64_t *out, hipStream_t stream, int words = kWords32);
 // Persistence directions (x, y, z of each int4) into out, 3 x n_labels int32.
 hipError_t launch_copy_dirs(const int4 *pdir, int32_t n_labels, int32_t *out, hipStream_t stream);
 hipError_t launch_copy_counters(const int32_t *pairs, int32_t n_labels, int32_t *v_out,

@@ -1,5 +1,7 @@
 // HIP kernels around the sweep: counting volumes / surfaces from the lattice,
 // centroid sums, activity decay, fills and counter copies.
+#include <type_traits>
+
 #include "cpm_device.hpp"
 
 namespace cpm {
@@ -53,11 +55,18 @@ __device__ __forceinline__ int map_slot(LabelMap &m, int label)
 
 // The kSitesPerThread consecutive labels from site i0 (n of them valid),
 // vector loads where the row of them is whole and 16-byte aligned.
-template <bool M16>
+// A label from an int32 lattice word: the label itself, or a packed word.
+template <int WORDS>
+__device__ __forceinline__ int word_label(int32_t v)
+{
+    return WORDS == kWordsPacked ? label_of((uint32_t)v) : v;
+}
+
+template <int WORDS>
 __device__ __forceinline__ void load_run_labels(const SweepArgs &a, int64_t i0, int n, int (&lab)[kSitesPerThread])
 {
     static_assert(kSitesPerThread == 16, "vector loads below assume 16 sites per thread");
-    if (M16) {
+    if (WORDS == kWords16) {
         const uint16_t *src = reinterpret_cast<const uint16_t *>(a.cells) + i0;
         if (n == kSitesPerThread && (reinterpret_cast<uintptr_t>(src) & 15) == 0) {
             const uint4 v[2] = {reinterpret_cast<const uint4 *>(src)[0], reinterpret_cast<const uint4 *>(src)[1]};
@@ -77,20 +86,21 @@ __device__ __forceinline__ void load_run_labels(const SweepArgs &a, int64_t i0, 
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const int4 v = reinterpret_cast<const int4 *>(src)[k];
-                lab[4 * k] = v.x;
-                lab[4 * k + 1] = v.y;
-                lab[4 * k + 2] = v.z;
-                lab[4 * k + 3] = v.w;
+                lab[4 * k] = word_label<WORDS>(v.x);
+                lab[4 * k + 1] = word_label<WORDS>(v.y);
+                lab[4 * k + 2] = word_label<WORDS>(v.z);
+                lab[4 * k + 3] = word_label<WORDS>(v.w);
             }
         } else {
 #pragma unroll
-            for (int k = 0; k < kSitesPerThread; ++k) lab[k] = k < n ? src[k] : 0;
+            for (int k = 0; k < kSitesPerThread; ++k) lab[k] = k < n ? word_label<WORDS>(src[k]) : 0;
         }
     }
 }
 
 // One workgroup's share of a reduction over lattice a, read from its int32
-// labels or (M16) its 16-bit working copy.  kCount: kSitesPerBlock sites
+// labels, its 16-bit working copy or its packed words (WORDS).  kCount
+// (int32 labels only): kSitesPerBlock sites
 // from `block`, thread t taking sites t, t + kBlock, ... (its neighbours'
 // reads coalesce).  kRef, kCentroid: brick `block` (ReduceBrick), thread t
 // taking kSitesPerThread consecutive sites of one row and touching the label
@@ -98,7 +108,7 @@ __device__ __forceinline__ void load_run_labels(const SweepArgs &a, int64_t i0, 
 // of the run) for kRef, with the run's summed coordinates for kCentroid.
 // Bricks rather than row strips keep the workgroups that see one cell, and
 // so the global atomics per cell, few.
-template <int D, int MODE, bool M16 = false>
+template <int D, int MODE, int WORDS = kWords32>
 __device__ __forceinline__ void reduce_block(const SweepArgs &a, int64_t block, int32_t *v_out, int32_t *s_out,
                                              int stride, int32_t *ref, int64_t *cent)
 {
@@ -149,7 +159,7 @@ __device__ __forceinline__ void reduce_block(const SweepArgs &a, int64_t block, 
             const int n = min(kSitesPerThread, L0 - x);
             const int first = (z * L1 + y) * L0 + x;  // lattices hold fewer than 2^31 sites
             int lab[kSitesPerThread];
-            load_run_labels<M16>(a, first, n, lab);
+            load_run_labels<WORDS>(a, first, n, lab);
             int cur = INT32_MIN;  // label of the open run
             int r[3] = {0, 0, 0};
             int64_t acc[3] = {0, 0, 0};
@@ -215,12 +225,12 @@ __device__ __forceinline__ void reduce_block(const SweepArgs &a, int64_t block, 
     }
 }
 
-template <int D, int MODE, bool M16 = false>
+template <int D, int MODE, int WORDS = kWords32>
 __global__ void __launch_bounds__(kBlock) reduce_kernel(SweepArgs a, int32_t *v_out, int32_t *s_out, int stride,
                                                         int32_t *ref, int64_t *cent)
 {
-    static_assert(!M16 || MODE != kCount, "counts read the int32 labels");
-    reduce_block<D, MODE, M16>(a, blockIdx.x, v_out, s_out, stride, ref, cent);
+    static_assert(WORDS == kWords32 || MODE != kCount, "counts read the int32 labels");
+    reduce_block<D, MODE, WORDS>(a, blockIdx.x, v_out, s_out, stride, ref, cent);
 }
 
 // Every lattice of a batch in one launch: blockIdx.y is the lattice, outputs
@@ -431,25 +441,31 @@ hipError_t launch_act_decay(uint8_t *act, size_t n, hipStream_t stream)
 }
 
 hipError_t launch_centroids(const SweepArgs &a, int ndim, int32_t n_cells, int32_t *ref, int64_t *out,
-                            hipStream_t stream, bool from_mirror)
+                            hipStream_t stream, int words)
 {
     const unsigned grid = (unsigned)(ndim == 2 ? reduce_bricks<2>(a.L) : reduce_bricks<3>(a.L));
     hipError_t e = launch_fill_i32(ref, INT32_MAX, (size_t)n_cells + 1, stream);
     if (e != hipSuccess) return e;
     e = launch_fill_i32(reinterpret_cast<int32_t *>(out), 0, ((size_t)n_cells + 1) * ndim * 2, stream);
     if (e != hipSuccess) return e;
-    if (ndim == 2 && from_mirror) {
-        reduce_kernel<2, kRef, true><<<grid, kBlock, 0, stream>>>(a, nullptr, nullptr, 0, ref, nullptr);
-        reduce_kernel<2, kCentroid, true><<<grid, kBlock, 0, stream>>>(a, nullptr, nullptr, 0, ref, out);
-    } else if (ndim == 2) {
-        reduce_kernel<2, kRef><<<grid, kBlock, 0, stream>>>(a, nullptr, nullptr, 0, ref, nullptr);
-        reduce_kernel<2, kCentroid><<<grid, kBlock, 0, stream>>>(a, nullptr, nullptr, 0, ref, out);
-    } else if (from_mirror) {
-        reduce_kernel<3, kRef, true><<<grid, kBlock, 0, stream>>>(a, nullptr, nullptr, 0, ref, nullptr);
-        reduce_kernel<3, kCentroid, true><<<grid, kBlock, 0, stream>>>(a, nullptr, nullptr, 0, ref, out);
+    auto run = [&](auto d_tag, auto w_tag) {
+        constexpr int D = decltype(d_tag)::value, W = decltype(w_tag)::value;
+        reduce_kernel<D, kRef, W><<<grid, kBlock, 0, stream>>>(a, nullptr, nullptr, 0, ref, nullptr);
+        reduce_kernel<D, kCentroid, W><<<grid, kBlock, 0, stream>>>(a, nullptr, nullptr, 0, ref, out);
+    };
+    using D2 = std::integral_constant<int, 2>;
+    using D3 = std::integral_constant<int, 3>;
+    using W32 = std::integral_constant<int, kWords32>;
+    using W16 = std::integral_constant<int, kWords16>;
+    using WP = std::integral_constant<int, kWordsPacked>;
+    if (ndim == 2) {
+        if (words == kWords16) run(D2{}, W16{});
+        else if (words == kWordsPacked) run(D2{}, WP{});
+        else run(D2{}, W32{});
     } else {
-        reduce_kernel<3, kRef><<<grid, kBlock, 0, stream>>>(a, nullptr, nullptr, 0, ref, nullptr);
-        reduce_kernel<3, kCentroid><<<grid, kBlock, 0, stream>>>(a, nullptr, nullptr, 0, ref, out);
+        if (words == kWords16) run(D3{}, W16{});
+        else if (words == kWordsPacked) run(D3{}, WP{});
+        else run(D3{}, W32{});
     }
     return hipGetLastError();
 }

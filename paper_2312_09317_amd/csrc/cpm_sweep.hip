@@ -121,20 +121,18 @@ template <typename Cell, int D, bool ACT, bool SINGLE, int LAYOUT, bool EXT, typ
 __device__ __forceinline__ bool evaluate_nb(const SweepArgs &a, const ThrTables &tb, const JRows &jr,
                                             const SharedTables &st, const NB &nbl, Cell *lab, uint8_t *lact,
                                             const LdsMap<LAYOUT> &map, int tx_, int ty_, int tz_, int sx_, int sy_,
-                                            int sz_, int src_gi, int lt, int ls, int2 cnt_t, int2 cnt_s, uint32_t u2,
-                                            int64_t &dso_out, int64_t &dsn_out)
+                                            int sz_, int src_gi, int lt, int ls, int tt, int ts, int2 cnt_t, int2 cnt_s,
+                                            uint32_t u2, int64_t &dso_out, int64_t &dsn_out)
 {
     constexpr int NNB = D == 2 ? 8 : 26;
     const DeviceModel *m = a.model;
-    const int tc = a.single_type, to = a.obstacle_type;
-    const int tt = lt == 0 ? 0 : (SINGLE ? tc : a.cell_type[lt]);
-    const int ts = ls == 0 ? 0 : (SINGLE ? tc : a.cell_type[ls]);
     int k_old = 0, k_new = 0;
     int n_cell = 0, n_med = 0, n_obs = 0;
     int64_t adh = 0;
 #pragma unroll
     for (int n = 0; n < NNB; ++n) {
-        const int lu = nbl(n);
+        const Cell word = nbl(n);
+        const int lu = label_of(word);
         k_old += lu == lt;
         k_new += lu == ls;
         if (SINGLE) {
@@ -142,7 +140,7 @@ __device__ __forceinline__ bool evaluate_nb(const SweepArgs &a, const ThrTables 
             n_med += lu == 0;
             n_obs += lu < 0;
         } else {
-            const int tu = lu < 0 ? to : a.cell_type[lu];
+            const int tu = type_of_word(a, word, lu);
             if (lu != ls) adh += st.J[ts * kMaxTypes + tu];
             if (lu != lt) adh -= st.J[tt * kMaxTypes + tu];
         }
@@ -206,17 +204,17 @@ template <typename Cell, int D, bool ACT, bool SINGLE, int LAYOUT, bool EXT>
 __device__ __forceinline__ bool evaluate(const SweepArgs &a, const ThrTables &tb, const JRows &jr,
                                          const SharedTables &st, Cell *lab, uint8_t *lact,
                                          const LdsMap<LAYOUT> &map, int tx_, int ty_, int tz_, int sx_, int sy_,
-                                         int sz_, int src_gi, int lt, int ls, int2 cnt_t, int2 cnt_s, uint32_t u2,
-                                         int64_t &dso_out, int64_t &dsn_out)
+                                         int sz_, int src_gi, int lt, int ls, int tt, int ts, int2 cnt_t, int2 cnt_s,
+                                         uint32_t u2, int64_t &dso_out, int64_t &dsn_out)
 {
     const int xm = map.x(tx_ - 1), x0 = map.x(tx_), xp = map.x(tx_ + 1);
     auto nbl = [&](int n) {
         const int dx = nb_dx<D>(n);
         const int xx = dx < 0 ? xm : (dx > 0 ? xp : x0);
-        return label_of(lab[xx + map.row(ty_ + nb_dy<D>(n), tz_ + nb_dz<D>(n))]);
+        return lab[xx + map.row(ty_ + nb_dy<D>(n), tz_ + nb_dz<D>(n))];
     };
     return evaluate_nb<Cell, D, ACT, SINGLE, LAYOUT, EXT>(a, tb, jr, st, nbl, lab, lact, map, tx_, ty_, tz_, sx_, sy_,
-                                                     sz_, src_gi, lt, ls, cnt_t, cnt_s, u2, dso_out, dsn_out);
+                                                     sz_, src_gi, lt, ls, tt, ts, cnt_t, cnt_s, u2, dso_out, dsn_out);
 }
 
 // Counters of label c as an attempt of this thread sees them: the read
@@ -335,11 +333,17 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
         const int gz = D == 3 ? wrap_once(o2 + vz, L2) : 0;
         return (int)(((size_t)gz * L1 + gy) * L0 + gx);
     };
-    auto commit = [&](int t, int gi, int lt, int ls, int64_t dso, int64_t dsn) {
-        if (!DIRECT) lab[t] = stored_label<Cell>(ls);
-        cells[gi] = stored_label<Cell>(ls);
+    // the cell types of an attempt's two labels (their stored words at hand)
+    auto types = [&](Cell wt, int lt_, Cell ws, int ls_, int &tt_, int &ts_) {
+        tt_ = lt_ == 0 ? 0 : (SINGLE ? a.single_type : type_of_word(a, wt, lt_));
+        ts_ = ls_ == 0 ? 0 : (SINGLE ? a.single_type : type_of_word(a, ws, ls_));
+    };
+    // the target takes the source's stored word (its label, and its type in
+    // packed words)
+    auto commit = [&](int t, int gi, int lt, int ls, Cell ws, int ts, int64_t dso, int64_t dsn) {
+        if (!DIRECT) lab[t] = ws;
+        cells[gi] = ws;
         if (ACT) {
-            const int ts = ls == 0 ? 0 : (a.single_type >= 0 ? a.single_type : a.cell_type[ls]);
             const uint8_t na = (ls >= 1 && a.model->max_act[ts] > 0) ? (uint8_t)a.model->max_act[ts] : (uint8_t)0;
             if (!DIRECT) lact[t] = na;
             a.act[gi] = na;
@@ -358,12 +362,15 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
         const int prev_n = a.dcount[parity ^ 1][tile];
         const int4 prev_rec = tid < a.dlist_cap ? dl_prev[tid] : make_int4(0, 0, 0, 0);
         int ttx = 0, tty = 0, ttz = 0, ssx = 0, ssy = 0, ssz = 0, lt = 0, ls = 0;
+        Cell wt = 0, ws = 0;
         uint32_t u2 = 0, area_id = 0;
         const bool mine = tid < areas;
         if (mine) {
             draw(tid, 0, ttx, tty, ttz, ssx, ssy, ssz, u2, area_id);
-            lt = label_of(lab[map.at(ttx, tty, ttz)]);
-            ls = label_of(lab[map.at(ssx, ssy, ssz)]);
+            wt = lab[map.at(ttx, tty, ttz)];
+            ws = lab[map.at(ssx, ssy, ssz)];
+            lt = label_of(wt);
+            ls = label_of(ws);
         }
         __syncthreads();  // LDS counters and tables initialised
         if (tid < prev_n) add_deltas(wr, prev_rec);
@@ -377,12 +384,15 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
                 jr = JRows{J[tc * kMaxTypes + tc], J[tc * kMaxTypes], J[tc * kMaxTypes + to], J[tc], J[0], J[to]};
             }
             int64_t dso, dsn;
+            int tt, ts;
+            types(wt, lt, ws, ls, tt, ts);
             if (evaluate<Cell, D, ACT, SINGLE, LAYOUT, EXT>(a, tb, jr, sht, lab, lact, map, ttx, tty, ttz, ssx, ssy, ssz,
-                                                       map.at(ssx, ssy, ssz), lt, ls, seen_counters(rd, lt, nullptr, 0),
+                                                       map.at(ssx, ssy, ssz), lt, ls, tt, ts,
+                                                       seen_counters(rd, lt, nullptr, 0),
                                                        seen_counters(rd, ls, nullptr, 0), u2, dso, dsn)) {
                 accepted = 1;
                 const int gi = map.at(ttx, tty, ttz);
-                commit(gi, gi, lt, ls, dso, dsn);
+                commit(gi, gi, lt, ls, ws, ts, dso, dsn);
             }
         }
         if (nontrivial) atomicAdd(&n_nontrivial, 1u);
@@ -402,6 +412,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
     // memory then, measured slower on gfx950 (the wait for the labels also
     // waits for every staging load issued before them).
     int d_ttx = 0, d_tty = 0, d_ttz = 0, d_ssx = 0, d_ssy = 0, d_ssz = 0, d_lt = 0, d_ls = 0;
+    Cell d_wt = 0, d_ws = 0;
     uint32_t d_u2 = 0;
     bool d_nontrivial = false;
     int2 d_ct = make_int2(0, 0), d_cs = make_int2(0, 0);
@@ -409,8 +420,10 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
         if (!K1 || tid >= areas) return;
         uint32_t area_id;
         draw(tid, 0, d_ttx, d_tty, d_ttz, d_ssx, d_ssy, d_ssz, d_u2, area_id);
-        d_lt = label_of(lab[map.at(d_ttx, d_tty, d_ttz)]);
-        d_ls = label_of(lab[map.at(d_ssx, d_ssy, d_ssz)]);
+        d_wt = lab[map.at(d_ttx, d_tty, d_ttz)];
+        d_ws = lab[map.at(d_ssx, d_ssy, d_ssz)];
+        d_lt = label_of(d_wt);
+        d_ls = label_of(d_ws);
         d_nontrivial = d_lt != d_ls && d_lt >= 0 && d_ls >= 0;
         if (d_nontrivial) {
             d_ct = seen_counters(rd, d_lt, nullptr, 0);
@@ -536,11 +549,14 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
             } else {
                 // queue full: evaluate here (no other attempt reads this sub-area)
                 int64_t dso, dsn;
+                int tt, ts;
+                types(d_wt, d_lt, d_ws, d_ls, tt, ts);
                 if (evaluate<Cell, D, ACT, SINGLE, LAYOUT, EXT>(a, tb, jr, sht, lab, lact, map, d_ttx, d_tty, d_ttz, d_ssx,
                                                             d_ssy, d_ssz, EXT && a.chem ? global_index(d_ssx, d_ssy, d_ssz) : 0,
-                                                            d_lt, d_ls, d_ct, d_cs, d_u2, dso, dsn)) {
+                                                            d_lt, d_ls, tt, ts, d_ct, d_cs, d_u2, dso, dsn)) {
                     ++my_accepted;
-                    commit(map.at(d_ttx, d_tty, d_ttz), global_index(d_ttx, d_tty, d_ttz), d_lt, d_ls, dso, dsn);
+                    commit(map.at(d_ttx, d_tty, d_ttz), global_index(d_ttx, d_tty, d_ttz), d_lt, d_ls, d_ws, ts, dso,
+                           dsn);
                 }
             }
         }
@@ -553,14 +569,17 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
             const int ttx = e.x & 0xFFFF, tty = e.x >> 16, ttz = e.y & 0xFFFF;
             const int ssz = e.y >> 16, ssx = (int)(int16_t)(e.z & 0xFFFF), ssy = e.z >> 16;
             const int t = map.at(ttx, tty, ttz);
-            const int lt = label_of(lab[t]), ls = label_of(lab[map.at(ssx, ssy, ssz)]);
+            const Cell wt = lab[t], ws = lab[map.at(ssx, ssy, ssz)];
+            const int lt = label_of(wt), ls = label_of(ws);
             int64_t dso, dsn;
+            int tt, ts;
+            types(wt, lt, ws, ls, tt, ts);
             if (evaluate<Cell, D, ACT, SINGLE, LAYOUT, EXT>(a, tb, jr, sht, lab, lact, map, ttx, tty, ttz, ssx, ssy, ssz,
-                                                        EXT && a.chem ? global_index(ssx, ssy, ssz) : 0, lt, ls,
+                                                        EXT && a.chem ? global_index(ssx, ssy, ssz) : 0, lt, ls, tt, ts,
                                                         make_int2(c.x, c.y), make_int2(c.z, c.w), (uint32_t)e.w,
                                                         dso, dsn)) {
                 ++my_accepted;
-                commit(t, global_index(ttx, tty, ttz), lt, ls, dso, dsn);
+                commit(t, global_index(ttx, tty, ttz), lt, ls, ws, ts, dso, dsn);
             }
         }
         if (tid == 0) n_nontrivial = (uint32_t)qn;
@@ -573,17 +592,20 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
                 uint32_t u2, area_id;
                 draw(tid, j, ttx, tty, ttz, ssx, ssy, ssz, u2, area_id);
                 const int t = map.at(ttx, tty, ttz);
-                const int lt = label_of(lab[t]), ls = label_of(lab[map.at(ssx, ssy, ssz)]);
+                const Cell wt = lab[t], ws = lab[map.at(ssx, ssy, ssz)];
+                const int lt = label_of(wt), ls = label_of(ws);
                 int4 rec = make_int4(0, 0, 0, 0);
                 if (lt != ls && lt >= 0 && ls >= 0) {
                     ++my_nontrivial;
                     int64_t dso, dsn;
+                    int tt, ts;
+                    types(wt, lt, ws, ls, tt, ts);
                     if (evaluate<Cell, D, ACT, SINGLE, LAYOUT, EXT>(a, tb, jr, sht, lab, lact, map, ttx, tty, ttz, ssx, ssy,
                                                                 ssz, EXT && a.chem ? global_index(ssx, ssy, ssz) : 0, lt, ls,
-                                                                seen_counters(rd, lt, own, j),
+                                                                tt, ts, seen_counters(rd, lt, own, j),
                                                                 seen_counters(rd, ls, own, j), u2, dso, dsn)) {
                         ++my_accepted;
-                        rec = commit(t, global_index(ttx, tty, ttz), lt, ls, dso, dsn);
+                        rec = commit(t, global_index(ttx, tty, ttz), lt, ls, ws, ts, dso, dsn);
                     }
                 }
 #pragma unroll
@@ -662,6 +684,33 @@ hipError_t launch_c(const SweepArgs &a, int ndim, bool act, uint32_t mcs, uint32
                : launch_s<Cell, 3, false>(a, mcs, alpha, parity, lds, st);
 }
 
+// Packed words (multi-type models only): no single-type kernels needed.
+template <int D, bool ACT>
+hipError_t launch_packed_s(const SweepArgs &a, uint32_t mcs, uint32_t alpha, int parity, size_t lds, hipStream_t st)
+{
+    const bool k1 = a.k == 1;
+    const int layout = a.tg.layout;
+    return (a.pdir || a.chem) ? launch_k<uint32_t, D, ACT, false, true>(a, k1, layout, mcs, alpha, parity, lds, st)
+                              : launch_k<uint32_t, D, ACT, false, false>(a, k1, layout, mcs, alpha, parity, lds, st);
+}
+
+// The caller's int32 lattice rewritten in place as packed words and back.
+__global__ void pack_kernel(int32_t *lat, const int32_t *cell_type, int obstacle_type, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int v = lat[i];
+    const int t = v < 0 ? obstacle_type : cell_type[v];
+    lat[i] = (int32_t)packed_word(v, t);
+}
+
+__global__ void unpack_kernel(int32_t *lat, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    lat[i] = label_of((uint32_t)lat[i]);
+}
+
 __device__ __forceinline__ ushort4 encode4(int4 v)
 {
     ushort4 w;
@@ -728,12 +777,31 @@ size_t sweep_lds_bytes(int ndim, bool act, bool mirror, int box_sites)
     return (size_t)align16(box_sites * cell) + (act ? (size_t)align16(box_sites) : 0);
 }
 
-hipError_t launch_activation(const SweepArgs &a, int ndim, bool act, bool mirror, uint32_t mcs, uint32_t alpha,
+hipError_t launch_activation(const SweepArgs &a, int ndim, bool act, int words, uint32_t mcs, uint32_t alpha,
                              int parity, hipStream_t stream)
 {
     const size_t lds = (size_t)a.tg.lds_bytes;
-    return mirror ? launch_c<uint16_t>(a, ndim, act, mcs, alpha, parity, lds, stream)
-                  : launch_c<int32_t>(a, ndim, act, mcs, alpha, parity, lds, stream);
+    if (words == kWords16) return launch_c<uint16_t>(a, ndim, act, mcs, alpha, parity, lds, stream);
+    if (words == kWordsPacked) {
+        if (ndim == 2)
+            return act ? launch_packed_s<2, true>(a, mcs, alpha, parity, lds, stream)
+                       : launch_packed_s<2, false>(a, mcs, alpha, parity, lds, stream);
+        return act ? launch_packed_s<3, true>(a, mcs, alpha, parity, lds, stream)
+                   : launch_packed_s<3, false>(a, mcs, alpha, parity, lds, stream);
+    }
+    return launch_c<int32_t>(a, ndim, act, mcs, alpha, parity, lds, stream);
+}
+
+hipError_t launch_pack(int32_t *lat, const int32_t *cell_type, int obstacle_type, size_t n, hipStream_t stream)
+{
+    pack_kernel<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, stream>>>(lat, cell_type, obstacle_type, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack(int32_t *lat, size_t n, hipStream_t stream)
+{
+    unpack_kernel<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, stream>>>(lat, n);
+    return hipGetLastError();
 }
 
 namespace {

@@ -32,12 +32,12 @@ def oracle_model(w):
                         lambda_P=w.lambda_P, mu_P=w.mu_P, dt_P=w.dt_P, lambda_C=w.lambda_C, C_field=w.C_field)
 
 
-def run_both(torch, w, n_mcs, chunks=None):
+def run_both(torch, w, n_mcs, chunks=None, **over):
     _say(f"case {w.name}: dims={w.dims} s={w.s} k={w.k} cells={w.n_cells} mcs={n_mcs} "
-         f"act={w.lambda_act is not None}")
+         f"act={w.lambda_act is not None} over={over}")
     st = oracle.State(oracle_model(w), w.lattice, w.cell_type, w.act)
     st.sweep(n_mcs)
-    sim = cpm.Simulation(cpm.Params.from_workload(w), w.lattice, w.cell_type, w.act)
+    sim = cpm.Simulation(cpm.Params.from_workload(w, **over), w.lattice, w.cell_type, w.act)
     for c in (chunks or [n_mcs]):
         sim.sweep(c)
     torch.cuda.synchronize()
@@ -135,6 +135,22 @@ def test_wide_labels(torch_cuda, single, dims, n_cells, labels16):
     assert cpm.cpm_tile_shape(cpm.Params.from_workload(w), w.n_cells)["labels16"] == labels16
     st, sim = run_both(torch_cuda, w, 4)
     assert_same(st, sim, torch_cuda)
+
+
+@pytest.mark.parametrize("layout,k,act", [("in_place", 1, False), ("full_rows", 1, True), ("box", 1, True),
+                                          ("box", 4, False), ("auto", 1, True)])
+def test_packed_words(torch_cuda, layout, k, act):
+    # more than 65,534 cells of several types: the sweep rewrites the int32
+    # lattice in place as (label, type) words and restores it afterwards
+    dims = (48, 48, 48)
+    w = _multi(dims, 3, seed=33 + k, n_cells=70000, obstacles=0.02, act=act, s=2, k=k, T=15.0)
+    assert w.lattice.max() > 65534
+    st, sim = run_both(torch_cuda, w, 3, chunks=[1, 2], layout=layout)
+    assert_same(st, sim, torch_cuda)
+    v, s, c = sim.cell_stats()
+    torch_cuda.cuda.synchronize()
+    V, S, C = oracle.cell_stats(oracle_model(w), st.lattice, w.n_cells)
+    np.testing.assert_array_equal(c.cpu().numpy()[1:], C[1:])
 
 
 def test_edge_cases(torch_cuda):
