@@ -634,6 +634,26 @@ __global__ void __launch_bounds__(kBlock) tile_sweep_kernel(SweepArgs a, uint32_
     sweep_tile<Cell, D, ACT, SINGLE, K1, LAYOUT, EXT>(a, tile, mcs, alpha, parity);
 }
 
+// Packed words serve large multi-type lattices, whose sweeps wait on HBM:
+// more waves per SIMD hide more of that latency than the registers the
+// limit takes away cost.
+#ifndef CPM_PACKED_WAVES
+#define CPM_PACKED_WAVES 8
+#endif
+#if CPM_PACKED_WAVES > 0
+#define CPM_PACKED_ATTR __attribute__((amdgpu_waves_per_eu(CPM_PACKED_WAVES)))
+#else
+#define CPM_PACKED_ATTR
+#endif
+template <int D, bool ACT, bool SINGLE, bool K1, int LAYOUT, bool EXT>
+__global__ void __launch_bounds__(kBlock) CPM_PACKED_ATTR tile_sweep_kernel_packed(SweepArgs a, uint32_t mcs,
+                                                                                    uint32_t alpha, int parity)
+{
+    const int tile = (int)(blockIdx.x % kXcds) * a.tg.tiles_per_xcd + (int)(blockIdx.x / kXcds);
+    if (tile >= a.tg.n_tiles) return;  // uniform over the block
+    sweep_tile<uint32_t, D, ACT, SINGLE, K1, LAYOUT, EXT>(a, tile, mcs, alpha, parity);
+}
+
 // Many lattices advanced together: work[b] = (lattice, tile) of workgroup b;
 // all lattices share the MCS counter at *mcs.
 template <typename Cell, int D, bool ACT, bool SINGLE, bool K1, int LAYOUT, bool EXT>
@@ -685,13 +705,27 @@ hipError_t launch_c(const SweepArgs &a, int ndim, bool act, uint32_t mcs, uint32
 }
 
 // Packed words (multi-type models only): no single-type kernels needed.
-template <int D, bool ACT>
-hipError_t launch_packed_s(const SweepArgs &a, uint32_t mcs, uint32_t alpha, int parity, size_t lds, hipStream_t st)
+template <int D, bool ACT, bool EXT>
+hipError_t launch_packed_k(const SweepArgs &a, uint32_t mcs, uint32_t alpha, int parity, size_t lds, hipStream_t st)
 {
     const bool k1 = a.k == 1;
     const int layout = a.tg.layout;
-    return (a.pdir || a.chem) ? launch_k<uint32_t, D, ACT, false, true>(a, k1, layout, mcs, alpha, parity, lds, st)
-                              : launch_k<uint32_t, D, ACT, false, false>(a, k1, layout, mcs, alpha, parity, lds, st);
+    if (k1 && layout == kDirect)
+        tile_sweep_kernel_packed<D, ACT, false, true, kDirect, EXT><<<a.tg.grid, kBlock, lds, st>>>(a, mcs, alpha, parity);
+    else if (k1 && layout == kFullRow)
+        tile_sweep_kernel_packed<D, ACT, false, true, kFullRow, EXT><<<a.tg.grid, kBlock, lds, st>>>(a, mcs, alpha, parity);
+    else if (k1)
+        tile_sweep_kernel_packed<D, ACT, false, true, kBox, EXT><<<a.tg.grid, kBlock, lds, st>>>(a, mcs, alpha, parity);
+    else
+        tile_sweep_kernel_packed<D, ACT, false, false, kBox, EXT><<<a.tg.grid, kBlock, lds, st>>>(a, mcs, alpha, parity);
+    return hipGetLastError();
+}
+
+template <int D, bool ACT>
+hipError_t launch_packed_s(const SweepArgs &a, uint32_t mcs, uint32_t alpha, int parity, size_t lds, hipStream_t st)
+{
+    return (a.pdir || a.chem) ? launch_packed_k<D, ACT, true>(a, mcs, alpha, parity, lds, st)
+                              : launch_packed_k<D, ACT, false>(a, mcs, alpha, parity, lds, st);
 }
 
 // The caller's int32 lattice rewritten in place as packed words and back.
