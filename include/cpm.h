@@ -174,7 +174,11 @@ int cpm_init(const cpm_params *params, int32_t *d_lattice, const int32_t *d_cell
              void *stream, cpm_handle **out);
 
 /* Advances the lattice by n_mcs Monte Carlo steps (n_mcs >= 0) and the MCS
- * counter with it.  Asynchronous on `stream`. */
+ * counter with it.  Asynchronous on `stream`.  While the call's work runs,
+ * d_lattice may hold an internal encoding (lattices of more than 65,534
+ * cells of several types are rewritten in place as label-and-type words and
+ * restored at the end of the call's work); read or write it only on
+ * `stream` or after that work, as for any buffer the sweep updates. */
 int cpm_sweep(cpm_handle *h, int32_t n_mcs, void *stream);
 
 /*
