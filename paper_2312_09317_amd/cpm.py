@@ -195,14 +195,20 @@ class Params:
     def act_enabled(self) -> bool:
         return bool(self.c.act_enabled)
 
-    def on_device(self, device):
+    def on_device(self, device, cache=None):
         """These parameters with a host (numpy) chemotaxis field copied to
-        `device` (the copy is kept alive by the returned Params)."""
+        `device` (the copy is kept alive by the returned Params).  `cache`
+        (a dict) shares one device copy among parameters holding the same
+        host array."""
         f = self._field
         if f is None or hasattr(f, "data_ptr"):
             return self
         import torch
-        dev = torch.as_tensor(np.ascontiguousarray(f, dtype=np.int16).reshape(-1)).to(device)
+        dev = None if cache is None else cache.get(id(f))
+        if dev is None:
+            dev = torch.as_tensor(np.ascontiguousarray(f, dtype=np.int16).reshape(-1)).to(device)
+            if cache is not None:
+                cache[id(f)] = dev
         return self.replace(chemotaxis_field=dev)
 
     @classmethod
@@ -479,7 +485,8 @@ class Batch:
         import torch
         self.torch = torch
         self.device = torch.device(device)
-        self.params = [p.on_device(self.device) for p in params]
+        fields = {}  # one device copy per distinct host field (ensembles share one)
+        self.params = [p.on_device(self.device, fields) for p in params]
         self.n = len(self.params)
         self.sizes = [int(np.asarray(l).size) for l in lattices]
         self.n_cells = [int(len(t)) - 1 for t in cell_types]
