@@ -175,10 +175,12 @@ int cpm_init(const cpm_params *params, int32_t *d_lattice, const int32_t *d_cell
 
 /* Advances the lattice by n_mcs Monte Carlo steps (n_mcs >= 0) and the MCS
  * counter with it.  Asynchronous on `stream`.  While the call's work runs,
- * d_lattice may hold an internal encoding (lattices of more than 65,534
- * cells of several types are rewritten in place as label-and-type words and
- * restored at the end of the call's work); read or write it only on
- * `stream` or after that work, as for any buffer the sweep updates. */
+ * d_lattice and d_act may hold an internal encoding (lattices of more than
+ * 65,534 cells of several types are rewritten in place as label-and-type
+ * words, with the activity in the same word when the Act term is on and
+ * there are at most 2^20 - 2 cells, and restored at the end of the call's
+ * work); read or write them only on `stream` or after that work, as for
+ * any buffer the sweep updates. */
 int cpm_sweep(cpm_handle *h, int32_t n_mcs, void *stream);
 
 /*

@@ -116,6 +116,8 @@ struct Layout {
 bool use_mirror(int32_t n_cells) { return n_cells <= 65534; }
 // Packed words hold label + 1 in 24 bits.
 constexpr int32_t kMaxPackedCells = (1 << 24) - 2;
+// ... and in 20 bits when the activity shares the word.
+constexpr int32_t kMaxPackedActCells = (1 << 20) - 2;
 
 // Widest load (16, 8 or 4 bytes) that divides both a row and the base address.
 int32_t chunk_for(const void *base, size_t row_bytes)
@@ -630,8 +632,11 @@ int cpm_init(const cpm_params *params, int32_t *d_lattice, const int32_t *d_cell
         return device_fail(e, "persistence init");
     // multi-type lattices too large for the 16-bit copy sweep on packed
     // words (label and type in one word) written over the int32 lattice
+    // (with the Act term and up to 2^20 - 2 cells the word holds the activity too)
     h->words = h->mirror ? cpm::kWords16
-                         : (single < 0 && n_cells <= kMaxPackedCells ? cpm::kWordsPacked : cpm::kWords32);
+               : single >= 0 ? cpm::kWords32
+               : h->act && n_cells <= kMaxPackedActCells ? cpm::kWordsPackedAct
+               : n_cells <= kMaxPackedCells ? cpm::kWordsPacked : cpm::kWords32;
     *out = h.release();
     return CPM_OK;
 }
@@ -651,6 +656,10 @@ int sweep_impl(cpm_handle *h, int32_t n_mcs, hipStream_t st)
     if (h->words == cpm::kWordsPacked &&
         (e = cpm::launch_pack(h->args.lat, h->args.cell_type, h->args.obstacle_type, n_sites, st)) != hipSuccess)
         return device_fail(e, "pack label and type words");
+    if (h->words == cpm::kWordsPackedAct &&
+        (e = cpm::launch_pack_act(h->args.lat, h->args.act, h->args.cell_type, h->args.obstacle_type, n_sites, st)) !=
+            hipSuccess)
+        return device_fail(e, "pack label, type and activity words");
     if (h->mirror && (e = cpm::launch_to_mirror(h->args.lat, h->mirror_cells, n_sites, st)) != hipSuccess)
         return device_fail(e, "to 16-bit working copy");
     for (int32_t i = 0; i < n_mcs; ++i) {
@@ -660,8 +669,10 @@ int sweep_impl(cpm_handle *h, int32_t n_mcs, hipStream_t st)
             if (e != hipSuccess) return device_fail(e, "activation");
             ++h->activation;
         }
-        if (h->act && (e = cpm::launch_act_decay(h->args.act, n_sites, st)) != hipSuccess)
-            return device_fail(e, "act decay");
+        if (h->act)
+            e = h->words == cpm::kWordsPackedAct ? cpm::launch_act_decay_words(h->args.lat, n_sites, st)
+                                                 : cpm::launch_act_decay(h->args.act, n_sites, st);
+        if (h->act && e != hipSuccess) return device_fail(e, "act decay");
         if (h->pdir && (e = persist_step(h, ++h->persist_t, h->words, st)) != hipSuccess)
             return device_fail(e, "persistence update");
         ++h->mcs;
@@ -671,6 +682,9 @@ int sweep_impl(cpm_handle *h, int32_t n_mcs, hipStream_t st)
         return device_fail(e, "from 16-bit working copy");
     if (h->words == cpm::kWordsPacked && (e = cpm::launch_unpack(h->args.lat, n_sites, st)) != hipSuccess)
         return device_fail(e, "unpack labels");
+    if (h->words == cpm::kWordsPackedAct &&
+        (e = cpm::launch_unpack_act(h->args.lat, h->args.act, n_sites, st)) != hipSuccess)
+        return device_fail(e, "unpack labels and activity");
     return CPM_OK;
 }
 

@@ -43,8 +43,31 @@ __device__ __forceinline__ uint32_t packed_word(int label, int type)
     return (uint32_t)(label + 1) | ((uint32_t)type << 24);
 }
 
+// Packed words with activity (char32_t; Act models of up to 2^20 - 2
+// cells): label + 1 in bits 0..19, the cell type in bits 20..23, the site's
+// activity in bits 24..31, so the Act term reads a neighbourhood's activity
+// with its labels.
+__device__ __forceinline__ int label_of(char32_t v) { return (int)((uint32_t)v & 0xFFFFFu) - 1; }
+__device__ __forceinline__ char32_t act_word(int label, int type, uint32_t act)
+{
+    return (char32_t)((uint32_t)(label + 1) | ((uint32_t)type << 20) | (act << 24));
+}
+
+// Activity of LDS / lattice index i: from the word, or from the activity array.
+template <typename Cell>
+__device__ __forceinline__ uint32_t act_at(const Cell *lab, const uint8_t *lact, int i) { return lact[i]; }
+template <>
+__device__ __forceinline__ uint32_t act_at<char32_t>(const char32_t *lab, const uint8_t *, int i)
+{
+    return (uint32_t)lab[i] >> 24;
+}
+
 // Cell type of a site from its stored word (`label` = label_of(word)).
 __device__ __forceinline__ int type_of_word(const SweepArgs &a, uint32_t word, int) { return (int)(word >> 24); }
+__device__ __forceinline__ int type_of_word(const SweepArgs &a, char32_t word, int)
+{
+    return (int)(((uint32_t)word >> 20) & 15u);
+}
 __device__ __forceinline__ int type_of_word(const SweepArgs &a, int32_t, int label)
 {
     return label < 0 ? a.obstacle_type : a.cell_type[label];

@@ -155,11 +155,16 @@ hipError_t launch_count(const SweepArgs &a, int ndim, int32_t *v_out, int32_t *s
                         hipStream_t stream);
 // Stored words the sweep works on: the caller's int32 labels, the 16-bit
 // working copy, or the int32 lattice rewritten in place as packed words.
-enum Words { kWords32 = 0, kWords16 = 1, kWordsPacked = 2 };
+enum Words { kWords32 = 0, kWords16 = 1, kWordsPacked = 2, kWordsPackedAct = 3 };
 hipError_t launch_activation(const SweepArgs &a, int ndim, bool act, int words, uint32_t mcs, uint32_t alpha,
                              int parity, hipStream_t stream);
 hipError_t launch_pack(int32_t *lat, const int32_t *cell_type, int obstacle_type, size_t n, hipStream_t stream);
 hipError_t launch_unpack(int32_t *lat, size_t n, hipStream_t stream);
+// The same with the activity in bits 24..31 (label + 1 in 0..19, type in 20..23).
+hipError_t launch_pack_act(int32_t *lat, const uint8_t *act, const int32_t *cell_type, int obstacle_type, size_t n,
+                           hipStream_t stream);
+hipError_t launch_unpack_act(int32_t *lat, uint8_t *act, size_t n, hipStream_t stream);
+hipError_t launch_act_decay_words(int32_t *lat, size_t n, hipStream_t stream);
 hipError_t launch_to_mirror(const int32_t *lat, uint16_t *mirror, size_t n, hipStream_t stream);
 hipError_t launch_from_mirror(const uint16_t *mirror, int32_t *lat, size_t n, hipStream_t stream);
 // Every lattice of a batch (args[i].lat <-> args[i].cells) in one launch.

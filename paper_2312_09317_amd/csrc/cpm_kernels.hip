@@ -59,7 +59,9 @@ __device__ __forceinline__ int map_slot(LabelMap &m, int label)
 template <int WORDS>
 __device__ __forceinline__ int word_label(int32_t v)
 {
-    return WORDS == kWordsPacked ? label_of((uint32_t)v) : v;
+    if (WORDS == kWordsPacked) return label_of((uint32_t)v);
+    if (WORDS == kWordsPackedAct) return label_of((char32_t)(uint32_t)v);
+    return v;
 }
 
 template <int WORDS>
@@ -458,13 +460,16 @@ hipError_t launch_centroids(const SweepArgs &a, int ndim, int32_t n_cells, int32
     using W32 = std::integral_constant<int, kWords32>;
     using W16 = std::integral_constant<int, kWords16>;
     using WP = std::integral_constant<int, kWordsPacked>;
+    using WPA = std::integral_constant<int, kWordsPackedAct>;
     if (ndim == 2) {
         if (words == kWords16) run(D2{}, W16{});
         else if (words == kWordsPacked) run(D2{}, WP{});
+        else if (words == kWordsPackedAct) run(D2{}, WPA{});
         else run(D2{}, W32{});
     } else {
         if (words == kWords16) run(D3{}, W16{});
         else if (words == kWordsPacked) run(D3{}, WP{});
+        else if (words == kWordsPackedAct) run(D3{}, WPA{});
         else run(D3{}, W32{});
     }
     return hipGetLastError();

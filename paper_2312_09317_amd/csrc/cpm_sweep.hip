@@ -29,6 +29,7 @@
 // g-1 (kept per tile in `dlist`) into buffer (g+1)&1, which so becomes the
 // exact state at the start of g+1.
 #include <algorithm>
+#include <type_traits>
 
 #include "cpm_device.hpp"
 
@@ -79,7 +80,7 @@ __device__ __forceinline__ int64_t gm_lds(const DeviceModel *m, const int64_t *l
 {
     if (cell <= 0 || !motile) return 0;
     const int c = map.at(x, y, z);
-    const uint32_t a0 = lact[c];
+    const uint32_t a0 = act_at(lab, lact, c);
     uint64_t sum = (uint64_t)lg[a0];
     uint32_t cnt = 1;
     bool zero = a0 == 0;
@@ -90,7 +91,7 @@ __device__ __forceinline__ int64_t gm_lds(const DeviceModel *m, const int64_t *l
     for (int n = 0; n < NNB; ++n) {
         const int u = map.at(x + nb_dx<D>(n), y + nb_dy<D>(n), z + nb_dz<D>(n));
         const int lu = label_of(lab[u]);
-        const uint32_t au = lact[u];
+        const uint32_t au = act_at(lab, lact, u);
         if (lu == cell) {
             zero |= au == 0;
             sum += (uint64_t)lg[au];
@@ -339,12 +340,15 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
         ts_ = ls_ == 0 ? 0 : (SINGLE ? a.single_type : type_of_word(a, ws, ls_));
     };
     // the target takes the source's stored word (its label, and its type in
-    // packed words)
+    // packed words); words with activity carry the target's new activity
+    constexpr bool kActWord = std::is_same<Cell, char32_t>::value;
     auto commit = [&](int t, int gi, int lt, int ls, Cell ws, int ts, int64_t dso, int64_t dsn) {
-        if (!DIRECT) lab[t] = ws;
-        cells[gi] = ws;
-        if (ACT) {
-            const uint8_t na = (ls >= 1 && a.model->max_act[ts] > 0) ? (uint8_t)a.model->max_act[ts] : (uint8_t)0;
+        uint8_t na = 0;
+        if (ACT) na = (ls >= 1 && a.model->max_act[ts] > 0) ? (uint8_t)a.model->max_act[ts] : (uint8_t)0;
+        const Cell nw = kActWord ? (Cell)(((uint32_t)ws & 0xFFFFFFu) | ((uint32_t)na << 24)) : ws;
+        if (!DIRECT) lab[t] = nw;
+        cells[gi] = nw;
+        if (ACT && !kActWord) {
             if (!DIRECT) lact[t] = na;
             a.act[gi] = na;
         }
@@ -645,13 +649,13 @@ __global__ void __launch_bounds__(kBlock) tile_sweep_kernel(SweepArgs a, uint32_
 #else
 #define CPM_PACKED_ATTR
 #endif
-template <int D, bool ACT, bool SINGLE, bool K1, int LAYOUT, bool EXT>
+template <typename Word, int D, bool ACT, bool SINGLE, bool K1, int LAYOUT, bool EXT>
 __global__ void __launch_bounds__(kBlock) CPM_PACKED_ATTR tile_sweep_kernel_packed(SweepArgs a, uint32_t mcs,
                                                                                     uint32_t alpha, int parity)
 {
     const int tile = (int)(blockIdx.x % kXcds) * a.tg.tiles_per_xcd + (int)(blockIdx.x / kXcds);
     if (tile >= a.tg.n_tiles) return;  // uniform over the block
-    sweep_tile<uint32_t, D, ACT, SINGLE, K1, LAYOUT, EXT>(a, tile, mcs, alpha, parity);
+    sweep_tile<Word, D, ACT, SINGLE, K1, LAYOUT, EXT>(a, tile, mcs, alpha, parity);
 }
 
 // Many lattices advanced together: work[b] = (lattice, tile) of workgroup b;
@@ -705,27 +709,27 @@ hipError_t launch_c(const SweepArgs &a, int ndim, bool act, uint32_t mcs, uint32
 }
 
 // Packed words (multi-type models only): no single-type kernels needed.
-template <int D, bool ACT, bool EXT>
+template <typename Word, int D, bool ACT, bool EXT>
 hipError_t launch_packed_k(const SweepArgs &a, uint32_t mcs, uint32_t alpha, int parity, size_t lds, hipStream_t st)
 {
     const bool k1 = a.k == 1;
     const int layout = a.tg.layout;
     if (k1 && layout == kDirect)
-        tile_sweep_kernel_packed<D, ACT, false, true, kDirect, EXT><<<a.tg.grid, kBlock, lds, st>>>(a, mcs, alpha, parity);
+        tile_sweep_kernel_packed<Word, D, ACT, false, true, kDirect, EXT><<<a.tg.grid, kBlock, lds, st>>>(a, mcs, alpha, parity);
     else if (k1 && layout == kFullRow)
-        tile_sweep_kernel_packed<D, ACT, false, true, kFullRow, EXT><<<a.tg.grid, kBlock, lds, st>>>(a, mcs, alpha, parity);
+        tile_sweep_kernel_packed<Word, D, ACT, false, true, kFullRow, EXT><<<a.tg.grid, kBlock, lds, st>>>(a, mcs, alpha, parity);
     else if (k1)
-        tile_sweep_kernel_packed<D, ACT, false, true, kBox, EXT><<<a.tg.grid, kBlock, lds, st>>>(a, mcs, alpha, parity);
+        tile_sweep_kernel_packed<Word, D, ACT, false, true, kBox, EXT><<<a.tg.grid, kBlock, lds, st>>>(a, mcs, alpha, parity);
     else
-        tile_sweep_kernel_packed<D, ACT, false, false, kBox, EXT><<<a.tg.grid, kBlock, lds, st>>>(a, mcs, alpha, parity);
+        tile_sweep_kernel_packed<Word, D, ACT, false, false, kBox, EXT><<<a.tg.grid, kBlock, lds, st>>>(a, mcs, alpha, parity);
     return hipGetLastError();
 }
 
-template <int D, bool ACT>
+template <typename Word, int D, bool ACT>
 hipError_t launch_packed_s(const SweepArgs &a, uint32_t mcs, uint32_t alpha, int parity, size_t lds, hipStream_t st)
 {
-    return (a.pdir || a.chem) ? launch_packed_k<D, ACT, true>(a, mcs, alpha, parity, lds, st)
-                              : launch_packed_k<D, ACT, false>(a, mcs, alpha, parity, lds, st);
+    return (a.pdir || a.chem) ? launch_packed_k<Word, D, ACT, true>(a, mcs, alpha, parity, lds, st)
+                              : launch_packed_k<Word, D, ACT, false>(a, mcs, alpha, parity, lds, st);
 }
 
 // The caller's int32 lattice rewritten in place as packed words and back.
@@ -743,6 +747,34 @@ __global__ void unpack_kernel(int32_t *lat, size_t n)
     const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= n) return;
     lat[i] = label_of((uint32_t)lat[i]);
+}
+
+__global__ void pack_act_kernel(int32_t *lat, const uint8_t *act, const int32_t *cell_type, int obstacle_type,
+                                size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int v = lat[i];
+    const int t = v < 0 ? obstacle_type : cell_type[v];
+    lat[i] = (int32_t)(uint32_t)act_word(v, t, act[i]);
+}
+
+__global__ void unpack_act_kernel(int32_t *lat, uint8_t *act, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const char32_t w = (char32_t)(uint32_t)lat[i];
+    lat[i] = label_of(w);
+    act[i] = (uint8_t)((uint32_t)w >> 24);
+}
+
+// Act decay (one per MCS, to 0) in the activity bits of the words.
+__global__ void act_decay_words_kernel(int32_t *lat, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t w = (uint32_t)lat[i];
+    if (w >> 24) lat[i] = (int32_t)(w - (1u << 24));
 }
 
 __device__ __forceinline__ ushort4 encode4(int4 v)
@@ -818,17 +850,39 @@ hipError_t launch_activation(const SweepArgs &a, int ndim, bool act, int words, 
     if (words == kWords16) return launch_c<uint16_t>(a, ndim, act, mcs, alpha, parity, lds, stream);
     if (words == kWordsPacked) {
         if (ndim == 2)
-            return act ? launch_packed_s<2, true>(a, mcs, alpha, parity, lds, stream)
-                       : launch_packed_s<2, false>(a, mcs, alpha, parity, lds, stream);
-        return act ? launch_packed_s<3, true>(a, mcs, alpha, parity, lds, stream)
-                   : launch_packed_s<3, false>(a, mcs, alpha, parity, lds, stream);
+            return act ? launch_packed_s<uint32_t, 2, true>(a, mcs, alpha, parity, lds, stream)
+                       : launch_packed_s<uint32_t, 2, false>(a, mcs, alpha, parity, lds, stream);
+        return act ? launch_packed_s<uint32_t, 3, true>(a, mcs, alpha, parity, lds, stream)
+                   : launch_packed_s<uint32_t, 3, false>(a, mcs, alpha, parity, lds, stream);
     }
+    if (words == kWordsPackedAct)  // Act models only
+        return ndim == 2 ? launch_packed_s<char32_t, 2, true>(a, mcs, alpha, parity, lds, stream)
+                         : launch_packed_s<char32_t, 3, true>(a, mcs, alpha, parity, lds, stream);
     return launch_c<int32_t>(a, ndim, act, mcs, alpha, parity, lds, stream);
 }
 
 hipError_t launch_pack(int32_t *lat, const int32_t *cell_type, int obstacle_type, size_t n, hipStream_t stream)
 {
     pack_kernel<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, stream>>>(lat, cell_type, obstacle_type, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_act(int32_t *lat, const uint8_t *act, const int32_t *cell_type, int obstacle_type, size_t n,
+                           hipStream_t stream)
+{
+    pack_act_kernel<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, stream>>>(lat, act, cell_type, obstacle_type, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack_act(int32_t *lat, uint8_t *act, size_t n, hipStream_t stream)
+{
+    unpack_act_kernel<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, stream>>>(lat, act, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_act_decay_words(int32_t *lat, size_t n, hipStream_t stream)
+{
+    act_decay_words_kernel<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, stream>>>(lat, n);
     return hipGetLastError();
 }
 
