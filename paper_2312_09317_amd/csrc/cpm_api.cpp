@@ -44,6 +44,7 @@ struct cpm_batch {
     int32_t n = 0;
     int32_t ndim = 0, s = 0, k = 0;
     bool act = false, mirror = false, single = false;
+    bool act_words = false;          // Act batches sweep on label-type-activity words
     int layout = 0;
     std::vector<SweepArgs> args;                     // host copies, one per lattice
     std::vector<int32_t> n_cells;
@@ -808,8 +809,10 @@ struct BatchLayout {
     size_t total_labels;
     int grid;
     bool mirror, feasible;
+    bool act_words;
     int layout;
 };
+
 
 int validate_batch(const cpm_params *p, int32_t n, const int32_t *n_cells)
 {
@@ -828,7 +831,12 @@ int validate_batch(const cpm_params *p, int32_t n, const int32_t *n_cells)
 BatchLayout batch_layout_of(const cpm_params *p, int32_t n, const int32_t *n_cells)
 {
     BatchLayout b{};
-    b.mirror = true;
+    // Act batches of up to 2^20 - 2 cells per lattice sweep on label, type
+    // and activity words written over their int32 lattices; others on the
+    // 16-bit copy when every lattice fits it
+    b.act_words = p[0].act_enabled != 0;
+    for (int32_t i = 0; i < n; ++i) b.act_words = b.act_words && n_cells[i] <= kMaxPackedActCells;
+    b.mirror = !b.act_words;
     for (int32_t i = 0; i < n; ++i) b.mirror = b.mirror && use_mirror(n_cells[i]);
     // one kernel variant for the whole batch: the layout every lattice
     // chooses, else halo boxes (valid for all)
@@ -912,6 +920,7 @@ int cpm_batch_init(const cpm_params *params, int32_t n, const int32_t *n_cells, 
     b->k = params[0].attempts;
     b->act = params[0].act_enabled != 0;
     b->mirror = bl.mirror;
+    b->act_words = bl.act_words;
     b->layout = bl.layout;
     b->lattices = d_lattices;
     b->act_field = d_act;
@@ -991,6 +1000,7 @@ int cpm_batch_init(const cpm_params *params, int32_t n, const int32_t *n_cells, 
     L.mirror = b->mirror;
     L.single = b->single;
     L.k1 = b->k == 1;
+    L.act_words = b->act_words;
     L.ext = false;
     for (const SweepArgs &a : b->args) L.ext = L.ext || a.chem != nullptr;
     L.layout = b->layout;
@@ -1009,7 +1019,11 @@ hipError_t enqueue_mcs(const cpm_batch *b, uint32_t n_act, hipStream_t st)
     hipError_t e;
     for (uint32_t alpha = 0; alpha < n_act; ++alpha)
         if ((e = cpm::launch_batch_activation(b->launch, alpha, (int)(alpha & 1), st)) != hipSuccess) return e;
-    if (b->act && (e = cpm::launch_act_decay(b->act_field, b->total_sites, st)) != hipSuccess) return e;
+    if (b->act) {
+        e = b->act_words ? cpm::launch_act_decay_words(b->lattices, b->total_sites, st)
+                         : cpm::launch_act_decay(b->act_field, b->total_sites, st);
+        if (e != hipSuccess) return e;
+    }
     return cpm::launch_add_u32(b->d_mcs, 1u, st);
 }
 
@@ -1051,6 +1065,8 @@ int cpm_batch_sweep(cpm_batch *b, int32_t n_mcs, void *stream)
         return device_fail(e, "capture MCS graph");
     if (b->mirror && (e = cpm::launch_batch_mirror(b->d_args, b->n, b->max_sites, true, st)) != hipSuccess)
         return device_fail(e, "to 16-bit working copy");
+    if (b->act_words && (e = cpm::launch_batch_act_words(b->d_args, b->n, b->max_sites, true, st)) != hipSuccess)
+        return device_fail(e, "to label-type-activity words");
     if ((e = cpm::launch_set_u32(b->d_mcs, (uint32_t)b->mcs, st)) != hipSuccess) return device_fail(e, "set mcs");
     for (int32_t m = 0; m < n_mcs; ++m) {
         e = b->use_graph ? hipGraphLaunch(b->mcs_graph, st) : enqueue_mcs(b, n_act, st);
@@ -1061,6 +1077,8 @@ int cpm_batch_sweep(cpm_batch *b, int32_t n_mcs, void *stream)
     }
     if (b->mirror && (e = cpm::launch_batch_mirror(b->d_args, b->n, b->max_sites, false, st)) != hipSuccess)
         return device_fail(e, "from 16-bit working copy");
+    if (b->act_words && (e = cpm::launch_batch_act_words(b->d_args, b->n, b->max_sites, false, st)) != hipSuccess)
+        return device_fail(e, "from label-type-activity words");
     return CPM_OK;
 }
 

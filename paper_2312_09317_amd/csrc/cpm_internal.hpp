@@ -105,6 +105,7 @@ struct BatchLaunch {
     int ndim;
     bool act, mirror, single, k1;
     bool ext;               // some lattice uses the chemotaxis term
+    bool act_words;         // lattices hold label-type-activity words during the sweep
     int layout;
 };
 
@@ -165,6 +166,9 @@ hipError_t launch_pack_act(int32_t *lat, const uint8_t *act, const int32_t *cell
                            hipStream_t stream);
 hipError_t launch_unpack_act(int32_t *lat, uint8_t *act, size_t n, hipStream_t stream);
 hipError_t launch_act_decay_words(int32_t *lat, size_t n, hipStream_t stream);
+// Every lattice of a batch to (to_words) or from label-type-activity words.
+hipError_t launch_batch_act_words(const SweepArgs *d_args, int n_lattices, size_t max_sites, bool to_words,
+                                  hipStream_t stream);
 hipError_t launch_to_mirror(const int32_t *lat, uint16_t *mirror, size_t n, hipStream_t stream);
 hipError_t launch_from_mirror(const uint16_t *mirror, int32_t *lat, size_t n, hipStream_t stream);
 // Every lattice of a batch (args[i].lat <-> args[i].cells) in one launch.

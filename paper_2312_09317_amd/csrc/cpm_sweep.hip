@@ -834,6 +834,25 @@ __global__ void batch_mirror_kernel(const SweepArgs *__restrict__ args)
     }
 }
 
+// All lattices of a batch to / from label-type-activity words in place
+// (blockIdx.y is the lattice).
+template <bool TO>
+__global__ void batch_act_words_kernel(const SweepArgs *__restrict__ args)
+{
+    const SweepArgs &a = args[blockIdx.y];
+    const size_t n = (size_t)a.L[0] * a.L[1] * a.L[2];
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
+        if (TO) {
+            const int v = a.lat[i];
+            a.lat[i] = (int32_t)(uint32_t)act_word(v, v < 0 ? a.obstacle_type : a.cell_type[v], a.act[i]);
+        } else {
+            const char32_t w = (char32_t)(uint32_t)a.lat[i];
+            a.lat[i] = label_of(w);
+            a.act[i] = (uint8_t)((uint32_t)w >> 24);
+        }
+    }
+}
+
 }  // namespace
 
 size_t sweep_lds_bytes(int ndim, bool act, bool mirror, int box_sites)
@@ -930,7 +949,20 @@ hipError_t launch_batch_c(const BatchLaunch &b, uint32_t alpha, int parity, hipS
 
 hipError_t launch_batch_activation(const BatchLaunch &b, uint32_t alpha, int parity, hipStream_t stream)
 {
+    if (b.act_words)
+        return b.ndim == 2 ? launch_batch_s<char32_t, 2, true>(b, alpha, parity, stream)
+                           : launch_batch_s<char32_t, 3, true>(b, alpha, parity, stream);
     return b.mirror ? launch_batch_c<uint16_t>(b, alpha, parity, stream) : launch_batch_c<int32_t>(b, alpha, parity, stream);
+}
+
+hipError_t launch_batch_act_words(const SweepArgs *d_args, int n_lattices, size_t max_sites, bool to_words,
+                                  hipStream_t stream)
+{
+    const size_t groups = (max_sites + kBlock - 1) / kBlock;
+    const dim3 grid((unsigned)std::min<size_t>(groups, 256), (unsigned)n_lattices);
+    if (to_words) batch_act_words_kernel<true><<<grid, kBlock, 0, stream>>>(d_args);
+    else batch_act_words_kernel<false><<<grid, kBlock, 0, stream>>>(d_args);
+    return hipGetLastError();
 }
 
 hipError_t launch_to_mirror(const int32_t *lat, uint16_t *mirror, size_t n, hipStream_t stream)
