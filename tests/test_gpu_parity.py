@@ -153,6 +153,16 @@ def test_packed_words(torch_cuda, layout, k, act):
     np.testing.assert_array_equal(c.cpu().numpy()[1:], C[1:])
 
 
+def test_act_beyond_activity_words(torch_cuda):
+    # an Act model with more than 2^20 - 2 cells: label-type words and the
+    # separate activity array (fewer cells put the activity in the word)
+    dims = (128, 128, 128)
+    w = _multi(dims, 3, seed=41, n_cells=1_100_000, obstacles=0.02, act=True, T=15.0)
+    assert w.lattice.max() > (1 << 20) - 2
+    st, sim = run_both(torch_cuda, w, 2)
+    assert_same(st, sim, torch_cuda)
+
+
 def test_edge_cases(torch_cuda):
     # all medium: nothing can change
     w = _multi((16, 16, 1), 2, seed=2)
