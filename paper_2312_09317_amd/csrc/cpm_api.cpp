@@ -115,10 +115,17 @@ struct Layout {
 // Labels fit the 16-bit working copy (label + 1): cells 1..65534, medium 0,
 // obstacle -1.
 bool use_mirror(int32_t n_cells) { return n_cells <= 65534; }
+// Act models of up to 2^20 - 2 cells sweep on label-type-activity words
+// instead (one load per neighbour for label and activity).
+bool use_act_words(const cpm_params *p, int32_t n_cells);
+// The 16-bit copy for a single lattice of this model.
+bool use_mirror(const cpm_params *p, int32_t n_cells) { return use_mirror(n_cells) && !use_act_words(p, n_cells); }
 // Packed words hold label + 1 in 24 bits.
 constexpr int32_t kMaxPackedCells = (1 << 24) - 2;
 // ... and in 20 bits when the activity shares the word.
 constexpr int32_t kMaxPackedActCells = (1 << 20) - 2;
+
+bool use_act_words(const cpm_params *p, int32_t n_cells) { return p->act_enabled && n_cells <= kMaxPackedActCells; }
 
 // Widest load (16, 8 or 4 bytes) that divides both a row and the base address.
 int32_t chunk_for(const void *base, size_t row_bytes)
@@ -260,7 +267,7 @@ int requested_layout(const cpm_params *p) { return p->layout >= 1 && p->layout <
 Layout layout_of(const cpm_params *p, int32_t n_cells, int mirror = -1, int force_layout = -1)
 {
     Layout l{};
-    l.mirror_on = mirror < 0 ? use_mirror(n_cells) : mirror != 0;
+    l.mirror_on = mirror < 0 ? use_mirror(p, n_cells) : mirror != 0;
     tile_geometry(p, l.mirror_on, force_layout >= 0 ? force_layout : requested_layout(p), l.tg);
     l.dlist_cap = l.tg.T[0] * l.tg.T[1] * l.tg.T[2] * p->attempts;
     int64_t n_sites = (int64_t)p->dims[0] * p->dims[1] * p->dims[2];
@@ -341,7 +348,7 @@ int validate(const cpm_params *p, int32_t n_cells)
         if (p->ndim == 2 && p->tile[2] > 1) return fail(CPM_EINVAL, "tile[2] must be 0 or 1 in 2D");
         if (p->layout >= 2 && p->attempts != 1) return fail(CPM_ENOTSUP, "layouts 2 and 3 need attempts == 1");
         cpm::TileGeometry g;
-        if (!tile_geometry(p, use_mirror(n_cells), requested_layout(p), g))
+        if (!tile_geometry(p, use_mirror(p, n_cells), requested_layout(p), g))
             return fail(CPM_ENOTSUP, "the requested layout / tile does not fit this model");
     }
     const int n = p->n_types;
@@ -635,8 +642,8 @@ int cpm_init(const cpm_params *params, int32_t *d_lattice, const int32_t *d_cell
     // words (label and type in one word) written over the int32 lattice
     // (with the Act term and up to 2^20 - 2 cells the word holds the activity too)
     h->words = h->mirror ? cpm::kWords16
+               : use_act_words(params, n_cells) ? cpm::kWordsPackedAct
                : single >= 0 ? cpm::kWords32
-               : h->act && n_cells <= kMaxPackedActCells ? cpm::kWordsPackedAct
                : n_cells <= kMaxPackedCells ? cpm::kWordsPacked : cpm::kWords32;
     *out = h.release();
     return CPM_OK;
@@ -834,8 +841,8 @@ BatchLayout batch_layout_of(const cpm_params *p, int32_t n, const int32_t *n_cel
     // Act batches of up to 2^20 - 2 cells per lattice sweep on label, type
     // and activity words written over their int32 lattices; others on the
     // 16-bit copy when every lattice fits it
-    b.act_words = p[0].act_enabled != 0;
-    for (int32_t i = 0; i < n; ++i) b.act_words = b.act_words && n_cells[i] <= kMaxPackedActCells;
+    b.act_words = true;
+    for (int32_t i = 0; i < n; ++i) b.act_words = b.act_words && use_act_words(&p[i], n_cells[i]);
     b.mirror = !b.act_words;
     for (int32_t i = 0; i < n; ++i) b.mirror = b.mirror && use_mirror(n_cells[i]);
     // one kernel variant for the whole batch: the layout every lattice

@@ -709,27 +709,35 @@ hipError_t launch_c(const SweepArgs &a, int ndim, bool act, uint32_t mcs, uint32
 }
 
 // Packed words (multi-type models only): no single-type kernels needed.
-template <typename Word, int D, bool ACT, bool EXT>
+template <typename Word, int D, bool ACT, bool SINGLE, bool EXT>
 hipError_t launch_packed_k(const SweepArgs &a, uint32_t mcs, uint32_t alpha, int parity, size_t lds, hipStream_t st)
 {
     const bool k1 = a.k == 1;
     const int layout = a.tg.layout;
     if (k1 && layout == kDirect)
-        tile_sweep_kernel_packed<Word, D, ACT, false, true, kDirect, EXT><<<a.tg.grid, kBlock, lds, st>>>(a, mcs, alpha, parity);
+        tile_sweep_kernel_packed<Word, D, ACT, SINGLE, true, kDirect, EXT><<<a.tg.grid, kBlock, lds, st>>>(a, mcs, alpha, parity);
     else if (k1 && layout == kFullRow)
-        tile_sweep_kernel_packed<Word, D, ACT, false, true, kFullRow, EXT><<<a.tg.grid, kBlock, lds, st>>>(a, mcs, alpha, parity);
+        tile_sweep_kernel_packed<Word, D, ACT, SINGLE, true, kFullRow, EXT><<<a.tg.grid, kBlock, lds, st>>>(a, mcs, alpha, parity);
     else if (k1)
-        tile_sweep_kernel_packed<Word, D, ACT, false, true, kBox, EXT><<<a.tg.grid, kBlock, lds, st>>>(a, mcs, alpha, parity);
+        tile_sweep_kernel_packed<Word, D, ACT, SINGLE, true, kBox, EXT><<<a.tg.grid, kBlock, lds, st>>>(a, mcs, alpha, parity);
     else
-        tile_sweep_kernel_packed<Word, D, ACT, false, false, kBox, EXT><<<a.tg.grid, kBlock, lds, st>>>(a, mcs, alpha, parity);
+        tile_sweep_kernel_packed<Word, D, ACT, SINGLE, false, kBox, EXT><<<a.tg.grid, kBlock, lds, st>>>(a, mcs, alpha, parity);
     return hipGetLastError();
 }
 
+// Label-type words serve multi-type models only; label-type-activity words
+// serve every Act model that fits them.
 template <typename Word, int D, bool ACT>
 hipError_t launch_packed_s(const SweepArgs &a, uint32_t mcs, uint32_t alpha, int parity, size_t lds, hipStream_t st)
 {
-    return (a.pdir || a.chem) ? launch_packed_k<Word, D, ACT, true>(a, mcs, alpha, parity, lds, st)
-                              : launch_packed_k<Word, D, ACT, false>(a, mcs, alpha, parity, lds, st);
+    const bool ext = a.pdir || a.chem;
+    if constexpr (std::is_same<Word, char32_t>::value) {
+        if (a.single_type >= 0)
+            return ext ? launch_packed_k<Word, D, ACT, true, true>(a, mcs, alpha, parity, lds, st)
+                       : launch_packed_k<Word, D, ACT, true, false>(a, mcs, alpha, parity, lds, st);
+    }
+    return ext ? launch_packed_k<Word, D, ACT, false, true>(a, mcs, alpha, parity, lds, st)
+               : launch_packed_k<Word, D, ACT, false, false>(a, mcs, alpha, parity, lds, st);
 }
 
 // The caller's int32 lattice rewritten in place as packed words and back.
