@@ -111,7 +111,7 @@ def main():
                          "scheme against the serial CPM (2D circular chemotaxis ensembles); polarisation: "
                          "directional autocorrelation of Act cells, serial CPM vs parallel scheme; batch: 512 uneven "
                          "2D lattices; emulator: "
-                         "train the emulator on batched runs and judge it against fresh ones")
+                         "train the emulator on batched runs and score it against fresh ones")
     ap.add_argument("--layout", default="tune", choices=("tune", "auto", "box", "full_rows", "in_place"),
                     help="sweep layout: tune = time the candidates first and take the fastest (default)")
     ap.add_argument("--tune-mcs", type=int, default=6, help="MCS timed per candidate layout when tuning")

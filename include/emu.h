@@ -7,7 +7,7 @@
  * cpm_batch_summary() computes from such a run (means and variances of cell
  * volume, surface, speed and persistence time; speed and directional
  * persistence are the motility read-outs of the paper's Results, Fig. 5B).
- * The plain model stays the fallback and the judge of the emulator's error.
+ * The plain model stays the fallback and the reference for the emulator's error.
  *
  * Network: 6 -> 256 -> 256 -> 256 -> 8, exact (erf) GELU after each hidden
  * layer, linear output.  A point's six inputs are, in order, ln lambda_V,

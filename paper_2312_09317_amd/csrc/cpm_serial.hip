@@ -1,7 +1,7 @@
 // The serial CPM on the GPU (Methods, first paragraph): per MCS, N copy
 // attempts at uniformly drawn targets, each seeing the lattice and the
 // per-cell counters exactly as the attempt before it left them.  It is the
-// reference the parallel scheme is judged against (Fig. 5, Fig. 6E), run for
+// reference the parallel scheme is compared with (Fig. 5, Fig. 6E), run for
 // every lattice of a batch at once: one wave per lattice, attempts one after
 // another.
 //

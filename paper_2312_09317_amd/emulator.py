@@ -184,7 +184,7 @@ def inference_seconds_per_point(sur, x, n_points=65536, repeats=20):
 
 def study(n_train=8192, n_test=256, reps=8, plan=RunPlan(), L_min=64, L_max=512, epochs=300, batch=512,
           lr=2e-3, lr_final=5e-5, seed=1, log=None, data_path=None):
-    """Train the emulator on n_train single CPM runs and judge it on n_test
+    """Train the emulator on n_train single CPM runs and score it on n_test
     fresh parameter points against the mean of `reps` fresh CPM replicates
     each (new Philox seeds).  Returns per-statistic median relative errors
     of the emulator, of a linear fit and of one fresh CPM run, the
