@@ -133,7 +133,7 @@ def main():
         copy_calibration(args.copy_bytes)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "this implementation runs on one GPU; --gpus must be 1"}))
         log("bench.py runs on one GPU only: the sweep is not sharded across GPUs")
         sys.exit(2)
 

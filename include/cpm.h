@@ -70,7 +70,7 @@ extern "C" {
 #define CPM_ERANGE 2  /* a fixed-point energy could overflow int64 */
 #define CPM_ENOMEM 3  /* workspace smaller than cpm_workspace_bytes() */
 #define CPM_EDEVICE 4 /* HIP runtime error */
-#define CPM_ENOTSUP 5 /* valid model this build does not run */
+#define CPM_ENOTSUP 5 /* valid model the library does not run */
 
 #define CPM_MAX_TYPES 16
 

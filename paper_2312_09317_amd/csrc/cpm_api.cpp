@@ -417,7 +417,7 @@ int validate(const cpm_params *p, int32_t n_cells)
         if (bound + 65536.0 * 6.0 * lcmax >= 4.0e18) return fail(CPM_ERANGE, "fixed-point energy change could overflow int64");
     }
     if (table_length(p->temperature) > cpm::kMaxTI) return fail(CPM_ENOTSUP, "temperature too high for the threshold table");
-    if (p->attempts > cpm::kMaxAttempts) return fail(CPM_ENOTSUP, "this build runs at most 8 attempts per activation");
+    if (p->attempts > cpm::kMaxAttempts) return fail(CPM_ENOTSUP, "the library runs at most 8 attempts per activation");
     return CPM_OK;
 }
 
@@ -796,7 +796,7 @@ const char *cpm_strerror(int code)
     case CPM_ERANGE: return "fixed-point range exceeded";
     case CPM_ENOMEM: return "workspace too small";
     case CPM_EDEVICE: return "HIP runtime error";
-    case CPM_ENOTSUP: return "not supported by this build";
+    case CPM_ENOTSUP: return "not supported by the library";
     default: return "unknown error";
     }
 }
