@@ -71,7 +71,9 @@ def _declare(l):
                                       ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32, _P, _P]
     l.oracle_replicates.argtypes = [ctypes.POINTER(OrcModel), _P, _P, ctypes.c_int32, ctypes.c_int32,
                                     ctypes.c_int32, ctypes.c_int32, _P]
-    for f in ("oracle_replicates", "oracle_philox", "oracle_tables", "oracle_threshold", "oracle_recount",
+    l.oracle_replicates_act.argtypes = [ctypes.POINTER(OrcModel), _P, _P, _P, ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.c_int32, _P, _P]
+    for f in ("oracle_replicates", "oracle_replicates_act", "oracle_philox", "oracle_tables", "oracle_threshold", "oracle_recount",
               "oracle_cell_stats", "oracle_delta_h", "oracle_gm_act", "oracle_sweep",
               "oracle_serial_sweep", "oracle_persist_init", "oracle_sweep_p", "oracle_persist_update"):
         getattr(l, f).restype = ctypes.c_int
@@ -280,6 +282,20 @@ def replicates(model, lattice, cell_type, n_mcs, n_rep, mode="dcs"):
     _check(lib().oracle_replicates(ctypes.byref(model.c), _ptr(lat), _ptr(ct), len(ct) - 1, n_mcs,
                                    n_rep, code, _ptr(out)), "replicates")
     return out
+
+
+def replicates_act(model, lattice, act, cell_type, n_mcs, n_rep):
+    """Final lattices and activities of n_rep independent runs of an Act
+    model under the parallel scheme, all starting from (lattice, act);
+    replicate r uses lattice id model.lattice_id + r."""
+    lat = np.ascontiguousarray(lattice, dtype=np.int32).reshape(-1)
+    a0 = np.ascontiguousarray(act, dtype=np.uint8).reshape(-1)
+    ct = np.ascontiguousarray(cell_type, dtype=np.int32)
+    out_l = np.zeros((n_rep, lat.size), dtype=np.int32)
+    out_a = np.zeros((n_rep, lat.size), dtype=np.uint8)
+    _check(lib().oracle_replicates_act(ctypes.byref(model.c), _ptr(lat), _ptr(a0), _ptr(ct), len(ct) - 1,
+                                       n_mcs, n_rep, _ptr(out_l), _ptr(out_a)), "replicates_act")
+    return out_l, out_a
 
 
 class Persistence:

@@ -916,6 +916,34 @@ static int sweep_serial(const orc_model *m, const orc_q *qp, int32_t *lat, const
  * gives it its own Philox stream.  mode 0 = parallel scheme, 1 = serial CPM,
  * 2 = serial symmetric proposal.  Writes the final lattices (n_rep x N).
  */
+/* Replicates of an Act model under the parallel scheme: replicate r starts
+ * from lat0 and act0 with lattice id m->lattice_id + r and runs n_mcs MCS;
+ * its final labels and activities go to final_lat and final_act. */
+int oracle_replicates_act(const orc_model *m, const int32_t *lat0, const uint8_t *act0, const int32_t *type,
+                          int32_t C, int32_t n_mcs, int32_t n_rep, int32_t *final_lat, uint8_t *final_act)
+{
+    if (!m->act_enabled) return ORC_EINVAL;
+    int64_t N = (int64_t)m->L[0] * m->L[1] * m->L[2];
+    orc_q *qp = (orc_q *)malloc(sizeof(orc_q));
+    int64_t *V = (int64_t *)malloc(sizeof(int64_t) * (size_t)(C + 1));
+    int64_t *S = (int64_t *)malloc(sizeof(int64_t) * (size_t)(C + 1));
+    int rc = (qp && V && S) ? ORC_OK : ORC_ENOMEM;
+    if (rc == ORC_OK) rc = model_prepare(m, qp);
+    orc_model mr = *m;
+    for (int32_t r = 0; r < n_rep && rc == ORC_OK; r++) {
+        int32_t *lat = final_lat + (int64_t)r * N;
+        uint8_t *act = final_act + (int64_t)r * N;
+        memcpy(lat, lat0, sizeof(int32_t) * (size_t)N);
+        memcpy(act, act0, (size_t)N);
+        rc = oracle_recount(m, lat, C, V, S);
+        if (rc != ORC_OK) break;
+        mr.lattice_id = m->lattice_id + (uint32_t)r;
+        rc = sweep_dcs(&mr, qp, lat, type, C, act, V, S, 0, n_mcs, NULL, NULL, NULL);
+    }
+    free(qp); free(V); free(S);
+    return rc;
+}
+
 int oracle_replicates(const orc_model *m, const int32_t *lat0, const int32_t *type, int32_t C,
                       int32_t n_mcs, int32_t n_rep, int32_t mode, int32_t *final_lat)
 {
