@@ -39,6 +39,12 @@ KERNEL_SOURCES = ("cpm_sweep.hip", "cpm_device.hpp", "cpm_internal.hpp")
 # (label-type-activity words).
 MEASURED_TRAFFIC_TISSUE = {"sources_sha256": "a6292773102e85c3", "layout": "in_place", "fetch_kib": 2570054.3,
                            "write_kib": 255357.3, "fetch_scale": 2.0, "write_scale": 1.0}
+# The 2048^2 sorting workload's activation kernel (16-bit labels, in place).
+MEASURED_TRAFFIC_SORTING = {"sources_sha256": "a6292773102e85c3", "layout": "in_place", "fetch_kib": 6178.4,
+                            "write_kib": 266.1, "fetch_scale": 2.0, "write_scale": 1.0}
+# The 512-lattice 2D batch's activation kernel (label-type-activity words).
+MEASURED_TRAFFIC_BATCH = {"sources_sha256": "a6292773102e85c3", "layout": None, "fetch_kib": 138426.3,
+                          "write_kib": 11193.9, "fetch_scale": 2.0, "write_scale": 1.0}
 
 
 def measured_traffic_bytes(layout=None, table=None):
@@ -336,7 +342,10 @@ def bench_sorting(args):
                    "tuning_ms_per_mcs": tuning, "homotypic_contacts_before": h0,
                    "homotypic_contacts_after": h1, "mcs_run": args.warmup + args.steps},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "tile_sweep_kernel",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic_bytes(cpm.cpm_tile_shape(params, w.n_cells)["layout"],
+                                                       MEASURED_TRAFFIC_SORTING),
+                     "kernel": "tile_sweep_kernel",
                      "avg_launch_us": avg_launch_s * 1e6, "bytes_per_attempt": bytes_per_attempt(2, w.s, w.k, p_acc)},
         "cpu_baseline": {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")} if cpu else None}),
         flush=True)
@@ -508,7 +517,8 @@ def bench_batch(args):
         "config": {"workload": "2d-batch-512-L64..512", "n_lattices": len(ws), "sites": sites, "sub": ws[0].s,
                    "attempts_per_activation": ws[0].k, "act": True, "graph": True},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "batch_sweep_kernel",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic_bytes(None, MEASURED_TRAFFIC_BATCH),
+                     "kernel": "batch_sweep_kernel",
                      "avg_launch_us": avg_launch_s * 1e6},
         "cpu_baseline": None}), flush=True)
     b.close()
