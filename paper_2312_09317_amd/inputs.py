@@ -245,12 +245,15 @@ def circular_field(L):
     """The paper's circular chemotaxis field on an L x L lattice: at every
     site the unit vector at 90 degrees (counter-clockwise) to the radial
     vector from the lattice centre to the site's centre, as int16 in units of
-    2^-14 (x, y per site, sites in lattice order)."""
+    2^-14 (x, y per site, sites in lattice order).  For odd L one site centre
+    is the lattice centre, where the direction is undefined: its vector is
+    zero."""
     c = L / 2.0
     y, x = np.mgrid[0:L, 0:L].astype(np.float64)
     rx, ry = x + 0.5 - c, y + 0.5 - c
     r = np.hypot(rx, ry)
-    f = np.stack([-ry / r, rx / r], axis=-1)
+    rr = np.where(r > 0, r, 1.0)
+    f = np.where((r > 0)[..., None], np.stack([-ry / rr, rx / rr], axis=-1), 0.0)
     return np.rint(f * 16384.0).astype(np.int16).reshape(-1)
 
 
