@@ -27,7 +27,9 @@ ones from the first attempt on, and the final states carry the decay.  Laws
 built with the Act term dropped, with its sign flipped, with an arithmetic
 mean for GM, with GM over every neighbour regardless of label, or without
 decay are rejected by the same samples (p below 1e-100 for each), so a
-mistake of that kind in the oracle would fail here.
+mistake of that kind in the oracle would fail here.  With k = 4 attempts per
+activation (each area's attempts back to back, seeing its own deltas) the
+law is pinned the same way, and the k = 1 law is rejected by those samples.
 The oracle's fixed-point energies differ from these float64 ones by far less
 than the test can resolve.
 """
@@ -110,14 +112,17 @@ def _merge(keys, w):
     return u[keep], p[keep]
 
 
-def _law(H, init_lab, init_act, variant=None):
-    """Exact law of (labels, activities) after N_MCS MCS, as (keys, probs)."""
+def _law(H, init_lab, init_act, variant=None, k=1):
+    """Exact law of (labels, activities) after N_MCS MCS, as (keys, probs).
+    k attempts per activation: 16 / k activations per MCS, colour alpha mod
+    4, each making k attempts one after another in its sub-area (each sees
+    the lattice and the counters the previous one left)."""
     R = LAM_ACT / MAX_ACT
     keys = _encode(init_lab.reshape(1, -1).astype(np.int64), init_act.reshape(1, -1).astype(np.int64))
     p = np.ones(1)
     for _ in range(N_MCS):
-        for alpha in range(16):
-            phi = alpha % 4
+        for step in range(16):
+            phi = (step // k) % 4
             cx, cy = phi & 1, (phi >> 1) & 1
             lab, act = _decode(keys)
             hk = H[(lab << np.arange(N)[None, :]).sum(axis=1)]
@@ -168,15 +173,18 @@ def _initial():
     return lab, act
 
 
-@pytest.fixture(scope="module")
-def runs():
+def _oracle_runs(k, seed):
     lab, act = _initial()
     m = oracle.Model(2, (L, L), [[0.0, J_CM], [J_CM, 0.0]], [0.0, LAM_V], [0, V_T], [0.0, LAM_S], [0, S_T],
-                     lambda_act=[0.0, LAM_ACT], max_act=[0, MAX_ACT], T=T, s=2, k=1, seed=2024)
+                     lambda_act=[0.0, LAM_ACT], max_act=[0, MAX_ACT], T=T, s=2, k=k, seed=seed)
     fl, fa = oracle.replicates_act(m, lab, act, [0, 1], N_MCS, R_REP)
     # activities of medium sites are 0 by construction; the key holds them as they are
-    keys = _encode(fl.astype(np.int64), fa.astype(np.int64))
-    return keys
+    return _encode(fl.astype(np.int64), fa.astype(np.int64))
+
+
+@pytest.fixture(scope="module")
+def runs():
+    return _oracle_runs(1, 2024)
 
 
 @pytest.fixture(scope="module")
@@ -214,3 +222,18 @@ def test_act_law_has_power(runs, table, variant):
     k, p = _law(table, lab, act, variant)
     counts, outside = _counts(runs, k)
     assert outside > 0 or _chi2_pvalue(counts, p * R_REP) < 1e-6
+
+
+def test_act_law_four_attempts_per_activation(table):
+    # k = 4: four activations per MCS, one per colour, each running its four
+    # attempts back to back; the law of k = 1 (colours taking turns after
+    # every attempt) is rejected by the same samples
+    lab, act = _initial()
+    keys = _oracle_runs(4, 77)
+    k4, p4 = _law(table, lab, act, k=4)
+    counts, outside = _counts(keys, k4)
+    assert outside == 0
+    assert _chi2_pvalue(counts, p4 * R_REP) > 1e-4
+    k1, p1 = _law(table, lab, act, k=1)
+    counts, outside = _counts(keys, k1)
+    assert outside > 0 or _chi2_pvalue(counts, p1 * R_REP) < 1e-6
