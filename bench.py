@@ -91,6 +91,11 @@ def cpu_baseline(w, n_mcs):
             "p_acc": float(st.stats[2]) / max(1, attempts)}
 
 
+def sample_mcs(args, default):
+    """MCS of the oracle sample: --cpu-mcs, else the workload's default."""
+    return default if args.cpu_mcs is None else args.cpu_mcs
+
+
 def copy_calibration(nbytes):
     import torch
     a = torch.empty(nbytes // 4, dtype=torch.int32, device="cuda:0").fill_(1)
@@ -107,7 +112,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--cpu-mcs", type=int, default=4, help="MCS of the oracle sample (0 to skip)")
+    ap.add_argument("--cpu-mcs", type=int, default=None,
+                    help="MCS of the oracle sample (0 to skip; default: about 10-15 s of oracle work per "
+                         "workload: 6 for the 256^3 sweep, 120 for sorting, 2 for the collective)")
     ap.add_argument("--workload", choices=("sweep", "tissue", "sorting", "collective", "accuracy", "polarisation",
                                            "batch", "emulator"),
                     default="sweep",
@@ -172,6 +179,7 @@ def main():
     sim.sweep(args.warmup)
     torch.cuda.synchronize()
     log(f"warm-up done ({args.warmup} MCS)")
+    att0 = sim.attempt_stats()
 
     n_act = (2 * w.s) ** w.ndim // w.k
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -199,8 +207,11 @@ def main():
 
     attempts = args.steps * w.n_sites
     value = attempts / (total_ms / 1e3)
-    cpu = cpu_baseline(w, args.cpu_mcs) if args.cpu_mcs > 0 else None
-    p_acc = cpu["p_acc"] if cpu else 0.0
+    # accepted copies per attempt of the timed region, from the kernels' own counts
+    att1 = sim.attempt_stats()
+    p_acc = (att1[2] - att0[2]) / max(1, att1[0] - att0[0])
+    n_cpu = sample_mcs(args, 6)
+    cpu = cpu_baseline(w, n_cpu) if n_cpu > 0 else None
     launches = args.steps * n_act
     # the activation kernels run back to back on one stream: the timed
     # region's time per launch is their average duration (the MCS loop
@@ -331,7 +342,8 @@ def bench_sorting(args):
     avg_launch_s = sweep_ms / 1e3 / (args.steps * n_act)
     per_launch_bytes = bytes_per_attempt(2, w.s, w.k, p_acc) * (w.n_sites // n_act)
     achieved = per_launch_bytes / avg_launch_s / 1e9
-    cpu = cpu_baseline(w, args.cpu_mcs) if args.cpu_mcs > 0 else None
+    n_cpu = sample_mcs(args, 120)
+    cpu = cpu_baseline(w, n_cpu) if n_cpu > 0 else None
     print(json.dumps({
         "metric": "site copy-attempts/s on 2D 2048² cell sorting", "value": w.n_sites * args.steps / (total_ms / 1e3),
         "unit": "attempts/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -396,7 +408,8 @@ def bench_collective(args):
     avg_launch_s = sweep_ms / 1e3 / (args.steps * n_act)
     per_launch_bytes = bytes_per_attempt(3, w.s, w.k, p_acc) * (w.n_sites // n_act)
     achieved = per_launch_bytes / avg_launch_s / 1e9
-    cpu = cpu_baseline(w, args.cpu_mcs) if args.cpu_mcs > 0 else None
+    n_cpu = sample_mcs(args, 2)
+    cpu = cpu_baseline(w, n_cpu) if n_cpu > 0 else None
     print(json.dumps({
         "metric": "site copy-attempts/s on a 3D 256³ persistent cell collective",
         "value": w.n_sites * args.steps / (total_ms / 1e3), "unit": "attempts/s", "n_gpus": 1,
@@ -430,7 +443,7 @@ def bench_accuracy(args):
     out = accuracy.study(w, configs, n_runs=args.acc_runs, n_mcs=args.acc_mcs, log=log)
     main_row = next(r for r in out["parallel"] if (r["s"], r["k"]) == (2, 1))
     cpu = None
-    if args.cpu_mcs > 0:
+    if sample_mcs(args, 1) > 0:
         # the oracle runs an ensemble sample of the same shape: 32 runs of
         # the parallel scheme at s = 2, k = 1 over --acc-mcs MCS
         import oracle
