@@ -42,6 +42,9 @@ MEASURED_TRAFFIC_TISSUE = {"sources_sha256": "a6292773102e85c3", "layout": "in_p
 # The 2048^2 sorting workload's activation kernel (16-bit labels, in place).
 MEASURED_TRAFFIC_SORTING = {"sources_sha256": "a6292773102e85c3", "layout": "in_place", "fetch_kib": 6178.4,
                             "write_kib": 266.1, "fetch_scale": 2.0, "write_scale": 1.0}
+# The 256^3 collective's activation kernel (16-bit labels, persistence term).
+MEASURED_TRAFFIC_COLLECTIVE = {"sources_sha256": "a6292773102e85c3", "layout": "in_place", "fetch_kib": 18822.7,
+                               "write_kib": 4253.4, "fetch_scale": 2.0, "write_scale": 1.0}
 # The 512-lattice 2D batch's activation kernel (label-type-activity words).
 MEASURED_TRAFFIC_BATCH = {"sources_sha256": "a6292773102e85c3", "layout": None, "fetch_kib": 138426.3,
                           "write_kib": 11193.9, "fetch_scale": 2.0, "write_scale": 1.0}
@@ -421,7 +424,10 @@ def bench_collective(args):
                    "tiling": cpm.cpm_tile_shape(params, w.n_cells), "tuning_ms_per_mcs": tuning,
                    "order_before": o0, "order_after": o1, "mcs_run": args.warmup + args.steps},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "tile_sweep_kernel",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic_bytes(cpm.cpm_tile_shape(params, w.n_cells)["layout"],
+                                                       MEASURED_TRAFFIC_COLLECTIVE),
+                     "kernel": "tile_sweep_kernel",
                      "avg_launch_us": avg_launch_s * 1e6, "bytes_per_attempt": bytes_per_attempt(3, w.s, w.k, p_acc)},
         "cpu_baseline": {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")} if cpu else None}),
         flush=True)
