@@ -50,14 +50,21 @@ MEASURED_TRAFFIC_BATCH = {"sources_sha256": "a6292773102e85c3", "layout": None, 
                           "write_kib": 11193.9, "fetch_scale": 2.0, "write_scale": 1.0}
 
 
-def measured_traffic_bytes(layout=None, table=None):
+def kernel_sources_sha():
+    """sha256 prefix of the activation kernels' sources, as the traffic tables record it."""
     import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2312_09317_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic_bytes(layout=None, table=None):
+    """HBM bytes per launch of a traffic table, or None when the kernel
+    sources or the layout differ from those the counters were taken on."""
     t = MEASURED_TRAFFIC if table is None else table
-    if h.hexdigest()[:16] != t["sources_sha256"] or (layout is not None and layout != t["layout"]):
+    if kernel_sources_sha() != t["sources_sha256"] or (layout is not None and layout != t["layout"]):
         return None
     return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0
 
