@@ -109,6 +109,24 @@ def test_act_model(torch_cuda, ndim, dims):
     assert_same(st, sim, torch_cuda)
 
 
+@pytest.mark.parametrize("ndim,dims,s,k", [
+    (2, (32, 24, 1), 2, 4), (2, (36, 36, 1), 3, 3), (2, (32, 32, 1), 4, 8), (2, (4, 4, 1), 2, 4),
+    (3, (16, 12, 12), 2, 2), (3, (16, 16, 8), 2, 8),
+])
+def test_act_sub_and_attempts(torch_cuda, ndim, dims, s, k):
+    # the Act term with several attempts per activation (each seeing its own
+    # earlier copies and activities) and larger sub-areas; every cell site
+    # starts at its type's Max_act, so the geometric means are nonzero from
+    # the first attempt on
+    w = _multi(dims, ndim, seed=43 + 5 * s + k, s=s, k=k, act=True, obstacles=0.03, T=20.0,
+               n_cells=12 if dims[0] > 4 else 2)
+    lab = w.lattice
+    w.act = np.where(lab > 0, w.max_act[w.cell_type[np.maximum(lab, 0)]], 0).astype(np.uint8)
+    st, sim = run_both(torch_cuda, w, 6)
+    assert_same(st, sim, torch_cuda)
+    assert st.stats[2] > 0 and (st.act > 0).any()
+
+
 def test_resume_and_chunking(torch_cuda):
     w = _multi((24, 24, 1), 2, seed=5)
     st, sim = run_both(torch_cuda, w, 7, chunks=[1, 2, 0, 4])
