@@ -32,8 +32,8 @@ HBM_PEAK_GBS = 8000.0
 # counters read for a plain 256 MiB copy (FETCH x 2.0, WRITE x 1.0), for the
 # kernel sources whose sha256 prefix is given; reported only while the
 # sources are unchanged.
-MEASURED_TRAFFIC = {"sources_sha256": "a6292773102e85c3", "layout": "in_place", "fetch_kib": 17170.0,
-                    "write_kib": 1116.9, "fetch_scale": 2.0, "write_scale": 1.0}
+MEASURED_TRAFFIC = {"sources_sha256": "a6292773102e85c3", "layout": "in_place", "tile": [64, 4, 1],
+                    "fetch_kib": 17170.0, "write_kib": 1116.9, "fetch_scale": 2.0, "write_scale": 1.0}
 KERNEL_SOURCES = ("cpm_sweep.hip", "cpm_device.hpp", "cpm_internal.hpp")
 # The same for the 1024^3 tissue workload's activation kernel
 # (label-type-activity words).
@@ -60,11 +60,14 @@ def kernel_sources_sha():
     return h.hexdigest()[:16]
 
 
-def measured_traffic_bytes(layout=None, table=None):
+def measured_traffic_bytes(layout=None, table=None, tile=None):
     """HBM bytes per launch of a traffic table, or None when the kernel
-    sources or the layout differ from those the counters were taken on."""
+    sources, the layout or the tile shape differ from those the counters
+    were taken on."""
     t = MEASURED_TRAFFIC if table is None else table
     if kernel_sources_sha() != t["sources_sha256"] or (layout is not None and layout != t["layout"]):
+        return None
+    if tile is not None and t.get("tile") is not None and list(tile) != list(t["tile"]):
         return None
     return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0
 
@@ -137,6 +140,9 @@ def main():
                          "train the emulator on batched runs and score it against fresh ones")
     ap.add_argument("--layout", default="tune", choices=("tune", "auto", "box", "full_rows", "in_place"),
                     help="sweep layout: tune = time the candidates first and take the fastest (default)")
+    ap.add_argument("--tile", default=None,
+                    help="thread areas per workgroup tile as X,Y,Z (with a named --layout; default: the "
+                         "library's choice)")
     ap.add_argument("--tune-mcs", type=int, default=6, help="MCS timed per candidate layout when tuning")
     ap.add_argument("--acc-runs", type=int, default=250, help="accuracy workload: runs per ensemble")
     ap.add_argument("--acc-mcs", type=int, default=200, help="accuracy workload: MCS per run")
@@ -230,6 +236,8 @@ def main():
     avg_launch_s = (sweep_ms / 1e3) / launches
     per_launch_bytes = bytes_per_attempt(w.ndim, w.s, w.k, p_acc) * (w.n_sites // n_act)
     achieved = per_launch_bytes / avg_launch_s / 1e9
+    tiling = cpm.cpm_tile_shape(params, w.n_cells)
+    traffic = measured_traffic_bytes(tiling["layout"], tile=tiling["areas"])
     out = {
         "metric": METRIC,
         "value": value,
@@ -241,26 +249,46 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int32",
+        "dtype": "int64",
         "data": "synthetic",
         "config": {"workload": w.name, "lattice": list(w.dims), "n_cells": w.n_cells, "sub": w.s,
                    "attempts_per_activation": w.k, "mcs_per_step": 1, "activations_per_mcs": n_act,
-                   "temperature": w.T, "seed": w.seed, "tiling": cpm.cpm_tile_shape(params, w.n_cells),
+                   "temperature": w.T, "seed": w.seed, "tiling": tiling,
+                   "label_storage": label_storage(tiling), "energy_arithmetic": "int64, 2^-16 fixed point",
                    "tuning_ms_per_mcs": tuning},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic_bytes(cpm.cpm_tile_shape(params, w.n_cells)["layout"]),
-                     "kernel": "tile_sweep_kernel", "avg_launch_us": avg_launch_s * 1e6,
-                     "bytes_per_attempt": bytes_per_attempt(w.ndim, w.s, w.k, p_acc)},
+        "roofline": roofline_fields(achieved, traffic, avg_launch_s, "tile_sweep_kernel",
+                                    bytes_per_attempt(w.ndim, w.s, w.k, p_acc)),
         "cpu_baseline": {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")} if cpu else None,
     }
     print(json.dumps(out), flush=True)
     sim.close()
 
 
+def label_storage(tiling, act_words=False):
+    """What the activation kernel reads per site, for the report."""
+    if act_words:
+        return "uint32 words: label + 1, type and activity, written over the int32 lattice during a sweep"
+    if tiling.get("labels16"):
+        return "uint16 mirror (label + 1) of the int32 lattice"
+    return "int32 labels"
+
+
+def roofline_fields(achieved_gbs, traffic, avg_launch_s, kernel, bpa):
+    """The roofline object: `frac` from the algorithmic bytes (the staged
+    scheme's int32 sites per attempt) and, beside it, the fraction the
+    measured HBM-side bytes per launch give at the same launch time."""
+    real = traffic / avg_launch_s / 1e9 if traffic else None
+    return {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved_gbs / HBM_PEAK_GBS, "traffic": traffic,
+            "achieved_measured_bytes": real, "frac_measured_bytes": real / HBM_PEAK_GBS if real else None,
+            "kernel": kernel, "avg_launch_us": avg_launch_s * 1e6, "bytes_per_attempt": bpa}
+
+
 def choose_layout(args, cpm, params, w):
     """The sweep layout: timed candidates (--layout tune) or the one named."""
     if args.layout != "tune":
-        return params.replace(layout=args.layout), None
+        tile = tuple(int(v) for v in args.tile.split(",")) if args.tile else (0, 0, 0)
+        return params.replace(layout=args.layout, tile=tile), None
     r = cpm.autotune(params, w.lattice, w.cell_type, w.act, trial_mcs=args.tune_mcs)
     log("autotune (ms per MCS): " + ", ".join(f"{k[0]}{list(k[1])}: {v:.3f}" for k, v in sorted(r["times"].items(), key=lambda kv: kv[1])))
     lay, tile = r["best"]

@@ -166,8 +166,10 @@ int cpm_tile_shape(const cpm_params *params, int32_t n_cells, int32_t *out);
  *   d_workspace device buffer of at least cpm_workspace_bytes(), 256-byte
  *               aligned, contents arbitrary; owned by the library until
  *               cpm_destroy
- * Labels outside [-1, n_cells] are not checked on the device; the caller
- * guarantees them.  The MCS counter starts at 0.
+ * Every label is checked on the device before anything else runs (the call
+ * waits for the stream): a label outside [-1, n_cells], or -1 in a model
+ * with obstacle_type = -1, gives CPM_EINVAL and no handle.  The MCS counter
+ * starts at 0.
  */
 int cpm_init(const cpm_params *params, int32_t *d_lattice, const int32_t *d_cell_type,
              int32_t n_cells, uint8_t *d_act, void *d_workspace, size_t workspace_bytes,
@@ -212,6 +214,23 @@ int cpm_persistence(cpm_handle *h, int32_t *d_dir, void *stream);
 /* Copies the volume / surface counters the sweep tracks (int32[n_cells + 1]
  * each, device; entry 0 unused and written as 0).  Asynchronous. */
 int cpm_counters(cpm_handle *h, int32_t *d_volume, int32_t *d_surface, void *stream);
+
+/*
+ * Failure detection.  The scheme guarantees that a cell's tracked size
+ * equals the number of lattice sites it occupies, whatever order the atomic
+ * updates of concurrent copies land in (paper, Results, "Designing a
+ * parallel execution scheme", Fig. 2B: atomic updates of per-cell
+ * variables).  This call recounts every label's volume and surface from the
+ * lattice on the device (as cpm_cell_stats does) and compares them with the
+ * counters the sweep tracks: *h_ok (host) = 1 when every site's label lies
+ * in [-1, n_cells] (-1 only with an obstacle type) and every cell's tracked
+ * (V, S) equals the recount, else 0.  Labels are checked first; out-of-range
+ * labels give 0 without a recount.  Uses the check section of the handle's
+ * workspace; changes neither the lattice nor the counters.  Waits for the
+ * stream.  Returns CPM_OK whatever the verdict (CPM_EINVAL for NULL
+ * arguments, CPM_EDEVICE for a HIP error).
+ */
+int cpm_check_invariants(cpm_handle *h, void *stream, int32_t *h_ok);
 
 /* Copy-attempt statistics since cpm_init, read synchronously on `stream`
  * (waits for the stream): out[0] attempts, out[1] attempts past the early
@@ -280,6 +299,10 @@ int cpm_batch_cell_stats(cpm_batch *b, int32_t *d_volume, int32_t *d_surface, in
                          void *stream);
 /* out: 3 entries per lattice, as cpm_attempt_stats; waits for the stream. */
 int cpm_batch_attempt_stats(cpm_batch *b, uint64_t *out, void *stream);
+/* cpm_check_invariants for every lattice of a batch: h_ok (host, n
+ * entries), 1 where lattice i passes.  cpm_batch_init checks every label
+ * of every lattice as cpm_init does (CPM_EINVAL). */
+int cpm_batch_check_invariants(cpm_batch *b, void *stream, int32_t *h_ok);
 /*
  * Cell-level summary statistics of a batch.  cpm_batch_sample records, for
  * every lattice i and label c, the record (V, S, x, y, z) of sample k:

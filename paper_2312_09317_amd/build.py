@@ -10,7 +10,10 @@ OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libcpm.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
-SOURCES = ["cpm_sweep.hip", "cpm_serial.hip", "cpm_kernels.hip", "cpm_stats.hip", "emu_kernels.hip", "cpm_api.cpp", "emu_api.cpp"]
+SOURCES = ["cpm_sweep.hip", "cpm_sweep_inst.hip", "cpm_serial.hip", "cpm_kernels.hip", "cpm_stats.hip",
+           "emu_kernels.hip", "cpm_api.cpp", "emu_api.cpp"]
+# the activation kernels are instantiated in groups, one compilation each
+SWEEP_PARTS = 7
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
     # keep the compiler from emitting packed FP32 instructions
@@ -23,17 +26,28 @@ def sources():
     return [os.path.join(CSRC, s) for s in SOURCES]
 
 
+def units():
+    """(source, extra flags, object) of every compilation."""
+    out = []
+    for src in sources():
+        base = os.path.join(OUT_DIR, os.path.basename(src))
+        if src.endswith("cpm_sweep_inst.hip"):
+            out += [(src, [f"-DCPM_SWEEP_PART={i}"], f"{base}.{i}.o") for i in range(SWEEP_PARTS)]
+        else:
+            out.append((src, [], base + ".o"))
+    return out
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(OUT_DIR, exist_ok=True)
     jobs = []
-    for src in sources():
-        obj = os.path.join(OUT_DIR, os.path.basename(src) + ".o")
-        cmd = ["hipcc", *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC, "-x", "hip", "-c", src, "-o", obj]
+    for src, extra, obj in units():
+        cmd = ["hipcc", *HIPCC_FLAGS, *extra, "-I", INCLUDE, "-I", CSRC, "-x", "hip", "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd))
         jobs.append((cmd, obj))
-    # one compiler process per source, at most four at a time
-    with concurrent.futures.ThreadPoolExecutor(max_workers=4) as pool:
+    # one compiler process per compilation, at most eight at a time
+    with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 4)) as pool:
         for f in [pool.submit(subprocess.run, cmd, check=True) for cmd, _ in jobs]:
             f.result()
     objs = [obj for _, obj in jobs]

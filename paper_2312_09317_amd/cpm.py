@@ -60,9 +60,9 @@ LAYOUTS = {"auto": 0, "box": 1, "full_rows": 2, "in_place": 3}
 
 
 EXPORTS = ("cpm_validate", "cpm_workspace_bytes", "cpm_tile_shape", "cpm_init", "cpm_sweep", "cpm_cell_stats", "cpm_contacts",
-           "cpm_persistence", "cpm_counters", "cpm_attempt_stats", "cpm_set_mcs", "cpm_get_mcs", "cpm_destroy",
+           "cpm_persistence", "cpm_counters", "cpm_check_invariants", "cpm_attempt_stats", "cpm_set_mcs", "cpm_get_mcs", "cpm_destroy",
            "cpm_batch_workspace_bytes", "cpm_batch_init", "cpm_batch_sweep", "cpm_batch_sweep_serial", "cpm_batch_occupancy", "cpm_batch_use_graph", "cpm_batch_counters",
-           "cpm_batch_cell_stats", "cpm_batch_attempt_stats", "cpm_batch_sample", "cpm_batch_summary", "cpm_batch_autocorrelation",
+           "cpm_batch_cell_stats", "cpm_batch_attempt_stats", "cpm_batch_check_invariants", "cpm_batch_sample", "cpm_batch_summary", "cpm_batch_autocorrelation",
            "cpm_batch_set_mcs", "cpm_batch_get_mcs",
            "cpm_batch_destroy", "cpm_strerror", "cpm_last_error")
 
@@ -94,6 +94,7 @@ def load(path: str = LIB_PATH):
     l.cpm_persistence.argtypes = [P, P, P]
     l.cpm_counters.argtypes = [P, P, P, P]
     l.cpm_attempt_stats.argtypes = [P, P, P]
+    l.cpm_check_invariants.argtypes = [P, P, P]
     l.cpm_set_mcs.argtypes = [P, U64]
     l.cpm_get_mcs.argtypes = [P, ctypes.POINTER(U64)]
     l.cpm_destroy.argtypes = [P]
@@ -106,6 +107,7 @@ def load(path: str = LIB_PATH):
     l.cpm_batch_counters.argtypes = [P, P, P, P]
     l.cpm_batch_cell_stats.argtypes = [P, P, P, P, P]
     l.cpm_batch_attempt_stats.argtypes = [P, P, P]
+    l.cpm_batch_check_invariants.argtypes = [P, P, P]
     l.cpm_batch_sample.argtypes = [P, P, I32, I32, P]
     l.cpm_batch_summary.argtypes = [P, P, I32, ctypes.c_double, P, P]
     l.cpm_batch_autocorrelation.argtypes = [P, P, I32, P, P]
@@ -276,6 +278,12 @@ def cpm_counters(h: int, d_volume, d_surface, stream: int) -> None:
     _check(load().cpm_counters(h, _ptr(d_volume), _ptr(d_surface), stream), "cpm_counters")
 
 
+def cpm_check_invariants(h: int, stream: int) -> bool:
+    ok = ctypes.c_int32(0)
+    _check(load().cpm_check_invariants(h, stream, ctypes.byref(ok)), "cpm_check_invariants")
+    return bool(ok.value)
+
+
 def cpm_attempt_stats(h: int, stream: int):
     out = (ctypes.c_uint64 * 3)()
     _check(load().cpm_attempt_stats(h, out, stream), "cpm_attempt_stats")
@@ -363,6 +371,11 @@ class Simulation:
         """(attempts, attempts past the early rejection, accepted copies)."""
         return cpm_attempt_stats(self.handle, self.stream)
 
+    def check_invariants(self) -> bool:
+        """True when every label is in range and the tracked (V, S) of every
+        cell equals a recount from the lattice (waits for the stream)."""
+        return cpm_check_invariants(self.handle, self.stream)
+
     @property
     def mcs(self) -> int:
         return cpm_get_mcs(self.handle)
@@ -444,6 +457,12 @@ def cpm_batch_attempt_stats(h: int, n: int, stream: int):
     out = (ctypes.c_uint64 * (3 * n))()
     _check(load().cpm_batch_attempt_stats(h, out, stream), "cpm_batch_attempt_stats")
     return np.array(list(out), dtype=np.uint64).reshape(n, 3)
+
+
+def cpm_batch_check_invariants(h: int, n: int, stream: int):
+    out = (ctypes.c_int32 * n)()
+    _check(load().cpm_batch_check_invariants(h, stream, out), "cpm_batch_check_invariants")
+    return [bool(v) for v in out]
 
 
 def cpm_batch_sample(h: int, d_samples, k: int, n_samples: int, stream: int) -> None:
@@ -554,6 +573,10 @@ class Batch:
 
     def attempt_stats(self):
         return cpm_batch_attempt_stats(self.handle, self.n, self.stream)
+
+    def check_invariants(self):
+        """Per lattice, cpm_check_invariants' verdict (list of bools)."""
+        return cpm_batch_check_invariants(self.handle, self.n, self.stream)
 
     def run_with_samples(self, burn_in: int, n_samples: int, interval: int, serial: bool = False):
         """Sweep burn_in MCS, then take n_samples samples interval MCS apart

@@ -28,6 +28,8 @@ struct cpm_handle {
     int words = cpm::kWords32;       // what sweeps read: int32 labels, the 16-bit copy or packed words
     SweepArgs args{};
     int32_t *ref = nullptr;          // centroid reference sites, n_cells + 1
+    int32_t *check = nullptr;        // invariant checks: flag word, then recounted V and S
+    bool obstacles = false;          // the model has an obstacle type (label -1 allowed)
     // persistence (NULL pdir = off): directions, centroid history, centroid sums
     int4 *pdir = nullptr;
     int64_t *hist = nullptr;
@@ -45,11 +47,15 @@ struct cpm_batch {
     int32_t ndim = 0, s = 0, k = 0;
     bool act = false, mirror = false, single = false;
     bool act_words = false;          // Act batches sweep on label-type-activity words
+    bool act16 = false;              // ... or, with small lattices of one cell type, on 16-bit label-activity words
+    uint16_t *words16 = nullptr;     // those words, packed like the int32 lattices
     int layout = 0;
     std::vector<SweepArgs> args;                     // host copies, one per lattice
     std::vector<int32_t> n_cells;
     std::vector<size_t> site_off, label_off;         // packed offsets of lattices / cell-type arrays
     std::vector<int32_t *> ref;
+    std::vector<int32_t *> check;                    // per lattice: flag word, then recounted V and S
+    std::vector<uint8_t> obstacles;                  // per lattice: label -1 allowed
     std::vector<uint16_t *> mirror_cells;
     std::vector<std::unique_ptr<DeviceModel>> models;
     std::vector<int2> work;
@@ -106,7 +112,7 @@ int64_t to_fixed(double x) { return (int64_t)std::llround(x * 65536.0); }
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t model, counters0, counters1, dlist, dcount, stats, ref, mirror, pdir, hist, csum, total;
+    size_t model, counters0, counters1, dlist, dcount, stats, own, ref, check, mirror, pdir, hist, csum, total;
     cpm::TileGeometry tg;
     bool mirror_on;
     int32_t dlist_cap;
@@ -146,11 +152,13 @@ constexpr size_t kLdsLimit = 160 * 1024;  // LDS per workgroup on gfx950
 // Tile geometry for layout L (0 = halo boxes, 1 = full rows, 2 = in place;
 // -1 = choose), honouring the requested tile (p->tile, 0 = choose).  Returns
 // false when the layout cannot run this model.
-bool tile_geometry(const cpm_params *p, bool mirror, int force_layout, cpm::TileGeometry &g)
+// act_in_word: the stored words carry the activity, so no activity array is
+// staged next to them.
+bool tile_geometry(const cpm_params *p, bool mirror, int force_layout, cpm::TileGeometry &g, bool act_in_word = false)
 {
     g = cpm::TileGeometry{};
     const int s = p->sub, R = p->act_enabled ? 2 : 1;
-    const bool act = p->act_enabled != 0;
+    const bool act = p->act_enabled != 0 && !act_in_word;  // an activity array staged in LDS
     const int cell = mirror ? 2 : 4;
     int na[3] = {1, 1, 1};
     for (int d = 0; d < p->ndim; ++d) na[d] = p->dims[d] / (2 * s);
@@ -264,11 +272,14 @@ bool tile_geometry(const cpm_params *p, bool mirror, int force_layout, cpm::Tile
 // The layout the parameters ask for (0 in cpm_params = the library's choice).
 int requested_layout(const cpm_params *p) { return p->layout >= 1 && p->layout <= 3 ? p->layout - 1 : -1; }
 
+constexpr size_t kCheckPad = 64;
+
 Layout layout_of(const cpm_params *p, int32_t n_cells, int mirror = -1, int force_layout = -1)
 {
     Layout l{};
     l.mirror_on = mirror < 0 ? use_mirror(p, n_cells) : mirror != 0;
-    tile_geometry(p, l.mirror_on, force_layout >= 0 ? force_layout : requested_layout(p), l.tg);
+    tile_geometry(p, l.mirror_on, force_layout >= 0 ? force_layout : requested_layout(p), l.tg,
+                  !l.mirror_on && use_act_words(p, n_cells));
     l.dlist_cap = l.tg.T[0] * l.tg.T[1] * l.tg.T[2] * p->attempts;
     int64_t n_sites = (int64_t)p->dims[0] * p->dims[1] * p->dims[2];
     size_t off = 0;
@@ -283,7 +294,12 @@ Layout layout_of(const cpm_params *p, int32_t n_cells, int mirror = -1, int forc
     l.dlist = take(2 * sizeof(int4) * (size_t)l.tg.n_tiles * (size_t)l.dlist_cap);
     l.dcount = take(2 * sizeof(int32_t) * (size_t)l.tg.n_tiles);
     l.stats = take(sizeof(uint64_t) * 2 * (size_t)l.tg.n_tiles);
+    // own accepted copies past the first kOwnInRegs of a thread in one activation
+    const size_t spill = p->attempts > cpm::kOwnInRegs ? (size_t)(p->attempts - cpm::kOwnInRegs) : 0;
+    l.own = take(sizeof(int4) * (size_t)l.tg.n_tiles * (size_t)(l.tg.T[0] * l.tg.T[1] * l.tg.T[2]) * spill);
     l.ref = take(sizeof(int32_t) * ((size_t)n_cells + 1));
+    // invariant checks: a flag word (padded to 64 words), then a recount of V and S
+    l.check = take(sizeof(int32_t) * (kCheckPad + 2 * ((size_t)n_cells + 1)));
     l.mirror = take(l.mirror_on ? sizeof(uint16_t) * (size_t)n_sites : 0);
     const bool pers = p->lambda_persistence != nullptr;
     const size_t labels = (size_t)n_cells + 1;
@@ -348,7 +364,7 @@ int validate(const cpm_params *p, int32_t n_cells)
         if (p->ndim == 2 && p->tile[2] > 1) return fail(CPM_EINVAL, "tile[2] must be 0 or 1 in 2D");
         if (p->layout >= 2 && p->attempts != 1) return fail(CPM_ENOTSUP, "layouts 2 and 3 need attempts == 1");
         cpm::TileGeometry g;
-        if (!tile_geometry(p, use_mirror(p, n_cells), requested_layout(p), g))
+        if (!tile_geometry(p, use_mirror(p, n_cells), requested_layout(p), g, use_act_words(p, n_cells)))
             return fail(CPM_ENOTSUP, "the requested layout / tile does not fit this model");
     }
     const int n = p->n_types;
@@ -417,7 +433,6 @@ int validate(const cpm_params *p, int32_t n_cells)
         if (bound + 65536.0 * 6.0 * lcmax >= 4.0e18) return fail(CPM_ERANGE, "fixed-point energy change could overflow int64");
     }
     if (table_length(p->temperature) > cpm::kMaxTI) return fail(CPM_ENOTSUP, "temperature too high for the threshold table");
-    if (p->attempts > cpm::kMaxAttempts) return fail(CPM_ENOTSUP, "the library runs at most 8 attempts per activation");
     return CPM_OK;
 }
 
@@ -502,6 +517,7 @@ void fill_args(SweepArgs &a, const cpm_params *p, const Layout &lay, char *ws, i
     a.dcount[0] = reinterpret_cast<int32_t *>(ws + lay.dcount);
     a.dcount[1] = a.dcount[0] + lay.tg.n_tiles;
     a.stats = reinterpret_cast<uint64_t *>(ws + lay.stats);
+    a.own_spill = p->attempts > cpm::kOwnInRegs ? reinterpret_cast<int4 *>(ws + lay.own) : nullptr;
     uint32_t n_areas = 1;
     for (int d = 0; d < 3; ++d) {
         a.L[d] = p->dims[d];
@@ -538,6 +554,19 @@ hipError_t start_lattice(const SweepArgs &a, const Layout &lay, char *ws, const 
 }
 
 hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Number of sites of an int32 lattice labelled outside [-1, n_cells] (or -1
+// without an obstacle type), counted on the device into *flag and read back
+// (waits for the stream).
+hipError_t count_bad_labels(const int32_t *lat, size_t n_sites, int32_t n_cells, bool obstacles, int32_t *flag,
+                            hipStream_t st, int32_t *bad)
+{
+    hipError_t e = cpm::launch_fill_i32(flag, 0, 1, st);
+    if (e == hipSuccess) e = cpm::launch_bad_labels(lat, n_sites, n_cells, obstacles, flag, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(bad, flag, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    return e;
+}
 
 // Persistence directions after update t (t = 0: initialisation) from the
 // current lattice: centroid sums, then one thread per cell.
@@ -616,6 +645,12 @@ int cpm_init(const cpm_params *params, int32_t *d_lattice, const int32_t *d_cell
     if ((rc = check_types(params, types.data(), n_cells, &single)) != CPM_OK) return rc;
 
     char *ws = static_cast<char *>(d_workspace);
+    const size_t n_sites = (size_t)params->dims[0] * params->dims[1] * params->dims[2];
+    int32_t n_bad = 0;
+    if ((e = count_bad_labels(d_lattice, n_sites, n_cells, params->obstacle_type >= 0,
+                              reinterpret_cast<int32_t *>(ws + lay.check), st, &n_bad)) != hipSuccess)
+        return device_fail(e, "check labels");
+    if (n_bad) return fail(CPM_EINVAL, "lattice labels must lie in [-1, n_cells], -1 only with an obstacle type");
     h->ndim = params->ndim;
     for (int d = 0; d < 3; ++d) h->L[d] = params->dims[d];
     h->s = params->sub;
@@ -626,6 +661,8 @@ int cpm_init(const cpm_params *params, int32_t *d_lattice, const int32_t *d_cell
     h->mirror = lay.mirror_on;
     h->mirror_cells = lay.mirror_on ? reinterpret_cast<uint16_t *>(ws + lay.mirror) : nullptr;
     h->ref = reinterpret_cast<int32_t *>(ws + lay.ref);
+    h->check = reinterpret_cast<int32_t *>(ws + lay.check);
+    h->obstacles = params->obstacle_type >= 0;
     fill_args(h->args, params, lay, ws, d_lattice, d_cell_type, d_act, single);
     if (params->lambda_persistence) {
         h->pdir = reinterpret_cast<int4 *>(ws + lay.pdir);
@@ -768,6 +805,31 @@ int cpm_counters(cpm_handle *h, int32_t *d_volume, int32_t *d_surface, void *str
     return CPM_OK;
 }
 
+int cpm_check_invariants(cpm_handle *h, void *stream, int32_t *h_ok)
+{
+    if (!h || !h_ok) return fail(CPM_EINVAL, "NULL argument");
+    *h_ok = 0;
+    hipStream_t st = as_stream(stream);
+    const size_t n_sites = (size_t)h->L[0] * h->L[1] * h->L[2];
+    const size_t labels = (size_t)h->n_cells + 1;
+    int32_t *flag = h->check, *rv = h->check + kCheckPad, *rs = rv + labels;
+    int32_t bad = 0;
+    // labels first: the recount indexes its outputs by label
+    hipError_t e = count_bad_labels(h->args.lat, n_sites, h->n_cells, h->obstacles, flag, st, &bad);
+    if (e != hipSuccess) return device_fail(e, "check labels");
+    if (bad) return CPM_OK;
+    if ((e = cpm::launch_fill_i32(rv, 0, 2 * labels, st)) == hipSuccess &&
+        (e = cpm::launch_count(h->args, h->ndim, rv, rs, 1, st)) == hipSuccess &&
+        (e = cpm::launch_fill_i32(flag, 0, 1, st)) == hipSuccess &&
+        (e = cpm::launch_compare_counters(h->args.counters[h->activation & 1], rv, rs, (int32_t)labels, flag, st)) ==
+            hipSuccess &&
+        (e = hipMemcpyAsync(&bad, flag, sizeof(int32_t), hipMemcpyDeviceToHost, st)) == hipSuccess)
+        e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return device_fail(e, "check counters");
+    *h_ok = bad == 0 ? 1 : 0;
+    return CPM_OK;
+}
+
 int cpm_set_mcs(cpm_handle *h, uint64_t mcs)
 {
     if (!h) return fail(CPM_EINVAL, "handle is NULL");
@@ -817,6 +879,8 @@ struct BatchLayout {
     int grid;
     bool mirror, feasible;
     bool act_words;
+    bool act16_ok;             // every lattice fits 16-bit label-activity words
+    size_t words16;            // their region: one uint16 per site of the batch
     int layout;
 };
 
@@ -844,6 +908,14 @@ BatchLayout batch_layout_of(const cpm_params *p, int32_t n, const int32_t *n_cel
     b.act_words = true;
     for (int32_t i = 0; i < n; ++i) b.act_words = b.act_words && use_act_words(&p[i], n_cells[i]);
     b.mirror = !b.act_words;
+    // Act batches of small lattices (at most 2,046 cells, Max_act <= 31, no
+    // chemotaxis) sweep on 16-bit label-activity words when their cells are
+    // of one type (known at init), halving the bytes per site
+    b.act16_ok = b.act_words;
+    for (int32_t i = 0; i < n && b.act16_ok; ++i) {
+        b.act16_ok = n_cells[i] <= cpm::kMaxAct16Cells && p[i].lambda_chemotaxis == nullptr;
+        for (int t = 0; t < p[i].n_types && b.act16_ok; ++t) b.act16_ok = p[i].max_act[t] <= cpm::kMaxAct16Activity;
+    }
     for (int32_t i = 0; i < n; ++i) b.mirror = b.mirror && use_mirror(n_cells[i]);
     // one kernel variant for the whole batch: the layout every lattice
     // chooses, else halo boxes (valid for all)
@@ -856,10 +928,12 @@ BatchLayout batch_layout_of(const cpm_params *p, int32_t n, const int32_t *n_cel
         for (int32_t i = 0; i < n; ++i) b.lat[i] = layout_of(&p[i], n_cells[i], b.mirror ? 1 : 0, 0);
     for (int32_t i = 0; i < n; ++i) {
         cpm::TileGeometry g;
-        b.feasible = b.feasible && tile_geometry(&p[i], b.mirror, b.layout, g);
+        b.feasible = b.feasible && tile_geometry(&p[i], b.mirror, b.layout, g, b.act_words);
     }
+    // workgroups: every (lattice, tile) pair, padded to a multiple of the XCD count
     b.grid = 0;
     for (const Layout &l : b.lat) b.grid += l.tg.n_tiles;
+    b.grid = (b.grid + cpm::kXcds - 1) / cpm::kXcds * cpm::kXcds;
     size_t off = 0;
     b.args = off;
     off = align_up(off + sizeof(SweepArgs) * (size_t)n);
@@ -881,6 +955,10 @@ BatchLayout batch_layout_of(const cpm_params *p, int32_t n, const int32_t *n_cel
     off = align_up(off + sizeof(int64_t) * 3 * b.total_labels);
     b.scratch_ref = off;
     off = align_up(off + sizeof(int32_t) * b.total_labels);
+    size_t total_sites = 0;
+    for (int32_t i = 0; i < n; ++i) total_sites += (size_t)p[i].dims[0] * p[i].dims[1] * p[i].dims[2];
+    b.words16 = off;
+    off = align_up(off + (b.act16_ok ? sizeof(uint16_t) * total_sites : 0));
     for (const Layout &l : b.lat) {
         b.base.push_back(off);
         off = align_up(off + l.total);
@@ -952,6 +1030,21 @@ int cpm_batch_init(const cpm_params *params, int32_t n, const int32_t *n_cells, 
     if (e != hipSuccess) return device_fail(e, "read cell types");
 
     char *ws = static_cast<char *>(d_workspace);
+    // every label in range before the first recount indexes counters by it
+    {
+        int32_t *flag = reinterpret_cast<int32_t *>(ws + bl.base[0] + bl.lat[0].check);
+        int32_t n_bad = 0;
+        e = cpm::launch_fill_i32(flag, 0, 1, st);
+        for (int32_t i = 0; i < n && e == hipSuccess; ++i)
+            e = cpm::launch_bad_labels(d_lattices + b->site_off[i],
+                                       (size_t)params[i].dims[0] * params[i].dims[1] * params[i].dims[2], n_cells[i],
+                                       params[i].obstacle_type >= 0, flag, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(&n_bad, flag, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return device_fail(e, "check labels");
+        if (n_bad)
+            return fail(CPM_EINVAL, "lattice labels must lie in [-1, n_cells], -1 only with an obstacle type");
+    }
     b->single = true;
     size_t lds = 0;
     for (int32_t i = 0; i < n; ++i) {
@@ -965,6 +1058,8 @@ int cpm_batch_init(const cpm_params *params, int32_t n, const int32_t *n_cells, 
                   b->act ? d_act + b->site_off[i] : nullptr, single);
         b->args.push_back(a);
         b->ref.push_back(reinterpret_cast<int32_t *>(lws + lay.ref));
+        b->check.push_back(reinterpret_cast<int32_t *>(lws + lay.check));
+        b->obstacles.push_back(params[i].obstacle_type >= 0 ? 1 : 0);
         b->mirror_cells.push_back(lay.mirror_on ? reinterpret_cast<uint16_t *>(lws + lay.mirror) : nullptr);
         b->models.emplace_back(new (std::nothrow) DeviceModel);
         if (!b->models.back()) return fail(CPM_EINVAL, "host allocation failed");
@@ -977,6 +1072,31 @@ int cpm_batch_init(const cpm_params *params, int32_t n, const int32_t *n_cells, 
     b->d_args = reinterpret_cast<SweepArgs *>(ws + bl.args);
     b->d_work = reinterpret_cast<int2 *>(ws + bl.work);
     b->d_mcs = reinterpret_cast<uint32_t *>(ws + bl.mcs);
+    // one cell type throughout and small lattices: 16-bit label-activity words
+    b->act16 = bl.act16_ok && b->single;
+    if (b->act16) {
+        b->words16 = reinterpret_cast<uint16_t *>(ws + bl.words16);
+        b->act_words = false;
+        for (int32_t i = 0; i < n; ++i) {
+            SweepArgs &a = b->args[i];
+            a.cells = b->words16 + b->site_off[i];
+            a.tg.row_chunk = chunk_for(a.cells, (size_t)a.L[0] * sizeof(uint16_t));
+        }
+    }
+    // Workgroups go to the XCDs round-robin: workgroup g takes entry
+    // (g mod 8) * (grid / 8) + g div 8 of the (lattice, tile) list, so each
+    // XCD sweeps one contiguous run of it and neighbouring tiles of a
+    // lattice, whose halos overlap, share that XCD's L2.  Padding entries
+    // are (-1, -1).
+    {
+        const size_t grid = (size_t)bl.grid, per = grid / cpm::kXcds;
+        std::vector<int2> order(grid, make_int2(-1, -1));
+        for (size_t g = 0; g < grid; ++g) {
+            const size_t src = (g % cpm::kXcds) * per + g / cpm::kXcds;
+            if (src < b->work.size()) order[g] = b->work[src];
+        }
+        b->work.swap(order);
+    }
     e = hipMemcpyAsync(b->d_args, b->args.data(), sizeof(SweepArgs) * (size_t)n, hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->d_work, b->work.data(), sizeof(int2) * b->work.size(), hipMemcpyHostToDevice, st);
@@ -1008,6 +1128,7 @@ int cpm_batch_init(const cpm_params *params, int32_t n, const int32_t *n_cells, 
     L.single = b->single;
     L.k1 = b->k == 1;
     L.act_words = b->act_words;
+    L.act16 = b->act16;
     L.ext = false;
     for (const SweepArgs &a : b->args) L.ext = L.ext || a.chem != nullptr;
     L.layout = b->layout;
@@ -1027,8 +1148,9 @@ hipError_t enqueue_mcs(const cpm_batch *b, uint32_t n_act, hipStream_t st)
     for (uint32_t alpha = 0; alpha < n_act; ++alpha)
         if ((e = cpm::launch_batch_activation(b->launch, alpha, (int)(alpha & 1), st)) != hipSuccess) return e;
     if (b->act) {
-        e = b->act_words ? cpm::launch_act_decay_words(b->lattices, b->total_sites, st)
-                         : cpm::launch_act_decay(b->act_field, b->total_sites, st);
+        e = b->act16       ? cpm::launch_act16_decay(b->words16, b->total_sites, st)
+            : b->act_words ? cpm::launch_act_decay_words(b->lattices, b->total_sites, st)
+                           : cpm::launch_act_decay(b->act_field, b->total_sites, st);
         if (e != hipSuccess) return e;
     }
     return cpm::launch_add_u32(b->d_mcs, 1u, st);
@@ -1074,6 +1196,8 @@ int cpm_batch_sweep(cpm_batch *b, int32_t n_mcs, void *stream)
         return device_fail(e, "to 16-bit working copy");
     if (b->act_words && (e = cpm::launch_batch_act_words(b->d_args, b->n, b->max_sites, true, st)) != hipSuccess)
         return device_fail(e, "to label-type-activity words");
+    if (b->act16 && (e = cpm::launch_to_act16(b->lattices, b->act_field, b->words16, b->total_sites, st)) != hipSuccess)
+        return device_fail(e, "to 16-bit label-activity words");
     if ((e = cpm::launch_set_u32(b->d_mcs, (uint32_t)b->mcs, st)) != hipSuccess) return device_fail(e, "set mcs");
     for (int32_t m = 0; m < n_mcs; ++m) {
         e = b->use_graph ? hipGraphLaunch(b->mcs_graph, st) : enqueue_mcs(b, n_act, st);
@@ -1086,6 +1210,8 @@ int cpm_batch_sweep(cpm_batch *b, int32_t n_mcs, void *stream)
         return device_fail(e, "from 16-bit working copy");
     if (b->act_words && (e = cpm::launch_batch_act_words(b->d_args, b->n, b->max_sites, false, st)) != hipSuccess)
         return device_fail(e, "from label-type-activity words");
+    if (b->act16 && (e = cpm::launch_from_act16(b->words16, b->lattices, b->act_field, b->total_sites, st)) != hipSuccess)
+        return device_fail(e, "from 16-bit label-activity words");
     return CPM_OK;
 }
 
@@ -1208,6 +1334,44 @@ int cpm_batch_autocorrelation(cpm_batch *b, const double *d_samples, int32_t n_s
     if (n_samples < 2) return fail(CPM_EINVAL, "need at least two samples");
     const hipError_t e = cpm::launch_autocorrelation(b->stats_tables, d_samples, n_samples, d_out, as_stream(stream));
     return e == hipSuccess ? CPM_OK : device_fail(e, "autocorrelation");
+}
+
+int cpm_batch_check_invariants(cpm_batch *b, void *stream, int32_t *h_ok)
+{
+    if (!b || !h_ok) return fail(CPM_EINVAL, "NULL argument");
+    hipStream_t st = as_stream(stream);
+    const int32_t n = b->n;
+    std::vector<int32_t> bad((size_t)n, 0);
+    auto sites = [&](int32_t i) { return (size_t)b->args[i].L[0] * b->args[i].L[1] * b->args[i].L[2]; };
+    auto read_flags = [&]() {
+        hipError_t e = hipSuccess;
+        for (int32_t i = 0; i < n && e == hipSuccess; ++i)
+            e = hipMemcpyAsync(&bad[i], b->check[i], sizeof(int32_t), hipMemcpyDeviceToHost, st);
+        return e == hipSuccess ? hipStreamSynchronize(st) : e;
+    };
+    hipError_t e = hipSuccess;
+    for (int32_t i = 0; i < n && e == hipSuccess; ++i) {
+        h_ok[i] = 0;
+        if ((e = cpm::launch_fill_i32(b->check[i], 0, 1, st)) == hipSuccess)
+            e = cpm::launch_bad_labels(b->args[i].lat, sites(i), b->n_cells[i], b->obstacles[i] != 0, b->check[i], st);
+    }
+    if (e == hipSuccess) e = read_flags();
+    if (e != hipSuccess) return device_fail(e, "check labels");
+    std::vector<uint8_t> labels_ok((size_t)n);
+    for (int32_t i = 0; i < n; ++i) labels_ok[i] = bad[i] == 0;
+    const int parity = (int)(b->activation & 1);
+    for (int32_t i = 0; i < n && e == hipSuccess; ++i) {
+        if (!labels_ok[i]) continue;  // the recount indexes its outputs by label
+        const size_t labels = (size_t)b->n_cells[i] + 1;
+        int32_t *rv = b->check[i] + kCheckPad, *rs = rv + labels;
+        if ((e = cpm::launch_fill_i32(rv, 0, 2 * labels, st)) == hipSuccess &&
+            (e = cpm::launch_count(b->args[i], b->ndim, rv, rs, 1, st)) == hipSuccess)
+            e = cpm::launch_compare_counters(b->args[i].counters[parity], rv, rs, (int32_t)labels, b->check[i], st);
+    }
+    if (e == hipSuccess) e = read_flags();
+    if (e != hipSuccess) return device_fail(e, "check counters");
+    for (int32_t i = 0; i < n; ++i) h_ok[i] = labels_ok[i] && bad[i] == 0 ? 1 : 0;
+    return CPM_OK;
 }
 
 int cpm_batch_set_mcs(cpm_batch *b, uint64_t mcs)

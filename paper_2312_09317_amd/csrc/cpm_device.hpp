@@ -53,6 +53,32 @@ __device__ __forceinline__ char32_t act_word(int label, int type, uint32_t act)
     return (char32_t)((uint32_t)(label + 1) | ((uint32_t)type << 20) | (act << 24));
 }
 
+// 16-bit label-activity words (char16_t; Act batches whose lattices hold at
+// most 2,046 cells of one type, Max_act <= 31): label + 1 in bits 0..10, the
+// site's activity in bits 11..15.
+__device__ __forceinline__ int label_of(char16_t v) { return (int)((uint32_t)v & 0x7FFu) - 1; }
+
+// Where a stored word keeps the site's activity (kIn): bits kShift and up,
+// the rest (kKeep) being label and type.
+template <typename Cell>
+struct WordAct {
+    static constexpr bool kIn = false;
+    static constexpr int kShift = 0;
+    static constexpr uint32_t kKeep = 0xFFFFFFFFu;
+};
+template <>
+struct WordAct<char32_t> {
+    static constexpr bool kIn = true;
+    static constexpr int kShift = 24;
+    static constexpr uint32_t kKeep = 0xFFFFFFu;
+};
+template <>
+struct WordAct<char16_t> {
+    static constexpr bool kIn = true;
+    static constexpr int kShift = 11;
+    static constexpr uint32_t kKeep = 0x7FFu;
+};
+
 // Activity of LDS / lattice index i: from the word, or from the activity array.
 template <typename Cell>
 __device__ __forceinline__ uint32_t act_at(const Cell *lab, const uint8_t *lact, int i) { return lact[i]; }
@@ -60,6 +86,11 @@ template <>
 __device__ __forceinline__ uint32_t act_at<char32_t>(const char32_t *lab, const uint8_t *, int i)
 {
     return (uint32_t)lab[i] >> 24;
+}
+template <>
+__device__ __forceinline__ uint32_t act_at<char16_t>(const char16_t *lab, const uint8_t *, int i)
+{
+    return (uint32_t)lab[i] >> 11;
 }
 
 // Cell type of a site from its stored word (`label` = label_of(word)).
@@ -73,6 +104,10 @@ __device__ __forceinline__ int type_of_word(const SweepArgs &a, int32_t, int lab
     return label < 0 ? a.obstacle_type : a.cell_type[label];
 }
 __device__ __forceinline__ int type_of_word(const SweepArgs &a, uint16_t, int label)
+{
+    return label < 0 ? a.obstacle_type : a.cell_type[label];
+}
+__device__ __forceinline__ int type_of_word(const SweepArgs &a, char16_t, int label)
 {
     return label < 0 ? a.obstacle_type : a.cell_type[label];
 }

@@ -10,9 +10,16 @@ namespace cpm {
 
 constexpr int kMaxTypes = 16;
 constexpr int kMaxTI = 4096;  // TI entries: enough for T up to ~184
-constexpr int kMaxAttempts = 8;
+// A thread keeps the records of its own accepted copies of one activation
+// (the deltas its later attempts see) in registers, up to kOwnInRegs of
+// them; with more attempts per activation (k > kOwnInRegs) the rest go to a
+// per-thread-area spill array in the workspace.
+constexpr int kOwnInRegs = 8;
 constexpr int kBlock = 256;   // threads per sweep workgroup (one per thread area)
 constexpr int kXcds = 8;      // MI355X: workgroups go round-robin to 8 XCDs, each with its own L2
+// 16-bit label-activity words: label + 1 in 11 bits, activity in 5
+constexpr int kMaxAct16Cells = 2046;
+constexpr int kMaxAct16Activity = 31;
 
 // Records msg as the calling thread's last error (cpm_last_error) and returns code.
 int report_error(int code, const char *msg);
@@ -82,6 +89,7 @@ struct SweepArgs {
     int4 *dlist[2];        // per tile: accepted copies of an activation, by activation parity
     int32_t *dcount[2];    // per tile: number of records in dlist[parity]
     uint64_t *stats;       // per tile: attempts past the early rejection, accepted copies
+    int4 *own_spill;       // k > kOwnInRegs: per tile and area, k - kOwnInRegs own records; else NULL
     int32_t L[3];
     int32_t na[3];         // thread areas per axis
     uint32_t n_areas;
@@ -106,6 +114,7 @@ struct BatchLaunch {
     bool act, mirror, single, k1;
     bool ext;               // some lattice uses the chemotaxis term
     bool act_words;         // lattices hold label-type-activity words during the sweep
+    bool act16;             // lattices sweep on 16-bit label-activity words (one cell type, no chemotaxis)
     int layout;
 };
 
@@ -159,6 +168,13 @@ hipError_t launch_count(const SweepArgs &a, int ndim, int32_t *v_out, int32_t *s
 enum Words { kWords32 = 0, kWords16 = 1, kWordsPacked = 2, kWordsPackedAct = 3 };
 hipError_t launch_activation(const SweepArgs &a, int ndim, bool act, int words, uint32_t mcs, uint32_t alpha,
                              int parity, hipStream_t stream);
+// The activation kernels for stored words Cell in D dimensions (defined in
+// cpm_sweep_kernels.hpp, instantiated in cpm_sweep_inst.hip).
+template <typename Cell, int D>
+hipError_t sweep_words(const SweepArgs &a, bool act, uint32_t mcs, uint32_t alpha, int parity, size_t lds,
+                       hipStream_t st);
+template <typename Cell, int D>
+hipError_t batch_words(const BatchLaunch &b, uint32_t alpha, int parity, hipStream_t st);
 hipError_t launch_pack(int32_t *lat, const int32_t *cell_type, int obstacle_type, size_t n, hipStream_t stream);
 hipError_t launch_unpack(int32_t *lat, size_t n, hipStream_t stream);
 // The same with the activity in bits 24..31 (label + 1 in 0..19, type in 20..23).
@@ -175,6 +191,12 @@ hipError_t launch_from_mirror(const uint16_t *mirror, int32_t *lat, size_t n, hi
 hipError_t launch_batch_mirror(const SweepArgs *d_args, int n_lattices, size_t max_sites, bool to_mirror,
                                hipStream_t stream);
 hipError_t launch_act_decay(uint8_t *act, size_t n, hipStream_t stream);
+// 16-bit label-activity words of a whole batch (n sites, packed like the
+// int32 lattices): from / to the int32 labels and uint8 activities, and the
+// per-MCS Act decay in the words.
+hipError_t launch_to_act16(const int32_t *lat, const uint8_t *act, uint16_t *words, size_t n, hipStream_t stream);
+hipError_t launch_from_act16(const uint16_t *words, int32_t *lat, uint8_t *act, size_t n, hipStream_t stream);
+hipError_t launch_act16_decay(uint16_t *words, size_t n, hipStream_t stream);
 hipError_t launch_centroids(const SweepArgs &a, int ndim, int32_t n_cells, int32_t *ref,
                             int64_t *out, hipStream_t stream, int words = kWords32);
 // Persistence directions (x, y, z of each int4) into out, 3 x n_labels int32.
@@ -183,6 +205,14 @@ hipError_t launch_copy_counters(const int32_t *pairs, int32_t n_labels, int32_t 
                                 int32_t *s_out, hipStream_t stream);
 hipError_t launch_batch_activation(const BatchLaunch &b, uint32_t alpha, int parity, hipStream_t stream);
 hipError_t launch_set_u32(uint32_t *p, uint32_t value, hipStream_t stream);
+// Adds to *bad the number of sites of an int32 lattice labelled outside
+// [-1, n_cells] (or -1 when !allow_obstacle).
+hipError_t launch_bad_labels(const int32_t *lat, size_t n, int32_t n_cells, bool allow_obstacle, int32_t *bad,
+                             hipStream_t stream);
+// Adds to *bad the number of labels 1..n_labels-1 whose (V, S) pair in
+// `pairs` differs from v[label], s[label].
+hipError_t launch_compare_counters(const int32_t *pairs, const int32_t *v, const int32_t *s, int32_t n_labels,
+                                   int32_t *bad, hipStream_t stream);
 hipError_t launch_add_u32(uint32_t *p, uint32_t value, hipStream_t stream);
 hipError_t launch_sample(const StatsTables &t, const int32_t *vol, const int32_t *surf, const int64_t *csum,
                          double *samples, int k, int n_samples, hipStream_t stream);

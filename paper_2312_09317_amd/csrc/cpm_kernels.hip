@@ -1,5 +1,6 @@
 // HIP kernels around the sweep: counting volumes / surfaces from the lattice,
 // centroid sums, activity decay, fills and counter copies.
+#include <algorithm>
 #include <type_traits>
 
 #include "cpm_device.hpp"
@@ -391,6 +392,31 @@ __global__ void copy_counters_kernel(const int32_t *pairs, int32_t n_labels, int
     s_out[i] = i == 0 ? 0 : pairs[2 * i + 1];
 }
 
+// Sites whose label lies outside [-1, n_cells], or is an obstacle (-1) in a
+// model without an obstacle type: counted into *bad (one atomic per wave).
+__global__ void __launch_bounds__(kBlock) bad_label_kernel(const int32_t *lat, size_t n, int32_t n_cells,
+                                                           int allow_obstacle, int32_t *bad)
+{
+    const int lo = allow_obstacle ? -1 : 0;
+    int cnt = 0;
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
+        const int v = lat[i];
+        cnt += v < lo || v > n_cells;
+    }
+    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+    if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(bad, cnt);
+}
+
+// Labels 1..n_labels-1 whose tracked (V, S) pair differs from the recount
+// (v, s): counted into *bad.
+__global__ void compare_counters_kernel(const int32_t *pairs, const int32_t *v, const int32_t *s, int32_t n_labels,
+                                        int32_t *bad)
+{
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < 1 || i >= n_labels) return;
+    if (pairs[2 * i] != v[i] || pairs[2 * i + 1] != s[i]) atomicAdd(bad, 1);
+}
+
 __global__ void set_u32_kernel(uint32_t *p, uint32_t v) { *p = v; }
 __global__ void add_u32_kernel(uint32_t *p, uint32_t v) { *p += v; }
 
@@ -542,6 +568,22 @@ hipError_t launch_copy_counters(const int32_t *pairs, int32_t n_labels, int32_t 
                                 hipStream_t stream)
 {
     copy_counters_kernel<<<blocks_for((size_t)n_labels), kBlock, 0, stream>>>(pairs, n_labels, v_out, s_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_bad_labels(const int32_t *lat, size_t n, int32_t n_cells, bool allow_obstacle, int32_t *bad,
+                             hipStream_t stream)
+{
+    if (n == 0) return hipSuccess;
+    const unsigned grid = std::min<unsigned>(blocks_for(n), 4096u);
+    bad_label_kernel<<<grid, kBlock, 0, stream>>>(lat, n, n_cells, allow_obstacle ? 1 : 0, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_compare_counters(const int32_t *pairs, const int32_t *v, const int32_t *s, int32_t n_labels,
+                                   int32_t *bad, hipStream_t stream)
+{
+    compare_counters_kernel<<<blocks_for((size_t)n_labels), kBlock, 0, stream>>>(pairs, v, s, n_labels, bad);
     return hipGetLastError();
 }
 

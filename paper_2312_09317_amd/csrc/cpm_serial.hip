@@ -12,6 +12,8 @@
 // load of data the kernel writes (labels, activity, counters) has a
 // lane-dependent address, so it is a vector load that sees the wave's earlier
 // stores; lane 0 commits.
+#include <type_traits>
+
 #include "cpm_device.hpp"
 
 namespace cpm {
@@ -50,7 +52,9 @@ __global__ void __launch_bounds__(64) serial_mcs_kernel(const SweepArgs *args, u
     const int half = lane >> 5, hl = lane & 31;
     const int L[3] = {a.L[0], a.L[1], a.L[2]};
     const uint32_t N = (uint32_t)L[0] * (uint32_t)L[1] * (uint32_t)L[2];
-    Cell *cells = reinterpret_cast<Cell *>(a.cells);
+    // int32 labels: the caller's lattice itself (a batch may keep other words
+    // for its parallel sweeps in a.cells)
+    Cell *cells = std::is_same<Cell, int32_t>::value ? reinterpret_cast<Cell *>(a.lat) : reinterpret_cast<Cell *>(a.cells);
     int32_t *cnt = a.counters[parity];
     const ThrTables tb{m->TM32, m->TL32, m->TI32, m->n_ti};
     uint32_t n_nontrivial = 0, n_accepted = 0;

@@ -1,0 +1,806 @@
+#pragma once
+// The activation kernel of the CPM sweep for gfx950 (templates; instantiated
+// per stored-word type and dimension in cpm_sweep_inst.hip).
+//
+// One launch runs one activation of the checkerboard scheme (paper, Results,
+// "Designing a parallel execution scheme", Fig. 2A; one barrier per copy
+// attempt, Fig. 3A): every thread area makes k copy attempts inside its
+// sub-area of the active colour.
+//
+// Work split: one workgroup per tile of up to 256 thread areas (one thread
+// per area).  The tile's active sub-areas plus their read halo are staged
+// into LDS with coalesced loads (paper, Methods, "GPU implementation
+// details": shared-memory caching of the active regions, write-through on
+// accepted copies).  Two LDS layouts:
+//   full rows - the tile spans whole lattice rows along x; each LDS row holds
+//               one whole lattice row, copied with aligned 16-byte loads, and
+//               neighbours wrap around x inside LDS;
+//   box       - any tile shape; the staged box is the tile's sub-areas plus
+//               the halo, copied element by element.
+// Tiles go to XCDs in contiguous slabs (workgroups are dispatched to the 8
+// XCDs round-robin), so every activation of a sweep finds the XCD's slab in
+// the same L2.
+//
+// For k = 1 the copy attempts of a workgroup run in two phases: all threads
+// draw their attempt and drop the trivial ones (equal labels or an
+// obstacle); the rest are compacted into an LDS queue and worked off by the
+// first threads, so the energy evaluation runs on as few waves as needed.
+//
+// Per-cell counters are double buffered: activation g reads buffer g&1 (the
+// exact state at its start) and adds its own deltas plus those of activation
+// g-1 (kept per tile in `dlist`) into buffer (g+1)&1, which so becomes the
+// exact state at the start of g+1.
+#include <algorithm>
+#include <type_traits>
+
+#include "cpm_device.hpp"
+
+namespace cpm {
+namespace {
+
+__device__ __forceinline__ void add_deltas(int32_t *wr, int4 d)
+{
+    if (d.x >= 1) {
+        atomicAdd(&wr[2 * d.x], -1);
+        atomicAdd(&wr[2 * d.x + 1], d.z);
+    }
+    if (d.y >= 1) {
+        atomicAdd(&wr[2 * d.y], 1);
+        atomicAdd(&wr[2 * d.y + 1], d.w);
+    }
+}
+
+__host__ __device__ constexpr int align16(int v) { return (v + 15) & ~15; }
+
+constexpr int kQueue = 128;  // queued attempts per workgroup; the rest are evaluated where drawn
+
+// Where the sites an attempt reads live.  kBox: an LDS box, coordinates
+// box-local; kFullRow: LDS rows spanning the lattice along x, x global and
+// wrapping, y, z box-local; kDirect: the lattice itself in global memory,
+// every coordinate global and wrapping.
+enum Layout { kBox = 0, kFullRow = 1, kDirect = 2 };
+
+template <int LAYOUT>
+struct LdsMap {
+    int pitch;  // sites per row
+    int rows;   // rows per z plane
+    int L0, L1, L2;
+    __device__ __forceinline__ int x(int v) const { return LAYOUT == kBox ? v : wrap_once(v, L0); }
+    __device__ __forceinline__ int row(int vy, int vz) const
+    {
+        return LAYOUT == kDirect ? L0 * (wrap_once(vy, L1) + L1 * wrap_once(vz, L2)) : pitch * (vy + rows * vz);
+    }
+    __device__ __forceinline__ int at(int vx, int vy, int vz) const { return x(vx) + row(vy, vz); }
+};
+
+// Geometric mean of the activity over the site at (x,y,z) (label `cell`) and
+// its Moore neighbours of the same cell (eq. 8), 2^16 fixed point.
+template <typename Cell, int D, int LAYOUT>
+__device__ __forceinline__ int64_t gm_lds(const DeviceModel *m, const int64_t *lg, const Cell *lab,
+                                          const uint8_t *lact, const LdsMap<LAYOUT> &map, int x, int y, int z,
+                                          int cell, bool motile)
+{
+    if (cell <= 0 || !motile) return 0;
+    const int c = map.at(x, y, z);
+    const uint32_t a0 = act_at(lab, lact, c);
+    uint64_t sum = (uint64_t)lg[a0];
+    uint32_t cnt = 1;
+    bool zero = a0 == 0;
+    constexpr int NNB = D == 2 ? 8 : 26;
+    // every label and activity of the neighbourhood is loaded before any is
+    // used, so the in-place layout reads them in one round
+#pragma unroll
+    for (int n = 0; n < NNB; ++n) {
+        const int u = map.at(x + nb_dx<D>(n), y + nb_dy<D>(n), z + nb_dz<D>(n));
+        const int lu = label_of(lab[u]);
+        const uint32_t au = act_at(lab, lact, u);
+        if (lu == cell) {
+            zero |= au == 0;
+            sum += (uint64_t)lg[au];
+            ++cnt;
+        }
+    }
+    return zero ? 0 : exp_log24(m, sum / cnt);
+}
+
+// J rows of the medium type and of the single cell type (when all cells share one type).
+struct JRows {
+    int64_t cc, cm, co, mc, mm, mo;
+};
+
+// One copy attempt past the early rejection: energy change of copying label
+// ls into the target (x,y,z) (eq. 1, eq. 3, eq. 7) and the Metropolis test
+// (eq. 2).  cnt_t / cnt_s are the (V, S) counters of the two cells as the
+// attempt sees them.  Returns acceptance; dso / dsn are the surface deltas.
+// Per-workgroup LDS copies of the model tables the energy change reads per
+// neighbour: J (multi-type models) and the Act log table.
+struct SharedTables {
+    const int64_t *J;
+    const int64_t *lg;
+};
+
+// nbl(n) gives the label of the target's n-th Moore neighbour.
+template <typename Cell, int D, bool ACT, bool SINGLE, int LAYOUT, bool EXT, typename NB>
+__device__ __forceinline__ bool evaluate_nb(const SweepArgs &a, const ThrTables &tb, const JRows &jr,
+                                            const SharedTables &st, const NB &nbl, Cell *lab, uint8_t *lact,
+                                            const LdsMap<LAYOUT> &map, int tx_, int ty_, int tz_, int sx_, int sy_,
+                                            int sz_, int src_gi, int lt, int ls, int tt, int ts, int2 cnt_t, int2 cnt_s,
+                                            uint32_t u2, int64_t &dso_out, int64_t &dsn_out)
+{
+    constexpr int NNB = D == 2 ? 8 : 26;
+    const DeviceModel *m = a.model;
+    int k_old = 0, k_new = 0;
+    int n_cell = 0, n_med = 0, n_obs = 0;
+    int64_t adh = 0;
+#pragma unroll
+    for (int n = 0; n < NNB; ++n) {
+        const Cell word = nbl(n);
+        const int lu = label_of(word);
+        k_old += lu == lt;
+        k_new += lu == ls;
+        if (SINGLE) {
+            n_cell += lu > 0;
+            n_med += lu == 0;
+            n_obs += lu < 0;
+        } else {
+            const int tu = type_of_word(a, word, lu);
+            if (lu != ls) adh += st.J[ts * kMaxTypes + tu];
+            if (lu != lt) adh -= st.J[tt * kMaxTypes + tu];
+        }
+    }
+    if (SINGLE) {
+        // neighbours unlike the label, weighted by J(label type, their type)
+        const int64_t cs = n_cell - (ls > 0 ? k_new : 0), ms = n_med - (ls == 0 ? k_new : 0);
+        const int64_t ct = n_cell - (lt > 0 ? k_old : 0), mt = n_med - (lt == 0 ? k_old : 0);
+        adh = (ls > 0 ? jr.cc * cs + jr.cm * ms + jr.co * n_obs : jr.mc * cs + jr.mm * ms + jr.mo * n_obs) -
+              (lt > 0 ? jr.cc * ct + jr.cm * mt + jr.co * n_obs : jr.mc * ct + jr.mm * mt + jr.mo * n_obs);
+    }
+    const int64_t dso = 2 * k_old - NNB;
+    const int64_t dsn = NNB - 2 * k_new;
+    int64_t q = adh;
+    if (lt >= 1) {
+        q += m->lam_v[tt] * (1 - 2 * ((int64_t)cnt_t.x - m->v_target[tt]));
+        q += m->lam_s[tt] * (2 * dso * ((int64_t)cnt_t.y - m->s_target[tt]) + dso * dso);
+    }
+    if (ls >= 1) {
+        q += m->lam_v[ts] * (2 * ((int64_t)cnt_s.x - m->v_target[ts]) + 1);
+        q += m->lam_s[ts] * (2 * dsn * ((int64_t)cnt_s.y - m->s_target[ts]) + dsn * dsn);
+    }
+    if (ACT) {
+        const int64_t gt = gm_lds<Cell, D, LAYOUT>(m, st.lg, lab, lact, map, tx_, ty_, tz_, lt,
+                                                    lt > 0 && m->max_act[tt] > 0);
+        const int64_t gs = gm_lds<Cell, D, LAYOUT>(m, st.lg, lab, lact, map, sx_, sy_, sz_, ls,
+                                                    ls > 0 && m->max_act[ts] > 0);
+        const int64_t rt = lt >= 1 ? m->r_act[tt] : 0;
+        const int64_t rs = ls >= 1 ? m->r_act[ts] : 0;
+        q += (rt * gt - rs * gs) >> 16;
+    }
+    if (EXT && a.pdir && ls >= 1) {
+        // persistence: the copying cell ls extends from the source into the
+        // target; copies along its direction are favoured
+        const int o = (tx_ - sx_ + 1) + 3 * (ty_ - sy_ + 1) + 9 * (tz_ - sz_ + 1);
+        const int4 pd = a.pdir[ls];
+        const int64_t dot = (int64_t)m->unit[o][0] * pd.x + (int64_t)m->unit[o][1] * pd.y +
+                            (int64_t)m->unit[o][2] * pd.z;
+        q -= (m->lam_p[ts] * dot) >> 28;
+    }
+    if (EXT && a.chem && ls >= 1) {
+        // chemotaxis: the field at the source, dotted with the copy's direction
+        const int o = (tx_ - sx_ + 1) + 3 * (ty_ - sy_ + 1) + 9 * (tz_ - sz_ + 1);
+        int64_t dot;
+        if (D == 2) {
+            const short2 c = reinterpret_cast<const short2 *>(a.chem)[src_gi];
+            dot = (int64_t)m->unit[o][0] * c.x + (int64_t)m->unit[o][1] * c.y;
+        } else {
+            const int16_t *c = a.chem + 3 * (size_t)src_gi;
+            dot = (int64_t)m->unit[o][0] * c[0] + (int64_t)m->unit[o][1] * c[1] + (int64_t)m->unit[o][2] * c[2];
+        }
+        q -= (m->lam_c[ts] * dot) >> 28;
+    }
+    dso_out = dso;
+    dsn_out = dsn;
+    return metropolis32(tb, q, u2);
+}
+
+// evaluate_nb with the neighbour labels read through `map`.
+template <typename Cell, int D, bool ACT, bool SINGLE, int LAYOUT, bool EXT>
+__device__ __forceinline__ bool evaluate(const SweepArgs &a, const ThrTables &tb, const JRows &jr,
+                                         const SharedTables &st, Cell *lab, uint8_t *lact,
+                                         const LdsMap<LAYOUT> &map, int tx_, int ty_, int tz_, int sx_, int sy_,
+                                         int sz_, int src_gi, int lt, int ls, int tt, int ts, int2 cnt_t, int2 cnt_s,
+                                         uint32_t u2, int64_t &dso_out, int64_t &dsn_out)
+{
+    const int xm = map.x(tx_ - 1), x0 = map.x(tx_), xp = map.x(tx_ + 1);
+    auto nbl = [&](int n) {
+        const int dx = nb_dx<D>(n);
+        const int xx = dx < 0 ? xm : (dx > 0 ? xp : x0);
+        return lab[xx + map.row(ty_ + nb_dy<D>(n), tz_ + nb_dz<D>(n))];
+    };
+    return evaluate_nb<Cell, D, ACT, SINGLE, LAYOUT, EXT>(a, tb, jr, st, nbl, lab, lact, map, tx_, ty_, tz_, sx_, sy_,
+                                                     sz_, src_gi, lt, ls, tt, ts, cnt_t, cnt_s, u2, dso_out, dsn_out);
+}
+
+// Counters of label c as an attempt of this thread sees them: the read
+// buffer plus the deltas of the thread's own earlier accepted copies in this
+// activation (n_own records: the first kOwnInRegs in registers, the rest in
+// its spill array).
+__device__ __forceinline__ int2 seen_counters(const int32_t *rd, int c, const int4 *own, int n_own,
+                                              const int4 *spill = nullptr)
+{
+    if (c < 1) return make_int2(0, 0);
+    int2 v = reinterpret_cast<const int2 *>(rd)[c];
+#pragma unroll
+    for (int jj = 0; jj < kOwnInRegs; ++jj) {
+        if (jj < n_own && own[jj].x == c) { v.x -= 1; v.y += own[jj].z; }
+        if (jj < n_own && own[jj].y == c) { v.x += 1; v.y += own[jj].w; }
+    }
+    for (int jj = kOwnInRegs; jj < n_own; ++jj) {
+        const int4 r = spill[jj - kOwnInRegs];
+        if (r.x == c) { v.x -= 1; v.y += r.z; }
+        if (r.y == c) { v.x += 1; v.y += r.w; }
+    }
+    return v;
+}
+
+// One workgroup's share of one activation: tile `tile` of the lattice `a`.
+template <typename Cell, int D, bool ACT, bool SINGLE, bool K1, int LAYOUT, bool EXT>
+__device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_t mcs, uint32_t alpha, int parity)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int list_n, queue_n;
+    __shared__ uint32_t n_nontrivial, n_accepted;
+    // compacted attempts: packed target / source coordinates and draw, and the
+    // counters (V, S) of both cells fetched while drawing
+    __shared__ int4 queue[K1 ? kQueue : 1];
+    __shared__ int4 queue_cnt[K1 ? kQueue : 1];
+    __shared__ int64_t j_lds[SINGLE ? 1 : kMaxTypes * kMaxTypes];
+    __shared__ int64_t lg_lds[ACT ? 256 : 1];
+    constexpr int R = ACT ? 2 : 1;           // read radius: the Act term reads neighbours of the source
+    constexpr int NNB = D == 2 ? 8 : 26;
+
+    const TileGeometry &tg = a.tg;
+    const int tid = threadIdx.x;
+    const int L0 = a.L[0], L1 = a.L[1], L2 = a.L[2];
+    const int s = a.s;
+    const uint32_t phi = alpha & ((1u << D) - 1);
+    const int cx = (int)(phi & 1), cy = (int)((phi >> 1) & 1), cz = (int)((phi >> 2) & 1);
+    const int tx = tile % tg.nt[0], ty = (tile / tg.nt[0]) % tg.nt[1], tz = tile / (tg.nt[0] * tg.nt[1]);
+    const int A0 = tx * tg.T[0], A1 = ty * tg.T[1], A2 = tz * tg.T[2];
+    const int n0 = min(tg.T[0], a.na[0] - A0), n1 = min(tg.T[1], a.na[1] - A1);
+    const int n2 = D == 3 ? min(tg.T[2], a.na[2] - A2) : 1;
+    constexpr bool FULLROW = LAYOUT == kFullRow, DIRECT = LAYOUT == kDirect;
+    // staged box: sub-areas of the active colour plus the read halo (none
+    // for the direct layout, which reads the lattice in place)
+    const int b0 = FULLROW ? L0 : 2 * s * (n0 - 1) + s + 2 * R;
+    const int b1 = 2 * s * (n1 - 1) + s + 2 * R;
+    const int b2 = D == 3 ? 2 * s * (n2 - 1) + s + 2 * R : 1;
+    const int o0 = FULLROW || DIRECT ? 0 : 2 * s * A0 + s * cx - R;
+    const int o1 = DIRECT ? 0 : 2 * s * A1 + s * cy - R;
+    const int o2 = D == 3 && !DIRECT ? 2 * s * A2 + s * cz - R : 0;
+    const LdsMap<LAYOUT> map{DIRECT ? L0 : b0, DIRECT ? L1 : b1, L0, L1, L2};
+    Cell *cells = reinterpret_cast<Cell *>(a.cells);
+    Cell *lab = DIRECT ? cells : reinterpret_cast<Cell *>(smem);
+    uint8_t *lact = DIRECT ? a.act : smem + align16(tg.box_sites * (int)sizeof(Cell));
+    const int32_t *rd = a.counters[parity];
+    int32_t *wr = a.counters[parity ^ 1];
+    // delta lists: this activation's records go to the list of its parity;
+    // the previous activation's (other parity) are re-added into wr
+    int4 *dl = a.dlist[parity] + (size_t)tile * a.dlist_cap;
+    const int4 *dl_prev = a.dlist[parity ^ 1] + (size_t)tile * a.dlist_cap;
+
+    if (tid == 0) {
+        list_n = 0;
+        queue_n = 0;
+        n_nontrivial = 0;
+        n_accepted = 0;
+    }
+    // model tables read per neighbour, copied to LDS (visible after the
+    // staging barrier)
+    if (!SINGLE)
+        for (int i = tid; i < kMaxTypes * kMaxTypes; i += kBlock) j_lds[i] = a.model->J[i];
+    if (ACT)
+        for (int i = tid; i < 256; i += kBlock) lg_lds[i] = a.model->LG[i];
+    const SharedTables sht{j_lds, lg_lds};
+    // deltas of the previous activation go into the write buffer as well
+    // k = 1 in place: every attempt is evaluated by the thread that draws it
+    // (no queue): measured faster than queueing the nontrivial attempts across
+    // the workgroup (9.3 vs 9.8 us per 3D activation, 2.34 vs 2.92 ms per MCS
+    // of 512 batched 2D lattices with the Act term)
+    constexpr bool EAGER = DIRECT && K1;
+    if (!EAGER) {
+        const int prev_n = a.dcount[parity ^ 1][tile];
+        for (int i = tid; i < prev_n; i += kBlock) add_deltas(wr, dl_prev[i]);
+    }
+    // threshold tables, read from the model (they stay in L2: every tile reads them)
+    const ThrTables tb{a.model->TM32, a.model->TL32, a.model->TI32, a.model->n_ti};
+
+    const int areas = n0 * n1 * n2;
+    const uint32_t sd = D == 2 ? (uint32_t)(s * s) : (uint32_t)(s * s * s);
+    // draw of one attempt: target and source in LDS coordinates
+    const FastDiv by_n0((uint32_t)n0), by_n1((uint32_t)n1), by_s((uint32_t)s);
+    auto draw = [&](int area_local, int j, int &ttx, int &tty, int &ttz, int &ssx, int &ssy, int &ssz, uint32_t &u2,
+                    uint32_t &area_id) {
+        const int q0 = (int)by_n0.div((uint32_t)area_local), ax = area_local - q0 * n0;
+        const int az = (int)by_n1.div((uint32_t)q0), ay = q0 - az * n1;
+        area_id = (uint32_t)(A0 + ax) + (uint32_t)a.na[0] * ((uint32_t)(A1 + ay) + (uint32_t)a.na[1] * (uint32_t)(A2 + az));
+        const uint4 u = philox4x32_10(make_uint4(area_id, mcs, (alpha << 8) | (uint32_t)j, a.lattice_id), a.key0, a.key1);
+        const uint32_t o = (uint32_t)(((uint64_t)u.x * sd) >> 32);
+        const int q1 = (int)by_s.div(o), ox = (int)o - q1 * s;
+        const int oz = D == 3 ? (int)by_s.div((uint32_t)q1) : 0, oy = q1 - oz * s;
+        ttx = DIRECT ? 2 * s * (A0 + ax) + s * cx + ox : (FULLROW ? 2 * s * ax + s * cx + ox : 2 * s * ax + R + ox);
+        tty = DIRECT ? 2 * s * (A1 + ay) + s * cy + oy : 2 * s * ay + R + oy;
+        ttz = D == 3 ? (DIRECT ? 2 * s * (A2 + az) + s * cz + oz : 2 * s * az + R + oz) : 0;
+        const int nsel = (int)(((uint64_t)u.y * (uint32_t)NNB) >> 32);
+        const int msel = nsel < NNB / 2 ? nsel : nsel + 1;
+        ssx = ttx + msel % 3 - 1;
+        ssy = tty + (msel / 3) % 3 - 1;
+        ssz = D == 3 ? ttz + msel / 9 - 1 : 0;
+        u2 = u.z;
+    };
+    auto global_index = [&](int vx, int vy, int vz) {
+        if (DIRECT) return map.at(vx, vy, vz);
+        const int gx = FULLROW ? wrap_once(vx, L0) : wrap_once(o0 + vx, L0);
+        const int gy = wrap_once(o1 + vy, L1);
+        const int gz = D == 3 ? wrap_once(o2 + vz, L2) : 0;
+        return (int)(((size_t)gz * L1 + gy) * L0 + gx);
+    };
+    // the cell types of an attempt's two labels (their stored words at hand)
+    auto types = [&](Cell wt, int lt_, Cell ws, int ls_, int &tt_, int &ts_) {
+        tt_ = lt_ == 0 ? 0 : (SINGLE ? a.single_type : type_of_word(a, wt, lt_));
+        ts_ = ls_ == 0 ? 0 : (SINGLE ? a.single_type : type_of_word(a, ws, ls_));
+    };
+    // the target takes the source's stored word (its label, and its type in
+    // packed words); words with activity carry the target's new activity
+    constexpr bool kActWord = WordAct<Cell>::kIn;
+    auto commit = [&](int t, int gi, int lt, int ls, Cell ws, int ts, int64_t dso, int64_t dsn) {
+        uint8_t na = 0;
+        if (ACT) na = (ls >= 1 && a.model->max_act[ts] > 0) ? (uint8_t)a.model->max_act[ts] : (uint8_t)0;
+        const Cell nw = kActWord ? (Cell)(((uint32_t)ws & WordAct<Cell>::kKeep) | ((uint32_t)na << WordAct<Cell>::kShift))
+                                 : ws;
+        if (!DIRECT) lab[t] = nw;
+        cells[gi] = nw;
+        if (ACT && !kActWord) {
+            if (!DIRECT) lact[t] = na;
+            a.act[gi] = na;
+        }
+        const int4 rec = make_int4(lt, ls, (int)dso, (int)dsn);
+        add_deltas(wr, rec);
+        dl[atomicAdd(&list_n, 1)] = rec;
+        return rec;
+    };
+
+    if (EAGER) {
+        // round 1: the previous list's count and this thread's record of it
+        // (valid when tid < count), and the attempt's two labels; round 2,
+        // nontrivial attempts only: the target's neighbours and both cells'
+        // counters; round 3: the acceptance threshold
+        const int prev_n = a.dcount[parity ^ 1][tile];
+        const int4 prev_rec = tid < a.dlist_cap ? dl_prev[tid] : make_int4(0, 0, 0, 0);
+        int ttx = 0, tty = 0, ttz = 0, ssx = 0, ssy = 0, ssz = 0, lt = 0, ls = 0;
+        Cell wt = 0, ws = 0;
+        uint32_t u2 = 0, area_id = 0;
+        const bool mine = tid < areas;
+        if (mine) {
+            draw(tid, 0, ttx, tty, ttz, ssx, ssy, ssz, u2, area_id);
+            wt = lab[map.at(ttx, tty, ttz)];
+            ws = lab[map.at(ssx, ssy, ssz)];
+            lt = label_of(wt);
+            ls = label_of(ws);
+        }
+        __syncthreads();  // LDS counters and tables initialised
+        if (tid < prev_n) add_deltas(wr, prev_rec);
+        uint32_t nontrivial = 0, accepted = 0;
+        if (mine && lt != ls && lt >= 0 && ls >= 0) {
+            nontrivial = 1;
+            JRows jr{0, 0, 0, 0, 0, 0};
+            if (SINGLE) {
+                const int64_t *J = a.model->J;
+                const int tc = a.single_type, to = a.obstacle_type;
+                jr = JRows{J[tc * kMaxTypes + tc], J[tc * kMaxTypes], J[tc * kMaxTypes + to], J[tc], J[0], J[to]};
+            }
+            int64_t dso, dsn;
+            int tt, ts;
+            types(wt, lt, ws, ls, tt, ts);
+            if (evaluate<Cell, D, ACT, SINGLE, LAYOUT, EXT>(a, tb, jr, sht, lab, lact, map, ttx, tty, ttz, ssx, ssy, ssz,
+                                                       map.at(ssx, ssy, ssz), lt, ls, tt, ts,
+                                                       seen_counters(rd, lt, nullptr, 0),
+                                                       seen_counters(rd, ls, nullptr, 0), u2, dso, dsn)) {
+                accepted = 1;
+                const int gi = map.at(ttx, tty, ttz);
+                commit(gi, gi, lt, ls, ws, ts, dso, dsn);
+            }
+        }
+        if (nontrivial) atomicAdd(&n_nontrivial, 1u);
+        if (accepted) atomicAdd(&n_accepted, 1u);
+        __syncthreads();
+        if (tid == 0) {
+            a.dcount[parity][tile] = list_n;
+            a.stats[2 * tile] += n_nontrivial;
+            a.stats[2 * tile + 1] += n_accepted;
+        }
+        return;
+    }
+
+    // k = 1: the attempt of this thread's area, its two labels (from LDS) and,
+    // when nontrivial, their counters as the activation began.  Drawing while
+    // the staging loads are in flight, or reading the labels from global
+    // memory then, measured slower on gfx950 (the wait for the labels also
+    // waits for every staging load issued before them).
+    int d_ttx = 0, d_tty = 0, d_ttz = 0, d_ssx = 0, d_ssy = 0, d_ssz = 0, d_lt = 0, d_ls = 0;
+    Cell d_wt = 0, d_ws = 0;
+    uint32_t d_u2 = 0;
+    bool d_nontrivial = false;
+    int2 d_ct = make_int2(0, 0), d_cs = make_int2(0, 0);
+    auto draw_k1 = [&]() {
+        if (!K1 || tid >= areas) return;
+        uint32_t area_id;
+        draw(tid, 0, d_ttx, d_tty, d_ttz, d_ssx, d_ssy, d_ssz, d_u2, area_id);
+        d_wt = lab[map.at(d_ttx, d_tty, d_ttz)];
+        d_ws = lab[map.at(d_ssx, d_ssy, d_ssz)];
+        d_lt = label_of(d_wt);
+        d_ls = label_of(d_ws);
+        d_nontrivial = d_lt != d_ls && d_lt >= 0 && d_ls >= 0;
+        if (d_nontrivial) {
+            d_ct = seen_counters(rd, d_lt, nullptr, 0);
+            d_cs = seen_counters(rd, d_ls, nullptr, 0);
+        }
+    };
+
+    // stage the box (labels, and activity for the Act term)
+    const int rows = b1 * b2;
+    if (DIRECT) {
+        // nothing to stage: attempts read the lattice in place (no other
+        // attempt of this activation writes a site that one reads)
+    } else if (FULLROW) {
+        // whole rows in the widest chunks (16, 8 or 4 bytes) that tile a row,
+        // eight loads in flight per thread
+        const FastDiv by_b1((uint32_t)b1);
+        auto copy_rows = [&](auto chunk, const void *src_v, void *dst_v, int row_bytes) {
+            using Chunk = decltype(chunk);
+            const Chunk *src = reinterpret_cast<const Chunk *>(src_v);
+            Chunk *dst = reinterpret_cast<Chunk *>(dst_v);
+            const int per_row = row_bytes / (int)sizeof(Chunk);
+            const FastDiv by_row((uint32_t)per_row);
+            auto row_chunk = [&](int c) {
+                const int r = (int)by_row.div((uint32_t)c), off = c - r * per_row;
+                const int rz = (int)by_b1.div((uint32_t)r), ry = r - rz * b1;
+                const int gy = wrap_once(o1 + ry, L1);
+                const int gz = D == 3 ? wrap_once(o2 + rz, L2) : 0;
+                return ((size_t)gz * L1 + gy) * per_row + off;
+            };
+            const int total = rows * per_row;
+            int c0 = tid;
+            for (; c0 + 7 * kBlock < total; c0 += 8 * kBlock) {
+                // eight independent loads before the first LDS store
+                const Chunk v0 = src[row_chunk(c0)];
+                const Chunk v1 = src[row_chunk(c0 + kBlock)];
+                const Chunk v2 = src[row_chunk(c0 + 2 * kBlock)];
+                const Chunk v3 = src[row_chunk(c0 + 3 * kBlock)];
+                const Chunk v4 = src[row_chunk(c0 + 4 * kBlock)];
+                const Chunk v5 = src[row_chunk(c0 + 5 * kBlock)];
+                const Chunk v6 = src[row_chunk(c0 + 6 * kBlock)];
+                const Chunk v7 = src[row_chunk(c0 + 7 * kBlock)];
+                dst[c0] = v0;
+                dst[c0 + kBlock] = v1;
+                dst[c0 + 2 * kBlock] = v2;
+                dst[c0 + 3 * kBlock] = v3;
+                dst[c0 + 4 * kBlock] = v4;
+                dst[c0 + 5 * kBlock] = v5;
+                dst[c0 + 6 * kBlock] = v6;
+                dst[c0 + 7 * kBlock] = v7;
+            }
+            for (; c0 < total; c0 += kBlock) dst[c0] = src[row_chunk(c0)];
+        };
+        auto copy_any = [&](int chunk, const void *src, void *dst, int row_bytes) {
+            if (chunk == 16) copy_rows(uint4{}, src, dst, row_bytes);
+            else if (chunk == 8) copy_rows(uint2{}, src, dst, row_bytes);
+            else copy_rows(uint32_t{}, src, dst, row_bytes);
+        };
+        copy_any(tg.row_chunk, cells, lab, L0 * (int)sizeof(Cell));
+        if (ACT && !WordAct<Cell>::kIn) copy_any(tg.act_chunk, a.act, lact, L0);
+    } else {
+        // the box x fastest, site c of the box at LDS index c: consecutive
+        // threads read consecutive sites of a row, eight loads (and eight
+        // activity loads) in flight per thread before the LDS stores
+        const int total = b0 * rows;
+        const FastDiv by_b0((uint32_t)b0), by_b1((uint32_t)b1);
+        auto src = [&](int c) {
+            const int r = (int)by_b0.div((uint32_t)c), x = c - r * b0;
+            const int rz = (int)by_b1.div((uint32_t)r), ry = r - rz * b1;
+            const int gx = wrap_once(o0 + x, L0);
+            const int gy = wrap_once(o1 + ry, L1);
+            const int gz = D == 3 ? wrap_once(o2 + rz, L2) : 0;
+            return (int)(((size_t)gz * L1 + gy) * L0 + gx);
+        };
+        // kBatch sites per thread per round: all their loads are issued
+        // before the first LDS store (the arrays are indexed by unrolled
+        // constants only, so they stay in registers)
+        constexpr int kBatch = 8;
+        int c0 = tid;
+        for (; c0 + (kBatch - 1) * kBlock < total; c0 += kBatch * kBlock) {
+            int idx[kBatch];
+            Cell v[kBatch];
+            uint8_t w[kBatch];
+#pragma unroll
+            for (int q = 0; q < kBatch; ++q) idx[q] = src(c0 + q * kBlock);
+#pragma unroll
+            for (int q = 0; q < kBatch; ++q) v[q] = cells[idx[q]];
+            if (ACT && !WordAct<Cell>::kIn) {
+#pragma unroll
+                for (int q = 0; q < kBatch; ++q) w[q] = a.act[idx[q]];
+            }
+#pragma unroll
+            for (int q = 0; q < kBatch; ++q) lab[c0 + q * kBlock] = v[q];
+            if (ACT && !WordAct<Cell>::kIn) {
+#pragma unroll
+                for (int q = 0; q < kBatch; ++q) lact[c0 + q * kBlock] = w[q];
+            }
+        }
+        for (; c0 < total; c0 += kBlock) {
+            const int i = src(c0);
+            lab[c0] = cells[i];
+            if (ACT && !WordAct<Cell>::kIn) lact[c0] = a.act[i];
+        }
+    }
+    __syncthreads();
+
+    uint32_t my_accepted = 0;
+    JRows jr{0, 0, 0, 0, 0, 0};
+    if (SINGLE) {
+        const int64_t *J = a.model->J;
+        const int tc = a.single_type, to = a.obstacle_type;
+        jr = JRows{J[tc * kMaxTypes + tc], J[tc * kMaxTypes], J[tc * kMaxTypes + to],
+                   J[tc], J[0], J[to]};
+    }
+    if (K1) {
+        draw_k1();
+        // phase 1: queue the nontrivial attempts with their counters
+        if (d_nontrivial) {
+            const int slot = atomicAdd(&queue_n, 1);
+            if (slot < kQueue) {
+                queue[slot] = make_int4(d_ttx | (d_tty << 16), d_ttz | (d_ssz << 16), (d_ssx & 0xFFFF) | (d_ssy << 16),
+                                        (int)d_u2);
+                queue_cnt[slot] = make_int4(d_ct.x, d_ct.y, d_cs.x, d_cs.y);
+            } else {
+                // queue full: evaluate here (no other attempt reads this sub-area)
+                int64_t dso, dsn;
+                int tt, ts;
+                types(d_wt, d_lt, d_ws, d_ls, tt, ts);
+                if (evaluate<Cell, D, ACT, SINGLE, LAYOUT, EXT>(a, tb, jr, sht, lab, lact, map, d_ttx, d_tty, d_ttz, d_ssx,
+                                                            d_ssy, d_ssz, EXT && a.chem ? global_index(d_ssx, d_ssy, d_ssz) : 0,
+                                                            d_lt, d_ls, tt, ts, d_ct, d_cs, d_u2, dso, dsn)) {
+                    ++my_accepted;
+                    commit(map.at(d_ttx, d_tty, d_ttz), global_index(d_ttx, d_tty, d_ttz), d_lt, d_ls, d_ws, ts, dso,
+                           dsn);
+                }
+            }
+        }
+        __syncthreads();
+        // phase 2: energy change and Metropolis test of the queued attempts
+        const int qn = queue_n;
+        // entry i goes to lane i / 4 of wave i % 4: the work spreads over all waves
+        for (int i = ((tid & 63) << 2) | (tid >> 6); i < min(qn, kQueue); i += kBlock) {
+            const int4 e = queue[i], c = queue_cnt[i];
+            const int ttx = e.x & 0xFFFF, tty = e.x >> 16, ttz = e.y & 0xFFFF;
+            const int ssz = e.y >> 16, ssx = (int)(int16_t)(e.z & 0xFFFF), ssy = e.z >> 16;
+            const int t = map.at(ttx, tty, ttz);
+            const Cell wt = lab[t], ws = lab[map.at(ssx, ssy, ssz)];
+            const int lt = label_of(wt), ls = label_of(ws);
+            int64_t dso, dsn;
+            int tt, ts;
+            types(wt, lt, ws, ls, tt, ts);
+            if (evaluate<Cell, D, ACT, SINGLE, LAYOUT, EXT>(a, tb, jr, sht, lab, lact, map, ttx, tty, ttz, ssx, ssy, ssz,
+                                                        EXT && a.chem ? global_index(ssx, ssy, ssz) : 0, lt, ls, tt, ts,
+                                                        make_int2(c.x, c.y), make_int2(c.z, c.w), (uint32_t)e.w,
+                                                        dso, dsn)) {
+                ++my_accepted;
+                commit(t, global_index(ttx, tty, ttz), lt, ls, ws, ts, dso, dsn);
+            }
+        }
+        if (tid == 0) n_nontrivial = (uint32_t)qn;
+    } else {
+        uint32_t my_nontrivial = 0;
+        if (tid < areas) {
+            // own accepted copies of this activation: registers, then the spill array
+            int4 own[kOwnInRegs];
+            int n_own = 0;
+            const size_t slot = (size_t)tile * (size_t)(tg.T[0] * tg.T[1] * tg.T[2]) + (size_t)tid;
+            int4 *spill = a.own_spill ? a.own_spill + slot * (size_t)(a.k - kOwnInRegs) : nullptr;
+            for (int j = 0; j < a.k; ++j) {
+                int ttx, tty, ttz, ssx, ssy, ssz;
+                uint32_t u2, area_id;
+                draw(tid, j, ttx, tty, ttz, ssx, ssy, ssz, u2, area_id);
+                const int t = map.at(ttx, tty, ttz);
+                const Cell wt = lab[t], ws = lab[map.at(ssx, ssy, ssz)];
+                const int lt = label_of(wt), ls = label_of(ws);
+                if (lt != ls && lt >= 0 && ls >= 0) {
+                    ++my_nontrivial;
+                    int64_t dso, dsn;
+                    int tt, ts;
+                    types(wt, lt, ws, ls, tt, ts);
+                    if (evaluate<Cell, D, ACT, SINGLE, LAYOUT, EXT>(a, tb, jr, sht, lab, lact, map, ttx, tty, ttz, ssx, ssy,
+                                                                ssz, EXT && a.chem ? global_index(ssx, ssy, ssz) : 0, lt, ls,
+                                                                tt, ts, seen_counters(rd, lt, own, n_own, spill),
+                                                                seen_counters(rd, ls, own, n_own, spill), u2, dso, dsn)) {
+                        ++my_accepted;
+                        const int4 rec = commit(t, global_index(ttx, tty, ttz), lt, ls, ws, ts, dso, dsn);
+#pragma unroll
+                        for (int jj = 0; jj < kOwnInRegs; ++jj)
+                            if (jj == n_own) own[jj] = rec;
+                        if (n_own >= kOwnInRegs) spill[n_own - kOwnInRegs] = rec;
+                        ++n_own;
+                    }
+                }
+            }
+        }
+        if (my_nontrivial) atomicAdd(&n_nontrivial, my_nontrivial);
+    }
+    if (my_accepted) atomicAdd(&n_accepted, my_accepted);
+    __syncthreads();
+    if (tid == 0) {
+        a.dcount[parity][tile] = list_n;
+        a.stats[2 * tile] += n_nontrivial;
+        a.stats[2 * tile + 1] += n_accepted;
+    }
+}
+
+// One lattice: workgroup b takes tile (b mod 8) * tiles_per_xcd + b div 8, so
+// each XCD sweeps one contiguous slab of tiles in every activation.
+template <typename Cell, int D, bool ACT, bool SINGLE, bool K1, int LAYOUT, bool EXT>
+__global__ void __launch_bounds__(kBlock) tile_sweep_kernel(SweepArgs a, uint32_t mcs, uint32_t alpha, int parity)
+{
+    const int tile = (int)(blockIdx.x % kXcds) * a.tg.tiles_per_xcd + (int)(blockIdx.x / kXcds);
+    if (tile >= a.tg.n_tiles) return;  // uniform over the block
+    sweep_tile<Cell, D, ACT, SINGLE, K1, LAYOUT, EXT>(a, tile, mcs, alpha, parity);
+}
+
+// Packed words serve large multi-type lattices, whose sweeps wait on HBM:
+// more waves per SIMD hide more of that latency than the registers the
+// limit takes away cost.
+#ifndef CPM_PACKED_WAVES
+#define CPM_PACKED_WAVES 8
+#endif
+#if CPM_PACKED_WAVES > 0
+#define CPM_PACKED_ATTR __attribute__((amdgpu_waves_per_eu(CPM_PACKED_WAVES)))
+#else
+#define CPM_PACKED_ATTR
+#endif
+template <typename Word, int D, bool ACT, bool SINGLE, bool K1, int LAYOUT, bool EXT>
+__global__ void __launch_bounds__(kBlock) CPM_PACKED_ATTR tile_sweep_kernel_packed(SweepArgs a, uint32_t mcs,
+                                                                                    uint32_t alpha, int parity)
+{
+    const int tile = (int)(blockIdx.x % kXcds) * a.tg.tiles_per_xcd + (int)(blockIdx.x / kXcds);
+    if (tile >= a.tg.n_tiles) return;  // uniform over the block
+    sweep_tile<Word, D, ACT, SINGLE, K1, LAYOUT, EXT>(a, tile, mcs, alpha, parity);
+}
+
+// Many lattices advanced together: work[b] = (lattice, tile) of workgroup b
+// (lattice -1: padding); all lattices share the MCS counter at *mcs.
+template <typename Cell, int D, bool ACT, bool SINGLE, bool K1, int LAYOUT, bool EXT>
+__global__ void __launch_bounds__(kBlock) batch_sweep_kernel(const SweepArgs *args, const int2 *work,
+                                                             const uint32_t *mcs, uint32_t alpha, int parity)
+{
+    const int2 w = work[blockIdx.x];
+    if (w.x < 0) return;  // uniform over the block
+    sweep_tile<Cell, D, ACT, SINGLE, K1, LAYOUT, EXT>(args[w.x], w.y, *mcs, alpha, parity);
+}
+
+template <typename Cell, int D, bool ACT, bool SINGLE, bool EXT>
+hipError_t launch_k(const SweepArgs &a, bool k1, int layout, uint32_t mcs, uint32_t alpha, int parity, size_t lds,
+                    hipStream_t st)
+{
+    if (k1 && layout == kDirect)
+        tile_sweep_kernel<Cell, D, ACT, SINGLE, true, kDirect, EXT><<<a.tg.grid, kBlock, lds, st>>>(a, mcs, alpha, parity);
+    else if (k1 && layout == kFullRow)
+        tile_sweep_kernel<Cell, D, ACT, SINGLE, true, kFullRow, EXT><<<a.tg.grid, kBlock, lds, st>>>(a, mcs, alpha, parity);
+    else if (k1)
+        tile_sweep_kernel<Cell, D, ACT, SINGLE, true, kBox, EXT><<<a.tg.grid, kBlock, lds, st>>>(a, mcs, alpha, parity);
+    else
+        tile_sweep_kernel<Cell, D, ACT, SINGLE, false, kBox, EXT><<<a.tg.grid, kBlock, lds, st>>>(a, mcs, alpha, parity);
+    return hipGetLastError();
+}
+
+template <typename Cell, int D, bool ACT>
+hipError_t launch_s(const SweepArgs &a, uint32_t mcs, uint32_t alpha, int parity, size_t lds, hipStream_t st)
+{
+    const bool k1 = a.k == 1;
+    const int layout = a.tg.layout;
+    // the persistence and chemotaxis terms are compiled in only where used
+    const bool ext = a.pdir || a.chem;
+    if (a.single_type >= 0)
+        return ext ? launch_k<Cell, D, ACT, true, true>(a, k1, layout, mcs, alpha, parity, lds, st)
+                   : launch_k<Cell, D, ACT, true, false>(a, k1, layout, mcs, alpha, parity, lds, st);
+    return ext ? launch_k<Cell, D, ACT, false, true>(a, k1, layout, mcs, alpha, parity, lds, st)
+               : launch_k<Cell, D, ACT, false, false>(a, k1, layout, mcs, alpha, parity, lds, st);
+}
+
+// Packed words (multi-type models only): no single-type kernels needed.
+template <typename Word, int D, bool ACT, bool SINGLE, bool EXT>
+hipError_t launch_packed_k(const SweepArgs &a, uint32_t mcs, uint32_t alpha, int parity, size_t lds, hipStream_t st)
+{
+    const bool k1 = a.k == 1;
+    const int layout = a.tg.layout;
+    if (k1 && layout == kDirect)
+        tile_sweep_kernel_packed<Word, D, ACT, SINGLE, true, kDirect, EXT><<<a.tg.grid, kBlock, lds, st>>>(a, mcs, alpha, parity);
+    else if (k1 && layout == kFullRow)
+        tile_sweep_kernel_packed<Word, D, ACT, SINGLE, true, kFullRow, EXT><<<a.tg.grid, kBlock, lds, st>>>(a, mcs, alpha, parity);
+    else if (k1)
+        tile_sweep_kernel_packed<Word, D, ACT, SINGLE, true, kBox, EXT><<<a.tg.grid, kBlock, lds, st>>>(a, mcs, alpha, parity);
+    else
+        tile_sweep_kernel_packed<Word, D, ACT, SINGLE, false, kBox, EXT><<<a.tg.grid, kBlock, lds, st>>>(a, mcs, alpha, parity);
+    return hipGetLastError();
+}
+
+// Label-type words serve multi-type models only; label-type-activity words
+// serve every Act model that fits them.
+template <typename Word, int D, bool ACT>
+hipError_t launch_packed_s(const SweepArgs &a, uint32_t mcs, uint32_t alpha, int parity, size_t lds, hipStream_t st)
+{
+    const bool ext = a.pdir || a.chem;
+    if constexpr (std::is_same<Word, char32_t>::value) {
+        if (a.single_type >= 0)
+            return ext ? launch_packed_k<Word, D, ACT, true, true>(a, mcs, alpha, parity, lds, st)
+                       : launch_packed_k<Word, D, ACT, true, false>(a, mcs, alpha, parity, lds, st);
+    }
+    return ext ? launch_packed_k<Word, D, ACT, false, true>(a, mcs, alpha, parity, lds, st)
+               : launch_packed_k<Word, D, ACT, false, false>(a, mcs, alpha, parity, lds, st);
+}
+
+
+template <typename Cell, int D, bool ACT, bool SINGLE, bool EXT>
+hipError_t launch_batch_k(const BatchLaunch &b, uint32_t alpha, int parity, hipStream_t st)
+{
+    if (b.k1 && b.layout == kDirect)
+        batch_sweep_kernel<Cell, D, ACT, SINGLE, true, kDirect, EXT><<<b.grid, kBlock, b.lds, st>>>(b.args, b.work, b.mcs, alpha, parity);
+    else if (b.k1 && b.layout == kFullRow)
+        batch_sweep_kernel<Cell, D, ACT, SINGLE, true, kFullRow, EXT><<<b.grid, kBlock, b.lds, st>>>(b.args, b.work, b.mcs, alpha, parity);
+    else if (b.k1)
+        batch_sweep_kernel<Cell, D, ACT, SINGLE, true, kBox, EXT><<<b.grid, kBlock, b.lds, st>>>(b.args, b.work, b.mcs, alpha, parity);
+    else
+        batch_sweep_kernel<Cell, D, ACT, SINGLE, false, kBox, EXT><<<b.grid, kBlock, b.lds, st>>>(b.args, b.work, b.mcs, alpha, parity);
+    return hipGetLastError();
+}
+
+template <typename Cell, int D, bool ACT>
+hipError_t launch_batch_s(const BatchLaunch &b, uint32_t alpha, int parity, hipStream_t st)
+{
+    if (b.single)
+        return b.ext ? launch_batch_k<Cell, D, ACT, true, true>(b, alpha, parity, st)
+                     : launch_batch_k<Cell, D, ACT, true, false>(b, alpha, parity, st);
+    return b.ext ? launch_batch_k<Cell, D, ACT, false, true>(b, alpha, parity, st)
+                 : launch_batch_k<Cell, D, ACT, false, false>(b, alpha, parity, st);
+}
+
+}  // namespace
+
+// One activation of a single lattice whose sweep reads stored words of type
+// Cell, in D dimensions: the kernel specialised for the model's terms,
+// cell types, k and layout.
+template <typename Cell, int D>
+hipError_t sweep_words(const SweepArgs &a, bool act, uint32_t mcs, uint32_t alpha, int parity, size_t lds,
+                       hipStream_t st)
+{
+    if constexpr (std::is_same<Cell, int32_t>::value || std::is_same<Cell, uint16_t>::value)
+        return act ? launch_s<Cell, D, true>(a, mcs, alpha, parity, lds, st)
+                   : launch_s<Cell, D, false>(a, mcs, alpha, parity, lds, st);
+    else if constexpr (std::is_same<Cell, uint32_t>::value)
+        return act ? launch_packed_s<Cell, D, true>(a, mcs, alpha, parity, lds, st)
+                   : launch_packed_s<Cell, D, false>(a, mcs, alpha, parity, lds, st);
+    else  // words that carry the activity serve Act models only
+        return launch_packed_s<Cell, D, true>(a, mcs, alpha, parity, lds, st);
+}
+
+// One activation of every lattice of a batch.
+template <typename Cell, int D>
+hipError_t batch_words(const BatchLaunch &b, uint32_t alpha, int parity, hipStream_t st)
+{
+    if constexpr (std::is_same<Cell, int32_t>::value || std::is_same<Cell, uint16_t>::value)
+        return b.act ? launch_batch_s<Cell, D, true>(b, alpha, parity, st)
+                     : launch_batch_s<Cell, D, false>(b, alpha, parity, st);
+    else if constexpr (std::is_same<Cell, char16_t>::value)  // one cell type, no chemotaxis
+        return launch_batch_k<Cell, D, true, true, false>(b, alpha, parity, st);
+    else
+        return launch_batch_s<Cell, D, true>(b, alpha, parity, st);
+}
+
+}  // namespace cpm

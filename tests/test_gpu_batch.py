@@ -143,3 +143,53 @@ def test_batch_graph_replays_match_eager_and_oracle(torch_cuda):
         assert torch_cuda.equal(g.act, e.act), step
         assert torch_cuda.equal(vg, ve) and torch_cuda.equal(sg, se) and torch_cuda.equal(cg, ce), step
     _check(torch_cuda, ws, g, 6)
+
+
+def _act_batch(types_per_lattice, seed):
+    """Small Act lattices (config3 recipe) whose cells take 1 or 2 cell types."""
+    ws = inputs.config3(n_lattices=5, L_min=24, L_max=72, seed=seed, n_mcs=0)
+    for w in ws:
+        if types_per_lattice == 2:
+            w.cell_type = np.array([0] + [1 + (c % 2) for c in range(w.n_cells)], dtype=np.int32)
+            w.J = np.array([[0, w.J[0, 1], w.J[0, 1] * 1.5], [w.J[1, 0], w.J[1, 1], w.J[1, 1] * 0.5],
+                            [w.J[0, 1] * 1.5, w.J[1, 1] * 0.5, w.J[1, 1] * 2]])
+            w.lambda_V = np.array([0, w.lambda_V[1], w.lambda_V[1] * 0.5])
+            w.V_target = np.array([0, 100, 80], dtype=np.int32)
+            w.lambda_S = np.array([0, 0.0, 0.0])
+            w.S_target = np.array([0, 0, 0], dtype=np.int32)
+            w.lambda_act = np.array([0, w.lambda_act[1], w.lambda_act[1] * 0.5])
+            w.max_act = np.array([0, 30, 20], dtype=np.int32)
+        lab = w.lattice
+        w.act = np.where(lab > 0, w.max_act[w.cell_type[np.maximum(lab, 0)]], 0).astype(np.uint8)
+    return ws
+
+
+@pytest.mark.parametrize("types_per_lattice", [1, 2])
+def test_act_batch_words_with_serial_steps(torch_cuda, types_per_lattice):
+    # one cell type: the batch sweeps on 16-bit label-activity words; two:
+    # on 32-bit label-type-activity words.  Serial MCS (on the int32
+    # lattices) interleave with the parallel ones.
+    ws = _act_batch(types_per_lattice, seed=31 + types_per_lattice)
+    for i, w in enumerate(ws):
+        w.lattice_id = 50 + i
+    _say(f"act batch, {types_per_lattice} cell type(s): sides {[w.dims[0] for w in ws]}")
+    states = [_oracle_state(w) for w in ws]
+    b = cpm.Batch([cpm.Params.from_workload(w) for w in ws], [w.lattice for w in ws], [w.cell_type for w in ws],
+                  [w.act for w in ws])
+    for step, n in (("dcs", 3), ("serial", 1), ("dcs", 2)):
+        for st in states:
+            st.sweep(n) if step == "dcs" else st.serial_sweep(n)
+        b.sweep(n) if step == "dcs" else b.sweep_serial(n)
+    v, s = b.counters()
+    stats = b.attempt_stats()
+    torch_cuda.cuda.synchronize()
+    v, s = v.cpu().numpy(), s.cpu().numpy()
+    for i, (w, st) in enumerate(zip(ws, states)):
+        np.testing.assert_array_equal(b.lattice(i).cpu().numpy(), st.lattice)
+        np.testing.assert_array_equal(b.activity(i).cpu().numpy(), st.act)
+        lo, hi = int(b.label_off[i]), int(b.label_off[i + 1])
+        np.testing.assert_array_equal(v[lo + 1:hi], st.V[1:])
+        np.testing.assert_array_equal(s[lo + 1:hi], st.S[1:])
+        assert tuple(int(x) for x in stats[i]) == tuple(int(x) for x in st.stats)
+    assert all(b.check_invariants())
+    assert sum(int(st.stats[2]) for st in states) > 0

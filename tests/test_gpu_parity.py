@@ -92,11 +92,12 @@ def test_config1_structure_small(torch_cuda):
 @pytest.mark.parametrize("ndim,dims,s,k", [
     (2, (40, 24, 1), 2, 1), (2, (36, 36, 1), 3, 3), (2, (20, 28, 1), 1, 1), (2, (16, 16, 1), 2, 4),
     (3, (12, 16, 20), 2, 1), (3, (12, 12, 12), 1, 1), (3, (16, 8, 8), 2, 8), (3, (12, 12, 24), 3, 9),
+    (2, (36, 24, 1), 3, 9), (2, (32, 24, 1), 4, 16), (3, (12, 12, 12), 3, 27),
     (2, (4, 4, 1), 2, 1), (3, (4, 4, 4), 2, 1),
 ])
 def test_multi_type_obstacles(torch_cuda, ndim, dims, s, k):
-    if k > 8:
-        pytest.skip("the library runs at most 8 attempts per activation")
+    # k = s^d (every activation one colour's whole sub-area worth of
+    # attempts by each thread) is the infrequent-switching end of the scheme
     w = _multi(dims, ndim, seed=dims[0] + 7 * s + k, s=s, k=k)
     st, sim = run_both(torch_cuda, w, 6)
     assert_same(st, sim, torch_cuda)
@@ -111,7 +112,7 @@ def test_act_model(torch_cuda, ndim, dims):
 
 @pytest.mark.parametrize("ndim,dims,s,k", [
     (2, (32, 24, 1), 2, 4), (2, (36, 36, 1), 3, 3), (2, (32, 32, 1), 4, 8), (2, (4, 4, 1), 2, 4),
-    (3, (16, 12, 12), 2, 2), (3, (16, 16, 8), 2, 8),
+    (3, (16, 12, 12), 2, 2), (3, (16, 16, 8), 2, 8), (2, (32, 32, 1), 4, 16), (3, (12, 12, 12), 3, 27),
 ])
 def test_act_sub_and_attempts(torch_cuda, ndim, dims, s, k):
     # the Act term with several attempts per activation (each seeing its own
@@ -125,6 +126,29 @@ def test_act_sub_and_attempts(torch_cuda, ndim, dims, s, k):
     st, sim = run_both(torch_cuda, w, 6)
     assert_same(st, sim, torch_cuda)
     assert st.stats[2] > 0 and (st.act > 0).any()
+
+
+@pytest.mark.parametrize("ndim,dims,s,k", [(2, (32, 32, 1), 4, 16), (3, (12, 12, 12), 3, 27)])
+def test_many_own_copies(torch_cuda, ndim, dims, s, k):
+    # labels drawn per site and a hot, weakly constrained model: nearly every
+    # attempt is nontrivial and accepted, so threads make more accepted
+    # copies per activation than they keep in registers and the rest of
+    # their own records spill to the workspace
+    rng = np.random.default_rng(7 + k)
+    n_cells = 10
+    lat = rng.integers(0, n_cells + 1, size=dims[::-1], dtype=np.int32)
+    J = np.array([[0, 1.0, 0.5], [1.0, 2.0, 1.5], [0.5, 1.5, 1.0]])
+    w = inputs.Workload(f"hot-{ndim}d-k{k}", ndim, dims, lat,
+                        np.array([0] + [1 + (i % 2) for i in range(n_cells)], dtype=np.int32), J,
+                        np.array([0, 0.01, 0.02]), np.array([0, 50, 80], dtype=np.int32),
+                        np.array([0, 0.005, 0.0]), np.array([0, 200, 0], dtype=np.int32),
+                        T=150.0, n_mcs=0, seed=11, lattice_id=3, s=s, k=k)
+    st, sim = run_both(torch_cuda, w, 3)
+    assert_same(st, sim, torch_cuda)
+    # well over 8 accepted copies per thread area and activation on average
+    n_act = (2 * s) ** ndim // k
+    areas = int(np.prod(dims)) // (2 * s) ** ndim
+    assert st.stats[2] / (3 * n_act * areas) > 8
 
 
 def test_resume_and_chunking(torch_cuda):
