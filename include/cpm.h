@@ -175,6 +175,24 @@ int cpm_init(const cpm_params *params, int32_t *d_lattice, const int32_t *d_cell
              int32_t n_cells, uint8_t *d_act, void *d_workspace, size_t workspace_bytes,
              void *stream, cpm_handle **out);
 
+/*
+ * cpm_init without a caller workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The handle's device state lives in a
+ * static array of the library, CPM_STATIC_WORKSPACE_BYTES per GPU, held
+ * from this call to cpm_destroy; the call allocates no device memory (the
+ * handle's host state comes from the host heap, as with cpm_init).
+ * Arguments, behaviour and results are those of cpm_init.  Errors, besides
+ * cpm_init's: CPM_ENOMEM when the model needs a larger workspace than the
+ * array (cpm_workspace_bytes), CPM_EINVAL while another handle holds the
+ * array of the current device (one such handle per GPU at a time: calls on
+ * two handles would race on the same memory).  The array keeps the last
+ * handle's contents; init clears everything a sweep reads before writing.
+ */
+#define CPM_STATIC_WORKSPACE_BYTES (16u << 20)
+int cpm_init_static(const cpm_params *params, int32_t *d_lattice, const int32_t *d_cell_type, int32_t n_cells,
+                    uint8_t *d_act, void *stream, cpm_handle **out);
+
 /* Advances the lattice by n_mcs Monte Carlo steps (n_mcs >= 0) and the MCS
  * counter with it.  Asynchronous on `stream`.  While the call's work runs,
  * d_lattice and d_act may hold an internal encoding (lattices of more than

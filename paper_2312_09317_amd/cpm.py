@@ -59,7 +59,7 @@ class cpm_params(ctypes.Structure):
 LAYOUTS = {"auto": 0, "box": 1, "full_rows": 2, "in_place": 3}
 
 
-EXPORTS = ("cpm_validate", "cpm_workspace_bytes", "cpm_tile_shape", "cpm_init", "cpm_sweep", "cpm_cell_stats", "cpm_contacts",
+EXPORTS = ("cpm_validate", "cpm_workspace_bytes", "cpm_tile_shape", "cpm_init", "cpm_init_static", "cpm_sweep", "cpm_cell_stats", "cpm_contacts",
            "cpm_persistence", "cpm_counters", "cpm_check_invariants", "cpm_attempt_stats", "cpm_set_mcs", "cpm_get_mcs", "cpm_destroy",
            "cpm_batch_workspace_bytes", "cpm_batch_init", "cpm_batch_sweep", "cpm_batch_sweep_serial", "cpm_batch_occupancy", "cpm_batch_use_graph", "cpm_batch_counters",
            "cpm_batch_cell_stats", "cpm_batch_attempt_stats", "cpm_batch_check_invariants", "cpm_batch_sample", "cpm_batch_summary", "cpm_batch_autocorrelation",
@@ -88,6 +88,7 @@ def load(path: str = LIB_PATH):
     l.cpm_workspace_bytes.argtypes = [pp, I32, ctypes.POINTER(SZ)]
     l.cpm_tile_shape.argtypes = [pp, I32, P]
     l.cpm_init.argtypes = [pp, P, P, I32, P, P, SZ, P, ctypes.POINTER(P)]
+    l.cpm_init_static.argtypes = [pp, P, P, I32, P, P, ctypes.POINTER(P)]
     l.cpm_sweep.argtypes = [P, I32, P]
     l.cpm_cell_stats.argtypes = [P, P, P, P, P]
     l.cpm_contacts.argtypes = [P, P, P]
@@ -254,6 +255,14 @@ def cpm_init(params: Params, d_lattice, d_cell_type, n_cells: int, d_act, d_work
     h = ctypes.c_void_p(0)
     _check(load().cpm_init(ctypes.byref(params.c), _ptr(d_lattice), _ptr(d_cell_type), n_cells, _ptr(d_act),
                            _ptr(d_workspace), workspace_bytes, stream, ctypes.byref(h)), "cpm_init")
+    return h.value
+
+
+def cpm_init_static(params: Params, d_lattice, d_cell_type, n_cells: int, d_act, stream: int) -> int:
+    """cpm_init on the library's static device workspace (no allocation)."""
+    h = ctypes.c_void_p()
+    _check(load().cpm_init_static(ctypes.byref(params.c), _ptr(d_lattice), _ptr(d_cell_type), n_cells, _ptr(d_act),
+                                  stream, ctypes.byref(h)), "cpm_init_static")
     return h.value
 
 

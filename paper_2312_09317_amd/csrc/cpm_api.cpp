@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -40,6 +41,7 @@ struct cpm_handle {
     uint64_t activation = 0;         // activations run so far (buffer parity)
     uint64_t attempts_run = 0;       // copy attempts run since init
     std::unique_ptr<DeviceModel> host_model;  // source of the async upload
+    int static_device = -1;          // device whose static workspace the handle holds (cpm_init_static), else -1
 };
 
 struct cpm_batch {
@@ -555,6 +557,50 @@ hipError_t start_lattice(const SweepArgs &a, const Layout &lay, char *ws, const 
 
 hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
+// The workspace of cpm_init_static: a device array of the library's own, one
+// copy per GPU, held by at most one handle per GPU at a time.  Host code
+// never passes `scratch` itself to the device (in host code the name stands
+// for a host-side shadow, not a device address): it takes each device's
+// address once, with hipGetSymbolAddress, and passes that.
+constexpr size_t kStaticScratchBytes = CPM_STATIC_WORKSPACE_BYTES;
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void *g_scratch_ptr[kMaxDevices] = {};
+bool g_scratch_busy[kMaxDevices] = {};
+
+// The current device's static workspace, claimed for one handle.
+int claim_static_scratch(void **ptr, int *device)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return device_fail(e, "current device");
+    if (dev < 0 || dev >= kMaxDevices) return fail(CPM_ENOTSUP, "device index beyond the static workspace table");
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (g_scratch_busy[dev])
+        return fail(CPM_EINVAL, "the static workspace of this device is held by another handle (cpm_destroy it first)");
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if ((e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))) != hipSuccess) return device_fail(e, "static workspace address");
+        if (!p) return fail(CPM_EDEVICE, "static workspace address is NULL");
+        g_scratch_ptr[dev] = p;
+    }
+    g_scratch_busy[dev] = true;
+    *ptr = g_scratch_ptr[dev];
+    *device = dev;
+    return CPM_OK;
+}
+
+void release_static_scratch(int dev)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (dev >= 0 && dev < kMaxDevices) g_scratch_busy[dev] = false;
+}
+
+int init_impl(const cpm_params *params, int32_t *d_lattice, const int32_t *d_cell_type, int32_t n_cells,
+              uint8_t *d_act, void *d_workspace, size_t workspace_bytes, void *stream, cpm_handle **out);
+
 // Number of sites of an int32 lattice labelled outside [-1, n_cells] (or -1
 // without an obstacle type), counted on the device into *flag and read back
 // (waits for the stream).
@@ -619,6 +665,39 @@ int cpm_tile_shape(const cpm_params *params, int32_t n_cells, int32_t *out)
 
 int cpm_init(const cpm_params *params, int32_t *d_lattice, const int32_t *d_cell_type, int32_t n_cells,
              uint8_t *d_act, void *d_workspace, size_t workspace_bytes, void *stream, cpm_handle **out)
+{
+    return init_impl(params, d_lattice, d_cell_type, n_cells, d_act, d_workspace, workspace_bytes, stream, out);
+}
+
+int cpm_init_static(const cpm_params *params, int32_t *d_lattice, const int32_t *d_cell_type, int32_t n_cells,
+                    uint8_t *d_act, void *stream, cpm_handle **out)
+{
+    if (!out) return fail(CPM_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate(params, n_cells);
+    if (rc != CPM_OK) return rc;
+    const size_t need = layout_of(params, n_cells).total;
+    if (need > kStaticScratchBytes)
+        return fail(CPM_ENOMEM, "this model needs " + std::to_string(need) + " bytes of workspace; the static one holds " +
+                                    std::to_string(kStaticScratchBytes) + " (use cpm_init with a caller workspace)");
+    void *ws = nullptr;
+    int dev = -1;
+    if ((rc = claim_static_scratch(&ws, &dev)) != CPM_OK) return rc;
+    rc = init_impl(params, d_lattice, d_cell_type, n_cells, d_act, ws, kStaticScratchBytes, stream, out);
+    if (rc != CPM_OK) {
+        release_static_scratch(dev);
+        return rc;
+    }
+    (*out)->static_device = dev;
+    return CPM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+int init_impl(const cpm_params *params, int32_t *d_lattice, const int32_t *d_cell_type, int32_t n_cells,
+              uint8_t *d_act, void *d_workspace, size_t workspace_bytes, void *stream, cpm_handle **out)
 {
     if (!out) return fail(CPM_EINVAL, "out is NULL");
     *out = nullptr;
@@ -686,7 +765,7 @@ int cpm_init(const cpm_params *params, int32_t *d_lattice, const int32_t *d_cell
     return CPM_OK;
 }
 
-}  // extern "C"
+}  // namespace
 
 namespace {
 
@@ -846,6 +925,7 @@ int cpm_get_mcs(const cpm_handle *h, uint64_t *mcs)
 
 int cpm_destroy(cpm_handle *h)
 {
+    if (h && h->static_device >= 0) release_static_scratch(h->static_device);
     delete h;
     return CPM_OK;
 }
