@@ -34,7 +34,7 @@ HBM_PEAK_GBS = 8000.0
 # sources are unchanged.
 MEASURED_TRAFFIC = {"sources_sha256": "a6292773102e85c3", "layout": "in_place", "tile": [64, 4, 1],
                     "fetch_kib": 17170.0, "write_kib": 1116.9, "fetch_scale": 2.0, "write_scale": 1.0}
-KERNEL_SOURCES = ("cpm_sweep.hip", "cpm_device.hpp", "cpm_internal.hpp")
+KERNEL_SOURCES = ("cpm_sweep_kernels.hpp", "cpm_sweep_inst.hip", "cpm_sweep.hip", "cpm_device.hpp", "cpm_internal.hpp")
 # The same for the 1024^3 tissue workload's activation kernel
 # (label-type-activity words).
 MEASURED_TRAFFIC_TISSUE = {"sources_sha256": "a6292773102e85c3", "layout": "in_place", "fetch_kib": 2570054.3,
@@ -88,20 +88,90 @@ def bytes_per_attempt(ndim, s, k, p_acc, act=False):
     return b
 
 
-def cpu_baseline(w, n_mcs):
+def host_cpus():
+    """CPUs of the host (nproc) and those this process may run on."""
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        allowed = os.cpu_count()
+    return {"nproc": os.cpu_count(), "allowed": allowed}
+
+
+def pinned(fn):
+    """fn() with the process pinned to one CPU, as taskset -c would pin it;
+    returns (fn's result, the CPU)."""
+    try:
+        old = os.sched_getaffinity(0)
+        cpu = max(old)
+        os.sched_setaffinity(0, {cpu})
+    except (AttributeError, OSError):
+        return fn(), None
+    try:
+        return fn(), cpu
+    finally:
+        os.sched_setaffinity(0, old)
+
+
+def oracle_model(w):
     import oracle
-    m = oracle.Model(w.ndim, w.dims[:w.ndim], w.J, w.lambda_V, w.V_target, w.lambda_S, w.S_target,
-                     T=w.T, seed=w.seed, s=w.s, k=w.k, lambda_P=w.lambda_P, mu_P=w.mu_P, dt_P=w.dt_P,
-                     lambda_C=w.lambda_C, C_field=w.C_field)
-    st = oracle.State(m, w.lattice, w.cell_type)
-    t0 = time.perf_counter()
-    st.sweep(n_mcs)
-    dt = time.perf_counter() - t0
+    return oracle.Model(w.ndim, w.dims[:w.ndim], w.J, w.lambda_V, w.V_target, w.lambda_S, w.S_target,
+                        lambda_act=w.lambda_act, max_act=w.max_act, T=w.T, seed=w.seed, lattice_id=w.lattice_id,
+                        s=w.s, k=w.k, obstacle_type=w.obstacle_type, lambda_P=w.lambda_P, mu_P=w.mu_P,
+                        dt_P=w.dt_P, lambda_C=w.lambda_C, C_field=w.C_field)
+
+
+def cpu_baseline(w, n_mcs):
+    """The oracle, pinned to one CPU, on the first n_mcs MCS of workload w."""
+    import oracle
+    st = oracle.State(oracle_model(w), w.lattice, w.cell_type, w.act)
+
+    def run():
+        t0 = time.perf_counter()
+        st.sweep(n_mcs)
+        return time.perf_counter() - t0
+    dt, cpu = pinned(run)
     attempts = int(st.stats[0])
     return {"value": attempts / dt, "unit": "attempts/s", "cores": 1, "kind": "oracle",
             "sample": f"first {n_mcs} MCS of the same {w.name} workload ({attempts} attempts, "
-                      f"{dt:.1f} s, one thread, initial recount excluded)",
-            "p_acc": float(st.stats[2]) / max(1, attempts)}
+                      f"{dt:.1f} s, one thread pinned to CPU {cpu}, initial recount excluded)",
+            "host_cpus": host_cpus(), "pinned_cpu": cpu, "p_acc": float(st.stats[2]) / max(1, attempts)}
+
+
+def cpu_fields(cpu):
+    """The cpu_baseline object of a bench line."""
+    if not cpu:
+        return None
+    return {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample", "host_cpus", "pinned_cpu") if k in cpu}
+
+
+def cpu_baseline_pool(ws, n_mcs, threads):
+    """The oracle on lattices ws (n_mcs MCS each), on one thread and then on
+    `threads` threads (the oracle's C calls release the GIL, so each thread
+    runs its own lattices on its own core)."""
+    import concurrent.futures
+    import oracle
+
+    def run(group):
+        n = 0
+        for w in group:
+            st = oracle.State(oracle_model(w), w.lattice, w.cell_type, w.act)
+            st.sweep(n_mcs)
+            n += int(st.stats[0])
+        return n
+
+    def timed(fn):
+        t0 = time.perf_counter()
+        n = fn()
+        return n, time.perf_counter() - t0
+    (n1, dt1), cpu = pinned(lambda: timed(lambda: run(ws)))
+    groups = [ws[i::threads] for i in range(threads)]
+    with concurrent.futures.ThreadPoolExecutor(max_workers=threads) as pool:
+        nn, dtn = timed(lambda: sum(pool.map(run, groups)))
+    return ({"value": n1 / dt1, "unit": "attempts/s", "cores": 1, "kind": "oracle",
+             "sample": f"{len(ws)} lattices x {n_mcs} MCS of the same workload ({n1} attempts, {dt1:.1f} s, one "
+                       f"thread pinned to CPU {cpu})", "host_cpus": host_cpus(), "pinned_cpu": cpu},
+            {"value": nn / dtn, "unit": "attempts/s", "cores": threads, "kind": "oracle",
+             "sample": f"the same {len(ws)} lattices x {n_mcs} MCS on {threads} threads ({dtn:.1f} s)"})
 
 
 def sample_mcs(args, default):
@@ -258,7 +328,7 @@ def main():
                    "tuning_ms_per_mcs": tuning},
         "roofline": roofline_fields(achieved, traffic, avg_launch_s, "tile_sweep_kernel",
                                     bytes_per_attempt(w.ndim, w.s, w.k, p_acc)),
-        "cpu_baseline": {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")} if cpu else None,
+        "cpu_baseline": cpu_fields(cpu),
     }
     print(json.dumps(out), flush=True)
     sim.close()
@@ -329,6 +399,14 @@ def bench_tissue(args):
     avg_launch_s = sweep_ms / 1e3 / (args.steps * n_act)
     per_launch_bytes = bytes_per_attempt(3, w.s, w.k, p_acc, act=True) * (w.n_sites // n_act)
     achieved = per_launch_bytes / avg_launch_s / 1e9
+    cpu = None
+    n_cpu = sample_mcs(args, 24)
+    if n_cpu > 0:
+        # the oracle on a 128^3 crop of the same recipe (obstacle field, cells
+        # of V_target 1000 at the same density, half of them motile)
+        crop = inputs.config2(L=128, grid=12, n_mcs=n_cpu)
+        cpu = cpu_baseline(crop, n_cpu)
+        cpu["sample"] = f"128^3 crop of the recipe ({crop.n_cells} cells): " + cpu["sample"]
     print(json.dumps({
         "metric": "site copy-attempts/s on 3D 1024³ tissue (HBM % peak)",
         "value": w.n_sites * args.steps / (total_ms / 1e3), "unit": "attempts/s", "n_gpus": 1,
@@ -343,7 +421,7 @@ def bench_tissue(args):
                                                        MEASURED_TRAFFIC_TISSUE),
                      "kernel": "tile_sweep_kernel_packed", "avg_launch_us": avg_launch_s * 1e6,
                      "bytes_per_attempt": bytes_per_attempt(3, w.s, w.k, p_acc, act=True)},
-        "cpu_baseline": None}), flush=True)
+        "cpu_baseline": cpu_fields(cpu)}), flush=True)
     sim.close()
 
 
@@ -397,7 +475,7 @@ def bench_sorting(args):
                                                        MEASURED_TRAFFIC_SORTING),
                      "kernel": "tile_sweep_kernel",
                      "avg_launch_us": avg_launch_s * 1e6, "bytes_per_attempt": bytes_per_attempt(2, w.s, w.k, p_acc)},
-        "cpu_baseline": {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")} if cpu else None}),
+        "cpu_baseline": cpu_fields(cpu)}),
         flush=True)
     sim.close()
 
@@ -464,7 +542,7 @@ def bench_collective(args):
                                                        MEASURED_TRAFFIC_COLLECTIVE),
                      "kernel": "tile_sweep_kernel",
                      "avg_launch_us": avg_launch_s * 1e6, "bytes_per_attempt": bytes_per_attempt(3, w.s, w.k, p_acc)},
-        "cpu_baseline": {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")} if cpu else None}),
+        "cpu_baseline": cpu_fields(cpu)}),
         flush=True)
     sim.close()
 
@@ -505,7 +583,7 @@ def bench_accuracy(args):
         "config": {"workload": w.name, "lattice": list(w.dims), "n_cells": w.n_cells, "runs": args.acc_runs,
                    "study": out},
         "roofline": None,
-        "cpu_baseline": {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")} if cpu else None}),
+        "cpu_baseline": cpu_fields(cpu)}),
         flush=True)
 
 
@@ -528,6 +606,30 @@ def bench_polarisation(args):
                      "mean_speed": np.round(m["mean_speed"], 4).tolist(), "gpu_s": m["ms"] / 1e3})
     n_att = len(lambdas) * out["n_runs"] * 200 * 200 * out["n_mcs"]
     main = out["modes"][1]
+    cpu = None
+    n_cpu = sample_mcs(args, 250)
+    if n_cpu > 0:
+        # the oracle on runs of the same ensemble: the parallel scheme at
+        # s = 2, k = 1, lambda_act 400, ten lattice ids
+        import oracle
+        from paper_2312_09317_amd import inputs
+        n1, dt, cpu_id = 0, 0.0, None
+        for r in range(10):
+            w = inputs.act_2d(lambda_act=400.0, n_mcs=n_cpu)
+            w.lattice_id = r
+            st = oracle.State(oracle_model(w), w.lattice, w.cell_type, w.act)
+
+            def run():
+                t0 = time.perf_counter()
+                st.sweep(n_cpu)
+                return time.perf_counter() - t0
+            d, cpu_id = pinned(run)
+            dt += d
+            n1 += int(st.stats[0])
+        cpu = {"value": n1 / dt, "unit": "attempts/s", "cores": 1, "kind": "oracle",
+               "sample": f"10 runs x {n_cpu} MCS of the same 200^2 Act cell at lambda_act 400, s = 2, k = 1 "
+                         f"({n1} attempts, {dt:.1f} s, one thread pinned to CPU {cpu_id})",
+               "host_cpus": host_cpus(), "pinned_cpu": cpu_id}
     print(json.dumps({
         "metric": "site copy-attempts/s of a 2D Act ensemble, with its directional autocorrelation against the serial CPM",
         "value": n_att / (main["ms"] / 1e3), "unit": "attempts/s", "n_gpus": 1, "steps": out["n_mcs"], "warmup": 0,
@@ -535,7 +637,7 @@ def bench_polarisation(args):
         "dtype": "int32", "data": "synthetic",
         "config": {"workload": "2d-200x200-act-single-cell", "lambdas": list(lambdas), "runs": out["n_runs"],
                    "interval": out["interval"], "modes": rows},
-        "roofline": None, "cpu_baseline": None}), flush=True)
+        "roofline": None, "cpu_baseline": cpu_fields(cpu)}), flush=True)
 
 
 def bench_batch(args):
@@ -563,6 +665,14 @@ def bench_batch(args):
     avg_launch_s = ms / 1e3 / (args.steps * n_act)
     per_launch_bytes = bytes_per_attempt(2, ws[0].s, ws[0].k, acc, act=True) * (sites // n_act)
     achieved = per_launch_bytes / avg_launch_s / 1e9
+    b.close()
+    cpu = cpu_threads = None
+    n_cpu = sample_mcs(args, 24)
+    if n_cpu > 0:
+        # the oracle on the first 64 lattices of the batch: one pinned
+        # thread, then one thread per allowed CPU (at most 16)
+        threads = max(1, min(16, host_cpus()["allowed"] or 1))
+        cpu, cpu_threads = cpu_baseline_pool(ws[:64], n_cpu, threads)
     print(json.dumps({
         "metric": "site copy-attempts/s, 512 batched uneven 2D lattices", "value": sites * args.steps / (ms / 1e3),
         "unit": "attempts/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -574,8 +684,7 @@ def bench_batch(args):
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic_bytes(None, MEASURED_TRAFFIC_BATCH),
                      "kernel": "batch_sweep_kernel",
                      "avg_launch_us": avg_launch_s * 1e6},
-        "cpu_baseline": None}), flush=True)
-    b.close()
+        "cpu_baseline": cpu_fields(cpu), "cpu_baseline_threads": cpu_fields(cpu_threads)}), flush=True)
 
 
 def bench_emulator(args):
@@ -586,13 +695,52 @@ def bench_emulator(args):
     r = emulator.study(n_train=args.emu_train, n_test=args.emu_test, reps=args.emu_reps, epochs=args.emu_epochs,
                        batch=args.emu_batch, lr=args.emu_lr, lr_final=args.emu_lr / 40, log=log,
                        data_path=args.emu_data)
+    cpu = emulator_cpu_baseline(args) if sample_mcs(args, 4) > 0 else None
     print(json.dumps({
         "metric": "emulator vs CPM cost per parameter point", "value": r["cost_ratio"], "unit": "x",
         "n_gpus": 1, "steps": args.emu_epochs, "warmup": 0, "ms_per_step": None, "higher_is_better": True,
         "scaling": "strong", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
         "config": {"workload": "emulator-6-256-256-256-8", **{k: r[k] for k in ("n_train", "n_test", "replicates",
                                                                                "plan", "L_range", "epochs")}},
-        "emulator": r, "roofline": None, "cpu_baseline": None}), flush=True)
+        "emulator": r, "roofline": None, "cpu_baseline": cpu_fields(cpu)}), flush=True)
+
+
+def emulator_cpu_baseline(args):
+    """The same cost ratio with both sides on one pinned CPU thread: the
+    oracle's CPM run per parameter point (a few MCS of sample points, scaled
+    to the study's MCS per run) against the FP64 reference MLP's forward pass
+    per point."""
+    import numpy as np
+    import oracle
+    from oracle import mlp
+    from paper_2312_09317_amd import emulator
+    plan = emulator.RunPlan()
+    pts = emulator.points(8, seed=1)
+    n_mcs = sample_mcs(args, 4)
+
+    def cpm_side():
+        t = 0.0
+        for q in pts:
+            w = q.workload()
+            st = oracle.State(oracle_model(w), w.lattice, w.cell_type, w.act)
+            t0 = time.perf_counter()
+            st.sweep(n_mcs)
+            t += time.perf_counter() - t0
+        return t / len(pts) * plan.n_mcs / n_mcs
+
+    def mlp_side():
+        W, b = mlp.init(0)
+        x = np.random.default_rng(0).standard_normal((65536, 6))
+        t0 = time.perf_counter()
+        mlp.forward(W, b, x)
+        return (time.perf_counter() - t0) / 65536
+    (cpm_s, cpu_id) = pinned(cpm_side)
+    (mlp_s, _) = pinned(mlp_side)
+    return {"value": cpm_s / mlp_s, "unit": "x", "cores": 1, "kind": "oracle",
+            "sample": f"oracle CPM: 8 parameter points x {n_mcs} MCS, scaled to {plan.n_mcs} MCS per run "
+                      f"({cpm_s:.2f} s per point); FP64 reference MLP: 65,536 points ({mlp_s * 1e6:.2f} us per "
+                      f"point); one thread pinned to CPU {cpu_id}",
+            "host_cpus": host_cpus(), "pinned_cpu": cpu_id}
 
 
 if __name__ == "__main__":

@@ -6,6 +6,8 @@ definitions it follows).  Only tests, the smoke check and the benchmark's
 CPU-baseline leg may import this package; the GPU library never does.
 """
 import ctypes
+import os
+
 import numpy as np
 
 from .build import ensure_built
@@ -14,9 +16,11 @@ _lib = None
 
 
 def lib():
+    """The oracle library: the built one, or the file CPM_ORACLE_LIB names
+    (e.g. a sanitizer build made by oracle.build.build(sanitize=True))."""
     global _lib
     if _lib is None:
-        _lib = ctypes.CDLL(ensure_built())
+        _lib = ctypes.CDLL(os.environ.get("CPM_ORACLE_LIB") or ensure_built())
         _declare(_lib)
     return _lib
 

@@ -41,3 +41,24 @@ def test_tables_are_well_formed():
         assert len(t["sources_sha256"]) == 16
         assert t["fetch_kib"] > 0 and t["write_kib"] > 0
         assert (t["fetch_scale"], t["write_scale"]) == (2.0, 1.0)
+
+
+def test_traffic_is_keyed_on_the_tile():
+    t = dict(_table(bench.kernel_sources_sha()), tile=[64, 2, 2])
+    assert bench.measured_traffic_bytes("in_place", t, tile=(64, 2, 2)) is not None
+    assert bench.measured_traffic_bytes("in_place", t, tile=(64, 4, 1)) is None
+
+
+def test_roofline_reports_both_fractions():
+    r = bench.roofline_fields(4000.0, 40e6, 10e-6, "k", 256.0)
+    assert r["frac"] == 0.5 and r["peak"] == 8000.0
+    assert abs(r["achieved_measured_bytes"] - 4000.0) < 1e-9 and abs(r["frac_measured_bytes"] - 0.5) < 1e-12
+    r = bench.roofline_fields(4000.0, None, 10e-6, "k", 256.0)
+    assert r["traffic"] is None and r["frac_measured_bytes"] is None
+
+
+def test_pinned_restores_the_affinity():
+    before = os.sched_getaffinity(0)
+    out, cpu = bench.pinned(lambda: os.sched_getaffinity(0))
+    assert out == {cpu} and cpu in before
+    assert os.sched_getaffinity(0) == before
