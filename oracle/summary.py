@@ -72,7 +72,9 @@ def summary(V, S, pos, dims, interval):
             else:
                 units.append(None)
         m = len(units)
-        a_prev = 1.0
+        # A(0) = 1; the crossing of 1/e is interpolated linearly between the
+        # last lag where A was defined and the first where it falls below
+        a_prev, last = 1.0, 0
         p = None
         any_lag = False
         for tau in range(1, m):
@@ -83,7 +85,7 @@ def summary(V, S, pos, dims, interval):
             any_lag = True
             a = sum(vals) / len(vals)
             if a < INV_E:
-                p = (tau - 1) + (a_prev - INV_E) / (a_prev - a)
+                p = last + (tau - last) * (a_prev - INV_E) / (a_prev - a)
                 break
             a_prev = a
             last = tau

@@ -154,7 +154,8 @@ __global__ void __launch_bounds__(256) summary_kernel(const StatsTables t, const
             any_lag = true;
             const double a = acc / (double)cnt;
             if (a < inv_e) {
-                p = (double)(tau - 1) + (a_prev - inv_e) / (a_prev - a);
+                // linear between the last defined lag and this one
+                p = (double)last + (double)(tau - last) * (a_prev - inv_e) / (a_prev - a);
                 done = true;
             } else {
                 a_prev = a;

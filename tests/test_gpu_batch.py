@@ -193,3 +193,28 @@ def test_act_batch_words_with_serial_steps(torch_cuda, types_per_lattice):
         assert tuple(int(x) for x in stats[i]) == tuple(int(x) for x in st.stats)
     assert all(b.check_invariants())
     assert sum(int(st.stats[2]) for st in states) > 0
+
+
+def test_summary_persistence_with_undefined_lags(torch_cuda):
+    # samples written directly: one cell that moves, rests, moves back,
+    # rests, moves on, so that A(1) is undefined; the library's persistence
+    # time must equal the oracle's interpolation from the last defined lag
+    from oracle import summary
+    torch = torch_cuda
+    w = inputs.config3(n_lattices=1, L_min=48, L_max=48, seed=2, n_mcs=0)[0]
+    b = cpm.Batch([cpm.Params.from_workload(w)], [w.lattice], [w.cell_type])
+    C = w.n_cells
+    xs = [10.0, 13.0, 13.0, 10.0, 10.0, 13.0]
+    K = len(xs)
+    smp = np.zeros((K, C + 1, 5))
+    for k, x in enumerate(xs):
+        smp[k, 1:, 0] = 100.0
+        smp[k, 1:, 1] = 40.0
+        smp[k, 1:, 2] = x
+        smp[k, 1:, 3] = 20.0
+    out = b.summary(torch.as_tensor(smp.reshape(-1)).cuda(), K, 4.0).cpu().numpy().reshape(-1)
+    V, S = smp[:, :, 0], smp[:, :, 1]
+    ref = summary.summary(V, S, smp[:, :, 2:4], w.dims, 4.0)
+    np.testing.assert_allclose(out[:8], ref, rtol=1e-12, atol=1e-12)
+    assert np.isclose(out[6], 4.0 * (1.0 - np.exp(-1.0)))
+    b.close()

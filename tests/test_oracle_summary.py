@@ -40,6 +40,20 @@ def test_alternating_direction():
     assert np.isclose(out[6], 5.0 * (1 - np.exp(-1)) / 2.0)
 
 
+def test_persistence_interpolates_from_the_last_defined_lag():
+    # the cell moves +x, rests, moves -x, rests, moves +x: no lag-1 pair of
+    # unit steps is defined (every pair holds a rest), lag 2 pairs are
+    # (+x, -x) and (-x, +x), so A(2) = -1 and A(1) is undefined; the 1/e
+    # crossing lies on the line from A(0) = 1 to A(2) = -1:
+    # tau = 2 (1 - 1/e) / 2 = 1 - 1/e sample intervals
+    xs = [10.0, 13.0, 13.0, 10.0, 10.0, 13.0]
+    pos = np.array([[[x, 20.0]] for x in xs])
+    V, S, P = _traj(pos)
+    out = summary.summary(V, S, P, (50, 50), interval=4.0)
+    assert np.isclose(out[6], 4.0 * (1.0 - np.exp(-1.0)))
+    assert out[7] == 0.0
+
+
 def test_minimum_image_and_dead_cells():
     # a jump from x = 49 to x = 1 is a step of +2 on a 50-periodic axis
     pos = np.array([[[49.0, 0.0], [10.0, 10.0]], [[1.0, 0.0], [10.0, 10.0]], [[3.0, 0.0], [12.0, 10.0]]])
