@@ -214,6 +214,8 @@ def main():
                     help="thread areas per workgroup tile as X,Y,Z (with a named --layout; default: the "
                          "library's choice)")
     ap.add_argument("--tune-mcs", type=int, default=6, help="MCS timed per candidate layout when tuning")
+    ap.add_argument("--batch-mode", default=None, choices=("graph", "eager", "persistent"),
+                    help="batch workload: how each sweep is launched (default: the tuner's choice, else graph)")
     ap.add_argument("--acc-runs", type=int, default=250, help="accuracy workload: runs per ensemble")
     ap.add_argument("--acc-mcs", type=int, default=200, help="accuracy workload: MCS per run")
     ap.add_argument("--emu-train", type=int, default=8192, help="emulator workload: training runs")
@@ -650,7 +652,22 @@ def bench_batch(args):
     ws = inputs.config3(n_lattices=512, seed=1, n_mcs=args.steps)
     sites = sum(w.n_sites for w in ws)
     log(f"batch of {len(ws)} lattices, {sites} sites")
-    b = cpm.Batch([cpm.Params.from_workload(w) for w in ws], [w.lattice for w in ws], [w.cell_type for w in ws])
+    params = [cpm.Params.from_workload(w) for w in ws]
+    lattices, types = [w.lattice for w in ws], [w.cell_type for w in ws]
+    cfg = {"layout": "in_place" if args.layout in ("tune", "auto") else args.layout, "tiles": ["auto"] * len(ws),
+           "mode": args.batch_mode or "graph"}
+    tuning = None
+    if args.layout == "tune":
+        r = cpm.autotune_batch(params, lattices, types, trial_mcs=args.tune_mcs, log=log)
+        cfg = dict(r["best"], mode=args.batch_mode or r["best"]["mode"])
+        tuning = {k: round(v, 4) for k, v in sorted(r["times"].items(), key=lambda kv: kv[1])}
+    b = cpm.Batch(cpm.batch_params(params, cfg), lattices, types)
+    b.launch_mode(cfg["mode"])
+    classes = cpm.size_classes(params)
+    tuned = {"layout": cfg["layout"], "mode": cfg["mode"],
+             "tile_by_size_class": [{"sides": [min(ws[i].dims[0] for i in c), max(ws[i].dims[0] for i in c)],
+                                     "lattices": len(c), "tile": cfg["tiles"][c[0]]} for c in classes]}
+    log(f"batch configuration: {tuned}")
     b.sweep(args.warmup)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -679,7 +696,9 @@ def bench_batch(args):
         "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "int32", "data": "synthetic",
         "config": {"workload": "2d-batch-512-L64..512", "n_lattices": len(ws), "sites": sites, "sub": ws[0].s,
-                   "attempts_per_activation": ws[0].k, "act": True, "graph": True},
+                   "attempts_per_activation": ws[0].k, "act": True, "launch": tuned, "tuning_ms_per_mcs": tuning,
+                   "label_storage": "uint16 words: label + 1 and activity (one cell type, at most 2,046 cells, "
+                                    "Max_act <= 31), written from the int32 lattices and activities per sweep call"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic_bytes(None, MEASURED_TRAFFIC_BATCH),
                      "kernel": "batch_sweep_kernel",

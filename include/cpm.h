@@ -296,6 +296,23 @@ int cpm_batch_sweep(cpm_batch *b, int32_t n_mcs, void *stream);
 /* enabled = 0: cpm_batch_sweep launches the same kernels one by one instead
  * of the graph (same results).  Pure host. */
 int cpm_batch_use_graph(cpm_batch *b, int32_t enabled);
+/* How cpm_batch_sweep launches its work (same results in every mode; pure
+ * host): 0 = one replay of the captured MCS graph per MCS (the default),
+ * 1 = the graph's kernels one by one, 2 = one persistent launch per call:
+ * as many workgroups as the GPU holds at once (launched cooperatively, so
+ * all are resident) loop over the (lattice, tile) work table and meet at a
+ * device-wide barrier after every activation and after every MCS's Act
+ * decay (paper, Results, "Designing a parallel execution scheme": the
+ * whole grid synchronises between activations).  Mode 2 needs batches swept
+ * in place (k = 1; CPM_ENOTSUP otherwise).  A barrier wait is bounded (see
+ * cpm_batch_set_barrier_spin_limit): a launch whose wait runs out ends
+ * early and leaves the batch invalid, which cpm_batch_attempt_stats and
+ * cpm_batch_check_invariants report as CPM_EDEVICE. */
+int cpm_batch_launch_mode(cpm_batch *b, int32_t mode);
+/* Polls of one barrier wait before a persistent launch gives up (default
+ * 2^20, about a second; a barrier normally completes in microseconds).
+ * Pure host. */
+int cpm_batch_set_barrier_spin_limit(cpm_batch *b, uint32_t polls);
 /* Runs n_mcs MCS of the serial CPM on every lattice (Methods, first
  * paragraph; the reference of Fig. 5 and Fig. 6E): per MCS, N = sites copy
  * attempts, attempt i at target floor(u0 * N / 2^32) with the Philox counter

@@ -61,7 +61,8 @@ LAYOUTS = {"auto": 0, "box": 1, "full_rows": 2, "in_place": 3}
 
 EXPORTS = ("cpm_validate", "cpm_workspace_bytes", "cpm_tile_shape", "cpm_init", "cpm_init_static", "cpm_sweep", "cpm_cell_stats", "cpm_contacts",
            "cpm_persistence", "cpm_counters", "cpm_check_invariants", "cpm_attempt_stats", "cpm_set_mcs", "cpm_get_mcs", "cpm_destroy",
-           "cpm_batch_workspace_bytes", "cpm_batch_init", "cpm_batch_sweep", "cpm_batch_sweep_serial", "cpm_batch_occupancy", "cpm_batch_use_graph", "cpm_batch_counters",
+           "cpm_batch_workspace_bytes", "cpm_batch_init", "cpm_batch_sweep", "cpm_batch_sweep_serial", "cpm_batch_occupancy", "cpm_batch_use_graph", "cpm_batch_launch_mode",
+           "cpm_batch_set_barrier_spin_limit", "cpm_batch_counters",
            "cpm_batch_cell_stats", "cpm_batch_attempt_stats", "cpm_batch_check_invariants", "cpm_batch_sample", "cpm_batch_summary", "cpm_batch_autocorrelation",
            "cpm_batch_set_mcs", "cpm_batch_get_mcs",
            "cpm_batch_destroy", "cpm_strerror", "cpm_last_error")
@@ -103,6 +104,8 @@ def load(path: str = LIB_PATH):
     l.cpm_batch_init.argtypes = [pp, I32, P, P, P, P, P, SZ, P, ctypes.POINTER(P)]
     l.cpm_batch_sweep.argtypes = [P, I32, P]
     l.cpm_batch_use_graph.argtypes = [P, I32]
+    l.cpm_batch_launch_mode.argtypes = [P, I32]
+    l.cpm_batch_set_barrier_spin_limit.argtypes = [P, ctypes.c_uint32]
     l.cpm_batch_sweep_serial.argtypes = [P, I32, P]
     l.cpm_batch_occupancy.argtypes = [P, P, P]
     l.cpm_batch_counters.argtypes = [P, P, P, P]
@@ -449,6 +452,18 @@ def cpm_batch_occupancy(h: int, d_counts, stream: int) -> None:
     _check(load().cpm_batch_occupancy(h, _ptr(d_counts), stream), "cpm_batch_occupancy")
 
 
+BATCH_MODES = {"graph": 0, "eager": 1, "persistent": 2}
+
+
+def cpm_batch_launch_mode(h: int, mode) -> None:
+    _check(load().cpm_batch_launch_mode(h, BATCH_MODES[mode] if isinstance(mode, str) else int(mode)),
+           "cpm_batch_launch_mode")
+
+
+def cpm_batch_set_barrier_spin_limit(h: int, polls: int) -> None:
+    _check(load().cpm_batch_set_barrier_spin_limit(h, polls), "cpm_batch_set_barrier_spin_limit")
+
+
 def cpm_batch_use_graph(h: int, enabled: bool) -> None:
     _check(load().cpm_batch_use_graph(h, 1 if enabled else 0), "cpm_batch_use_graph")
 
@@ -558,6 +573,10 @@ class Batch:
 
     def use_graph(self, enabled: bool) -> None:
         cpm_batch_use_graph(self.handle, enabled)
+
+    def launch_mode(self, mode) -> None:
+        """"graph" (one graph replay per MCS), "eager" or "persistent"."""
+        cpm_batch_launch_mode(self.handle, mode)
 
     def lattice(self, i):
         return self.lattices[int(self.site_off[i]):int(self.site_off[i + 1])]
@@ -687,3 +706,109 @@ def autotune(params: Params, lattice, cell_type, act=None, trial_mcs: int = 2, c
         sim.close()
     best = min(times, key=times.get)
     return {"best": best, "times": times}
+
+
+# ---------------------------------------------------------------- batch autotuner
+
+# Thread-area tile shapes tried for in-place batches, per axis (clipped to a
+# lattice's areas); None = the library's choice (whole rows of areas first).
+BATCH_TILE_RULES = {"auto": None, "16x16": (16, 16, 1), "32x8": (32, 8, 1), "64x4": (64, 4, 1), "8x8x4": (8, 8, 4)}
+
+
+def _tile_for(rule, p: Params):
+    c = p.c
+    if rule is None:
+        return (0, 0, 0)
+    na = [c.dims[d] // (2 * c.sub) if d < c.ndim else 1 for d in range(3)]
+    return tuple(min(rule[d], na[d]) for d in range(3))
+
+
+def size_classes(params, bounds=(160, 320)):
+    """Lattice index lists by largest side: <= bounds[0], <= bounds[1], larger."""
+    out = [[] for _ in range(len(bounds) + 1)]
+    for i, p in enumerate(params):
+        side = max(p.c.dims[d] for d in range(p.c.ndim))
+        out[sum(side > b for b in bounds)].append(i)
+    return [c for c in out if c]
+
+
+def autotune_batch(params, lattices, cell_types, acts=None, trial_mcs=3, device="cuda", log=None):
+    """Time launch configurations of a batch and return the fastest.
+
+    Candidates (each on a fresh copy of the batch, one warm-up MCS, then
+    trial_mcs timed MCS): the in-place layout with each tile rule of
+    BATCH_TILE_RULES for every lattice, the staged layouts, then, from the
+    best, one size class (size_classes) at a time given each other tile rule,
+    and the persistent launch.  Every candidate must leave the same lattices
+    and activities (results never depend on the launch), else RuntimeError.
+    Returns {"best": config, "times": {name: ms per MCS}} with config =
+    {"layout", "tiles" (one rule name per lattice), "mode"}; apply it with
+    batch_params(params, config)."""
+    import hashlib
+    import torch
+    say = log or (lambda m: None)
+    n = len(params)
+    k1 = params[0].c.attempts == 1
+    times, digest = {}, [None]
+    ndim = params[0].c.ndim
+    rules = [r for r in BATCH_TILE_RULES if ndim == 3 or BATCH_TILE_RULES[r] is None or BATCH_TILE_RULES[r][2] == 1]
+
+    def trial(name, cfg):
+        try:
+            b = Batch(batch_params(params, cfg), lattices, cell_types, acts, device=device)
+            b.launch_mode(cfg["mode"])
+        except CpmError as e:
+            say(f"autotune_batch: {name} not run ({e})")
+            return None
+        b.sweep(1)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.sweep(trial_mcs)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / trial_mcs
+        h = hashlib.sha256(b.lattices.cpu().numpy().tobytes())
+        if b.act is not None:
+            h.update(b.act.cpu().numpy().tobytes())
+        b.close()
+        if digest[0] is None:
+            digest[0] = h.hexdigest()
+        elif h.hexdigest() != digest[0]:
+            raise RuntimeError(f"batch configuration {name} changed the result of the sweep")
+        times[name] = ms
+        say(f"autotune_batch: {name} {ms:.3f} ms per MCS")
+        return ms
+
+    best_cfg, best_ms = None, None
+
+    def consider(name, cfg):
+        nonlocal best_cfg, best_ms
+        ms = trial(name, cfg)
+        if ms is not None and (best_ms is None or ms < best_ms):
+            best_cfg, best_ms = cfg, ms
+
+    if k1:
+        for r in rules:
+            consider(f"in_place/{r}/graph", {"layout": "in_place", "tiles": [r] * n, "mode": "graph"})
+        for lay in ("full_rows", "box"):
+            consider(f"{lay}/graph", {"layout": lay, "tiles": ["auto"] * n, "mode": "graph"})
+    else:
+        consider("box/graph", {"layout": "box", "tiles": ["auto"] * n, "mode": "graph"})
+    if best_cfg["layout"] == "in_place":
+        for ci, cls in enumerate(size_classes(params)):
+            for r in rules:
+                if all(best_cfg["tiles"][i] == r for i in cls):
+                    continue
+                tiles = list(best_cfg["tiles"])
+                for i in cls:
+                    tiles[i] = r
+                consider(f"in_place/class{ci}={r}/graph", dict(best_cfg, tiles=tiles))
+        consider("in_place/best/persistent", dict(best_cfg, mode="persistent"))
+    return {"best": best_cfg, "times": times}
+
+
+def batch_params(params, cfg):
+    """params with a batch configuration of autotune_batch applied."""
+    return [p.replace(layout=cfg["layout"], tile=_tile_for(BATCH_TILE_RULES[t], p))
+            for p, t in zip(params, cfg["tiles"])]

@@ -80,6 +80,9 @@ struct cpm_batch {
     size_t max_sites = 0;
     int64_t max_bricks = 0;          // largest centroid-reduction grid of the lattices
     bool use_graph = true;
+    int mode = 0;                    // 0: one graph replay per MCS, 1: kernels one by one, 2: persistent launch
+    cpm::GridBarrier *bar = nullptr; // barrier of the persistent launch
+    uint32_t spin_limit = 1u << 20;  // polls of a barrier wait before the launch gives up
     hipGraphExec_t mcs_graph = nullptr;  // one MCS: every activation, act decay, MCS counter
     ~cpm_batch()
     {
@@ -954,7 +957,7 @@ namespace {
 struct BatchLayout {
     std::vector<Layout> lat;
     std::vector<size_t> base;  // workspace offset of each lattice's sections
-    size_t args, work, mcs, label_off, dims, scratch_v, scratch_s, scratch_c, scratch_ref, total;
+    size_t args, work, mcs, barrier, label_off, dims, scratch_v, scratch_s, scratch_c, scratch_ref, total;
     size_t total_labels;
     int grid;
     bool mirror, feasible;
@@ -1021,6 +1024,8 @@ BatchLayout batch_layout_of(const cpm_params *p, int32_t n, const int32_t *n_cel
     off = align_up(off + sizeof(int2) * (size_t)b.grid);
     b.mcs = off;
     off = align_up(off + sizeof(uint32_t));
+    b.barrier = off;
+    off = align_up(off + sizeof(cpm::GridBarrier));
     b.total_labels = 0;
     for (int32_t i = 0; i < n; ++i) b.total_labels += (size_t)n_cells[i] + 1;
     b.label_off = off;
@@ -1152,6 +1157,9 @@ int cpm_batch_init(const cpm_params *params, int32_t n, const int32_t *n_cells, 
     b->d_args = reinterpret_cast<SweepArgs *>(ws + bl.args);
     b->d_work = reinterpret_cast<int2 *>(ws + bl.work);
     b->d_mcs = reinterpret_cast<uint32_t *>(ws + bl.mcs);
+    b->bar = reinterpret_cast<cpm::GridBarrier *>(ws + bl.barrier);
+    if ((e = cpm::launch_fill_i32(reinterpret_cast<int32_t *>(b->bar), 0, 4, st)) != hipSuccess)
+        return device_fail(e, "clear barrier");
     // one cell type throughout and small lattices: 16-bit label-activity words
     b->act16 = bl.act16_ok && b->single;
     if (b->act16) {
@@ -1236,6 +1244,20 @@ hipError_t enqueue_mcs(const cpm_batch *b, uint32_t n_act, hipStream_t st)
     return cpm::launch_add_u32(b->d_mcs, 1u, st);
 }
 
+// CPM_EDEVICE when a persistent launch of the batch gave up waiting at a
+// grid barrier (its state is then invalid); waits for the stream.
+int check_barrier(cpm_batch *b, hipStream_t st)
+{
+    cpm::GridBarrier g{};
+    hipError_t e = hipMemcpyAsync(&g, b->bar, sizeof(g), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return device_fail(e, "read barrier");
+    if (g.abort)
+        return fail(CPM_EDEVICE, "a persistent launch of this batch gave up at a grid barrier (spin limit reached); "
+                                 "the batch state is invalid");
+    return CPM_OK;
+}
+
 // Capture one MCS into an executable graph, on a private stream of default
 // priority (the caller's stream is never put into capture mode).  The graph
 // holds kernel nodes only.
@@ -1270,7 +1292,7 @@ int cpm_batch_sweep(cpm_batch *b, int32_t n_mcs, void *stream)
     for (int d = 0; d < b->ndim; ++d) sd *= b->s;
     const uint32_t n_act = (uint32_t)(((int64_t)1 << b->ndim) * sd / b->k);
     hipError_t e;
-    if (b->use_graph && !b->mcs_graph && (e = capture_mcs(b, n_act)) != hipSuccess)
+    if (b->mode == 0 && !b->mcs_graph && (e = capture_mcs(b, n_act)) != hipSuccess)
         return device_fail(e, "capture MCS graph");
     if (b->mirror && (e = cpm::launch_batch_mirror(b->d_args, b->n, b->max_sites, true, st)) != hipSuccess)
         return device_fail(e, "to 16-bit working copy");
@@ -1279,8 +1301,29 @@ int cpm_batch_sweep(cpm_batch *b, int32_t n_mcs, void *stream)
     if (b->act16 && (e = cpm::launch_to_act16(b->lattices, b->act_field, b->words16, b->total_sites, st)) != hipSuccess)
         return device_fail(e, "to 16-bit label-activity words");
     if ((e = cpm::launch_set_u32(b->d_mcs, (uint32_t)b->mcs, st)) != hipSuccess) return device_fail(e, "set mcs");
-    for (int32_t m = 0; m < n_mcs; ++m) {
-        e = b->use_graph ? hipGraphLaunch(b->mcs_graph, st) : enqueue_mcs(b, n_act, st);
+    if (b->mode == 2) {
+        // every MCS in one launch; the barrier's count and generation start
+        // at 0 (its abort flag is sticky)
+        cpm::PersistentLaunch p{};
+        p.bar = b->bar;
+        p.mcs0 = (uint32_t)b->mcs;
+        p.n_mcs = n_mcs;
+        p.n_act = n_act;
+        p.n_work = b->launch.grid;
+        p.spin_limit = b->spin_limit;
+        p.decay_mode = !b->act ? 0 : b->act16 ? 3 : b->act_words ? 2 : 1;
+        p.decay_ptr = !b->act ? nullptr : b->act16 ? static_cast<void *>(b->words16)
+                    : b->act_words ? static_cast<void *>(b->lattices) : static_cast<void *>(b->act_field);
+        p.n_sites = b->total_sites;
+        if ((e = cpm::launch_fill_i32(reinterpret_cast<int32_t *>(b->bar), 0, 2, st)) != hipSuccess ||
+            (e = cpm::launch_batch_persistent(b->launch, p, st)) != hipSuccess)
+            return device_fail(e, "persistent launch");
+        b->activation += (uint64_t)n_act * (uint64_t)n_mcs;
+        b->mcs += (uint64_t)n_mcs;
+        b->mcs_run += (uint64_t)n_mcs;
+    }
+    for (int32_t m = 0; m < n_mcs && b->mode != 2; ++m) {
+        e = b->mode == 0 ? hipGraphLaunch(b->mcs_graph, st) : enqueue_mcs(b, n_act, st);
         if (e != hipSuccess) return device_fail(e, "MCS");
         b->activation += n_act;
         ++b->mcs;
@@ -1337,10 +1380,29 @@ int cpm_batch_occupancy(cpm_batch *b, int32_t *d_counts, void *stream)
     return e == hipSuccess ? CPM_OK : device_fail(e, "occupancy");
 }
 
+int cpm_batch_launch_mode(cpm_batch *b, int32_t mode)
+{
+    if (!b) return fail(CPM_EINVAL, "batch is NULL");
+    if (mode < 0 || mode > 2) return fail(CPM_EINVAL, "mode must be 0, 1 or 2");
+    if (mode == 2 && !(b->k == 1 && b->layout == 2))
+        return fail(CPM_ENOTSUP, "the persistent launch runs batches swept in place (k = 1)");
+    b->mode = mode;
+    b->use_graph = mode == 0;
+    return CPM_OK;
+}
+
+int cpm_batch_set_barrier_spin_limit(cpm_batch *b, uint32_t polls)
+{
+    if (!b) return fail(CPM_EINVAL, "batch is NULL");
+    b->spin_limit = polls;
+    return CPM_OK;
+}
+
 int cpm_batch_use_graph(cpm_batch *b, int32_t enabled)
 {
     if (!b) return fail(CPM_EINVAL, "batch is NULL");
     b->use_graph = enabled != 0;
+    b->mode = enabled ? 0 : 1;
     return CPM_OK;
 }
 
@@ -1369,6 +1431,8 @@ int cpm_batch_attempt_stats(cpm_batch *b, uint64_t *out, void *stream)
 {
     if (!b || !out) return fail(CPM_EINVAL, "NULL argument");
     hipStream_t st = as_stream(stream);
+    int rc = check_barrier(b, st);
+    if (rc != CPM_OK) return rc;
     for (int32_t i = 0; i < b->n; ++i) {
         const SweepArgs &a = b->args[i];
         std::vector<uint64_t> per(2 * (size_t)a.tg.n_tiles);
@@ -1420,6 +1484,8 @@ int cpm_batch_check_invariants(cpm_batch *b, void *stream, int32_t *h_ok)
 {
     if (!b || !h_ok) return fail(CPM_EINVAL, "NULL argument");
     hipStream_t st = as_stream(stream);
+    int rc = check_barrier(b, st);
+    if (rc != CPM_OK) return rc;
     const int32_t n = b->n;
     std::vector<int32_t> bad((size_t)n, 0);
     auto sites = [&](int32_t i) { return (size_t)b->args[i].L[0] * b->args[i].L[1] * b->args[i].L[2]; };

@@ -118,6 +118,32 @@ struct BatchLaunch {
     int layout;
 };
 
+// State of the device-wide barrier of a persistent batch launch (device
+// memory): arrivals, generation, and a sticky flag raised by a workgroup
+// that gave up waiting.
+struct GridBarrier {
+    uint32_t count;
+    uint32_t gen;
+    uint32_t abort;
+    uint32_t pad;
+};
+
+// One persistent launch: n_mcs MCS of a batch (every activation, then the
+// Act decay) in one kernel, workgroups looping over the work table and
+// meeting at a grid barrier between phases.
+struct PersistentLaunch {
+    GridBarrier *bar;
+    uint32_t mcs0;           // MCS index of the first MCS
+    int32_t n_mcs;
+    uint32_t n_act;          // activations per MCS
+    int32_t n_work;          // entries of the work table
+    uint32_t spin_limit;     // polls of a barrier wait before giving up
+    int32_t decay_mode;      // Act decay after each MCS: 0 none, 1 uint8 array, 2 int32 words (bits 24..31),
+                             // 3 16-bit words (bits 11..15)
+    void *decay_ptr;
+    size_t n_sites;          // sites of the whole batch
+};
+
 // Per-lattice tables for the summary statistics of a batch (device arrays).
 struct StatsTables {
     const int64_t *label_off;  // n + 1 label offsets (labels of lattice i: [off[i], off[i+1]))
@@ -175,6 +201,12 @@ hipError_t sweep_words(const SweepArgs &a, bool act, uint32_t mcs, uint32_t alph
                        hipStream_t st);
 template <typename Cell, int D>
 hipError_t batch_words(const BatchLaunch &b, uint32_t alpha, int parity, hipStream_t st);
+// A persistent launch of a batch swept in place (k = 1): as many workgroups
+// as fit the device at once (a multiple of the XCD count), launched
+// cooperatively so that all are resident.
+template <typename Cell, int D>
+hipError_t batch_persistent_words(const BatchLaunch &b, const PersistentLaunch &p, hipStream_t st);
+hipError_t launch_batch_persistent(const BatchLaunch &b, const PersistentLaunch &p, hipStream_t stream);
 hipError_t launch_pack(int32_t *lat, const int32_t *cell_type, int obstacle_type, size_t n, hipStream_t stream);
 hipError_t launch_unpack(int32_t *lat, size_t n, hipStream_t stream);
 // The same with the activity in bits 24..31 (label + 1 in 0..19, type in 20..23).

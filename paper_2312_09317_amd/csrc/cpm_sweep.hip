@@ -251,6 +251,18 @@ hipError_t launch_batch_activation(const BatchLaunch &b, uint32_t alpha, int par
     return d2 ? batch_words<int32_t, 2>(b, alpha, parity, stream) : batch_words<int32_t, 3>(b, alpha, parity, stream);
 }
 
+hipError_t launch_batch_persistent(const BatchLaunch &b, const PersistentLaunch &p, hipStream_t stream)
+{
+    const bool d2 = b.ndim == 2;
+    if (b.act16)
+        return d2 ? batch_persistent_words<char16_t, 2>(b, p, stream) : batch_persistent_words<char16_t, 3>(b, p, stream);
+    if (b.act_words)
+        return d2 ? batch_persistent_words<char32_t, 2>(b, p, stream) : batch_persistent_words<char32_t, 3>(b, p, stream);
+    if (b.mirror)
+        return d2 ? batch_persistent_words<uint16_t, 2>(b, p, stream) : batch_persistent_words<uint16_t, 3>(b, p, stream);
+    return d2 ? batch_persistent_words<int32_t, 2>(b, p, stream) : batch_persistent_words<int32_t, 3>(b, p, stream);
+}
+
 hipError_t launch_batch_act_words(const SweepArgs *d_args, int n_lattices, size_t max_sites, bool to_words,
                                   hipStream_t stream)
 {

@@ -10,7 +10,9 @@ namespace cpm {
 
 #define CPM_SWEEP(CELL, D)                                                                                        \
     template hipError_t sweep_words<CELL, D>(const SweepArgs &, bool, uint32_t, uint32_t, int, size_t, hipStream_t);
-#define CPM_BATCH(CELL, D) template hipError_t batch_words<CELL, D>(const BatchLaunch &, uint32_t, int, hipStream_t);
+#define CPM_BATCH(CELL, D)                                                                                        \
+    template hipError_t batch_words<CELL, D>(const BatchLaunch &, uint32_t, int, hipStream_t);                  \
+    template hipError_t batch_persistent_words<CELL, D>(const BatchLaunch &, const PersistentLaunch &, hipStream_t);
 
 #if CPM_SWEEP_PART == 0
 CPM_SWEEP(int32_t, 2)

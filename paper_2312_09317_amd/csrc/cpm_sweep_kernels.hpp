@@ -685,6 +685,117 @@ __global__ void __launch_bounds__(kBlock) batch_sweep_kernel(const SweepArgs *ar
     sweep_tile<Cell, D, ACT, SINGLE, K1, LAYOUT, EXT>(args[w.x], w.y, *mcs, alpha, parity);
 }
 
+// Device-wide barrier of a persistent launch.  Thread 0 of each workgroup
+// arrives (agent-scope release of the workgroup's writes); the last arrival
+// resets the count and bumps the generation, the others poll it (acquire).
+// A wait is bounded: after spin_limit polls the workgroup raises the abort
+// flag, and every workgroup leaves at its next barrier once the flag is
+// raised, so the launch always ends.  Returns false when leaving.
+__device__ __forceinline__ bool grid_sync(const PersistentLaunch &p, uint32_t &gen)
+{
+    __shared__ uint32_t s_go;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        GridBarrier *bar = p.bar;
+        uint32_t go = 1;
+        __threadfence();
+        const uint32_t g = gen;
+        if (atomicAdd(&bar->count, 1u) == gridDim.x - 1) {
+            atomicExch(&bar->count, 0u);
+            __threadfence();
+            atomicAdd(&bar->gen, 1u);
+        } else {
+            uint32_t polls = 0;
+            while (__hip_atomic_load(&bar->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                if (__hip_atomic_load(&bar->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
+                    polls++ >= p.spin_limit) {
+                    atomicExch(&bar->abort, 1u);
+                    go = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        gen = g + 1;
+        __threadfence();
+        if (__hip_atomic_load(&bar->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) go = 0;
+        s_go = go;
+    }
+    __syncthreads();
+    return s_go != 0u;
+}
+
+// The Act decay of a whole batch (one MCS), grid-stride: the activity as
+// stored (uint8 array, or the bits of the words), lowered by one where
+// positive.
+__device__ __forceinline__ void decay_all(const PersistentLaunch &p)
+{
+    const size_t stride = (size_t)gridDim.x * kBlock;
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < p.n_sites; i += stride) {
+        if (p.decay_mode == 1) {
+            uint8_t *a = static_cast<uint8_t *>(p.decay_ptr);
+            const uint8_t v = a[i];
+            if (v) a[i] = (uint8_t)(v - 1);
+        } else if (p.decay_mode == 2) {
+            uint32_t *w = static_cast<uint32_t *>(p.decay_ptr);
+            const uint32_t v = w[i];
+            if (v >> 24) w[i] = v - (1u << 24);
+        } else if (p.decay_mode == 3) {
+            uint16_t *w = static_cast<uint16_t *>(p.decay_ptr);
+            const uint32_t v = w[i];
+            if (v >> 11) w[i] = (uint16_t)(v - (1u << 11));
+        }
+    }
+}
+
+// n_mcs MCS of a batch swept in place (k = 1) in one launch: the workgroups
+// (all resident) loop over the work table (entry w on workgroup w mod grid,
+// which keeps the table's XCD assignment when the grid is a multiple of the
+// XCD count), and meet at a grid barrier after each activation and after
+// each MCS's Act decay.
+template <typename Cell, int D, bool ACT, bool SINGLE, bool EXT>
+__global__ void __launch_bounds__(kBlock) batch_persistent_kernel(const SweepArgs *args, const int2 *work,
+                                                                  PersistentLaunch p)
+{
+    uint32_t gen = 0;
+    for (int m = 0; m < p.n_mcs; ++m) {
+        const uint32_t mcs = p.mcs0 + (uint32_t)m;
+        for (uint32_t alpha = 0; alpha < p.n_act; ++alpha) {
+            for (int w = (int)blockIdx.x; w < p.n_work; w += (int)gridDim.x) {
+                const int2 wk = work[w];
+                if (wk.x < 0) continue;  // uniform over the block
+                sweep_tile<Cell, D, ACT, SINGLE, true, kDirect, EXT>(args[wk.x], wk.y, mcs, alpha, (int)(alpha & 1));
+                __syncthreads();
+            }
+            if (!grid_sync(p, gen)) return;
+        }
+        if (ACT) {
+            decay_all(p);
+            if (!grid_sync(p, gen)) return;
+        }
+    }
+}
+
+template <typename Cell, int D, bool ACT, bool SINGLE, bool EXT>
+hipError_t launch_persistent_k(const BatchLaunch &b, const PersistentLaunch &p, hipStream_t st)
+{
+    const void *kern = reinterpret_cast<const void *>(&batch_persistent_kernel<Cell, D, ACT, SINGLE, EXT>);
+    int per_cu = 0, dev = 0, cus = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_persistent_kernel<Cell, D, ACT, SINGLE, EXT>,
+                                                               kBlock, b.lds);
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    int grid = std::min(per_cu * cus, b.grid);
+    grid = grid / kXcds * kXcds;
+    if (grid < kXcds) return hipErrorInvalidConfiguration;
+    const SweepArgs *args = b.args;
+    const int2 *work = b.work;
+    PersistentLaunch pl = p;
+    void *kargs[] = {(void *)&args, (void *)&work, (void *)&pl};
+    return hipLaunchCooperativeKernel(kern, dim3((unsigned)grid), dim3(kBlock), kargs, (unsigned)b.lds, st);
+}
+
 template <typename Cell, int D, bool ACT, bool SINGLE, bool EXT>
 hipError_t launch_k(const SweepArgs &a, bool k1, int layout, uint32_t mcs, uint32_t alpha, int parity, size_t lds,
                     hipStream_t st)
@@ -788,6 +899,30 @@ hipError_t sweep_words(const SweepArgs &a, bool act, uint32_t mcs, uint32_t alph
                    : launch_packed_s<Cell, D, false>(a, mcs, alpha, parity, lds, st);
     else  // words that carry the activity serve Act models only
         return launch_packed_s<Cell, D, true>(a, mcs, alpha, parity, lds, st);
+}
+
+// A persistent launch of a batch (in place, k = 1).
+template <typename Cell, int D>
+hipError_t batch_persistent_words(const BatchLaunch &b, const PersistentLaunch &p, hipStream_t st)
+{
+    constexpr bool kWordAct = WordAct<Cell>::kIn;
+    if constexpr (std::is_same<Cell, char16_t>::value)  // one cell type, no chemotaxis
+        return launch_persistent_k<Cell, D, true, true, false>(b, p, st);
+    else if constexpr (kWordAct)
+        return b.single ? (b.ext ? launch_persistent_k<Cell, D, true, true, true>(b, p, st)
+                                 : launch_persistent_k<Cell, D, true, true, false>(b, p, st))
+                        : (b.ext ? launch_persistent_k<Cell, D, true, false, true>(b, p, st)
+                                 : launch_persistent_k<Cell, D, true, false, false>(b, p, st));
+    else if (b.act)
+        return b.single ? (b.ext ? launch_persistent_k<Cell, D, true, true, true>(b, p, st)
+                                 : launch_persistent_k<Cell, D, true, true, false>(b, p, st))
+                        : (b.ext ? launch_persistent_k<Cell, D, true, false, true>(b, p, st)
+                                 : launch_persistent_k<Cell, D, true, false, false>(b, p, st));
+    else
+        return b.single ? (b.ext ? launch_persistent_k<Cell, D, false, true, true>(b, p, st)
+                                 : launch_persistent_k<Cell, D, false, true, false>(b, p, st))
+                        : (b.ext ? launch_persistent_k<Cell, D, false, false, true>(b, p, st)
+                                 : launch_persistent_k<Cell, D, false, false, false>(b, p, st));
 }
 
 // One activation of every lattice of a batch.

@@ -48,15 +48,17 @@ def _check(torch, ws, batch, n_mcs):
         assert tuple(int(x) for x in stats[i]) == tuple(int(x) for x in st.stats)
 
 
-@pytest.mark.parametrize("act", [True, False])
-def test_batch_uneven_2d(torch_cuda, act):
+@pytest.mark.parametrize("act,mode", [(True, "graph"), (False, "graph"), (True, "persistent"), (False, "persistent"),
+                                      (True, "eager")])
+def test_batch_uneven_2d(torch_cuda, act, mode):
     ws = inputs.config3(n_lattices=10, L_min=20, L_max=96, seed=3, n_mcs=5)
     if not act:
         for w in ws:
             w.lambda_act = None
             w.max_act = None
-    _say(f"batch of {len(ws)}: sides {[w.dims[0] for w in ws]} act={act}")
+    _say(f"batch of {len(ws)}: sides {[w.dims[0] for w in ws]} act={act} mode={mode}")
     b = cpm.Batch([cpm.Params.from_workload(w) for w in ws], [w.lattice for w in ws], [w.cell_type for w in ws])
+    b.launch_mode(mode)
     b.sweep(2)
     b.sweep(3)
     torch_cuda.cuda.synchronize()
@@ -164,8 +166,8 @@ def _act_batch(types_per_lattice, seed):
     return ws
 
 
-@pytest.mark.parametrize("types_per_lattice", [1, 2])
-def test_act_batch_words_with_serial_steps(torch_cuda, types_per_lattice):
+@pytest.mark.parametrize("types_per_lattice,mode", [(1, "graph"), (2, "graph"), (1, "persistent"), (2, "persistent")])
+def test_act_batch_words_with_serial_steps(torch_cuda, types_per_lattice, mode):
     # one cell type: the batch sweeps on 16-bit label-activity words; two:
     # on 32-bit label-type-activity words.  Serial MCS (on the int32
     # lattices) interleave with the parallel ones.
@@ -176,6 +178,7 @@ def test_act_batch_words_with_serial_steps(torch_cuda, types_per_lattice):
     states = [_oracle_state(w) for w in ws]
     b = cpm.Batch([cpm.Params.from_workload(w) for w in ws], [w.lattice for w in ws], [w.cell_type for w in ws],
                   [w.act for w in ws])
+    b.launch_mode(mode)
     for step, n in (("dcs", 3), ("serial", 1), ("dcs", 2)):
         for st in states:
             st.sweep(n) if step == "dcs" else st.serial_sweep(n)
@@ -217,4 +220,70 @@ def test_summary_persistence_with_undefined_lags(torch_cuda):
     ref = summary.summary(V, S, smp[:, :, 2:4], w.dims, 4.0)
     np.testing.assert_allclose(out[:8], ref, rtol=1e-12, atol=1e-12)
     assert np.isclose(out[6], 4.0 * (1.0 - np.exp(-1.0)))
+    b.close()
+
+
+def test_persistent_3d_mixed_types(torch_cuda):
+    # multi-type 3D lattices with obstacles, int32 / 16-bit labels, one
+    # persistent launch for three MCS
+    ws = []
+    for i, dims in enumerate([(8, 8, 8), (12, 8, 16), (16, 16, 8)]):
+        lat = inputs.random_blobs(dims, 6, seed=50 + i, fill=0.6, p_obstacle=0.03)
+        J = np.array([[0, 3, 5, 1.5], [3, 7, 1.25, -2], [5, 1.25, 9, 0.5], [1.5, -2, 0.5, 0]])
+        ws.append(inputs.Workload(f"3d-{dims}", 3, dims, lat, np.array([0, 1, 2, 1, 2, 1, 2], dtype=np.int32), J,
+                                  np.array([0, 2.5, 1.0, 0]), np.array([0, 30, 40, 0], dtype=np.int32),
+                                  np.array([0, 0.5, 0.25, 0]), np.array([0, 90, 120, 0], dtype=np.int32),
+                                  T=7.0 + i, n_mcs=3, seed=9, lattice_id=200 + i, obstacle_type=3))
+    _say("persistent batch 3d mixed types")
+    b = cpm.Batch([cpm.Params.from_workload(w) for w in ws], [w.lattice for w in ws], [w.cell_type for w in ws])
+    b.launch_mode("persistent")
+    b.sweep(3)
+    torch_cuda.cuda.synchronize()
+    _check(torch_cuda, ws, b, 3)
+
+
+def test_persistent_barrier_wait_is_bounded(torch_cuda):
+    # a spin limit of zero polls: workgroups that wait at the first barrier
+    # give up at once, the launch ends, and the batch reports the failure
+    ws = inputs.config3(n_lattices=8, L_min=64, L_max=128, seed=5, n_mcs=2)
+    _say("persistent launch with a zero spin limit")
+    b = cpm.Batch([cpm.Params.from_workload(w) for w in ws], [w.lattice for w in ws], [w.cell_type for w in ws])
+    b.launch_mode("persistent")
+    cpm.cpm_batch_set_barrier_spin_limit(b.handle, 0)
+    b.sweep(2)
+    torch_cuda.cuda.synchronize()
+    with pytest.raises(cpm.CpmError) as e:
+        b.attempt_stats()
+    assert e.value.code == cpm.CPM_EDEVICE
+    with pytest.raises(cpm.CpmError):
+        b.check_invariants()
+    b.close()
+
+
+def test_persistent_mode_needs_in_place_sweeps(torch_cuda):
+    ws = inputs.config3(n_lattices=2, L_min=32, L_max=48, seed=6, n_mcs=1)
+    b = cpm.Batch([cpm.Params.from_workload(w).replace(layout="box") for w in ws], [w.lattice for w in ws],
+                  [w.cell_type for w in ws])
+    with pytest.raises(cpm.CpmError) as e:
+        b.launch_mode("persistent")
+    assert e.value.code == cpm.CPM_ENOTSUP
+    b.close()
+
+
+def test_tuned_batch_matches_oracle(torch_cuda):
+    # the batch autotuner times layouts, tile rules per size class and the
+    # launch modes (each candidate must leave the same lattices), and the
+    # configuration it picks evolves every lattice as the oracle does
+    ws = inputs.config3(n_lattices=12, L_min=40, L_max=200, seed=12, n_mcs=4)
+    params = [cpm.Params.from_workload(w) for w in ws]
+    lattices, types = [w.lattice for w in ws], [w.cell_type for w in ws]
+    _say(f"batch autotune: sides {[w.dims[0] for w in ws]}")
+    r = cpm.autotune_batch(params, lattices, types, trial_mcs=1, log=_say)
+    assert len(r["times"]) >= 6 and any(k.endswith("/persistent") for k in r["times"])
+    cfg = r["best"]
+    b = cpm.Batch(cpm.batch_params(params, cfg), lattices, types)
+    b.launch_mode(cfg["mode"])
+    b.sweep(4)
+    torch_cuda.cuda.synchronize()
+    _check(torch_cuda, ws, b, 4)
     b.close()
