@@ -214,6 +214,10 @@ def main():
                     help="thread areas per workgroup tile as X,Y,Z (with a named --layout; default: the "
                          "library's choice)")
     ap.add_argument("--tune-mcs", type=int, default=6, help="MCS timed per candidate layout when tuning")
+    ap.add_argument("--batch-n", type=int, default=512, help="batch workload: lattices (512 in the benchmark)")
+    ap.add_argument("--batch-max-side", type=int, default=512,
+                    help="batch workload: largest side (512 in the benchmark; 64 gives a batch of 64^2 lattices "
+                         "whose MCS time is mostly launch or barrier overhead)")
     ap.add_argument("--batch-mode", default=None, choices=("graph", "eager", "persistent"),
                     help="batch workload: how each sweep is launched (default: the tuner's choice, else graph)")
     ap.add_argument("--acc-runs", type=int, default=250, help="accuracy workload: runs per ensemble")
@@ -649,7 +653,7 @@ def bench_batch(args):
     of every lattice."""
     import torch
     from paper_2312_09317_amd import cpm, inputs
-    ws = inputs.config3(n_lattices=512, seed=1, n_mcs=args.steps)
+    ws = inputs.config3(n_lattices=args.batch_n, seed=1, n_mcs=args.steps, L_max=args.batch_max_side)
     sites = sum(w.n_sites for w in ws)
     log(f"batch of {len(ws)} lattices, {sites} sites")
     params = [cpm.Params.from_workload(w) for w in ws]
@@ -695,7 +699,7 @@ def bench_batch(args):
         "unit": "attempts/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "int32", "data": "synthetic",
-        "config": {"workload": "2d-batch-512-L64..512", "n_lattices": len(ws), "sites": sites, "sub": ws[0].s,
+        "config": {"workload": f"2d-batch-{len(ws)}-L64..{args.batch_max_side}", "n_lattices": len(ws), "sites": sites, "sub": ws[0].s,
                    "attempts_per_activation": ws[0].k, "act": True, "launch": tuned, "tuning_ms_per_mcs": tuning,
                    "label_storage": "uint16 words: label + 1 and activity (one cell type, at most 2,046 cells, "
                                     "Max_act <= 31), written from the int32 lattices and activities per sweep call"},

@@ -686,11 +686,14 @@ __global__ void __launch_bounds__(kBlock) batch_sweep_kernel(const SweepArgs *ar
 }
 
 // Device-wide barrier of a persistent launch.  Thread 0 of each workgroup
-// arrives (agent-scope release of the workgroup's writes); the last arrival
-// resets the count and bumps the generation, the others poll it (acquire).
-// A wait is bounded: after spin_limit polls the workgroup raises the abort
-// flag, and every workgroup leaves at its next barrier once the flag is
-// raised, so the launch always ends.  Returns false when leaving.
+// arrives after an agent-scope release fence (the workgroup's writes, made
+// visible to it by the workgroup barrier, become visible device-wide); the
+// last arrival resets the count and bumps the generation, the others poll
+// it with relaxed agent-scope loads, and one acquire fence follows the wait
+// (an acquire per poll would invalidate the caches at every poll).  A wait
+// is bounded: after spin_limit polls the workgroup raises the abort flag,
+// and every workgroup leaves at its next barrier once the flag is raised,
+// so the launch always ends.  Returns false when leaving.
 __device__ __forceinline__ bool grid_sync(const PersistentLaunch &p, uint32_t &gen)
 {
     __shared__ uint32_t s_go;
@@ -698,18 +701,21 @@ __device__ __forceinline__ bool grid_sync(const PersistentLaunch &p, uint32_t &g
     if (threadIdx.x == 0) {
         GridBarrier *bar = p.bar;
         uint32_t go = 1;
-        __threadfence();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         const uint32_t g = gen;
-        if (atomicAdd(&bar->count, 1u) == gridDim.x - 1) {
-            atomicExch(&bar->count, 0u);
-            __threadfence();
-            atomicAdd(&bar->gen, 1u);
+        if (__hip_atomic_fetch_add(&bar->count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1) {
+            // the last arrival acquires every other workgroup's release (the
+            // count's increments form one release sequence) before its own
+            // release of the generation passes them on
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            __hip_atomic_store(&bar->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&bar->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             uint32_t polls = 0;
-            while (__hip_atomic_load(&bar->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+            while (__hip_atomic_load(&bar->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
                 if (__hip_atomic_load(&bar->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
                     polls++ >= p.spin_limit) {
-                    atomicExch(&bar->abort, 1u);
+                    __hip_atomic_store(&bar->abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     go = 0;
                     break;
                 }
@@ -717,7 +723,7 @@ __device__ __forceinline__ bool grid_sync(const PersistentLaunch &p, uint32_t &g
             }
         }
         gen = g + 1;
-        __threadfence();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         if (__hip_atomic_load(&bar->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) go = 0;
         s_go = go;
     }
