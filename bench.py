@@ -60,14 +60,16 @@ def kernel_sources_sha():
     return h.hexdigest()[:16]
 
 
-def measured_traffic_bytes(layout=None, table=None, tile=None):
+def measured_traffic_bytes(layout=None, table=None, tile=None, order=None):
     """HBM bytes per launch of a traffic table, or None when the kernel
-    sources, the layout or the tile shape differ from those the counters
-    were taken on."""
+    sources, the layout, the tile shape or the tile order differ from those
+    the counters were taken on."""
     t = MEASURED_TRAFFIC if table is None else table
     if kernel_sources_sha() != t["sources_sha256"] or (layout is not None and layout != t["layout"]):
         return None
     if tile is not None and t.get("tile") is not None and list(tile) != list(t["tile"]):
+        return None
+    if order is not None and order != t.get("order", "linear"):
         return None
     return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0
 
@@ -213,6 +215,8 @@ def main():
     ap.add_argument("--tile", default=None,
                     help="thread areas per workgroup tile as X,Y,Z (with a named --layout; default: the "
                          "library's choice)")
+    ap.add_argument("--tile-order", default="auto", choices=("auto", "linear", "bricks"),
+                    help="with a named --layout: the order in which each XCD takes its tiles")
     ap.add_argument("--tune-mcs", type=int, default=6, help="MCS timed per candidate layout when tuning")
     ap.add_argument("--batch-n", type=int, default=512, help="batch workload: lattices (512 in the benchmark)")
     ap.add_argument("--batch-max-side", type=int, default=512,
@@ -223,6 +227,8 @@ def main():
     ap.add_argument("--acc-runs", type=int, default=250, help="accuracy workload: runs per ensemble")
     ap.add_argument("--acc-mcs", type=int, default=200, help="accuracy workload: MCS per run")
     ap.add_argument("--emu-train", type=int, default=8192, help="emulator workload: training runs")
+    ap.add_argument("--emu-train-reps", type=int, default=1,
+                    help="emulator workload: runs per training point (the emulator learns their mean)")
     ap.add_argument("--emu-test", type=int, default=256, help="emulator workload: held-out points")
     ap.add_argument("--emu-reps", type=int, default=8, help="emulator workload: replicates per held-out point")
     ap.add_argument("--emu-epochs", type=int, default=2000)
@@ -313,7 +319,7 @@ def main():
     per_launch_bytes = bytes_per_attempt(w.ndim, w.s, w.k, p_acc) * (w.n_sites // n_act)
     achieved = per_launch_bytes / avg_launch_s / 1e9
     tiling = cpm.cpm_tile_shape(params, w.n_cells)
-    traffic = measured_traffic_bytes(tiling["layout"], tile=tiling["areas"])
+    traffic = measured_traffic_bytes(tiling["layout"], tile=tiling["areas"], order=tiling["order"])
     out = {
         "metric": METRIC,
         "value": value,
@@ -364,11 +370,13 @@ def choose_layout(args, cpm, params, w):
     """The sweep layout: timed candidates (--layout tune) or the one named."""
     if args.layout != "tune":
         tile = tuple(int(v) for v in args.tile.split(",")) if args.tile else (0, 0, 0)
-        return params.replace(layout=args.layout, tile=tile), None
+        return params.replace(layout=args.layout, tile=tile, tile_order=args.tile_order), None
     r = cpm.autotune(params, w.lattice, w.cell_type, w.act, trial_mcs=args.tune_mcs)
-    log("autotune (ms per MCS): " + ", ".join(f"{k[0]}{list(k[1])}: {v:.3f}" for k, v in sorted(r["times"].items(), key=lambda kv: kv[1])))
-    lay, tile = r["best"]
-    return params.replace(layout=lay, tile=tile), {f"{k[0]}{list(k[1])}": round(v, 4) for k, v in r["times"].items()}
+    name = lambda k: f"{k[0]}{list(k[1])}" + ("/bricks" if k[2] == "bricks" else "")
+    log("autotune (ms per MCS): " + ", ".join(f"{name(k)}: {v:.3f}" for k, v in sorted(r["times"].items(), key=lambda kv: kv[1])))
+    lay, tile, order = r["best"]
+    return (params.replace(layout=lay, tile=tile, tile_order=order),
+            {name(k): round(v, 4) for k, v in r["times"].items()})
 
 
 def bench_tissue(args):
@@ -717,13 +725,14 @@ def bench_emulator(args):
     from paper_2312_09317_amd import emulator
     r = emulator.study(n_train=args.emu_train, n_test=args.emu_test, reps=args.emu_reps, epochs=args.emu_epochs,
                        batch=args.emu_batch, lr=args.emu_lr, lr_final=args.emu_lr / 40, log=log,
-                       data_path=args.emu_data)
+                       data_path=args.emu_data, train_reps=args.emu_train_reps)
     cpu = emulator_cpu_baseline(args) if sample_mcs(args, 4) > 0 else None
     print(json.dumps({
         "metric": "emulator vs CPM cost per parameter point", "value": r["cost_ratio"], "unit": "x",
         "n_gpus": 1, "steps": args.emu_epochs, "warmup": 0, "ms_per_step": None, "higher_is_better": True,
         "scaling": "strong", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
-        "config": {"workload": "emulator-6-256-256-256-8", **{k: r[k] for k in ("n_train", "n_test", "replicates",
+        "config": {"workload": "emulator-6-256-256-256-8", **{k: r[k] for k in ("n_train", "n_train_points",
+                                                                               "train_reps", "n_test", "replicates",
                                                                                "plan", "L_range", "epochs")}},
         "emulator": r, "roofline": None, "cpu_baseline": cpu_fields(cpu)}), flush=True)
 

@@ -134,6 +134,13 @@ typedef struct cpm_params {
      * Medium copies get no term. */
     const double *lambda_chemotaxis;  /* n_types (2^-16 quantised like J) */
     const int16_t *d_chemotaxis_field;
+    /* Order in which each XCD works through its slab of tiles (results never
+     * depend on it): 0 = the library's choice, 1 = tile index order, 2 = 3D
+     * bricks of up to 16 x 16 tiles across y and z, so that the workgroups
+     * resident on an XCD at once share their halo planes in its L2 (3D
+     * lattices whose tiles span whole rows along x and divide evenly among
+     * the XCDs; CPM_ENOTSUP otherwise). */
+    int32_t tile_order;
 } cpm_params;
 
 typedef struct cpm_handle cpm_handle;

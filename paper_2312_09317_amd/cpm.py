@@ -54,9 +54,11 @@ class cpm_params(ctypes.Structure):
         ("persistence_dt", ctypes.c_int32),
         ("lambda_chemotaxis", ctypes.POINTER(ctypes.c_double)),
         ("d_chemotaxis_field", ctypes.c_void_p),
+        ("tile_order", ctypes.c_int32),
     ]
 
 LAYOUTS = {"auto": 0, "box": 1, "full_rows": 2, "in_place": 3}
+TILE_ORDERS = {"auto": 0, "linear": 1, "bricks": 2}
 
 
 EXPORTS = ("cpm_validate", "cpm_workspace_bytes", "cpm_tile_shape", "cpm_init", "cpm_init_static", "cpm_sweep", "cpm_cell_stats", "cpm_contacts",
@@ -141,7 +143,7 @@ class Params:
                  temperature: float = 20.0, seed: int = 1, lattice_id: int = 0, sub: int = 2,
                  attempts: int = 1, obstacle_type: int = -1, layout="auto", tile=(0, 0, 0),
                  lambda_persistence=None, persistence_mu=None, persistence_dt: int = 1,
-                 lambda_chemotaxis=None, chemotaxis_field=None):
+                 lambda_chemotaxis=None, chemotaxis_field=None, tile_order="auto"):
         n = len(lambda_volume)
         self._J = np.ascontiguousarray(np.asarray(J, dtype=np.float64).reshape(n, n))
         self._lv = np.ascontiguousarray(lambda_volume, dtype=np.float64)
@@ -182,6 +184,7 @@ class Params:
         c.persistence_dt = int(persistence_dt)
         c.lambda_chemotaxis = self._lc.ctypes.data_as(dp) if self._lc is not None else None
         c.d_chemotaxis_field = chemotaxis_field.data_ptr() if hasattr(chemotaxis_field, "data_ptr") else None
+        c.tile_order = TILE_ORDERS[tile_order] if isinstance(tile_order, str) else int(tile_order)
         self.c = c
         self._kw = dict(ndim=ndim, dims=dims, J=J, lambda_volume=lambda_volume, volume_target=volume_target,
                         lambda_surface=lambda_surface, surface_target=surface_target, lambda_act=lambda_act,
@@ -189,7 +192,7 @@ class Params:
                         attempts=attempts, obstacle_type=obstacle_type, layout=layout, tile=tile,
                         lambda_persistence=lambda_persistence, persistence_mu=persistence_mu,
                         persistence_dt=persistence_dt, lambda_chemotaxis=lambda_chemotaxis,
-                        chemotaxis_field=chemotaxis_field)
+                        chemotaxis_field=chemotaxis_field, tile_order=tile_order)
 
     def replace(self, **over) -> "Params":
         """A copy with some fields changed (e.g. layout, tile)."""
@@ -250,7 +253,7 @@ def cpm_tile_shape(params: Params, n_cells: int) -> dict:
     out = (ctypes.c_int32 * 7)()
     _check(load().cpm_tile_shape(ctypes.byref(params.c), n_cells, out), "cpm_tile_shape")
     return {"areas": (out[0], out[1], out[2]), "layout": ("box", "full_rows", "in_place")[out[3]], "lds_bytes": out[4],
-            "tiles": out[5], "labels16": bool(out[6])}
+            "tiles": out[5], "labels16": bool(out[6]), "order": "bricks" if params.c.tile_order == 2 else "linear"}
 
 
 def cpm_init(params: Params, d_lattice, d_cell_type, n_cells: int, d_act, d_workspace, workspace_bytes: int,
@@ -655,40 +658,48 @@ class Batch:
 # ---------------------------------------------------------------- autotuner
 
 def tuning_candidates(params: Params, n_cells: int):
-    """(layout, tile) pairs worth timing for this model: the library's
-    choice of each layout that fits, and in-place tiles of other shapes."""
+    """(layout, tile, tile order) triples worth timing for this model: the
+    library's choice of each layout that fits, in-place tiles of other
+    shapes, and in 3D the same in-place tiles taken in bricks."""
     c = params.c
     na = [c.dims[d] // (2 * c.sub) if d < c.ndim else 1 for d in range(3)]
     out = []
+
+    def add(lay, tile, order="linear"):
+        cand = (lay, tuple(tile), order)
+        if cand not in out and cpm_validate(params.replace(layout=lay, tile=tile, tile_order=order),
+                                            n_cells) == CPM_OK:
+            out.append(cand)
     layouts = ["box"] if c.attempts != 1 else ["in_place", "full_rows", "box"]
     for lay in layouts:
-        if cpm_validate(params.replace(layout=lay, tile=(0, 0, 0)), n_cells) == CPM_OK:
-            out.append((lay, (0, 0, 0)))
+        add(lay, (0, 0, 0))
     if c.attempts == 1:
         for t0 in (16, 32, 64, 128, 256):
             t0 = min(t0, na[0])
             rest = 256 // t0
             t1 = min(na[1], rest if c.ndim == 2 else max(1, int(round(rest ** 0.5))))
             t2 = min(na[2], max(1, rest // t1)) if c.ndim == 3 else 1
-            cand = ("in_place", (t0, t1, t2))
-            if cand not in out and cpm_validate(params.replace(layout="in_place", tile=cand[1]), n_cells) == CPM_OK:
-                out.append(cand)
+            add("in_place", (t0, t1, t2))
+        if c.ndim == 3:
+            for lay, tile, _ in list(out):
+                if lay == "in_place":
+                    add(lay, tile, "bricks")
     return out
 
 
 def autotune(params: Params, lattice, cell_type, act=None, trial_mcs: int = 2, candidates=None, device="cuda"):
-    """Time each candidate (layout, tile) on a copy of the lattice for
-    trial_mcs MCS after one warm-up MCS and return the fastest.  Every
-    candidate must leave the same lattice (results never depend on the
-    layout); a disagreement raises.  Returns {"best": (layout, tile),
-    "times": {(layout, tile): ms per MCS}}."""
+    """Time each candidate (layout, tile, tile order) on a copy of the
+    lattice for trial_mcs MCS after one warm-up MCS and return the fastest.
+    Every candidate must leave the same lattice (results never depend on the
+    layout); a disagreement raises.  Returns {"best": (layout, tile, order),
+    "times": {(layout, tile, order): ms per MCS}}."""
     import hashlib
     import torch
     n_cells = len(cell_type) - 1
     cands = candidates or tuning_candidates(params, n_cells)
     times, digest = {}, None
-    for lay, tile in cands:
-        p = params.replace(layout=lay, tile=tile)
+    for lay, tile, order in cands:
+        p = params.replace(layout=lay, tile=tile, tile_order=order)
         sim = Simulation(p, lattice, cell_type, act, device=device)
         sim.sweep(1)
         torch.cuda.synchronize()
@@ -697,12 +708,12 @@ def autotune(params: Params, lattice, cell_type, act=None, trial_mcs: int = 2, c
         sim.sweep(trial_mcs)
         e1.record()
         torch.cuda.synchronize()
-        times[(lay, tuple(tile))] = e0.elapsed_time(e1) / trial_mcs
+        times[(lay, tuple(tile), order)] = e0.elapsed_time(e1) / trial_mcs
         h = hashlib.sha256(sim.lattice.cpu().numpy().tobytes()).hexdigest()
         if digest is None:
             digest = h
         elif h != digest:
-            raise RuntimeError(f"layout {lay} tile {tile} changed the result of the sweep")
+            raise RuntimeError(f"layout {lay} tile {tile} order {order} changed the result of the sweep")
         sim.close()
     best = min(times, key=times.get)
     return {"best": best, "times": times}

@@ -182,6 +182,17 @@ bool tile_geometry(const cpm_params *p, bool mirror, int force_layout, cpm::Tile
         }
         g.tiles_per_xcd = (g.n_tiles + cpm::kXcds - 1) / cpm::kXcds;
         g.grid = g.tiles_per_xcd * cpm::kXcds;
+        if (p->tile_order == 2) {
+            // bricks need 3D tiles spanning whole rows and whole layers per XCD
+            if (p->ndim != 3 || g.nt[0] != 1 || g.nt[2] % cpm::kXcds != 0) return false;
+            g.layers_per_xcd = g.nt[2] / cpm::kXcds;
+            g.brick_y = 1;
+            for (int by = 1; by <= std::min(16, g.nt[1]); ++by)
+                if (g.nt[1] % by == 0) g.brick_y = by;
+            g.brick_z = 1;
+            for (int bz = 1; bz <= std::min(16, g.layers_per_xcd); ++bz)
+                if (g.layers_per_xcd % bz == 0 && g.brick_y * bz <= 256) g.brick_z = bz;
+        }
         return true;
     };
     const bool k1 = p->attempts == 1;
@@ -358,6 +369,7 @@ int validate(const cpm_params *p, int32_t n_cells)
         if (p->sub < 2) return fail(CPM_EINVAL, "the Act term reads two sites out: sub must be >= 2");
     }
     if (p->layout < 0 || p->layout > 3) return fail(CPM_EINVAL, "layout must be 0..3");
+    if (p->tile_order < 0 || p->tile_order > 2) return fail(CPM_EINVAL, "tile_order must be 0..2");
     {
         int areas = 1;
         for (int d = 0; d < 3; ++d) {
@@ -370,7 +382,7 @@ int validate(const cpm_params *p, int32_t n_cells)
         if (p->layout >= 2 && p->attempts != 1) return fail(CPM_ENOTSUP, "layouts 2 and 3 need attempts == 1");
         cpm::TileGeometry g;
         if (!tile_geometry(p, use_mirror(p, n_cells), requested_layout(p), g, use_act_words(p, n_cells)))
-            return fail(CPM_ENOTSUP, "the requested layout / tile does not fit this model");
+            return fail(CPM_ENOTSUP, "the requested layout / tile / tile order does not fit this model");
     }
     const int n = p->n_types;
     const int nnb = n_neighbours(p->ndim);

@@ -74,6 +74,11 @@ struct TileGeometry {
     int32_t layout;        // 0: halo boxes in LDS; 1: whole rows along x in LDS; 2: no staging (in place)
     int32_t row_chunk;     // bytes per load when staging label rows (16, 8 or 4)
     int32_t act_chunk;     // bytes per load when staging activity rows
+    // 3D bricks (0 = tile index order): an XCD's slab is layers_per_xcd
+    // layers of nt[1] x 1 tiles (tiles span whole rows, nt[0] == 1), taken in
+    // bricks of brick_y x brick_z tiles, y fastest inside a brick and bricks
+    // y fastest
+    int32_t brick_y, brick_z, layers_per_xcd;
 };
 
 // Everything a sweep kernel needs, passed by value.

@@ -370,12 +370,16 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
     };
 
     if (EAGER) {
-        // round 1: the previous list's count and this thread's record of it
-        // (valid when tid < count), and the attempt's two labels; round 2,
+        // round 1: the previous list's count, its first kEarlyRecords
+        // records (one per thread; a tile's accepted copies rarely fill more,
+        // and loading all of its slots would read one 16-byte slot per area
+        // in every activation) and the attempt's two labels; round 2,
         // nontrivial attempts only: the target's neighbours and both cells'
-        // counters; round 3: the acceptance threshold
+        // counters (and any later records of the previous list); round 3:
+        // the acceptance threshold
+        constexpr int kEarlyRecords = 16;
         const int prev_n = a.dcount[parity ^ 1][tile];
-        const int4 prev_rec = tid < a.dlist_cap ? dl_prev[tid] : make_int4(0, 0, 0, 0);
+        const int4 early_rec = tid < kEarlyRecords ? dl_prev[tid] : make_int4(0, 0, 0, 0);
         int ttx = 0, tty = 0, ttz = 0, ssx = 0, ssy = 0, ssz = 0, lt = 0, ls = 0;
         Cell wt = 0, ws = 0;
         uint32_t u2 = 0, area_id = 0;
@@ -388,7 +392,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
             ls = label_of(ws);
         }
         __syncthreads();  // LDS counters and tables initialised
-        if (tid < prev_n) add_deltas(wr, prev_rec);
+        if (tid < prev_n) add_deltas(wr, tid < kEarlyRecords ? early_rec : dl_prev[tid]);
         uint32_t nontrivial = 0, accepted = 0;
         if (mine && lt != ls && lt >= 0 && ls >= 0) {
             nontrivial = 1;
@@ -644,12 +648,28 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
     }
 }
 
-// One lattice: workgroup b takes tile (b mod 8) * tiles_per_xcd + b div 8, so
-// each XCD sweeps one contiguous slab of tiles in every activation.
+// The tile of workgroup b of a single lattice: workgroups go to the XCDs
+// round-robin, so b takes the (b div 8)-th tile of the slab of XCD b mod 8:
+// in index order, or brick by brick (TileGeometry).
+__device__ __forceinline__ int xcd_tile(const TileGeometry &tg, unsigned b)
+{
+    const int x = (int)(b % kXcds), j = (int)(b / kXcds);
+    if (tg.brick_y == 0) return x * tg.tiles_per_xcd + j;
+    const int per = tg.brick_y * tg.brick_z;
+    const int br = j / per, r = j - br * per;
+    const int nby = tg.nt[1] / tg.brick_y;
+    const int by = br % nby, bz = br / nby;
+    const int ty = by * tg.brick_y + r % tg.brick_y;
+    const int tz = x * tg.layers_per_xcd + bz * tg.brick_z + r / tg.brick_y;
+    return ty + tg.nt[1] * tz;
+}
+
+// One lattice: workgroup b takes tile xcd_tile(b), so each XCD sweeps one
+// contiguous slab of tiles in every activation.
 template <typename Cell, int D, bool ACT, bool SINGLE, bool K1, int LAYOUT, bool EXT>
 __global__ void __launch_bounds__(kBlock) tile_sweep_kernel(SweepArgs a, uint32_t mcs, uint32_t alpha, int parity)
 {
-    const int tile = (int)(blockIdx.x % kXcds) * a.tg.tiles_per_xcd + (int)(blockIdx.x / kXcds);
+    const int tile = xcd_tile(a.tg, blockIdx.x);
     if (tile >= a.tg.n_tiles) return;  // uniform over the block
     sweep_tile<Cell, D, ACT, SINGLE, K1, LAYOUT, EXT>(a, tile, mcs, alpha, parity);
 }
@@ -669,7 +689,7 @@ template <typename Word, int D, bool ACT, bool SINGLE, bool K1, int LAYOUT, bool
 __global__ void __launch_bounds__(kBlock) CPM_PACKED_ATTR tile_sweep_kernel_packed(SweepArgs a, uint32_t mcs,
                                                                                     uint32_t alpha, int parity)
 {
-    const int tile = (int)(blockIdx.x % kXcds) * a.tg.tiles_per_xcd + (int)(blockIdx.x / kXcds);
+    const int tile = xcd_tile(a.tg, blockIdx.x);
     if (tile >= a.tg.n_tiles) return;  // uniform over the block
     sweep_tile<Word, D, ACT, SINGLE, K1, LAYOUT, EXT>(a, tile, mcs, alpha, parity);
 }

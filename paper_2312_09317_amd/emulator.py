@@ -183,35 +183,46 @@ def inference_seconds_per_point(sur, x, n_points=65536, repeats=20):
 
 
 def study(n_train=8192, n_test=256, reps=8, plan=RunPlan(), L_min=64, L_max=512, epochs=300, batch=512,
-          lr=2e-3, lr_final=5e-5, seed=1, log=None, data_path=None):
-    """Train the emulator on n_train single CPM runs and score it on n_test
-    fresh parameter points against the mean of `reps` fresh CPM replicates
-    each (new Philox seeds).  Returns per-statistic median relative errors
-    of the emulator, of a linear fit and of one fresh CPM run, the
-    replicate noise floor (standard error / |mean|), and the cost per point
-    of the CPM (batched, GPU seconds) and of the emulator (inference)."""
+          lr=2e-3, lr_final=5e-5, seed=1, log=None, data_path=None, train_reps=1):
+    """Train the emulator on n_train CPM runs and score it on n_test fresh
+    parameter points against the mean of `reps` fresh CPM replicates each
+    (new Philox seeds).  The runs are n_train / train_reps parameter points
+    run train_reps times each (new Philox seeds), and the emulator learns
+    each point's replicate mean: at equal CPM cost, fewer points with less
+    noisy targets.  Returns per-statistic median relative errors of the
+    emulator, of a linear fit and of one fresh CPM run, the replicate noise
+    floor (standard error / |mean|), and the cost per point of the CPM (one
+    run, batched, GPU seconds) and of the emulator (inference)."""
     say = log or (lambda m: None)
-    train_pts = points(n_train, seed, L_min, L_max)
+    n_pts = n_train // train_reps
+    train_pts = points(n_pts, seed, L_min, L_max)
     test_pts = points(n_test, seed + 1000, L_min, L_max)
     import os
     if data_path and os.path.exists(data_path):
         # the same study's CPM runs, saved earlier (they depend only on the
         # points, seeds and plan, which are checked)
         d = np.load(data_path)
-        key = np.array([n_train, n_test, reps, plan.burn_in, plan.n_samples, plan.interval, L_min, L_max, seed])
+        key = np.array([n_train, n_test, reps, plan.burn_in, plan.n_samples, plan.interval, L_min, L_max, seed,
+                        train_reps])
         if not np.array_equal(d["key"], key):
             raise ValueError(f"{data_path} holds another study's runs")
         t_train, rep, cpm_s = d["t_train"], d["rep"], float(d["cpm_s"])
         say(f"loaded {n_train} training runs and {n_test} x {reps} test runs from {data_path}")
     else:
-        t_train, cpm_s = simulate(train_pts, plan, log=say)
-        say(f"training set: {n_train} runs, {cpm_s:.2f} s GPU")
+        runs, cpm_s = [], 0.0
+        for r in range(train_reps):
+            t_r, s_r = simulate(train_pts if r == 0 else reseed(train_pts, seed + 3000 + r), plan, log=say)
+            runs.append(t_r)
+            cpm_s += s_r
+        t_train = np.mean(runs, axis=0)
+        say(f"training set: {n_pts} points x {train_reps} runs, {cpm_s:.2f} s GPU")
         rep = np.stack([simulate(reseed(test_pts, seed + 2000 + r), plan)[0] for r in range(reps)])
         say(f"test set: {n_test} points x {reps} replicates")
         if data_path:
-            key = np.array([n_train, n_test, reps, plan.burn_in, plan.n_samples, plan.interval, L_min, L_max, seed])
+            key = np.array([n_train, n_test, reps, plan.burn_in, plan.n_samples, plan.interval, L_min, L_max, seed,
+                            train_reps])
             np.savez(data_path, key=key, t_train=t_train, rep=rep, cpm_s=cpm_s)
-    cpm_per_point = cpm_s / n_train
+    cpm_per_point = cpm_s / (n_pts * train_reps)  # one CPM run
     ref = rep.mean(axis=0)
     x_train, x_test = features(train_pts), features(test_pts)
     import torch
@@ -229,7 +240,7 @@ def study(n_train=8192, n_test=256, reps=8, plan=RunPlan(), L_min=64, L_max=512,
         noise = rep.std(axis=0, ddof=1) / np.sqrt(reps) / np.abs(ref)
     med = lambda e: {k: float(v) for k, v in zip(STAT_NAMES, np.nanmedian(e, axis=0))}
     return {
-        "n_train": n_train, "n_test": n_test, "replicates": reps,
+        "n_train": n_train, "n_train_points": n_pts, "train_reps": train_reps, "n_test": n_test, "replicates": reps,
         "plan": {"burn_in": plan.burn_in, "n_samples": plan.n_samples, "interval": plan.interval},
         "L_range": [L_min, L_max], "epochs": epochs, "final_loss": float(losses[-1]), "train_s": train_s,
         "outside_domain": int(outside.sum()),

@@ -309,6 +309,31 @@ def test_every_layout_matches_oracle(torch_cuda, layout, tile):
         sim.close()
 
 
+@pytest.mark.parametrize("case", ["config1-64", "multi-3d", "act-3d"])
+def test_brick_tile_order_matches_oracle(torch_cuda, case):
+    # each XCD taking its tiles brick by brick changes which workgroup runs
+    # which tile when, never the result (16-bit labels of one or several
+    # cell types, label-type-activity words)
+    if case == "config1-64":
+        w = inputs.config1(L=64, grid=6, n_mcs=2)
+        tiles = ((16, 4, 1), (16, 2, 2))
+    else:
+        w = _multi((24, 24, 64), 3, seed=61 if case == "multi-3d" else 62, act=case == "act-3d", obstacles=0.03,
+                   n_cells=40, T=12.0)
+        tiles = ((6, 2, 1), (6, 3, 2))
+    for tile in tiles:
+        p = cpm.Params.from_workload(w, layout="in_place", tile=tile, tile_order="bricks")
+        assert cpm.cpm_validate(p, w.n_cells) == cpm.CPM_OK
+        _say(f"{case}: bricks, tile {tile} -> {cpm.cpm_tile_shape(p, w.n_cells)}")
+        st = oracle.State(oracle_model(w), w.lattice, w.cell_type, w.act)
+        st.sweep(2)
+        sim = cpm.Simulation(p, w.lattice, w.cell_type, w.act)
+        sim.sweep(2)
+        torch_cuda.cuda.synchronize()
+        assert_same(st, sim, torch_cuda)
+        sim.close()
+
+
 def test_autotune_agrees_and_picks(torch_cuda):
     w = inputs.config1(L=48, grid=5, n_mcs=2)
     r = cpm.autotune(cpm.Params.from_workload(w), w.lattice, w.cell_type, trial_mcs=2)
