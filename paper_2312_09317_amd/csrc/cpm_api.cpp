@@ -547,6 +547,8 @@ void fill_args(SweepArgs &a, const cpm_params *p, const Layout &lay, char *ws, i
     a.dlist_cap = lay.dlist_cap;
     a.obstacle_type = p->obstacle_type < 0 ? 0 : p->obstacle_type;
     a.single_type = single;
+    a.n_types = p->n_types;
+    a.lg_entries = 256;
     a.key0 = (uint32_t)p->seed;
     a.key1 = (uint32_t)(p->seed >> 32);
     a.lattice_id = p->lattice_id;
@@ -1172,8 +1174,19 @@ int cpm_batch_init(const cpm_params *params, int32_t n, const int32_t *n_cells, 
     b->bar = reinterpret_cast<cpm::GridBarrier *>(ws + bl.barrier);
     if ((e = cpm::launch_fill_i32(reinterpret_cast<int32_t *>(b->bar), 0, 4, st)) != hipSuccess)
         return device_fail(e, "clear barrier");
-    // one cell type throughout and small lattices: 16-bit label-activity words
+    // one cell type throughout, small lattices and every activity within 5
+    // bits: 16-bit label-activity words
     b->act16 = bl.act16_ok && b->single;
+    if (b->act16) {
+        int32_t *flag = reinterpret_cast<int32_t *>(ws + bl.base[0] + bl.lat[0].check);
+        int32_t over = 0;
+        if ((e = cpm::launch_fill_i32(flag, 0, 1, st)) == hipSuccess &&
+            (e = cpm::launch_count_above(d_act, sites, cpm::kMaxAct16Activity, flag, st)) == hipSuccess &&
+            (e = hipMemcpyAsync(&over, flag, sizeof(int32_t), hipMemcpyDeviceToHost, st)) == hipSuccess)
+            e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return device_fail(e, "check activities");
+        b->act16 = over == 0;
+    }
     if (b->act16) {
         b->words16 = reinterpret_cast<uint16_t *>(ws + bl.words16);
         b->act_words = false;
@@ -1181,6 +1194,7 @@ int cpm_batch_init(const cpm_params *params, int32_t n, const int32_t *n_cells, 
             SweepArgs &a = b->args[i];
             a.cells = b->words16 + b->site_off[i];
             a.tg.row_chunk = chunk_for(a.cells, (size_t)a.L[0] * sizeof(uint16_t));
+            a.lg_entries = cpm::kMaxAct16Activity + 1;  // the words hold activities 0..31
         }
     }
     // Workgroups go to the XCDs round-robin: workgroup g takes entry
@@ -1267,6 +1281,9 @@ int check_barrier(cpm_batch *b, hipStream_t st)
     if (g.abort)
         return fail(CPM_EDEVICE, "a persistent launch of this batch gave up at a grid barrier (spin limit reached); "
                                  "the batch state is invalid");
+    if (g.act_overflow)
+        return fail(CPM_EDEVICE, "an activity above 31 was written into a batch that sweeps on 16-bit words; "
+                                 "the batch state is invalid");
     return CPM_OK;
 }
 
@@ -1310,7 +1327,9 @@ int cpm_batch_sweep(cpm_batch *b, int32_t n_mcs, void *stream)
         return device_fail(e, "to 16-bit working copy");
     if (b->act_words && (e = cpm::launch_batch_act_words(b->d_args, b->n, b->max_sites, true, st)) != hipSuccess)
         return device_fail(e, "to label-type-activity words");
-    if (b->act16 && (e = cpm::launch_to_act16(b->lattices, b->act_field, b->words16, b->total_sites, st)) != hipSuccess)
+    if (b->act16 &&
+        (e = cpm::launch_to_act16(b->lattices, b->act_field, b->words16, b->total_sites,
+                                  reinterpret_cast<int32_t *>(&b->bar->act_overflow), st)) != hipSuccess)
         return device_fail(e, "to 16-bit label-activity words");
     if ((e = cpm::launch_set_u32(b->d_mcs, (uint32_t)b->mcs, st)) != hipSuccess) return device_fail(e, "set mcs");
     if (b->mode == 2) {

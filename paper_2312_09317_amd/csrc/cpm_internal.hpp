@@ -103,6 +103,8 @@ struct SweepArgs {
     int32_t dlist_cap;     // records per tile
     int32_t obstacle_type;
     int32_t single_type;   // the one type of every cell, or -1 when cells differ in type
+    int32_t n_types;       // types of the model (rows of J a sweep reads)
+    int32_t lg_entries;    // entries of the Act log table a sweep can read: the largest activity + 1
     uint32_t key0, key1;
     uint32_t lattice_id;
     TileGeometry tg;
@@ -130,7 +132,7 @@ struct GridBarrier {
     uint32_t count;
     uint32_t gen;
     uint32_t abort;
-    uint32_t pad;
+    uint32_t act_overflow;  // sticky: an activity too large for 16-bit words was met
 };
 
 // One persistent launch: n_mcs MCS of a batch (every activation, then the
@@ -231,7 +233,12 @@ hipError_t launch_act_decay(uint8_t *act, size_t n, hipStream_t stream);
 // 16-bit label-activity words of a whole batch (n sites, packed like the
 // int32 lattices): from / to the int32 labels and uint8 activities, and the
 // per-MCS Act decay in the words.
-hipError_t launch_to_act16(const int32_t *lat, const uint8_t *act, uint16_t *words, size_t n, hipStream_t stream);
+// launch_to_act16 raises *overflow (sticky) when an activity exceeds the
+// 5 bits of the words.
+hipError_t launch_to_act16(const int32_t *lat, const uint8_t *act, uint16_t *words, size_t n, int32_t *overflow,
+                           hipStream_t stream);
+// Adds to *count the number of activities above `limit`.
+hipError_t launch_count_above(const uint8_t *act, size_t n, int limit, int32_t *count, hipStream_t stream);
 hipError_t launch_from_act16(const uint16_t *words, int32_t *lat, uint8_t *act, size_t n, hipStream_t stream);
 hipError_t launch_act16_decay(uint16_t *words, size_t n, hipStream_t stream);
 hipError_t launch_centroids(const SweepArgs &a, int ndim, int32_t n_cells, int32_t *ref,

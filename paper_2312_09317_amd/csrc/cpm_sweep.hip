@@ -119,11 +119,24 @@ __global__ void batch_mirror_kernel(const SweepArgs *__restrict__ args)
 // of a whole batch, four sites per thread (lattices hold multiples of 16
 // sites, so only the batch's end can be ragged).
 __global__ void to_act16_kernel(const int32_t *__restrict__ lat, const uint8_t *__restrict__ act,
-                                uint16_t *__restrict__ w, size_t n)
+                                uint16_t *__restrict__ w, size_t n, int32_t *overflow)
 {
     const size_t i = ((size_t)blockIdx.x * kBlock + threadIdx.x) * 4;
-    for (size_t j = i; j < i + 4 && j < n; ++j)
+    bool over = false;
+    for (size_t j = i; j < i + 4 && j < n; ++j) {
+        over |= act[j] > 31;
         w[j] = (uint16_t)((uint32_t)(lat[j] + 1) | ((uint32_t)act[j] << 11));
+    }
+    if (over) atomicOr(overflow, 1);
+}
+
+__global__ void count_above_kernel(const uint8_t *act, size_t n, int limit, int32_t *count)
+{
+    int cnt = 0;
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock)
+        cnt += act[i] > limit;
+    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+    if ((threadIdx.x & 63) == 0 && cnt) atomicAdd(count, cnt);
 }
 
 __global__ void from_act16_kernel(const uint16_t *__restrict__ w, int32_t *__restrict__ lat,
@@ -273,10 +286,19 @@ hipError_t launch_batch_act_words(const SweepArgs *d_args, int n_lattices, size_
     return hipGetLastError();
 }
 
-hipError_t launch_to_act16(const int32_t *lat, const uint8_t *act, uint16_t *words, size_t n, hipStream_t stream)
+hipError_t launch_to_act16(const int32_t *lat, const uint8_t *act, uint16_t *words, size_t n, int32_t *overflow,
+                           hipStream_t stream)
 {
     const size_t threads = (n + 3) / 4;
-    to_act16_kernel<<<(unsigned)((threads + kBlock - 1) / kBlock), kBlock, 0, stream>>>(lat, act, words, n);
+    to_act16_kernel<<<(unsigned)((threads + kBlock - 1) / kBlock), kBlock, 0, stream>>>(lat, act, words, n, overflow);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_above(const uint8_t *act, size_t n, int limit, int32_t *count, hipStream_t stream)
+{
+    if (n == 0) return hipSuccess;
+    const unsigned grid = (unsigned)std::min<size_t>((n + kBlock - 1) / kBlock, 4096);
+    count_above_kernel<<<grid, kBlock, 0, stream>>>(act, n, limit, count);
     return hipGetLastError();
 }
 

@@ -297,9 +297,9 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
     // model tables read per neighbour, copied to LDS (visible after the
     // staging barrier)
     if (!SINGLE)
-        for (int i = tid; i < kMaxTypes * kMaxTypes; i += kBlock) j_lds[i] = a.model->J[i];
+        for (int i = tid; i < a.n_types * kMaxTypes; i += kBlock) j_lds[i] = a.model->J[i];
     if (ACT)
-        for (int i = tid; i < 256; i += kBlock) lg_lds[i] = a.model->LG[i];
+        for (int i = tid; i < a.lg_entries; i += kBlock) lg_lds[i] = a.model->LG[i];
     const SharedTables sht{j_lds, lg_lds};
     // deltas of the previous activation go into the write buffer as well
     // k = 1 in place: every attempt is evaluated by the thread that draws it

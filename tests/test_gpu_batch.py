@@ -287,3 +287,41 @@ def test_tuned_batch_matches_oracle(torch_cuda):
     torch_cuda.cuda.synchronize()
     _check(torch_cuda, ws, b, 4)
     b.close()
+
+
+def test_act_batch_with_large_initial_activity(torch_cuda):
+    # activities above 31 do not fit the 16-bit words: the batch sweeps on
+    # 32-bit words instead and still follows the oracle
+    ws = _act_batch(1, seed=71)
+    for i, w in enumerate(ws):
+        w.lattice_id = 80 + i
+        w.act = np.where(w.lattice > 0, 40, 0).astype(np.uint8)
+    _say("act batch with initial activity 40")
+    states = [_oracle_state(w) for w in ws]
+    for st in states:
+        st.sweep(3)
+    b = cpm.Batch([cpm.Params.from_workload(w) for w in ws], [w.lattice for w in ws], [w.cell_type for w in ws],
+                  [w.act for w in ws])
+    b.sweep(3)
+    torch_cuda.cuda.synchronize()
+    for i, (w, st) in enumerate(zip(ws, states)):
+        np.testing.assert_array_equal(b.lattice(i).cpu().numpy(), st.lattice)
+        np.testing.assert_array_equal(b.activity(i).cpu().numpy(), st.act)
+    assert all(b.check_invariants())
+    b.close()
+
+
+def test_act16_batch_reports_an_activity_written_too_large(torch_cuda):
+    # a caller who writes an activity above 31 into a batch that sweeps on
+    # 16-bit words gets an error at the next synchronous call
+    ws = _act_batch(1, seed=72)
+    b = cpm.Batch([cpm.Params.from_workload(w) for w in ws], [w.lattice for w in ws], [w.cell_type for w in ws],
+                  [w.act for w in ws])
+    b.sweep(1)
+    b.activity(0)[5] = 60
+    b.sweep(1)
+    torch_cuda.cuda.synchronize()
+    with pytest.raises(cpm.CpmError) as e:
+        b.attempt_stats()
+    assert e.value.code == cpm.CPM_EDEVICE
+    b.close()
