@@ -27,27 +27,29 @@ sys.path.insert(0, ROOT)
 METRIC = "site copy-attempts/s on 3D 256³ (HBM % peak); emulator vs CPM cost per point"
 HBM_PEAK_GBS = 8000.0
 
-# HBM-side bytes per activation launch of this workload, from rocprofv3
-# FETCH_SIZE and WRITE_SIZE runs (KiB per dispatch) scaled by what the same
-# counters read for a plain 256 MiB copy (FETCH x 2.0, WRITE x 1.0), for the
-# kernel sources whose sha256 prefix is given; reported only while the
-# sources are unchanged.
-MEASURED_TRAFFIC = {"sources_sha256": "a6292773102e85c3", "layout": "in_place", "tile": [64, 4, 1],
-                    "fetch_kib": 17170.0, "write_kib": 1116.9, "fetch_scale": 2.0, "write_scale": 1.0}
+# HBM-side bytes per activation launch of each workload's activation kernel,
+# from rocprofv3 FETCH_SIZE and WRITE_SIZE runs (KiB per dispatch) scaled by
+# what the same counters read for a plain 256 MiB copy (FETCH x 2.0, WRITE x
+# 1.0), for the kernel sources whose sha256 prefix is given and the tiling
+# the counters were taken with; reported only while both are unchanged.
 KERNEL_SOURCES = ("cpm_sweep_kernels.hpp", "cpm_sweep_inst.hip", "cpm_sweep.hip", "cpm_device.hpp", "cpm_internal.hpp")
-# The same for the 1024^3 tissue workload's activation kernel
-# (label-type-activity words).
-MEASURED_TRAFFIC_TISSUE = {"sources_sha256": "a6292773102e85c3", "layout": "in_place", "fetch_kib": 2570054.3,
-                           "write_kib": 255357.3, "fetch_scale": 2.0, "write_scale": 1.0}
-# The 2048^2 sorting workload's activation kernel (16-bit labels, in place).
-MEASURED_TRAFFIC_SORTING = {"sources_sha256": "a6292773102e85c3", "layout": "in_place", "fetch_kib": 6178.4,
-                            "write_kib": 266.1, "fetch_scale": 2.0, "write_scale": 1.0}
-# The 256^3 collective's activation kernel (16-bit labels, persistence term).
-MEASURED_TRAFFIC_COLLECTIVE = {"sources_sha256": "a6292773102e85c3", "layout": "in_place", "fetch_kib": 18822.7,
-                               "write_kib": 4253.4, "fetch_scale": 2.0, "write_scale": 1.0}
-# The 512-lattice 2D batch's activation kernel (label-type-activity words).
-MEASURED_TRAFFIC_BATCH = {"sources_sha256": "a6292773102e85c3", "layout": None, "fetch_kib": 138426.3,
-                          "write_kib": 11193.9, "fetch_scale": 2.0, "write_scale": 1.0}
+_SHA = "c5de0e0b1ad7e1d3"
+# 3D 256^3 (16-bit labels, in place)
+MEASURED_TRAFFIC = {"sources_sha256": _SHA, "layout": "in_place", "tile": [64, 2, 2], "order": "linear",
+                    "fetch_kib": 15152.3, "write_kib": 388.3, "fetch_scale": 2.0, "write_scale": 1.0}
+# 1024^3 tissue (label-type-activity words)
+MEASURED_TRAFFIC_TISSUE = {"sources_sha256": _SHA, "layout": "in_place", "tile": [256, 1, 1], "order": "linear",
+                           "fetch_kib": 2436754.6, "write_kib": 255365.8, "fetch_scale": 2.0, "write_scale": 1.0}
+# 2048^2 sorting (16-bit labels)
+MEASURED_TRAFFIC_SORTING = {"sources_sha256": _SHA, "layout": "in_place", "tile": [256, 1, 1], "order": "linear",
+                            "fetch_kib": 4265.4, "write_kib": 245.4, "fetch_scale": 2.0, "write_scale": 1.0}
+# 256^3 collective (16-bit labels, persistence term)
+MEASURED_TRAFFIC_COLLECTIVE = {"sources_sha256": _SHA, "layout": "in_place", "tile": [64, 2, 2], "order": "linear",
+                               "fetch_kib": 16876.9, "write_kib": 3898.6, "fetch_scale": 2.0, "write_scale": 1.0}
+# 512 uneven 2D lattices (16-bit label-activity words; in place, the
+# library's tiles, graph replay)
+MEASURED_TRAFFIC_BATCH = {"sources_sha256": _SHA, "layout": "in_place", "tile": None, "order": "linear",
+                          "fetch_kib": 55418.1, "write_kib": 10502.9, "fetch_scale": 2.0, "write_scale": 1.0}
 
 
 def kernel_sources_sha():
@@ -346,6 +348,13 @@ def main():
     sim.close()
 
 
+def traffic_of(cpm, params, w, table):
+    """A traffic table's bytes per launch when the model's tiling is the one
+    the counters were taken with."""
+    t = cpm.cpm_tile_shape(params, w.n_cells)
+    return measured_traffic_bytes(t["layout"], table, tile=t["areas"], order=t["order"])
+
+
 def label_storage(tiling, act_words=False):
     """What the activation kernel reads per site, for the report."""
     if act_words:
@@ -414,7 +423,7 @@ def bench_tissue(args):
     per_launch_bytes = bytes_per_attempt(3, w.s, w.k, p_acc, act=True) * (w.n_sites // n_act)
     achieved = per_launch_bytes / avg_launch_s / 1e9
     cpu = None
-    n_cpu = sample_mcs(args, 24)
+    n_cpu = sample_mcs(args, 72)
     if n_cpu > 0:
         # the oracle on a 128^3 crop of the same recipe (obstacle field, cells
         # of V_target 1000 at the same density, half of them motile)
@@ -425,16 +434,13 @@ def bench_tissue(args):
         "metric": "site copy-attempts/s on 3D 1024³ tissue (HBM % peak)",
         "value": w.n_sites * args.steps / (total_ms / 1e3), "unit": "attempts/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": total_ms / args.steps,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
         "config": {"workload": w.name, "lattice": list(w.dims), "n_cells": w.n_cells,
                    "obstacle_voxels": w.extra["obstacle_voxels"], "sub": w.s, "attempts_per_activation": w.k,
-                   "act": True, "tiling": cpm.cpm_tile_shape(params, w.n_cells), "tuning_ms_per_mcs": tuning},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic_bytes(cpm.cpm_tile_shape(params, w.n_cells)["layout"],
-                                                       MEASURED_TRAFFIC_TISSUE),
-                     "kernel": "tile_sweep_kernel_packed", "avg_launch_us": avg_launch_s * 1e6,
-                     "bytes_per_attempt": bytes_per_attempt(3, w.s, w.k, p_acc, act=True)},
+                   "act": True, "tiling": cpm.cpm_tile_shape(params, w.n_cells), "tuning_ms_per_mcs": tuning,
+                   "label_storage": label_storage(None, act_words=True)},
+        "roofline": roofline_fields(achieved, traffic_of(cpm, params, w, MEASURED_TRAFFIC_TISSUE), avg_launch_s,
+                                    "tile_sweep_kernel_packed", bytes_per_attempt(3, w.s, w.k, p_acc, act=True)),
         "cpu_baseline": cpu_fields(cpu)}), flush=True)
     sim.close()
 
@@ -478,17 +484,13 @@ def bench_sorting(args):
         "metric": "site copy-attempts/s on 2D 2048² cell sorting", "value": w.n_sites * args.steps / (total_ms / 1e3),
         "unit": "attempts/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": total_ms / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "int32", "data": "synthetic",
+        "dtype": "int64", "data": "synthetic",
         "config": {"workload": w.name, "lattice": list(w.dims), "n_cells": w.n_cells, "sub": w.s,
                    "attempts_per_activation": w.k, "tiling": cpm.cpm_tile_shape(params, w.n_cells),
                    "tuning_ms_per_mcs": tuning, "homotypic_contacts_before": h0,
                    "homotypic_contacts_after": h1, "mcs_run": args.warmup + args.steps},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic_bytes(cpm.cpm_tile_shape(params, w.n_cells)["layout"],
-                                                       MEASURED_TRAFFIC_SORTING),
-                     "kernel": "tile_sweep_kernel",
-                     "avg_launch_us": avg_launch_s * 1e6, "bytes_per_attempt": bytes_per_attempt(2, w.s, w.k, p_acc)},
+        "roofline": roofline_fields(achieved, traffic_of(cpm, params, w, MEASURED_TRAFFIC_SORTING), avg_launch_s,
+                                    "tile_sweep_kernel", bytes_per_attempt(2, w.s, w.k, p_acc)),
         "cpu_baseline": cpu_fields(cpu)}),
         flush=True)
     sim.close()
@@ -544,18 +546,14 @@ def bench_collective(args):
         "metric": "site copy-attempts/s on a 3D 256³ persistent cell collective",
         "value": w.n_sites * args.steps / (total_ms / 1e3), "unit": "attempts/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": total_ms / args.steps,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
         "config": {"workload": w.name, "lattice": list(w.dims), "n_cells": w.n_cells,
                    "density": w.extra["density"], "sub": w.s, "attempts_per_activation": w.k,
                    "persistence": {"lambda": float(w.lambda_P[1]), "mu": float(w.mu_P[1]), "dt": w.dt_P},
                    "tiling": cpm.cpm_tile_shape(params, w.n_cells), "tuning_ms_per_mcs": tuning,
                    "order_before": o0, "order_after": o1, "mcs_run": args.warmup + args.steps},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic_bytes(cpm.cpm_tile_shape(params, w.n_cells)["layout"],
-                                                       MEASURED_TRAFFIC_COLLECTIVE),
-                     "kernel": "tile_sweep_kernel",
-                     "avg_launch_us": avg_launch_s * 1e6, "bytes_per_attempt": bytes_per_attempt(3, w.s, w.k, p_acc)},
+        "roofline": roofline_fields(achieved, traffic_of(cpm, params, w, MEASURED_TRAFFIC_COLLECTIVE), avg_launch_s,
+                                    "tile_sweep_kernel", bytes_per_attempt(3, w.s, w.k, p_acc)),
         "cpu_baseline": cpu_fields(cpu)}),
         flush=True)
     sim.close()
@@ -593,7 +591,7 @@ def bench_accuracy(args):
         "metric": "site copy-attempts/s of a 2D chemotaxis ensemble, with its accuracy against the serial CPM",
         "value": main_row["attempts_per_s"], "unit": "attempts/s", "n_gpus": 1, "steps": args.acc_mcs,
         "warmup": 1, "ms_per_step": main_row["ms_per_mcs"], "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "vs_baseline": None, "dtype": "int64", "data": "synthetic",
         "config": {"workload": w.name, "lattice": list(w.dims), "n_cells": w.n_cells, "runs": args.acc_runs,
                    "study": out},
         "roofline": None,
@@ -648,7 +646,7 @@ def bench_polarisation(args):
         "metric": "site copy-attempts/s of a 2D Act ensemble, with its directional autocorrelation against the serial CPM",
         "value": n_att / (main["ms"] / 1e3), "unit": "attempts/s", "n_gpus": 1, "steps": out["n_mcs"], "warmup": 0,
         "ms_per_step": main["ms"] / out["n_mcs"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "int32", "data": "synthetic",
+        "dtype": "int64", "data": "synthetic",
         "config": {"workload": "2d-200x200-act-single-cell", "lambdas": list(lambdas), "runs": out["n_runs"],
                    "interval": out["interval"], "modes": rows},
         "roofline": None, "cpu_baseline": cpu_fields(cpu)}), flush=True)
@@ -695,8 +693,11 @@ def bench_batch(args):
     per_launch_bytes = bytes_per_attempt(2, ws[0].s, ws[0].k, acc, act=True) * (sites // n_act)
     achieved = per_launch_bytes / avg_launch_s / 1e9
     b.close()
+    # measured traffic: taken in place with the library's tiles and graph replay
+    default_cfg = cfg["layout"] == "in_place" and all(t == "auto" for t in cfg["tiles"]) and cfg["mode"] == "graph"
+    batch_traffic = measured_traffic_bytes("in_place", MEASURED_TRAFFIC_BATCH) if default_cfg else None
     cpu = cpu_threads = None
-    n_cpu = sample_mcs(args, 24)
+    n_cpu = sample_mcs(args, 48)
     if n_cpu > 0:
         # the oracle on the first 64 lattices of the batch: one pinned
         # thread, then one thread per allowed CPU (at most 16)
@@ -706,15 +707,13 @@ def bench_batch(args):
         "metric": "site copy-attempts/s, 512 batched uneven 2D lattices", "value": sites * args.steps / (ms / 1e3),
         "unit": "attempts/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "int32", "data": "synthetic",
+        "dtype": "int64", "data": "synthetic",
         "config": {"workload": f"2d-batch-{len(ws)}-L64..{args.batch_max_side}", "n_lattices": len(ws), "sites": sites, "sub": ws[0].s,
                    "attempts_per_activation": ws[0].k, "act": True, "launch": tuned, "tuning_ms_per_mcs": tuning,
                    "label_storage": "uint16 words: label + 1 and activity (one cell type, at most 2,046 cells, "
                                     "Max_act <= 31), written from the int32 lattices and activities per sweep call"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic_bytes(None, MEASURED_TRAFFIC_BATCH),
-                     "kernel": "batch_sweep_kernel",
-                     "avg_launch_us": avg_launch_s * 1e6},
+        "roofline": roofline_fields(achieved, batch_traffic, avg_launch_s, "batch_sweep_kernel",
+                                    bytes_per_attempt(2, ws[0].s, ws[0].k, acc, act=True)),
         "cpu_baseline": cpu_fields(cpu), "cpu_baseline_threads": cpu_fields(cpu_threads)}), flush=True)
 
 
@@ -726,7 +725,7 @@ def bench_emulator(args):
     r = emulator.study(n_train=args.emu_train, n_test=args.emu_test, reps=args.emu_reps, epochs=args.emu_epochs,
                        batch=args.emu_batch, lr=args.emu_lr, lr_final=args.emu_lr / 40, log=log,
                        data_path=args.emu_data, train_reps=args.emu_train_reps)
-    cpu = emulator_cpu_baseline(args) if sample_mcs(args, 4) > 0 else None
+    cpu = emulator_cpu_baseline(args) if sample_mcs(args, 100) > 0 else None
     print(json.dumps({
         "metric": "emulator vs CPM cost per parameter point", "value": r["cost_ratio"], "unit": "x",
         "n_gpus": 1, "steps": args.emu_epochs, "warmup": 0, "ms_per_step": None, "higher_is_better": True,
@@ -747,8 +746,8 @@ def emulator_cpu_baseline(args):
     from oracle import mlp
     from paper_2312_09317_amd import emulator
     plan = emulator.RunPlan()
-    pts = emulator.points(8, seed=1)
-    n_mcs = sample_mcs(args, 4)
+    pts = emulator.points(16, seed=1)
+    n_mcs = sample_mcs(args, 100)
 
     def cpm_side():
         t = 0.0
@@ -769,7 +768,7 @@ def emulator_cpu_baseline(args):
     (cpm_s, cpu_id) = pinned(cpm_side)
     (mlp_s, _) = pinned(mlp_side)
     return {"value": cpm_s / mlp_s, "unit": "x", "cores": 1, "kind": "oracle",
-            "sample": f"oracle CPM: 8 parameter points x {n_mcs} MCS, scaled to {plan.n_mcs} MCS per run "
+            "sample": f"oracle CPM: {len(pts)} parameter points x {n_mcs} MCS, scaled to {plan.n_mcs} MCS per run "
                       f"({cpm_s:.2f} s per point); FP64 reference MLP: 65,536 points ({mlp_s * 1e6:.2f} us per "
                       f"point); one thread pinned to CPU {cpu_id}",
             "host_cpus": host_cpus(), "pinned_cpu": cpu_id}

@@ -199,9 +199,15 @@ bool tile_geometry(const cpm_params *p, bool mirror, int force_layout, cpm::Tile
     if (force_layout < 0) force_layout = k1 && kDirectForK1 ? 2 : -1;
     if (force_layout == 2) {
         if (!k1) return false;
-        // in place: tiles of up to kBlock areas, whole rows of areas first
+        // in place: tiles of up to kBlock areas, whole rows of areas first;
+        // in 3D the rest split evenly between y and z (a squarer cross
+        // section shares more of its neighbours' rows)
         T[0] = want[0] ? want[0] : std::min(na[0], cpm::kBlock);
-        T[1] = want[1] ? want[1] : std::min(na[1], cpm::kBlock / T[0]);
+        const int rest = cpm::kBlock / T[0];
+        int t1 = rest;
+        if (p->ndim == 3)
+            while (t1 > 1 && t1 * t1 > rest) --t1;
+        T[1] = want[1] ? want[1] : std::min(na[1], t1);
         T[2] = p->ndim == 3 ? (want[2] ? want[2] : std::min(na[2], cpm::kBlock / (T[0] * T[1]))) : 1;
         g.box_sites = 0;
         g.lds_bytes = 0;
