@@ -82,22 +82,46 @@ __device__ __forceinline__ int64_t gm_lds(const DeviceModel *m, const int64_t *l
 {
     if (cell <= 0 || !motile) return 0;
     const int c = map.at(x, y, z);
+    constexpr int NNB = D == 2 ? 8 : 26;
     const uint32_t a0 = act_at(lab, lact, c);
     uint64_t sum = (uint64_t)lg[a0];
     uint32_t cnt = 1;
     bool zero = a0 == 0;
-    constexpr int NNB = D == 2 ? 8 : 26;
-    // every label and activity of the neighbourhood is loaded before any is
-    // used, so the in-place layout reads them in one round
+    if (LAYOUT == kDirect) {
+        // in place (global memory): every word (and activity) of the
+        // neighbourhood is loaded, in a block without branches, before any
+        // is used, so they are read in one round; the sums then take every
+        // table entry and mask the ones of other labels (a branch around the
+        // lookups would split the loads into one round each)
+        Cell w[NNB];
+        uint32_t av[NNB];
 #pragma unroll
-    for (int n = 0; n < NNB; ++n) {
-        const int u = map.at(x + nb_dx<D>(n), y + nb_dy<D>(n), z + nb_dz<D>(n));
-        const int lu = label_of(lab[u]);
-        const uint32_t au = act_at(lab, lact, u);
-        if (lu == cell) {
-            zero |= au == 0;
-            sum += (uint64_t)lg[au];
-            ++cnt;
+        for (int n = 0; n < NNB; ++n) {
+            const int u = map.at(x + nb_dx<D>(n), y + nb_dy<D>(n), z + nb_dz<D>(n));
+            w[n] = lab[u];
+            av[n] = WordAct<Cell>::kIn ? 0u : (uint32_t)lact[u];
+        }
+#pragma unroll
+        for (int n = 0; n < NNB; ++n) {
+            const bool same = label_of(w[n]) == cell;
+            const uint32_t au = WordAct<Cell>::kIn ? (uint32_t)w[n] >> WordAct<Cell>::kShift : av[n];
+            const uint64_t v = (uint64_t)lg[au];
+            zero |= same && au == 0;
+            sum += same ? v : 0;
+            cnt += same ? 1u : 0u;
+        }
+    } else {
+        // staged in LDS: reads are cheap, only like labels are looked up
+#pragma unroll
+        for (int n = 0; n < NNB; ++n) {
+            const int u = map.at(x + nb_dx<D>(n), y + nb_dy<D>(n), z + nb_dz<D>(n));
+            const int lu = label_of(lab[u]);
+            const uint32_t au = act_at(lab, lact, u);
+            if (lu == cell) {
+                zero |= au == 0;
+                sum += (uint64_t)lg[au];
+                ++cnt;
+            }
         }
     }
     return zero ? 0 : exp_log24(m, sum / cnt);
@@ -132,9 +156,18 @@ __device__ __forceinline__ bool evaluate_nb(const SweepArgs &a, const ThrTables 
     int k_old = 0, k_new = 0;
     int n_cell = 0, n_med = 0, n_obs = 0;
     int64_t adh = 0;
+    // in place with several cell types the neighbourhood's words come first,
+    // in a block without branches (one round of global loads), then the
+    // sums, which read every J entry and mask the ones of like labels
+    constexpr bool GROUP = !SINGLE && LAYOUT == kDirect;
+    Cell nw[NNB];
+    if (GROUP) {
+#pragma unroll
+        for (int n = 0; n < NNB; ++n) nw[n] = nbl(n);
+    }
 #pragma unroll
     for (int n = 0; n < NNB; ++n) {
-        const Cell word = nbl(n);
+        const Cell word = GROUP ? nw[n] : nbl(n);
         const int lu = label_of(word);
         k_old += lu == lt;
         k_new += lu == ls;
@@ -142,6 +175,10 @@ __device__ __forceinline__ bool evaluate_nb(const SweepArgs &a, const ThrTables 
             n_cell += lu > 0;
             n_med += lu == 0;
             n_obs += lu < 0;
+        } else if (GROUP) {
+            const int tu = type_of_word(a, word, lu);
+            const int64_t js = st.J[ts * kMaxTypes + tu], jt = st.J[tt * kMaxTypes + tu];
+            adh += (lu != ls ? js : 0) - (lu != lt ? jt : 0);
         } else {
             const int tu = type_of_word(a, word, lu);
             if (lu != ls) adh += st.J[ts * kMaxTypes + tu];
@@ -676,18 +713,22 @@ __global__ void __launch_bounds__(kBlock) tile_sweep_kernel(SweepArgs a, uint32_
 
 // Packed words serve large multi-type lattices, whose sweeps wait on HBM:
 // more waves per SIMD hide more of that latency than the registers the
-// limit takes away cost.
+// limit takes away cost.  A 3D multi-type sweep in place holds the 26
+// neighbour words and their J entries at once (loaded in one round); its
+// cap is lower, so that they stay in registers.
 #ifndef CPM_PACKED_WAVES
 #define CPM_PACKED_WAVES 8
 #endif
-#if CPM_PACKED_WAVES > 0
-#define CPM_PACKED_ATTR __attribute__((amdgpu_waves_per_eu(CPM_PACKED_WAVES)))
-#else
-#define CPM_PACKED_ATTR
+#ifndef CPM_PACKED_WAVES_3D
+#define CPM_PACKED_WAVES_3D 3
 #endif
+template <int D, bool SINGLE, int LAYOUT>
+struct PackedWaves {
+    static constexpr int value = D == 3 && !SINGLE && LAYOUT == kDirect ? CPM_PACKED_WAVES_3D : CPM_PACKED_WAVES;
+};
 template <typename Word, int D, bool ACT, bool SINGLE, bool K1, int LAYOUT, bool EXT>
-__global__ void __launch_bounds__(kBlock) CPM_PACKED_ATTR tile_sweep_kernel_packed(SweepArgs a, uint32_t mcs,
-                                                                                    uint32_t alpha, int parity)
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PackedWaves<D, SINGLE, LAYOUT>::value)))
+tile_sweep_kernel_packed(SweepArgs a, uint32_t mcs, uint32_t alpha, int parity)
 {
     const int tile = xcd_tile(a.tg, blockIdx.x);
     if (tile >= a.tg.n_tiles) return;  // uniform over the block
