@@ -138,17 +138,25 @@ struct ThrTables {
 };
 
 // Accept iff q <= 0 or u < floor(TI[h] TM[m] TL[l] / 2^64), q = h*2^16 + m*2^8 + l.
+// The three table entries are read in one round (indices clamped into the
+// tables) and the decision is taken without branches: the entries a case
+// does not use are ignored.
 __device__ __forceinline__ bool metropolis32(const ThrTables &tb, int64_t q, uint32_t u)
 {
-    if (q <= 0) return true;
     const uint64_t h = (uint64_t)q >> 16;
-    if (h >= (uint64_t)tb.n_ti) return false;
-    const uint64_t two32 = (uint64_t)1 << 32;
-    const uint64_t ti = h == 0 ? two32 : (uint64_t)tb.ti[h];
-    if ((q & 0xFFFF) == 0) return (uint64_t)u < ti;
+    const bool in = q > 0 && h < (uint64_t)tb.n_ti;
     const int mm = (int)((q >> 8) & 255), ll = (int)(q & 255);
-    const uint64_t tm = mm ? (uint64_t)tb.tm[mm] : two32, tl = ll ? (uint64_t)tb.tl[ll] : two32;
-    return (uint64_t)u < __umul64hi(ti, tm * tl);  // tm * tl < 2^64 since (mm, ll) != (0, 0)
+    const uint64_t two32 = (uint64_t)1 << 32;
+    const uint32_t ti_w = tb.ti[in ? h : 0], tm_w = tb.tm[mm], tl_w = tb.tl[ll];
+    // an empty asm that takes the three entries keeps the compiler from
+    // moving the loads of tm and tl into the branch that uses them
+    asm volatile("" ::"v"(ti_w), "v"(tm_w), "v"(tl_w));
+    const uint64_t ti_e = ti_w, tm_e = tm_w, tl_e = tl_w;
+    const uint64_t ti = h == 0 ? two32 : ti_e;
+    const uint64_t tm = mm ? tm_e : two32, tl = ll ? tl_e : two32;
+    // tm * tl < 2^64 whenever (mm, ll) != (0, 0), the only case it is used
+    const uint64_t thr = (q & 0xFFFF) == 0 ? ti : __umul64hi(ti, tm * tl);
+    return (q <= 0) | (in & ((uint64_t)u < thr));
 }
 
 // exp(l * 2^-24) in 2^16 fixed point, floor-composed from the split tables.

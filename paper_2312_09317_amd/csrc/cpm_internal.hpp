@@ -59,6 +59,28 @@ struct DeviceModel {
     int32_t unit[27][3];
 };
 
+// The per-type energy parameters of DeviceModel (lam_v through max_act, in
+// its order): sweeps copy this block into LDS, where an attempt reads it
+// without a round trip to global memory.
+struct TypeParams {
+    int64_t lam_v[kMaxTypes];
+    int64_t lam_s[kMaxTypes];
+    int64_t r_act[kMaxTypes];
+    int32_t v_target[kMaxTypes];
+    int32_t s_target[kMaxTypes];
+    int32_t max_act[kMaxTypes];
+};
+static_assert(offsetof(DeviceModel, lam_v) % 16 == 0, "the block is copied in 16-byte words");
+static_assert(sizeof(TypeParams) % 16 == 0, "the block is copied in 16-byte words");
+static_assert(offsetof(DeviceModel, max_act) + sizeof(DeviceModel::max_act) - offsetof(DeviceModel, lam_v) ==
+                      sizeof(TypeParams) &&
+                  offsetof(DeviceModel, lam_s) - offsetof(DeviceModel, lam_v) == offsetof(TypeParams, lam_s) &&
+                  offsetof(DeviceModel, r_act) - offsetof(DeviceModel, lam_v) == offsetof(TypeParams, r_act) &&
+                  offsetof(DeviceModel, v_target) - offsetof(DeviceModel, lam_v) == offsetof(TypeParams, v_target) &&
+                  offsetof(DeviceModel, s_target) - offsetof(DeviceModel, lam_v) == offsetof(TypeParams, s_target) &&
+                  offsetof(DeviceModel, max_act) - offsetof(DeviceModel, lam_v) == offsetof(TypeParams, max_act),
+              "TypeParams mirrors the per-type block of DeviceModel");
+
 // How thread areas are grouped into workgroup tiles.  Tiles are numbered x
 // fastest; the tiles of XCD x are the contiguous range
 // [x * tiles_per_xcd, (x + 1) * tiles_per_xcd), so each XCD sweeps one slab

@@ -73,6 +73,32 @@ struct LdsMap {
     __device__ __forceinline__ int at(int vx, int vy, int vz) const { return x(vx) + row(vy, vz); }
 };
 
+// The mean of ln(activity) (2^-24 units) over a site and its Moore
+// neighbours of the same cell (the exponent of eq. 8), from words (and
+// activities) already loaded; `dead` when any of those activities is 0.
+// Every table entry is read and the ones of other labels masked, so the
+// loop has no branch.  The sum fits 32 bits: ln(255) 2^24 < 2^27, at most
+// 27 terms.
+template <typename Cell, int NNB>
+__device__ __forceinline__ uint32_t mean_log_act(const int64_t *lg, uint32_t a0, const Cell *w, const uint32_t *av,
+                                                 int cell, bool &dead)
+{
+    uint32_t sum = (uint32_t)lg[a0];
+    uint32_t cnt = 1;
+    bool zero = a0 == 0;
+#pragma unroll
+    for (int n = 0; n < NNB; ++n) {
+        const bool same = label_of(w[n]) == cell;
+        const uint32_t au = WordAct<Cell>::kIn ? (uint32_t)w[n] >> WordAct<Cell>::kShift : av[n];
+        const uint32_t v = (uint32_t)lg[au];
+        zero |= same && au == 0;
+        sum += same ? v : 0u;
+        cnt += same ? 1u : 0u;
+    }
+    dead = zero;
+    return sum / cnt;
+}
+
 // Geometric mean of the activity over the site at (x,y,z) (label `cell`) and
 // its Moore neighbours of the same cell (eq. 8), 2^16 fixed point.
 template <typename Cell, int D, int LAYOUT>
@@ -84,15 +110,9 @@ __device__ __forceinline__ int64_t gm_lds(const DeviceModel *m, const int64_t *l
     const int c = map.at(x, y, z);
     constexpr int NNB = D == 2 ? 8 : 26;
     const uint32_t a0 = act_at(lab, lact, c);
-    uint64_t sum = (uint64_t)lg[a0];
-    uint32_t cnt = 1;
-    bool zero = a0 == 0;
     if (LAYOUT == kDirect) {
-        // in place (global memory): every word (and activity) of the
-        // neighbourhood is loaded, in a block without branches, before any
-        // is used, so they are read in one round; the sums then take every
-        // table entry and mask the ones of other labels (a branch around the
-        // lookups would split the loads into one round each)
+        // in place (global memory): the neighbourhood's words (and
+        // activities) in one round, then the masked sums
         Cell w[NNB];
         uint32_t av[NNB];
 #pragma unroll
@@ -101,27 +121,23 @@ __device__ __forceinline__ int64_t gm_lds(const DeviceModel *m, const int64_t *l
             w[n] = lab[u];
             av[n] = WordAct<Cell>::kIn ? 0u : (uint32_t)lact[u];
         }
+        bool dead;
+        const uint32_t ell = mean_log_act<Cell, NNB>(lg, a0, w, av, cell, dead);
+        return dead ? 0 : exp_log24(m, ell);
+    }
+    // staged (LDS): reads are cheap, only like labels are looked up
+    uint64_t sum = (uint64_t)lg[a0];
+    uint32_t cnt = 1;
+    bool zero = a0 == 0;
 #pragma unroll
-        for (int n = 0; n < NNB; ++n) {
-            const bool same = label_of(w[n]) == cell;
-            const uint32_t au = WordAct<Cell>::kIn ? (uint32_t)w[n] >> WordAct<Cell>::kShift : av[n];
-            const uint64_t v = (uint64_t)lg[au];
-            zero |= same && au == 0;
-            sum += same ? v : 0;
-            cnt += same ? 1u : 0u;
-        }
-    } else {
-        // staged in LDS: reads are cheap, only like labels are looked up
-#pragma unroll
-        for (int n = 0; n < NNB; ++n) {
-            const int u = map.at(x + nb_dx<D>(n), y + nb_dy<D>(n), z + nb_dz<D>(n));
-            const int lu = label_of(lab[u]);
-            const uint32_t au = act_at(lab, lact, u);
-            if (lu == cell) {
-                zero |= au == 0;
-                sum += (uint64_t)lg[au];
-                ++cnt;
-            }
+    for (int n = 0; n < NNB; ++n) {
+        const int u = map.at(x + nb_dx<D>(n), y + nb_dy<D>(n), z + nb_dz<D>(n));
+        const int lu = label_of(lab[u]);
+        const uint32_t au = act_at(lab, lact, u);
+        if (lu == cell) {
+            zero |= au == 0;
+            sum += (uint64_t)lg[au];
+            ++cnt;
         }
     }
     return zero ? 0 : exp_log24(m, sum / cnt);
@@ -132,17 +148,18 @@ struct JRows {
     int64_t cc, cm, co, mc, mm, mo;
 };
 
+// Per-workgroup LDS copies of the model tables an attempt reads: J
+// (multi-type models), the Act log table and the per-type parameters.
+struct SharedTables {
+    const int64_t *J;
+    const int64_t *lg;
+    const TypeParams *tp;
+};
+
 // One copy attempt past the early rejection: energy change of copying label
 // ls into the target (x,y,z) (eq. 1, eq. 3, eq. 7) and the Metropolis test
 // (eq. 2).  cnt_t / cnt_s are the (V, S) counters of the two cells as the
 // attempt sees them.  Returns acceptance; dso / dsn are the surface deltas.
-// Per-workgroup LDS copies of the model tables the energy change reads per
-// neighbour: J (multi-type models) and the Act log table.
-struct SharedTables {
-    const int64_t *J;
-    const int64_t *lg;
-};
-
 // nbl(n) gives the label of the target's n-th Moore neighbour.
 template <typename Cell, int D, bool ACT, bool SINGLE, int LAYOUT, bool EXT, typename NB>
 __device__ __forceinline__ bool evaluate_nb(const SweepArgs &a, const ThrTables &tb, const JRows &jr,
@@ -152,19 +169,35 @@ __device__ __forceinline__ bool evaluate_nb(const SweepArgs &a, const ThrTables 
                                             uint32_t u2, int64_t &dso_out, int64_t &dsn_out)
 {
     constexpr int NNB = D == 2 ? 8 : 26;
+    constexpr bool kIn = WordAct<Cell>::kIn;
     const DeviceModel *m = a.model;
-    int k_old = 0, k_new = 0;
-    int n_cell = 0, n_med = 0, n_obs = 0;
-    int64_t adh = 0;
-    // in place with several cell types the neighbourhood's words come first,
-    // in a block without branches (one round of global loads), then the
-    // sums, which read every J entry and mask the ones of like labels
-    constexpr bool GROUP = !SINGLE && LAYOUT == kDirect;
+    const TypeParams *tp = st.tp;
+    // In place (global memory), the target's neighbourhood comes first, in
+    // a block without branches, so that it is read in one round (several
+    // cell types, or the Act term, whose target mean reuses it); staged
+    // layouts read LDS as they go.  The source's neighbourhood (Act) is read
+    // only for a motile source, in its own round: reading it with the
+    // target's measured slower (registers).
+    constexpr bool GROUP = LAYOUT == kDirect && (!SINGLE || ACT);
+    constexpr bool GACT = GROUP && ACT;
     Cell nw[NNB];
+    uint32_t nav[GACT && !kIn ? NNB : 1];
+    uint32_t ca_t = 0;
     if (GROUP) {
 #pragma unroll
         for (int n = 0; n < NNB; ++n) nw[n] = nbl(n);
+        if (GACT) {
+            ca_t = act_at(lab, lact, map.at(tx_, ty_, tz_));
+            if (!kIn) {
+#pragma unroll
+                for (int n = 0; n < NNB; ++n)
+                    nav[n] = lact[map.at(tx_ + nb_dx<D>(n), ty_ + nb_dy<D>(n), tz_ + nb_dz<D>(n))];
+            }
+        }
     }
+    int k_old = 0, k_new = 0;
+    int n_cell = 0, n_med = 0, n_obs = 0;
+    int64_t adh = 0;
 #pragma unroll
     for (int n = 0; n < NNB; ++n) {
         const Cell word = GROUP ? nw[n] : nbl(n);
@@ -176,6 +209,7 @@ __device__ __forceinline__ bool evaluate_nb(const SweepArgs &a, const ThrTables 
             n_med += lu == 0;
             n_obs += lu < 0;
         } else if (GROUP) {
+            // every J entry read, the ones of like labels masked
             const int tu = type_of_word(a, word, lu);
             const int64_t js = st.J[ts * kMaxTypes + tu], jt = st.J[tt * kMaxTypes + tu];
             adh += (lu != ls ? js : 0) - (lu != lt ? jt : 0);
@@ -196,20 +230,27 @@ __device__ __forceinline__ bool evaluate_nb(const SweepArgs &a, const ThrTables 
     const int64_t dsn = NNB - 2 * k_new;
     int64_t q = adh;
     if (lt >= 1) {
-        q += m->lam_v[tt] * (1 - 2 * ((int64_t)cnt_t.x - m->v_target[tt]));
-        q += m->lam_s[tt] * (2 * dso * ((int64_t)cnt_t.y - m->s_target[tt]) + dso * dso);
+        q += tp->lam_v[tt] * (1 - 2 * ((int64_t)cnt_t.x - tp->v_target[tt]));
+        q += tp->lam_s[tt] * (2 * dso * ((int64_t)cnt_t.y - tp->s_target[tt]) + dso * dso);
     }
     if (ls >= 1) {
-        q += m->lam_v[ts] * (2 * ((int64_t)cnt_s.x - m->v_target[ts]) + 1);
-        q += m->lam_s[ts] * (2 * dsn * ((int64_t)cnt_s.y - m->s_target[ts]) + dsn * dsn);
+        q += tp->lam_v[ts] * (2 * ((int64_t)cnt_s.x - tp->v_target[ts]) + 1);
+        q += tp->lam_s[ts] * (2 * dsn * ((int64_t)cnt_s.y - tp->s_target[ts]) + dsn * dsn);
     }
     if (ACT) {
-        const int64_t gt = gm_lds<Cell, D, LAYOUT>(m, st.lg, lab, lact, map, tx_, ty_, tz_, lt,
-                                                    lt > 0 && m->max_act[tt] > 0);
-        const int64_t gs = gm_lds<Cell, D, LAYOUT>(m, st.lg, lab, lact, map, sx_, sy_, sz_, ls,
-                                                    ls > 0 && m->max_act[ts] > 0);
-        const int64_t rt = lt >= 1 ? m->r_act[tt] : 0;
-        const int64_t rs = ls >= 1 ? m->r_act[ts] : 0;
+        const bool mot_t = lt > 0 && tp->max_act[tt] > 0, mot_s = ls > 0 && tp->max_act[ts] > 0;
+        int64_t gt;
+        if (GACT) {
+            bool dead_t;
+            const uint32_t ell_t = mean_log_act<Cell, NNB>(st.lg, ca_t, nw, nav, lt, dead_t);
+            const int64_t et = exp_log24(m, ell_t);
+            gt = mot_t && !dead_t ? et : 0;
+        } else {
+            gt = gm_lds<Cell, D, LAYOUT>(m, st.lg, lab, lact, map, tx_, ty_, tz_, lt, mot_t);
+        }
+        const int64_t gs = gm_lds<Cell, D, LAYOUT>(m, st.lg, lab, lact, map, sx_, sy_, sz_, ls, mot_s);
+        const int64_t rt = lt >= 1 ? tp->r_act[tt] : 0;
+        const int64_t rs = ls >= 1 ? tp->r_act[ts] : 0;
         q += (rt * gt - rs * gs) >> 16;
     }
     if (EXT && a.pdir && ls >= 1) {
@@ -292,6 +333,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
     __shared__ int4 queue_cnt[K1 ? kQueue : 1];
     __shared__ int64_t j_lds[SINGLE ? 1 : kMaxTypes * kMaxTypes];
     __shared__ int64_t lg_lds[ACT ? 256 : 1];
+    __shared__ __align__(16) TypeParams tp_lds;
     constexpr int R = ACT ? 2 : 1;           // read radius: the Act term reads neighbours of the source
     constexpr int NNB = D == 2 ? 8 : 26;
 
@@ -337,7 +379,9 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
         for (int i = tid; i < a.n_types * kMaxTypes; i += kBlock) j_lds[i] = a.model->J[i];
     if (ACT)
         for (int i = tid; i < a.lg_entries; i += kBlock) lg_lds[i] = a.model->LG[i];
-    const SharedTables sht{j_lds, lg_lds};
+    if (tid < (int)(sizeof(TypeParams) / sizeof(int4)))
+        reinterpret_cast<int4 *>(&tp_lds)[tid] = reinterpret_cast<const int4 *>(a.model->lam_v)[tid];
+    const SharedTables sht{j_lds, lg_lds, &tp_lds};
     // deltas of the previous activation go into the write buffer as well
     // k = 1 in place: every attempt is evaluated by the thread that draws it
     // (no queue): measured faster than queueing the nontrivial attempts across
@@ -391,7 +435,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
     constexpr bool kActWord = WordAct<Cell>::kIn;
     auto commit = [&](int t, int gi, int lt, int ls, Cell ws, int ts, int64_t dso, int64_t dsn) {
         uint8_t na = 0;
-        if (ACT) na = (ls >= 1 && a.model->max_act[ts] > 0) ? (uint8_t)a.model->max_act[ts] : (uint8_t)0;
+        if (ACT) na = (ls >= 1 && tp_lds.max_act[ts] > 0) ? (uint8_t)tp_lds.max_act[ts] : (uint8_t)0;
         const Cell nw = kActWord ? (Cell)(((uint32_t)ws & WordAct<Cell>::kKeep) | ((uint32_t)na << WordAct<Cell>::kShift))
                                  : ws;
         if (!DIRECT) lab[t] = nw;
@@ -421,6 +465,14 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
         Cell wt = 0, ws = 0;
         uint32_t u2 = 0, area_id = 0;
         const bool mine = tid < areas;
+        // the single type's J rows: uniform over the workgroup, read while
+        // the labels load
+        JRows jr{0, 0, 0, 0, 0, 0};
+        if (SINGLE) {
+            const int64_t *J = a.model->J;
+            const int tc = a.single_type, to = a.obstacle_type;
+            jr = JRows{J[tc * kMaxTypes + tc], J[tc * kMaxTypes], J[tc * kMaxTypes + to], J[tc], J[0], J[to]};
+        }
         if (mine) {
             draw(tid, 0, ttx, tty, ttz, ssx, ssy, ssz, u2, area_id);
             wt = lab[map.at(ttx, tty, ttz)];
@@ -433,12 +485,6 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
         uint32_t nontrivial = 0, accepted = 0;
         if (mine && lt != ls && lt >= 0 && ls >= 0) {
             nontrivial = 1;
-            JRows jr{0, 0, 0, 0, 0, 0};
-            if (SINGLE) {
-                const int64_t *J = a.model->J;
-                const int tc = a.single_type, to = a.obstacle_type;
-                jr = JRows{J[tc * kMaxTypes + tc], J[tc * kMaxTypes], J[tc * kMaxTypes + to], J[tc], J[0], J[to]};
-            }
             int64_t dso, dsn;
             int tt, ts;
             types(wt, lt, ws, ls, tt, ts);
@@ -737,8 +783,13 @@ tile_sweep_kernel_packed(SweepArgs a, uint32_t mcs, uint32_t alpha, int parity)
 
 // Many lattices advanced together: work[b] = (lattice, tile) of workgroup b
 // (lattice -1: padding); all lattices share the MCS counter at *mcs.
+#ifdef CPM_BATCH_WAVES
+#define CPM_BATCH_ATTR __attribute__((amdgpu_waves_per_eu(CPM_BATCH_WAVES)))
+#else
+#define CPM_BATCH_ATTR
+#endif
 template <typename Cell, int D, bool ACT, bool SINGLE, bool K1, int LAYOUT, bool EXT>
-__global__ void __launch_bounds__(kBlock) batch_sweep_kernel(const SweepArgs *args, const int2 *work,
+__global__ void __launch_bounds__(kBlock) CPM_BATCH_ATTR batch_sweep_kernel(const SweepArgs *args, const int2 *work,
                                                              const uint32_t *mcs, uint32_t alpha, int parity)
 {
     const int2 w = work[blockIdx.x];
