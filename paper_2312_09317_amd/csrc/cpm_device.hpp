@@ -94,20 +94,25 @@ __device__ __forceinline__ uint32_t act_at<char16_t>(const char16_t *lab, const 
 }
 
 // Cell type of a site from its stored word (`label` = label_of(word)).
-__device__ __forceinline__ int type_of_word(const SweepArgs &a, uint32_t word, int) { return (int)(word >> 24); }
-__device__ __forceinline__ int type_of_word(const SweepArgs &a, char32_t word, int)
+template <typename A>
+__device__ __forceinline__ int type_of_word(const A &a, uint32_t word, int) { return (int)(word >> 24); }
+template <typename A>
+__device__ __forceinline__ int type_of_word(const A &a, char32_t word, int)
 {
     return (int)(((uint32_t)word >> 20) & 15u);
 }
-__device__ __forceinline__ int type_of_word(const SweepArgs &a, int32_t, int label)
+template <typename A>
+__device__ __forceinline__ int type_of_word(const A &a, int32_t, int label)
 {
     return label < 0 ? a.obstacle_type : a.cell_type[label];
 }
-__device__ __forceinline__ int type_of_word(const SweepArgs &a, uint16_t, int label)
+template <typename A>
+__device__ __forceinline__ int type_of_word(const A &a, uint16_t, int label)
 {
     return label < 0 ? a.obstacle_type : a.cell_type[label];
 }
-__device__ __forceinline__ int type_of_word(const SweepArgs &a, char16_t, int label)
+template <typename A>
+__device__ __forceinline__ int type_of_word(const A &a, char16_t, int label)
 {
     return label < 0 ? a.obstacle_type : a.cell_type[label];
 }

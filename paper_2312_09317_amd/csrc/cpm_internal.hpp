@@ -103,20 +103,33 @@ struct TileGeometry {
     int32_t brick_y, brick_z, layers_per_xcd;
 };
 
+// Pointer types of the sweep arguments: plain ones (the host, and kernels
+// that take the struct by value); kernels that read the struct from device
+// memory (batches) use SweepArgsT with global-memory pointers (defined next
+// to them), so that the compiler reads through them with global, not flat,
+// loads.
+struct PlainPtrs {
+    template <typename T>
+    using ptr = T *;
+};
+
 // Everything a sweep kernel needs, passed by value.
-struct SweepArgs {
-    void *cells;           // lattice the sweep works on: the caller's int32 one or the 16-bit mirror (label + 1)
-    int32_t *lat;          // the caller's int32 lattice
-    const int32_t *cell_type;
-    uint8_t *act;
-    const int4 *pdir;      // persistence direction per label (x, y, z, unused), 2^-14; NULL when off
-    const int16_t *chem;   // chemotaxis field, ndim components per site, 2^-14; NULL when off
-    const DeviceModel *model;
-    int32_t *counters[2];  // ping-pong (V, S) pairs per label
-    int4 *dlist[2];        // per tile: accepted copies of an activation, by activation parity
-    int32_t *dcount[2];    // per tile: number of records in dlist[parity]
-    uint64_t *stats;       // per tile: attempts past the early rejection, accepted copies
-    int4 *own_spill;       // k > kOwnInRegs: per tile and area, k - kOwnInRegs own records; else NULL
+template <typename PP>
+struct SweepArgsT {
+    template <typename T>
+    using P = typename PP::template ptr<T>;
+    P<void> cells;            // lattice the sweep works on: the caller's int32 one or the 16-bit mirror (label + 1)
+    P<int32_t> lat;           // the caller's int32 lattice
+    P<const int32_t> cell_type;
+    P<uint8_t> act;
+    P<const int4> pdir;       // persistence direction per label (x, y, z, unused), 2^-14; NULL when off
+    P<const int16_t> chem;    // chemotaxis field, ndim components per site, 2^-14; NULL when off
+    P<const DeviceModel> model;
+    P<int32_t> counters[2];   // ping-pong (V, S) pairs per label
+    P<int4> dlist[2];         // per tile: accepted copies of an activation, by activation parity
+    P<int32_t> dcount[2];     // per tile: number of records in dlist[parity]
+    P<uint64_t> stats;        // per tile: attempts past the early rejection, accepted copies
+    P<int4> own_spill;        // k > kOwnInRegs: per tile and area, k - kOwnInRegs own records; else NULL
     int32_t L[3];
     int32_t na[3];         // thread areas per axis
     uint32_t n_areas;
@@ -131,6 +144,7 @@ struct SweepArgs {
     uint32_t lattice_id;
     TileGeometry tg;
 };
+using SweepArgs = SweepArgsT<PlainPtrs>;
 
 // A batched activation: all lattices of a batch in one launch.
 struct BatchLaunch {

@@ -60,6 +60,19 @@ constexpr int kQueue = 128;  // queued attempts per workgroup; the rest are eval
 // every coordinate global and wrapping.
 enum Layout { kBox = 0, kFullRow = 1, kDirect = 2 };
 
+// A pointer of the sweep arguments as a plain (generic) pointer; loads
+// through a global-memory one converted here stay global loads.
+template <typename T>
+__device__ __forceinline__ T *plain(T *p)
+{
+    return p;
+}
+template <typename T>
+__device__ __forceinline__ T *plain(__attribute__((address_space(1))) T *p)
+{
+    return (T *)p;
+}
+
 template <int LAYOUT>
 struct LdsMap {
     int pitch;  // sites per row
@@ -161,8 +174,8 @@ struct SharedTables {
 // (eq. 2).  cnt_t / cnt_s are the (V, S) counters of the two cells as the
 // attempt sees them.  Returns acceptance; dso / dsn are the surface deltas.
 // nbl(n) gives the label of the target's n-th Moore neighbour.
-template <typename Cell, int D, bool ACT, bool SINGLE, int LAYOUT, bool EXT, typename NB>
-__device__ __forceinline__ bool evaluate_nb(const SweepArgs &a, const ThrTables &tb, const JRows &jr,
+template <typename Cell, int D, bool ACT, bool SINGLE, int LAYOUT, bool EXT, typename NB, typename A>
+__device__ __forceinline__ bool evaluate_nb(const A &a, const ThrTables &tb, const JRows &jr,
                                             const SharedTables &st, const NB &nbl, Cell *lab, uint8_t *lact,
                                             const LdsMap<LAYOUT> &map, int tx_, int ty_, int tz_, int sx_, int sy_,
                                             int sz_, int src_gi, int lt, int ls, int tt, int ts, int2 cnt_t, int2 cnt_s,
@@ -170,7 +183,7 @@ __device__ __forceinline__ bool evaluate_nb(const SweepArgs &a, const ThrTables 
 {
     constexpr int NNB = D == 2 ? 8 : 26;
     constexpr bool kIn = WordAct<Cell>::kIn;
-    const DeviceModel *m = a.model;
+    const DeviceModel *m = plain(a.model);
     const TypeParams *tp = st.tp;
     // In place (global memory), the target's neighbourhood comes first, in
     // a block without branches, so that it is read in one round (several
@@ -257,7 +270,7 @@ __device__ __forceinline__ bool evaluate_nb(const SweepArgs &a, const ThrTables 
         // persistence: the copying cell ls extends from the source into the
         // target; copies along its direction are favoured
         const int o = (tx_ - sx_ + 1) + 3 * (ty_ - sy_ + 1) + 9 * (tz_ - sz_ + 1);
-        const int4 pd = a.pdir[ls];
+        const int4 pd = plain(a.pdir)[ls];
         const int64_t dot = (int64_t)m->unit[o][0] * pd.x + (int64_t)m->unit[o][1] * pd.y +
                             (int64_t)m->unit[o][2] * pd.z;
         q -= (m->lam_p[ts] * dot) >> 28;
@@ -267,10 +280,10 @@ __device__ __forceinline__ bool evaluate_nb(const SweepArgs &a, const ThrTables 
         const int o = (tx_ - sx_ + 1) + 3 * (ty_ - sy_ + 1) + 9 * (tz_ - sz_ + 1);
         int64_t dot;
         if (D == 2) {
-            const short2 c = reinterpret_cast<const short2 *>(a.chem)[src_gi];
+            const short2 c = reinterpret_cast<const short2 *>(plain(a.chem))[src_gi];
             dot = (int64_t)m->unit[o][0] * c.x + (int64_t)m->unit[o][1] * c.y;
         } else {
-            const int16_t *c = a.chem + 3 * (size_t)src_gi;
+            const int16_t *c = plain(a.chem) + 3 * (size_t)src_gi;
             dot = (int64_t)m->unit[o][0] * c[0] + (int64_t)m->unit[o][1] * c[1] + (int64_t)m->unit[o][2] * c[2];
         }
         q -= (m->lam_c[ts] * dot) >> 28;
@@ -281,8 +294,8 @@ __device__ __forceinline__ bool evaluate_nb(const SweepArgs &a, const ThrTables 
 }
 
 // evaluate_nb with the neighbour labels read through `map`.
-template <typename Cell, int D, bool ACT, bool SINGLE, int LAYOUT, bool EXT>
-__device__ __forceinline__ bool evaluate(const SweepArgs &a, const ThrTables &tb, const JRows &jr,
+template <typename Cell, int D, bool ACT, bool SINGLE, int LAYOUT, bool EXT, typename A>
+__device__ __forceinline__ bool evaluate(const A &a, const ThrTables &tb, const JRows &jr,
                                          const SharedTables &st, Cell *lab, uint8_t *lact,
                                          const LdsMap<LAYOUT> &map, int tx_, int ty_, int tz_, int sx_, int sy_,
                                          int sz_, int src_gi, int lt, int ls, int tt, int ts, int2 cnt_t, int2 cnt_s,
@@ -321,8 +334,8 @@ __device__ __forceinline__ int2 seen_counters(const int32_t *rd, int c, const in
 }
 
 // One workgroup's share of one activation: tile `tile` of the lattice `a`.
-template <typename Cell, int D, bool ACT, bool SINGLE, bool K1, int LAYOUT, bool EXT>
-__device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_t mcs, uint32_t alpha, int parity)
+template <typename Cell, int D, bool ACT, bool SINGLE, bool K1, int LAYOUT, bool EXT, typename A>
+__device__ __forceinline__ void sweep_tile(const A &a, int tile, uint32_t mcs, uint32_t alpha, int parity)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int list_n, queue_n;
@@ -357,15 +370,15 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
     const int o1 = DIRECT ? 0 : 2 * s * A1 + s * cy - R;
     const int o2 = D == 3 && !DIRECT ? 2 * s * A2 + s * cz - R : 0;
     const LdsMap<LAYOUT> map{DIRECT ? L0 : b0, DIRECT ? L1 : b1, L0, L1, L2};
-    Cell *cells = reinterpret_cast<Cell *>(a.cells);
+    Cell *cells = static_cast<Cell *>(plain(a.cells));
     Cell *lab = DIRECT ? cells : reinterpret_cast<Cell *>(smem);
-    uint8_t *lact = DIRECT ? a.act : smem + align16(tg.box_sites * (int)sizeof(Cell));
-    const int32_t *rd = a.counters[parity];
-    int32_t *wr = a.counters[parity ^ 1];
+    uint8_t *lact = DIRECT ? plain(a.act) : smem + align16(tg.box_sites * (int)sizeof(Cell));
+    const int32_t *rd = plain(a.counters[parity]);
+    int32_t *wr = plain(a.counters[parity ^ 1]);
     // delta lists: this activation's records go to the list of its parity;
     // the previous activation's (other parity) are re-added into wr
-    int4 *dl = a.dlist[parity] + (size_t)tile * a.dlist_cap;
-    const int4 *dl_prev = a.dlist[parity ^ 1] + (size_t)tile * a.dlist_cap;
+    int4 *dl = plain(a.dlist[parity]) + (size_t)tile * a.dlist_cap;
+    const int4 *dl_prev = plain(a.dlist[parity ^ 1]) + (size_t)tile * a.dlist_cap;
 
     if (tid == 0) {
         list_n = 0;
@@ -374,13 +387,23 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
         n_accepted = 0;
     }
     // model tables read per neighbour, copied to LDS (visible after the
-    // staging barrier)
-    if (!SINGLE)
-        for (int i = tid; i < a.n_types * kMaxTypes; i += kBlock) j_lds[i] = a.model->J[i];
-    if (ACT)
-        for (int i = tid; i < a.lg_entries; i += kBlock) lg_lds[i] = a.model->LG[i];
-    if (tid < (int)(sizeof(TypeParams) / sizeof(int4)))
-        reinterpret_cast<int4 *>(&tp_lds)[tid] = reinterpret_cast<const int4 *>(a.model->lam_v)[tid];
+    // staging barrier): at most one entry of each per thread, all loads
+    // issued before the first LDS store
+    static_assert(kMaxTypes * kMaxTypes <= kBlock && 256 <= kBlock, "one table entry per thread");
+    {
+        constexpr int kTpWords = (int)(sizeof(TypeParams) / sizeof(int4));
+        static_assert(kTpWords <= kBlock, "one 16-byte word of the type block per thread");
+        const DeviceModel *mdl = plain(a.model);
+        const bool j_mine = !SINGLE && tid < a.n_types * kMaxTypes;
+        const bool lg_mine = ACT && tid < a.lg_entries;
+        const bool tp_mine = tid < kTpWords;
+        const int64_t jv = j_mine ? mdl->J[tid] : 0;
+        const int64_t lgv = lg_mine ? mdl->LG[tid] : 0;
+        const int4 tpv = tp_mine ? reinterpret_cast<const int4 *>(mdl->lam_v)[tid] : make_int4(0, 0, 0, 0);
+        if (j_mine) j_lds[tid] = jv;
+        if (lg_mine) lg_lds[tid] = lgv;
+        if (tp_mine) reinterpret_cast<int4 *>(&tp_lds)[tid] = tpv;
+    }
     const SharedTables sht{j_lds, lg_lds, &tp_lds};
     // deltas of the previous activation go into the write buffer as well
     // k = 1 in place: every attempt is evaluated by the thread that draws it
@@ -393,7 +416,8 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
         for (int i = tid; i < prev_n; i += kBlock) add_deltas(wr, dl_prev[i]);
     }
     // threshold tables, read from the model (they stay in L2: every tile reads them)
-    const ThrTables tb{a.model->TM32, a.model->TL32, a.model->TI32, a.model->n_ti};
+    const DeviceModel *model = plain(a.model);
+    const ThrTables tb{model->TM32, model->TL32, model->TI32, model->n_ti};
 
     const int areas = n0 * n1 * n2;
     const uint32_t sd = D == 2 ? (uint32_t)(s * s) : (uint32_t)(s * s * s);
@@ -469,7 +493,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
         // the labels load
         JRows jr{0, 0, 0, 0, 0, 0};
         if (SINGLE) {
-            const int64_t *J = a.model->J;
+            const int64_t *J = model->J;
             const int tc = a.single_type, to = a.obstacle_type;
             jr = JRows{J[tc * kMaxTypes + tc], J[tc * kMaxTypes], J[tc * kMaxTypes + to], J[tc], J[0], J[to]};
         }
@@ -584,7 +608,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
             else copy_rows(uint32_t{}, src, dst, row_bytes);
         };
         copy_any(tg.row_chunk, cells, lab, L0 * (int)sizeof(Cell));
-        if (ACT && !WordAct<Cell>::kIn) copy_any(tg.act_chunk, a.act, lact, L0);
+        if (ACT && !WordAct<Cell>::kIn) copy_any(tg.act_chunk, plain(a.act), lact, L0);
     } else {
         // the box x fastest, site c of the box at LDS index c: consecutive
         // threads read consecutive sites of a row, eight loads (and eight
@@ -634,7 +658,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
     uint32_t my_accepted = 0;
     JRows jr{0, 0, 0, 0, 0, 0};
     if (SINGLE) {
-        const int64_t *J = a.model->J;
+        const int64_t *J = model->J;
         const int tc = a.single_type, to = a.obstacle_type;
         jr = JRows{J[tc * kMaxTypes + tc], J[tc * kMaxTypes], J[tc * kMaxTypes + to],
                    J[tc], J[0], J[to]};
@@ -692,7 +716,7 @@ __device__ __forceinline__ void sweep_tile(const SweepArgs &a, int tile, uint32_
             int4 own[kOwnInRegs];
             int n_own = 0;
             const size_t slot = (size_t)tile * (size_t)(tg.T[0] * tg.T[1] * tg.T[2]) + (size_t)tid;
-            int4 *spill = a.own_spill ? a.own_spill + slot * (size_t)(a.k - kOwnInRegs) : nullptr;
+            int4 *spill = a.own_spill ? plain(a.own_spill) + slot * (size_t)(a.k - kOwnInRegs) : nullptr;
             for (int j = 0; j < a.k; ++j) {
                 int ttx, tty, ttz, ssx, ssy, ssz;
                 uint32_t u2, area_id;
@@ -783,13 +807,20 @@ tile_sweep_kernel_packed(SweepArgs a, uint32_t mcs, uint32_t alpha, int parity)
 
 // Many lattices advanced together: work[b] = (lattice, tile) of workgroup b
 // (lattice -1: padding); all lattices share the MCS counter at *mcs.
-#ifdef CPM_BATCH_WAVES
-#define CPM_BATCH_ATTR __attribute__((amdgpu_waves_per_eu(CPM_BATCH_WAVES)))
-#else
-#define CPM_BATCH_ATTR
-#endif
+// The batch kernels read each lattice's arguments from device memory: seen
+// through global-memory pointer types, the pointers they hold are read
+// through with global loads (a pointer loaded from memory is otherwise a
+// flat one, whose loads also hold up the scalar loads' waits).
+struct GlobalPtrs {
+    template <typename T>
+    using ptr = __attribute__((address_space(1))) T *;
+};
+using SweepArgsG = SweepArgsT<GlobalPtrs>;
+static_assert(sizeof(SweepArgsG) == sizeof(SweepArgs) && offsetof(SweepArgsG, tg) == offsetof(SweepArgs, tg),
+              "the same bytes seen with other pointer types");
+
 template <typename Cell, int D, bool ACT, bool SINGLE, bool K1, int LAYOUT, bool EXT>
-__global__ void __launch_bounds__(kBlock) CPM_BATCH_ATTR batch_sweep_kernel(const SweepArgs *args, const int2 *work,
+__global__ void __launch_bounds__(kBlock) batch_sweep_kernel(const SweepArgsG *args, const int2 *work,
                                                              const uint32_t *mcs, uint32_t alpha, int parity)
 {
     const int2 w = work[blockIdx.x];
@@ -872,7 +903,7 @@ __device__ __forceinline__ void decay_all(const PersistentLaunch &p)
 // XCD count), and meet at a grid barrier after each activation and after
 // each MCS's Act decay.
 template <typename Cell, int D, bool ACT, bool SINGLE, bool EXT>
-__global__ void __launch_bounds__(kBlock) batch_persistent_kernel(const SweepArgs *args, const int2 *work,
+__global__ void __launch_bounds__(kBlock) batch_persistent_kernel(const SweepArgsG *args, const int2 *work,
                                                                   PersistentLaunch p)
 {
     uint32_t gen = 0;
@@ -907,7 +938,7 @@ hipError_t launch_persistent_k(const BatchLaunch &b, const PersistentLaunch &p, 
     int grid = std::min(per_cu * cus, b.grid);
     grid = grid / kXcds * kXcds;
     if (grid < kXcds) return hipErrorInvalidConfiguration;
-    const SweepArgs *args = b.args;
+    const SweepArgsG *args = reinterpret_cast<const SweepArgsG *>(b.args);
     const int2 *work = b.work;
     PersistentLaunch pl = p;
     void *kargs[] = {(void *)&args, (void *)&work, (void *)&pl};
@@ -980,13 +1011,13 @@ template <typename Cell, int D, bool ACT, bool SINGLE, bool EXT>
 hipError_t launch_batch_k(const BatchLaunch &b, uint32_t alpha, int parity, hipStream_t st)
 {
     if (b.k1 && b.layout == kDirect)
-        batch_sweep_kernel<Cell, D, ACT, SINGLE, true, kDirect, EXT><<<b.grid, kBlock, b.lds, st>>>(b.args, b.work, b.mcs, alpha, parity);
+        batch_sweep_kernel<Cell, D, ACT, SINGLE, true, kDirect, EXT><<<b.grid, kBlock, b.lds, st>>>(reinterpret_cast<const SweepArgsG *>(b.args), b.work, b.mcs, alpha, parity);
     else if (b.k1 && b.layout == kFullRow)
-        batch_sweep_kernel<Cell, D, ACT, SINGLE, true, kFullRow, EXT><<<b.grid, kBlock, b.lds, st>>>(b.args, b.work, b.mcs, alpha, parity);
+        batch_sweep_kernel<Cell, D, ACT, SINGLE, true, kFullRow, EXT><<<b.grid, kBlock, b.lds, st>>>(reinterpret_cast<const SweepArgsG *>(b.args), b.work, b.mcs, alpha, parity);
     else if (b.k1)
-        batch_sweep_kernel<Cell, D, ACT, SINGLE, true, kBox, EXT><<<b.grid, kBlock, b.lds, st>>>(b.args, b.work, b.mcs, alpha, parity);
+        batch_sweep_kernel<Cell, D, ACT, SINGLE, true, kBox, EXT><<<b.grid, kBlock, b.lds, st>>>(reinterpret_cast<const SweepArgsG *>(b.args), b.work, b.mcs, alpha, parity);
     else
-        batch_sweep_kernel<Cell, D, ACT, SINGLE, false, kBox, EXT><<<b.grid, kBlock, b.lds, st>>>(b.args, b.work, b.mcs, alpha, parity);
+        batch_sweep_kernel<Cell, D, ACT, SINGLE, false, kBox, EXT><<<b.grid, kBlock, b.lds, st>>>(reinterpret_cast<const SweepArgsG *>(b.args), b.work, b.mcs, alpha, parity);
     return hipGetLastError();
 }
 
