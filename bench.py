@@ -202,12 +202,14 @@ def main():
     ap.add_argument("--cpu-mcs", type=int, default=None,
                     help="MCS of the oracle sample (0 to skip; default: about 10-15 s of oracle work per "
                          "workload: 6 for the 256^3 sweep, 120 for sorting, 2 for the collective)")
-    ap.add_argument("--workload", choices=("sweep", "tissue", "sorting", "collective", "accuracy", "polarisation",
-                                           "batch", "emulator"),
+    ap.add_argument("--workload", choices=("sweep", "tissue", "sorting", "collective", "collective-order", "accuracy",
+                                           "polarisation", "batch", "emulator"),
                     default="sweep",
                     help="sweep: the 3D 256^3 benchmark (default); tissue: 3D 1024^3 with obstacles and the "
                          "Act term; sorting: 2D 2048^2 two-type cell sorting; collective: 3D 256^3 packed "
-                         "collective with the persistence term; accuracy: speed and accuracy of the parallel "
+                         "collective with the persistence term; collective-order: polar order of the 3D "
+                         "collective after --order-mcs MCS against cell density, k = 1 and k = s^d; "
+                         "accuracy: speed and accuracy of the parallel "
                          "scheme against the serial CPM (2D circular chemotaxis ensembles); polarisation: "
                          "directional autocorrelation of Act cells, serial CPM vs parallel scheme; batch: 512 uneven "
                          "2D lattices; emulator: "
@@ -226,6 +228,11 @@ def main():
                          "whose MCS time is mostly launch or barrier overhead)")
     ap.add_argument("--batch-mode", default=None, choices=("graph", "eager", "persistent"),
                     help="batch workload: how each sweep is launched (default: the tuner's choice, else graph)")
+    ap.add_argument("--order-densities", default="0.1,0.2,0.3,0.4,0.5,0.6,0.7,0.8,0.9",
+                    help="collective-order workload: cell densities")
+    ap.add_argument("--order-side", type=int, default=128, help="collective-order workload: lattice side")
+    ap.add_argument("--order-mcs", type=int, default=2000, help="collective-order workload: MCS per run")
+    ap.add_argument("--order-runs", type=int, default=3, help="collective-order workload: runs per density")
     ap.add_argument("--acc-runs", type=int, default=250, help="accuracy workload: runs per ensemble")
     ap.add_argument("--acc-mcs", type=int, default=200, help="accuracy workload: MCS per run")
     ap.add_argument("--emu-train", type=int, default=8192, help="emulator workload: training runs")
@@ -265,6 +272,8 @@ def main():
         return bench_sorting(args)
     if args.workload == "collective":
         return bench_collective(args)
+    if args.workload == "collective-order":
+        return bench_collective_order(args)
     if args.workload == "accuracy":
         return bench_accuracy(args)
     if args.workload == "polarisation":
@@ -597,6 +606,32 @@ def bench_accuracy(args):
         "roofline": None,
         "cpu_baseline": cpu_fields(cpu)}),
         flush=True)
+
+
+def bench_collective_order(args):
+    """Order index of the persistent 3D collective after --order-mcs MCS
+    against cell density (Fig. 5C): the parallel scheme at s = 2 with k = 1
+    (update statistics kept) and with k = 8 = s^d (each thread's attempts
+    back to back).  The line's value is the attempt rate over all runs."""
+    from paper_2312_09317_amd import collective
+    dens = [float(x) for x in args.order_densities.split(",")]
+    modes = []
+    for k in (1, 8):
+        modes.append(collective.order_vs_density(dens, L=args.order_side, n_mcs=args.order_mcs,
+                                                 runs=args.order_runs, s=2, k=k, log=log))
+    ms = sum(m["ms"] for m in modes)
+    att = sum(m["attempts"] for m in modes)
+    print(json.dumps({
+        "metric": "polar order index of a 3D persistent collective after N MCS, against cell density",
+        "value": att / (ms / 1e3), "unit": "attempts/s", "n_gpus": 1, "steps": args.order_mcs, "warmup": 0,
+        "ms_per_step": ms / (args.order_mcs * len(dens) * args.order_runs * len(modes)),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+        "config": {"workload": f"3d-{args.order_side}^3-collective-order", "mcs": args.order_mcs,
+                   "runs": args.order_runs,
+                   "modes": [{"s": m["s"], "k": m["k"],
+                              "rows": [{kk: r[kk] for kk in ("density", "cells", "order_mean", "order_sd")}
+                                       for r in m["rows"]]} for m in modes]},
+        "roofline": None, "cpu_baseline": None}), flush=True)
 
 
 def bench_polarisation(args):
