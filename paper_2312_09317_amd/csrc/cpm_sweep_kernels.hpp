@@ -340,10 +340,17 @@ __device__ __forceinline__ void sweep_tile(const A &a, int tile, uint32_t mcs, u
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int list_n, queue_n;
     __shared__ uint32_t n_nontrivial, n_accepted;
-    // compacted attempts: packed target / source coordinates and draw, and the
-    // counters (V, S) of both cells fetched while drawing
-    __shared__ int4 queue[K1 ? kQueue : 1];
-    __shared__ int4 queue_cnt[K1 ? kQueue : 1];
+    // compacted attempts.  Staged layouts: packed target / source
+    // coordinates and draw, and the counters (V, S) of both cells fetched
+    // while drawing.  In place: target coordinates and draw, source
+    // coordinates, and the two stored words.
+    constexpr bool EAGER_Q = LAYOUT == kDirect && K1;
+    // in place, 3D multi-type sweeps evaluate where they draw (below)
+    constexpr bool COMPACT = EAGER_Q && !(D == 3 && !SINGLE);
+    constexpr int kQ = COMPACT ? kBlock : (K1 && !EAGER_Q ? kQueue : 1);
+    __shared__ int4 queue[kQ];
+    __shared__ int4 queue_cnt[kQ];
+    __shared__ uint2 queue_w[COMPACT ? kBlock : 1];
     __shared__ int64_t j_lds[SINGLE ? 1 : kMaxTypes * kMaxTypes];
     __shared__ int64_t lg_lds[ACT ? 256 : 1];
     __shared__ __align__(16) TypeParams tp_lds;
@@ -410,7 +417,7 @@ __device__ __forceinline__ void sweep_tile(const A &a, int tile, uint32_t mcs, u
     // (no queue): measured faster than queueing the nontrivial attempts across
     // the workgroup (9.3 vs 9.8 us per 3D activation, 2.34 vs 2.92 ms per MCS
     // of 512 batched 2D lattices with the Act term)
-    constexpr bool EAGER = DIRECT && K1;
+    constexpr bool EAGER = EAGER_Q;
     if (!EAGER) {
         const int prev_n = a.dcount[parity ^ 1][tile];
         for (int i = tid; i < prev_n; i += kBlock) add_deltas(wr, dl_prev[i]);
@@ -479,9 +486,11 @@ __device__ __forceinline__ void sweep_tile(const A &a, int tile, uint32_t mcs, u
         // records (one per thread; a tile's accepted copies rarely fill more,
         // and loading all of its slots would read one 16-byte slot per area
         // in every activation) and the attempt's two labels; round 2,
-        // nontrivial attempts only: the target's neighbours and both cells'
-        // counters (and any later records of the previous list); round 3:
-        // the acceptance threshold
+        // nontrivial attempts only (packed into the first lanes, below): the
+        // target's neighbours and both cells' counters (and any later
+        // records of the previous list); round 3: the Act means' tables, or
+        // the source's neighbourhood of a motile source; last: the
+        // acceptance threshold
         constexpr int kEarlyRecords = 16;
         const int prev_n = a.dcount[parity ^ 1][tile];
         const int4 early_rec = tid < kEarlyRecords ? dl_prev[tid] : make_int4(0, 0, 0, 0);
@@ -506,9 +515,36 @@ __device__ __forceinline__ void sweep_tile(const A &a, int tile, uint32_t mcs, u
         }
         __syncthreads();  // LDS counters and tables initialised
         if (tid < prev_n) add_deltas(wr, tid < kEarlyRecords ? early_rec : dl_prev[tid]);
-        uint32_t nontrivial = 0, accepted = 0;
-        if (mine && lt != ls && lt >= 0 && ls >= 0) {
-            nontrivial = 1;
+        // The nontrivial attempts are packed into the first lanes of the
+        // workgroup: the energy change, which most attempts skip, then runs
+        // on as few waves as there are 64 of them, not on every wave that
+        // holds one (the sweep is bound by instruction issue more than by
+        // memory).  3D multi-type sweeps, bound by memory and with many
+        // nontrivial attempts, evaluate where they draw: the extra barrier
+        // measured slower there.
+        uint32_t accepted = 0;
+        int qn = 0;
+        if (COMPACT) {
+            if (mine && lt != ls && lt >= 0 && ls >= 0) {
+                const int slot = atomicAdd(&queue_n, 1);
+                queue[slot] = make_int4(ttx, tty, ttz, (int)u2);
+                queue_cnt[slot] = make_int4(ssx, ssy, ssz, 0);
+                queue_w[slot] = make_uint2((uint32_t)wt, (uint32_t)ws);
+            }
+            __syncthreads();
+            qn = queue_n;
+            if (tid < qn) {
+                const int4 e = queue[tid], c = queue_cnt[tid];
+                const uint2 ww = queue_w[tid];
+                ttx = e.x, tty = e.y, ttz = e.z, u2 = (uint32_t)e.w;
+                ssx = c.x, ssy = c.y, ssz = c.z;
+                wt = (Cell)ww.x, ws = (Cell)ww.y;
+                lt = label_of(wt), ls = label_of(ws);
+            }
+        } else if (mine && lt != ls && lt >= 0 && ls >= 0) {
+            atomicAdd(&n_nontrivial, 1u);
+        }
+        if (COMPACT ? tid < qn : (mine && lt != ls && lt >= 0 && ls >= 0)) {
             int64_t dso, dsn;
             int tt, ts;
             types(wt, lt, ws, ls, tt, ts);
@@ -521,12 +557,11 @@ __device__ __forceinline__ void sweep_tile(const A &a, int tile, uint32_t mcs, u
                 commit(gi, gi, lt, ls, ws, ts, dso, dsn);
             }
         }
-        if (nontrivial) atomicAdd(&n_nontrivial, 1u);
         if (accepted) atomicAdd(&n_accepted, 1u);
         __syncthreads();
         if (tid == 0) {
             a.dcount[parity][tile] = list_n;
-            a.stats[2 * tile] += n_nontrivial;
+            a.stats[2 * tile] += COMPACT ? (uint32_t)qn : n_nontrivial;
             a.stats[2 * tile + 1] += n_accepted;
         }
         return;
