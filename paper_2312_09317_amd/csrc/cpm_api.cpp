@@ -182,6 +182,17 @@ bool tile_geometry(const cpm_params *p, bool mirror, int force_layout, cpm::Tile
         }
         g.tiles_per_xcd = (g.n_tiles + cpm::kXcds - 1) / cpm::kXcds;
         g.grid = g.tiles_per_xcd * cpm::kXcds;
+        // floor(n / d) = umulhi(n, m) with m = floor((2^32 - 1) / d) + 1,
+        // exact for n d < 2^32 (the kernel's FastDiv)
+        auto magic = [](int d) { return d > 1 ? 0xFFFFFFFFu / (uint32_t)d + 1u : 0u; };
+        for (int d = 0; d < 2; ++d) {
+            g.div_nt[d] = magic(g.nt[d]);
+            g.div_T[d] = magic(T[d]);
+            g.div_last[d] = magic(na[d] - (g.nt[d] - 1) * T[d]);
+        }
+        g.div_s = magic(s);
+        // the tile index divisions are exact while n_tiles * nt < 2^32
+        if ((uint64_t)g.n_tiles * (uint64_t)std::max(g.nt[0], g.nt[1]) >= ((uint64_t)1 << 32)) return false;
         if (p->tile_order == 2) {
             // bricks need 3D tiles spanning whole rows and whole layers per XCD
             if (p->ndim != 3 || g.nt[0] != 1 || g.nt[2] % cpm::kXcds != 0) return false;

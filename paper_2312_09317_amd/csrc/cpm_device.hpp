@@ -12,8 +12,10 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
-        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+        // each product as one 32x32->64 multiply (both halves at once)
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x, p1 = (uint64_t)0xCD9E8D57u * c.z;
+        const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+        const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
         c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
@@ -124,6 +126,8 @@ __device__ __forceinline__ int type_of_word(const A &a, char16_t, int label)
 struct FastDiv {
     uint32_t d, m;
     __device__ __forceinline__ explicit FastDiv(uint32_t div) : d(div), m(div > 1 ? 0xFFFFFFFFu / div + 1u : 0u) {}
+    // with the multiplier computed beforehand (the host's tile geometry)
+    __device__ __forceinline__ FastDiv(uint32_t div, uint32_t mul) : d(div), m(mul) {}
     __device__ __forceinline__ uint32_t div(uint32_t n) const { return d > 1 ? __umulhi(n, m) : n; }
 };
 

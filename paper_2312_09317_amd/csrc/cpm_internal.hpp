@@ -101,6 +101,10 @@ struct TileGeometry {
     // bricks of brick_y x brick_z tiles, y fastest inside a brick and bricks
     // y fastest
     int32_t brick_y, brick_z, layers_per_xcd;
+    // multipliers of the divisions a workgroup makes (FastDiv): by nt[0] and
+    // nt[1], by T[0] and T[1], by the thread areas of the last tile along x
+    // and y (na - (nt - 1) T), and by the sub-area edge s; 0 for a divisor of 1
+    uint32_t div_nt[2], div_T[2], div_last[2], div_s;
 };
 
 // Pointer types of the sweep arguments: plain ones (the host, and kernels

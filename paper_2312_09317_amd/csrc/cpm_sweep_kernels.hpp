@@ -363,7 +363,11 @@ __device__ __forceinline__ void sweep_tile(const A &a, int tile, uint32_t mcs, u
     const int s = a.s;
     const uint32_t phi = alpha & ((1u << D) - 1);
     const int cx = (int)(phi & 1), cy = (int)((phi >> 1) & 1), cz = (int)((phi >> 2) & 1);
-    const int tx = tile % tg.nt[0], ty = (tile / tg.nt[0]) % tg.nt[1], tz = tile / (tg.nt[0] * tg.nt[1]);
+    // tile coordinates: tile = tx + nt0 (ty + nt1 tz), divisions by the
+    // geometry's multipliers (uniform over the workgroup)
+    const FastDiv by_nt0((uint32_t)tg.nt[0], tg.div_nt[0]), by_nt1((uint32_t)tg.nt[1], tg.div_nt[1]);
+    const int tq = (int)by_nt0.div((uint32_t)tile), tx = tile - tq * tg.nt[0];
+    const int tz = (int)by_nt1.div((uint32_t)tq), ty = tq - tz * tg.nt[1];
     const int A0 = tx * tg.T[0], A1 = ty * tg.T[1], A2 = tz * tg.T[2];
     const int n0 = min(tg.T[0], a.na[0] - A0), n1 = min(tg.T[1], a.na[1] - A1);
     const int n2 = D == 3 ? min(tg.T[2], a.na[2] - A2) : 1;
@@ -429,7 +433,9 @@ __device__ __forceinline__ void sweep_tile(const A &a, int tile, uint32_t mcs, u
     const int areas = n0 * n1 * n2;
     const uint32_t sd = D == 2 ? (uint32_t)(s * s) : (uint32_t)(s * s * s);
     // draw of one attempt: target and source in LDS coordinates
-    const FastDiv by_n0((uint32_t)n0), by_n1((uint32_t)n1), by_s((uint32_t)s);
+    const FastDiv by_n0((uint32_t)n0, tx == tg.nt[0] - 1 ? tg.div_last[0] : tg.div_T[0]);
+    const FastDiv by_n1((uint32_t)n1, ty == tg.nt[1] - 1 ? tg.div_last[1] : tg.div_T[1]);
+    const FastDiv by_s((uint32_t)s, tg.div_s);
     auto draw = [&](int area_local, int j, int &ttx, int &tty, int &ttz, int &ssx, int &ssy, int &ssz, uint32_t &u2,
                     uint32_t &area_id) {
         const int q0 = (int)by_n0.div((uint32_t)area_local), ax = area_local - q0 * n0;
