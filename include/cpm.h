@@ -141,6 +141,17 @@ typedef struct cpm_params {
      * lattices whose tiles span whole rows along x and divide evenly among
      * the XCDs; CPM_ENOTSUP otherwise). */
     int32_t tile_order;
+    /* How the persistence update gets each cell's centroid (Methods, eq. 6;
+     * composite variable tracking): 0 = recounted from the lattice at every
+     * update, each site taken as its periodic image nearest the cell's
+     * lowest-index site (the default; exact for cells of any shape); 1 =
+     * kept by the sweeps, each accepted copy moving its site between the two
+     * cells' integer sums as the image nearest each cell's reference point
+     * (its centroid rounded to a site at the last update).  The two agree,
+     * bit for bit in every direction, while every cell spans less than half
+     * the lattice along each axis; mode 1 saves the recount's two passes over
+     * the lattice per MCS.  Ignored without persistence. */
+    int32_t persistence_centroids;
 } cpm_params;
 
 typedef struct cpm_handle cpm_handle;

@@ -55,10 +55,13 @@ class cpm_params(ctypes.Structure):
         ("lambda_chemotaxis", ctypes.POINTER(ctypes.c_double)),
         ("d_chemotaxis_field", ctypes.c_void_p),
         ("tile_order", ctypes.c_int32),
+        ("persistence_centroids", ctypes.c_int32),
     ]
 
 LAYOUTS = {"auto": 0, "box": 1, "full_rows": 2, "in_place": 3}
 TILE_ORDERS = {"auto": 0, "linear": 1, "bricks": 2}
+# how the persistence update gets the cells' centroids (cpm_params.persistence_centroids)
+CENTROID_MODES = {"recount": 0, "incremental": 1}
 
 
 EXPORTS = ("cpm_validate", "cpm_workspace_bytes", "cpm_tile_shape", "cpm_init", "cpm_init_static", "cpm_sweep", "cpm_cell_stats", "cpm_contacts",
@@ -143,7 +146,8 @@ class Params:
                  temperature: float = 20.0, seed: int = 1, lattice_id: int = 0, sub: int = 2,
                  attempts: int = 1, obstacle_type: int = -1, layout="auto", tile=(0, 0, 0),
                  lambda_persistence=None, persistence_mu=None, persistence_dt: int = 1,
-                 lambda_chemotaxis=None, chemotaxis_field=None, tile_order="auto"):
+                 lambda_chemotaxis=None, chemotaxis_field=None, tile_order="auto",
+                 persistence_centroids="recount"):
         n = len(lambda_volume)
         self._J = np.ascontiguousarray(np.asarray(J, dtype=np.float64).reshape(n, n))
         self._lv = np.ascontiguousarray(lambda_volume, dtype=np.float64)
@@ -185,6 +189,8 @@ class Params:
         c.lambda_chemotaxis = self._lc.ctypes.data_as(dp) if self._lc is not None else None
         c.d_chemotaxis_field = chemotaxis_field.data_ptr() if hasattr(chemotaxis_field, "data_ptr") else None
         c.tile_order = TILE_ORDERS[tile_order] if isinstance(tile_order, str) else int(tile_order)
+        c.persistence_centroids = (CENTROID_MODES[persistence_centroids] if isinstance(persistence_centroids, str)
+                                   else int(persistence_centroids))
         self.c = c
         self._kw = dict(ndim=ndim, dims=dims, J=J, lambda_volume=lambda_volume, volume_target=volume_target,
                         lambda_surface=lambda_surface, surface_target=surface_target, lambda_act=lambda_act,
@@ -192,7 +198,8 @@ class Params:
                         attempts=attempts, obstacle_type=obstacle_type, layout=layout, tile=tile,
                         lambda_persistence=lambda_persistence, persistence_mu=persistence_mu,
                         persistence_dt=persistence_dt, lambda_chemotaxis=lambda_chemotaxis,
-                        chemotaxis_field=chemotaxis_field, tile_order=tile_order)
+                        chemotaxis_field=chemotaxis_field, tile_order=tile_order,
+                        persistence_centroids=persistence_centroids)
 
     def replace(self, **over) -> "Params":
         """A copy with some fields changed (e.g. layout, tile)."""

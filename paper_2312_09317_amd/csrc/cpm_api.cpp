@@ -31,10 +31,13 @@ struct cpm_handle {
     int32_t *ref = nullptr;          // centroid reference sites, n_cells + 1
     int32_t *check = nullptr;        // invariant checks: flag word, then recounted V and S
     bool obstacles = false;          // the model has an obstacle type (label -1 allowed)
-    // persistence (NULL pdir = off): directions, centroid history, centroid sums
+    // persistence (NULL pdir = off): directions, centroid history, centroid
+    // sums (kept by the sweeps) and the cells' reference points
     int4 *pdir = nullptr;
     int64_t *hist = nullptr;
     int64_t *csum = nullptr;
+    int4 *cpos = nullptr;
+    bool incremental = false;        // centroid sums kept by the sweeps (else recounted per update)
     int32_t persist_slots = 0;
     int64_t persist_t = 0;           // direction updates done
     uint64_t mcs = 0;                // next MCS index
@@ -117,7 +120,7 @@ int64_t to_fixed(double x) { return (int64_t)std::llround(x * 65536.0); }
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t model, counters0, counters1, dlist, dcount, stats, own, ref, check, mirror, pdir, hist, csum, total;
+    size_t model, counters0, counters1, dlist, dcount, stats, own, ref, check, mirror, pdir, hist, csum, cpos, total;
     cpm::TileGeometry tg;
     bool mirror_on;
     int32_t dlist_cap;
@@ -339,6 +342,7 @@ Layout layout_of(const cpm_params *p, int32_t n_cells, int mirror = -1, int forc
     l.pdir = take(pers ? sizeof(int4) * labels : 0);
     l.hist = take(pers ? sizeof(int64_t) * 3 * labels * (size_t)(p->persistence_dt + 1) : 0);
     l.csum = take(pers ? sizeof(int64_t) * (size_t)p->ndim * labels : 0);
+    l.cpos = take(pers ? sizeof(int4) * labels : 0);
     l.total = off;
     return l;
 }
@@ -438,6 +442,8 @@ int validate(const cpm_params *p, int32_t n_cells)
     if (p->lambda_persistence) {
         if (!p->persistence_mu) return fail(CPM_EINVAL, "persistence_mu NULL with persistence enabled");
         if (p->persistence_dt < 1 || p->persistence_dt > 4096) return fail(CPM_EINVAL, "persistence_dt must be in 1..4096");
+        if (p->persistence_centroids != 0 && p->persistence_centroids != 1)
+            return fail(CPM_EINVAL, "persistence_centroids must be 0 (recount) or 1 (incremental)");
         for (int d = 0; d < p->ndim; ++d)
             if (p->dims[d] < 4 || p->dims[d] > 32768)
                 return fail(CPM_EINVAL, "persistence needs every dim in 4..32768");
@@ -648,15 +654,21 @@ hipError_t count_bad_labels(const int32_t *lat, size_t n_sites, int32_t n_cells,
     return e;
 }
 
-// Persistence directions after update t (t = 0: initialisation) from the
-// current lattice: centroid sums, then one thread per cell.
+// Persistence directions after update t, one thread per cell, from the
+// centroid sums: recounted from the lattice (sites unwrapped around each
+// cell's lowest-index site) at every update, or, with incremental
+// centroids, only at t = 0 (initialisation), the sweeps keeping them after
+// that (each accepted copy moves its site between the two cells' sums).
 hipError_t persist_step(cpm_handle *h, int64_t t, int words, hipStream_t st)
 {
-    hipError_t e = cpm::launch_centroids(h->args, h->ndim, h->n_cells, h->ref, h->csum, st, words);
-    if (e != hipSuccess) return e;
+    if (t == 0 || !h->incremental) {
+        const hipError_t e = cpm::launch_centroids(h->args, h->ndim, h->n_cells, h->ref, h->csum, st, words);
+        if (e != hipSuccess) return e;
+    }
     cpm::PersistArgs p{};
     p.pdir = h->pdir;
     p.hist = h->hist;
+    p.cpos = h->cpos;
     p.csum = h->csum;
     p.pairs = h->args.counters[h->activation & 1];
     p.cell_type = h->args.cell_type;
@@ -781,8 +793,14 @@ int init_impl(const cpm_params *params, int32_t *d_lattice, const int32_t *d_cel
         h->pdir = reinterpret_cast<int4 *>(ws + lay.pdir);
         h->hist = reinterpret_cast<int64_t *>(ws + lay.hist);
         h->csum = reinterpret_cast<int64_t *>(ws + lay.csum);
+        h->cpos = reinterpret_cast<int4 *>(ws + lay.cpos);
         h->persist_slots = params->persistence_dt + 1;
+        h->incremental = params->persistence_centroids == 1;
         h->args.pdir = h->pdir;
+        if (h->incremental) {
+            h->args.csum = h->csum;
+            h->args.cpos = h->cpos;
+        }
     }
     if ((e = start_lattice(h->args, lay, ws, h->host_model.get(), params->ndim, n_cells, st)) != hipSuccess)
         return device_fail(e, "init");

@@ -134,6 +134,11 @@ struct SweepArgsT {
     P<int32_t> dcount[2];     // per tile: number of records in dlist[parity]
     P<uint64_t> stats;        // per tile: attempts past the early rejection, accepted copies
     P<int4> own_spill;        // k > kOwnInRegs: per tile and area, k - kOwnInRegs own records; else NULL
+    // persistence: per label, the centroid sums (ndim int64) an accepted
+    // copy updates, and the reference point (x, y, z, unused) its site is
+    // unwrapped against; NULL when off
+    P<int64_t> csum;
+    P<const int4> cpos;
     int32_t L[3];
     int32_t na[3];         // thread areas per axis
     uint32_t n_areas;
@@ -208,6 +213,7 @@ hipError_t launch_fill_i32(int32_t *p, int32_t value, size_t n, hipStream_t stre
 struct PersistArgs {
     int4 *pdir;
     int64_t *hist;         // per label: slots x 3 centroids, 2^-16
+    int4 *cpos;            // per label: the centroid rounded to a site, the sweeps' reference point
     const int64_t *csum;
     const int32_t *pairs;
     const int32_t *cell_type;

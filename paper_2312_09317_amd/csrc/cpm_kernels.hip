@@ -322,6 +322,13 @@ __global__ void persist_kernel(PersistArgs p, int64_t t)
     for (int d = 0; d < p.ndim; ++d)
         if (v > 0) X[d] = div_floor(p.csum[(int64_t)c * p.ndim + d] * 65536, v);
     int64_t *h = p.hist + (int64_t)c * p.slots * 3;
+    // the sweeps unwrap an accepted copy's site to the image nearest this
+    // point (the centroid rounded to a site), in the frame of the sums
+    if (v > 0) {
+        int r[3] = {0, 0, 0};
+        for (int d = 0; d < p.ndim; ++d) r[d] = (int)div_floor(X[d] + 32768, 65536);
+        p.cpos[c] = make_int4(r[0], r[1], r[2], 0);
+    }
     if (t == 0) {
         for (int k = 0; k < p.slots; ++k)
             for (int d = 0; d < 3; ++d) h[3 * k + d] = X[d];

@@ -333,6 +333,50 @@ __device__ __forceinline__ int2 seen_counters(const int32_t *rd, int c, const in
     return v;
 }
 
+// Composite variable tracking (Methods): an accepted copy moves its target
+// site (global index gi) from cell lt's centroid sums to cell ls's.  The
+// site enters each sum as its periodic image nearest that cell's reference
+// point (the centroid rounded to a site at the last direction update), so
+// the sums stay those of one unwrapped copy of the cell while it is smaller
+// than half the lattice.  Integer atomics: the result does not depend on
+// the order of the copies.
+// The site at (gx, gy, gz); ref_s / ref_t are the reference points of ls
+// and lt (read beforehand).
+template <int D, typename A>
+__device__ __forceinline__ void move_centroids_at(const A &a, int gx, int gy, int gz, int lt, int ls, int4 ref_t,
+                                                  int4 ref_s)
+{
+    const int L[3] = {a.L[0], a.L[1], a.L[2]};
+    const int g[3] = {gx, gy, gz};
+    unsigned long long *cs = reinterpret_cast<unsigned long long *>(plain(a.csum));
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+        const int c = side == 0 ? ls : lt;
+        if (c < 1) continue;
+        const int4 r4 = side == 0 ? ref_s : ref_t;
+        const int r[3] = {r4.x, r4.y, r4.z};
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            int u = (g[d] - r[d]) % L[d];
+            if (u < 0) u += L[d];
+            if (u >= L[d] - L[d] / 2) u -= L[d];  // into [-L/2, L/2)
+            const int64_t x = (int64_t)r[d] + u;
+            atomicAdd(cs + (size_t)c * D + d, (unsigned long long)(side == 0 ? x : -x));
+        }
+    }
+}
+
+// The same from the site's global index, reading the reference points here.
+template <int D, typename A>
+__device__ __forceinline__ void move_centroids(const A &a, int gi, int lt, int ls)
+{
+    const int L0 = a.L[0], L1 = a.L[1];
+    const int4 *cp = plain(a.cpos);
+    const int4 zero = make_int4(0, 0, 0, 0);
+    move_centroids_at<D>(a, gi % L0, (gi / L0) % L1, D == 3 ? gi / (L0 * L1) : 0, lt, ls, lt > 0 ? cp[lt] : zero,
+                         ls > 0 ? cp[ls] : zero);
+}
+
 // One workgroup's share of one activation: tile `tile` of the lattice `a`.
 template <typename Cell, int D, bool ACT, bool SINGLE, bool K1, int LAYOUT, bool EXT, typename A>
 __device__ __forceinline__ void sweep_tile(const A &a, int tile, uint32_t mcs, uint32_t alpha, int parity)
@@ -477,6 +521,7 @@ __device__ __forceinline__ void sweep_tile(const A &a, int tile, uint32_t mcs, u
                                  : ws;
         if (!DIRECT) lab[t] = nw;
         cells[gi] = nw;
+        if (EXT && !DIRECT && a.csum) move_centroids<D>(a, gi, lt, ls);
         if (ACT && !kActWord) {
             if (!DIRECT) lact[t] = na;
             a.act[gi] = na;
@@ -554,6 +599,14 @@ __device__ __forceinline__ void sweep_tile(const A &a, int tile, uint32_t mcs, u
             int64_t dso, dsn;
             int tt, ts;
             types(wt, lt, ws, ls, tt, ts);
+            // incremental centroids: both cells' reference points, read with
+            // the counters
+            int4 ref_t = make_int4(0, 0, 0, 0), ref_s = ref_t;
+            if (EXT && a.csum) {
+                const int4 *cp = plain(a.cpos);
+                if (lt > 0) ref_t = cp[lt];
+                if (ls > 0) ref_s = cp[ls];
+            }
             if (evaluate<Cell, D, ACT, SINGLE, LAYOUT, EXT>(a, tb, jr, sht, lab, lact, map, ttx, tty, ttz, ssx, ssy, ssz,
                                                        map.at(ssx, ssy, ssz), lt, ls, tt, ts,
                                                        seen_counters(rd, lt, nullptr, 0),
@@ -561,6 +614,7 @@ __device__ __forceinline__ void sweep_tile(const A &a, int tile, uint32_t mcs, u
                 accepted = 1;
                 const int gi = map.at(ttx, tty, ttz);
                 commit(gi, gi, lt, ls, ws, ts, dso, dsn);
+                if (EXT && a.csum) move_centroids_at<D>(a, ttx, tty, ttz, lt, ls, ref_t, ref_s);
             }
         }
         if (accepted) atomicAdd(&n_accepted, 1u);

@@ -104,19 +104,21 @@ def test_dying_cells_and_wide_labels(torch_cuda, dims, n_cells):
     assert dead.size > 0 and np.all(st.P.reshape(-1, 3)[1:][dead] == 0)
 
 
-def test_collective_crop(torch_cuda):
+@pytest.mark.parametrize("centroids", ["recount", "incremental"])
+def test_collective_crop(torch_cuda, centroids):
     # the 3D collective's recipe at 48^3 (density 0.5, dt 15, mu 0.95)
     w = inputs.collective_3d(L=48, n_mcs=20)
-    st, sim = run_pers(torch_cuda, w, 20, chunks=[5, 15])
+    st, sim = run_pers(torch_cuda, w, 20, chunks=[5, 15], persistence_centroids=centroids)
     assert_same(st, sim, torch_cuda)
     assert_dirs(st, sim, torch_cuda)
 
 
-def test_collective_full_size(torch_cuda):
+@pytest.mark.parametrize("centroids", ["recount", "incremental"])
+def test_collective_full_size(torch_cuda, centroids):
     # 256^3, 54,872 cells (16-bit labels) in the benchmark's launch
     # configuration: every site, counter and direction after 3 MCS
     w = inputs.collective_3d(n_mcs=3)
-    st, sim = run_pers(torch_cuda, w, 3)
+    st, sim = run_pers(torch_cuda, w, 3, persistence_centroids=centroids)
     assert_same(st, sim, torch_cuda)
     assert_dirs(st, sim, torch_cuda)
 
@@ -126,3 +128,46 @@ def test_directions_need_persistence(torch_cuda):
     sim = cpm.Simulation(cpm.Params.from_workload(plain), plain.lattice, plain.cell_type)
     with pytest.raises(cpm.CpmError):
         sim.persistence()
+
+
+def _boxes(dims, corners, edge):
+    # cells as boxes of `edge` sites per axis at the given corners, wrapped
+    lat = np.zeros(dims[::-1], dtype=np.int32)
+    for c, corner in enumerate(corners, start=1):
+        idx = [(np.arange(edge) + corner[a]) % dims[a] for a in range(len(corner))]
+        if len(corner) == 2:
+            lat[0][np.ix_(idx[1], idx[0])] = c
+        else:
+            lat[np.ix_(idx[2], idx[1], idx[0])] = c
+    return lat
+
+
+@pytest.mark.parametrize("ndim,layout,k", [(2, "in_place", 1), (2, "box", 4), (2, "full_rows", 1),
+                                           (3, "in_place", 1), (3, "box", 8)])
+@pytest.mark.parametrize("centroids", ["recount", "incremental"])
+def test_cells_crossing_the_boundary(torch_cuda, ndim, layout, k, centroids):
+    # persistent cells on a small periodic lattice, one of them straddling
+    # the edges from the start, run long enough to move across them.  With
+    # incremental centroids the sums the sweeps keep (each accepted copy
+    # moves its site between two cells' sums, unwrapped against each cell's
+    # reference point, in every layout's commit) must give the oracle's
+    # directions, which come from a recount every MCS: the cells stay
+    # smaller than half the lattice
+    if ndim == 2:
+        dims, edge, vt, s_t = (40, 40, 1), 6, 36, 30
+        lat = _boxes(dims, [(37, 37), (5, 10), (20, 3), (12, 28), (28, 18)], edge)
+    else:
+        dims, edge, vt, s_t = (16, 16, 16), 4, 64, 120
+        lat = _boxes(dims, [(14, 14, 14), (4, 4, 4), (9, 2, 8)], edge)
+    n = int(lat.max())
+    assert np.any(lat[..., 0] == 1) and np.any(lat[..., -1] == 1)  # cell 1 wraps along x
+    J, lv, vtarget, ls, stg = inputs._two_type(10.0, 4.0, 25.0, vt, 0.5, s_t)
+    w = inputs.Workload(f"crossing-{ndim}d", ndim, dims, lat, np.array([0] + [1] * n, dtype=np.int32),
+                        J, lv, vtarget, ls, stg, T=20.0, n_mcs=0, seed=31, k=k)
+    w = _with_persistence(w, lam=(0.0, 150.0), mu=(0.0, 0.9), dt=5)
+    n_mcs = 300 if ndim == 2 else 120
+    st, sim = run_pers(torch_cuda, w, n_mcs, chunks=[n_mcs // 3, n_mcs - n_mcs // 3], layout=layout,
+                       persistence_centroids=centroids)
+    assert_same(st, sim, torch_cuda)
+    assert_dirs(st, sim, torch_cuda)
+    assert np.count_nonzero(st.P.reshape(-1, 3)[1:]) > 0
