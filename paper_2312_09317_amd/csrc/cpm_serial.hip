@@ -34,6 +34,23 @@ __device__ __forceinline__ int half_or(int v)
     return v;
 }
 
+// The Metropolis decision of metropolis32, reading only the table entries
+// it needs, after the branches on q: attempts here run one at a time and
+// most decisions need no table, so an unconditional round of loads per
+// attempt would add up.
+__device__ __forceinline__ bool metropolis32_lazy(const ThrTables &tb, int64_t q, uint32_t u)
+{
+    if (q <= 0) return true;
+    const uint64_t h = (uint64_t)q >> 16;
+    if (h >= (uint64_t)tb.n_ti) return false;
+    const uint64_t two32 = (uint64_t)1 << 32;
+    const uint64_t ti = h == 0 ? two32 : (uint64_t)tb.ti[h];
+    if ((q & 0xFFFF) == 0) return (uint64_t)u < ti;
+    const int mm = (int)((q >> 8) & 255), ll = (int)(q & 255);
+    const uint64_t tm = mm ? (uint64_t)tb.tm[mm] : two32, tl = ll ? (uint64_t)tb.tl[ll] : two32;
+    return (uint64_t)u < __umul64hi(ti, tm * tl);  // tm * tl < 2^64 since (mm, ll) != (0, 0)
+}
+
 template <int D>
 __device__ __forceinline__ int site_at(const int *L, int x, int y, int z)
 {
@@ -131,7 +148,7 @@ __global__ void __launch_bounds__(64) serial_mcs_kernel(const SweepArgs *args, u
             q += (rt * gt - rs * gs) >> 16;
         }
         if (a.chem && ls >= 1) q -= (m->lam_c[ts] * chem_dot) >> 28;
-        if (!metropolis32(tb, q, u.z)) continue;
+        if (!metropolis32_lazy(tb, q, u.z)) continue;
         ++n_accepted;
         if (lane == 0) {
             cells[t] = stored_label<Cell>(ls);
