@@ -102,6 +102,14 @@ def test_persistence_workspace_and_batches():
     assert e.value.code == cpm.CPM_ENOTSUP
     wc = inputs.collective_3d(L=32, n_mcs=1)
     assert cpm.cpm_validate(cpm.Params.from_workload(wc), wc.n_cells) == cpm.CPM_OK
+    # incremental centroid sums: also a reference point (int4) per label
+    r, _ = _params(lambda_persistence=[0, 40.0], persistence_mu=[0, 0.95], persistence_dt=15,
+                   persistence_centroids="incremental")
+    assert cpm.cpm_validate(r, w.n_cells) == cpm.CPM_OK
+    assert cpm.cpm_workspace_bytes(r, w.n_cells) - cpm.cpm_workspace_bytes(p, w.n_cells) >= extra
+    bad, _ = _params(lambda_persistence=[0, 40.0], persistence_mu=[0, 0.95], persistence_dt=15,
+                     persistence_centroids=2)
+    assert cpm.cpm_validate(bad, w.n_cells) == cpm.CPM_EINVAL
 
 
 class _FakeDevicePtr:
