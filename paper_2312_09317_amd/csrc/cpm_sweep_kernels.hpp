@@ -383,7 +383,7 @@ __device__ __forceinline__ void sweep_tile(const A &a, int tile, uint32_t mcs, u
 {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int list_n, queue_n;
-    __shared__ uint32_t n_nontrivial, n_accepted;
+    __shared__ uint32_t n_nontrivial, n_accepted, waves_done;
     // compacted attempts.  Staged layouts: packed target / source
     // coordinates and draw, and the counters (V, S) of both cells fetched
     // while drawing.  In place: target coordinates and draw, source
@@ -440,6 +440,7 @@ __device__ __forceinline__ void sweep_tile(const A &a, int tile, uint32_t mcs, u
         queue_n = 0;
         n_nontrivial = 0;
         n_accepted = 0;
+        waves_done = 0;
     }
     // model tables read per neighbour, copied to LDS (visible after the
     // staging barrier): at most one entry of each per thread, all loads
@@ -618,11 +619,19 @@ __device__ __forceinline__ void sweep_tile(const A &a, int tile, uint32_t mcs, u
             }
         }
         if (accepted) atomicAdd(&n_accepted, 1u);
-        __syncthreads();
-        if (tid == 0) {
-            a.dcount[parity][tile] = list_n;
-            a.stats[2 * tile] += COMPACT ? (uint32_t)qn : n_nontrivial;
-            a.stats[2 * tile + 1] += n_accepted;
+        // The wave that finishes last writes the tile's list length and
+        // statistics, so that no wave waits at a barrier for the others:
+        // waves without nontrivial attempts leave at once and free their
+        // slots for the next workgroups.  Each wave's LDS updates complete
+        // before it counts itself done.
+        if ((tid & 63) == 0) {
+            __threadfence_block();
+            if (atomicAdd(&waves_done, 1u) == kBlock / 64 - 1) {
+                __threadfence_block();
+                a.dcount[parity][tile] = list_n;
+                a.stats[2 * tile] += COMPACT ? (uint32_t)qn : n_nontrivial;
+                a.stats[2 * tile + 1] += n_accepted;
+            }
         }
         return;
     }
