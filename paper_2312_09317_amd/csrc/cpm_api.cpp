@@ -210,9 +210,13 @@ bool tile_geometry(const cpm_params *p, bool mirror, int force_layout, cpm::Tile
         return true;
     };
     const bool k1 = p->attempts == 1;
-    if (force_layout < 0) force_layout = k1 && kDirectForK1 ? 2 : -1;
+    // in place needs every side below 2^16 (queued attempts hold their
+    // coordinates in 16 bits); larger lattices take a staged layout
+    bool direct_ok = k1;
+    for (int d = 0; d < p->ndim; ++d) direct_ok = direct_ok && p->dims[d] <= 65535;
+    if (force_layout < 0) force_layout = direct_ok && kDirectForK1 ? 2 : -1;
     if (force_layout == 2) {
-        if (!k1) return false;
+        if (!direct_ok) return false;
         // in place: tiles of up to kBlock areas, whole rows of areas first;
         // in 3D the rest split evenly between y and z (a squarer cross
         // section shares more of its neighbours' rows)

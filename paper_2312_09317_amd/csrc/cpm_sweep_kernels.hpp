@@ -386,17 +386,22 @@ __device__ __forceinline__ void sweep_tile(const A &a, int tile, uint32_t mcs, u
     __shared__ uint32_t n_nontrivial, n_accepted, waves_done;
     // compacted attempts.  Staged layouts: packed target / source
     // coordinates and draw, and the counters (V, S) of both cells fetched
-    // while drawing.  In place: target coordinates and draw, source
-    // coordinates, and the two stored words.
+    // while drawing.  In place, 16 bytes per attempt (the LDS a workgroup
+    // holds bounds how many fit on a CU): target x | y << 16, z | the
+    // source's Moore offset << 16, the draw, and the target's stored word
+    // (16-bit words: both words; wider ones: the source's in queue_ws).
     constexpr bool EAGER_Q = LAYOUT == kDirect && K1;
     // in place, 3D multi-type sweeps evaluate where they draw (below)
     constexpr bool COMPACT = EAGER_Q && !(D == 3 && !SINGLE);
+    constexpr bool kWideCell = sizeof(Cell) > 2;
     constexpr int kQ = COMPACT ? kBlock : (K1 && !EAGER_Q ? kQueue : 1);
     __shared__ int4 queue[kQ];
-    __shared__ int4 queue_cnt[kQ];
-    __shared__ uint2 queue_w[COMPACT ? kBlock : 1];
+    __shared__ int4 queue_cnt[COMPACT ? 1 : kQ];
+    __shared__ uint32_t queue_ws[COMPACT && kWideCell ? kBlock : 1];
     __shared__ int64_t j_lds[SINGLE ? 1 : kMaxTypes * kMaxTypes];
-    __shared__ int64_t lg_lds[ACT ? 256 : 1];
+    // the Act log table: 16-bit label-activity words index its first 32 entries
+    constexpr int kLgLds = std::is_same<Cell, char16_t>::value ? kMaxAct16Activity + 1 : 256;
+    __shared__ int64_t lg_lds[ACT ? kLgLds : 1];
     __shared__ __align__(16) TypeParams tp_lds;
     constexpr int R = ACT ? 2 : 1;           // read radius: the Act term reads neighbours of the source
     constexpr int NNB = D == 2 ? 8 : 26;
@@ -451,7 +456,7 @@ __device__ __forceinline__ void sweep_tile(const A &a, int tile, uint32_t mcs, u
         static_assert(kTpWords <= kBlock, "one 16-byte word of the type block per thread");
         const DeviceModel *mdl = plain(a.model);
         const bool j_mine = !SINGLE && tid < a.n_types * kMaxTypes;
-        const bool lg_mine = ACT && tid < a.lg_entries;
+        const bool lg_mine = ACT && tid < min(a.lg_entries, kLgLds);
         const bool tp_mine = tid < kTpWords;
         const int64_t jv = j_mine ? mdl->J[tid] : 0;
         const int64_t lgv = lg_mine ? mdl->LG[tid] : 0;
@@ -579,18 +584,23 @@ __device__ __forceinline__ void sweep_tile(const A &a, int tile, uint32_t mcs, u
         if (COMPACT) {
             if (mine && lt != ls && lt >= 0 && ls >= 0) {
                 const int slot = atomicAdd(&queue_n, 1);
-                queue[slot] = make_int4(ttx, tty, ttz, (int)u2);
-                queue_cnt[slot] = make_int4(ssx, ssy, ssz, 0);
-                queue_w[slot] = make_uint2((uint32_t)wt, (uint32_t)ws);
+                const uint32_t off = (uint32_t)((ssx - ttx + 1) + 3 * (ssy - tty + 1) + 9 * (ssz - ttz + 1));
+                const uint32_t words = kWideCell ? (uint32_t)wt : ((uint32_t)wt | ((uint32_t)ws << 16));
+                queue[slot] = make_int4((int)((uint32_t)ttx | ((uint32_t)tty << 16)),
+                                        (int)((uint32_t)ttz | (off << 16)), (int)u2, (int)words);
+                if (kWideCell) queue_ws[slot] = (uint32_t)ws;
             }
             __syncthreads();
             qn = queue_n;
             if (tid < qn) {
-                const int4 e = queue[tid], c = queue_cnt[tid];
-                const uint2 ww = queue_w[tid];
-                ttx = e.x, tty = e.y, ttz = e.z, u2 = (uint32_t)e.w;
-                ssx = c.x, ssy = c.y, ssz = c.z;
-                wt = (Cell)ww.x, ws = (Cell)ww.y;
+                const int4 e = queue[tid];
+                const uint32_t ex = (uint32_t)e.x, ey = (uint32_t)e.y, off = ey >> 16;
+                ttx = (int)(ex & 0xFFFFu), tty = (int)(ex >> 16), ttz = (int)(ey & 0xFFFFu);
+                ssx = ttx + (int)(off % 3u) - 1, ssy = tty + (int)((off / 3u) % 3u) - 1;
+                ssz = D == 3 ? ttz + (int)(off / 9u) - 1 : 0;
+                u2 = (uint32_t)e.z;
+                wt = kWideCell ? (Cell)(uint32_t)e.w : (Cell)((uint32_t)e.w & 0xFFFFu);
+                ws = kWideCell ? (Cell)queue_ws[tid] : (Cell)((uint32_t)e.w >> 16);
                 lt = label_of(wt), ls = label_of(ws);
             }
         } else if (mine && lt != ls && lt >= 0 && ls >= 0) {
