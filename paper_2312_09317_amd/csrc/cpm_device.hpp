@@ -103,21 +103,23 @@ __device__ __forceinline__ int type_of_word(const A &a, char32_t word, int)
 {
     return (int)(((uint32_t)word >> 20) & 15u);
 }
+// Type of a label from the cell-type array (obstacle: the obstacle type).
+// Both values are read and one of them kept: a choice between the two
+// addresses, one inside the argument block, makes the compiler copy the
+// whole block to scratch memory.  Entry 0 (medium) stands in for obstacles.
 template <typename A>
-__device__ __forceinline__ int type_of_word(const A &a, int32_t, int label)
+__device__ __forceinline__ int type_of_label(const A &a, int label)
 {
-    return label < 0 ? a.obstacle_type : a.cell_type[label];
+    const int to = a.obstacle_type;
+    const int tc = a.cell_type[label < 0 ? 0 : label];
+    return label < 0 ? to : tc;
 }
 template <typename A>
-__device__ __forceinline__ int type_of_word(const A &a, uint16_t, int label)
-{
-    return label < 0 ? a.obstacle_type : a.cell_type[label];
-}
+__device__ __forceinline__ int type_of_word(const A &a, int32_t, int label) { return type_of_label(a, label); }
 template <typename A>
-__device__ __forceinline__ int type_of_word(const A &a, char16_t, int label)
-{
-    return label < 0 ? a.obstacle_type : a.cell_type[label];
-}
+__device__ __forceinline__ int type_of_word(const A &a, uint16_t, int label) { return type_of_label(a, label); }
+template <typename A>
+__device__ __forceinline__ int type_of_word(const A &a, char16_t, int label) { return type_of_label(a, label); }
 
 // Division by a divisor fixed for a whole workgroup: q = floor(n / d) as one
 // multiply-high, exact whenever n * d < 2^32 (m = floor((2^32 - 1) / d) + 1

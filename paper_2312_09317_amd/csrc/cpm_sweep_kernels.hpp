@@ -895,23 +895,34 @@ __global__ void __launch_bounds__(kBlock) tile_sweep_kernel(SweepArgs a, uint32_
     sweep_tile<Cell, D, ACT, SINGLE, K1, LAYOUT, EXT>(a, tile, mcs, alpha, parity);
 }
 
-// Packed words serve large multi-type lattices, whose sweeps wait on HBM:
-// more waves per SIMD hide more of that latency than the registers the
-// limit takes away cost.  A 3D multi-type sweep in place holds the 26
-// neighbour words and their J entries at once (loaded in one round); its
-// cap is lower, so that they stay in registers.
+// Packed words serve large multi-type lattices and Act models, whose sweeps
+// wait on memory: more waves per SIMD hide more of that latency, up to the
+// point where the register budget the cap leaves (512 / waves per lane)
+// forces spills to scratch memory.  Each cap below is the largest that
+// leaves its instantiations spill-free: a 3D multi-type sweep in place holds
+// the 26 neighbour words and their J entries at once (loaded in one round);
+// k > 1 attempts per activation keep the attempt loop's state; 3D Act terms
+// and the persistence / chemotaxis terms of 2D Act models need more than 64
+// registers.
 #ifndef CPM_PACKED_WAVES
 #define CPM_PACKED_WAVES 8
 #endif
 #ifndef CPM_PACKED_WAVES_3D
 #define CPM_PACKED_WAVES_3D 3
 #endif
-template <int D, bool SINGLE, int LAYOUT>
+template <typename Word, int D, bool ACT, bool SINGLE, bool K1, int LAYOUT, bool EXT>
 struct PackedWaves {
-    static constexpr int value = D == 3 && !SINGLE && LAYOUT == kDirect ? CPM_PACKED_WAVES_3D : CPM_PACKED_WAVES;
+    static constexpr bool kWordAct = std::is_same<Word, char32_t>::value;
+    static constexpr int value =
+        !K1 ? (ACT && (D == 3 || (SINGLE && EXT)) ? 3 : 4)
+        : D == 3 && LAYOUT == kDirect && !SINGLE ? (ACT && !kWordAct ? 2 : CPM_PACKED_WAVES_3D)
+        : D == 3 && ACT ? (SINGLE ? 5 : 6)
+        : D == 2 && ACT && (EXT || (LAYOUT == kDirect && !kWordAct)) ? 6
+        : CPM_PACKED_WAVES;
 };
 template <typename Word, int D, bool ACT, bool SINGLE, bool K1, int LAYOUT, bool EXT>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PackedWaves<D, SINGLE, LAYOUT>::value)))
+__global__ void __launch_bounds__(kBlock)
+__attribute__((amdgpu_waves_per_eu(PackedWaves<Word, D, ACT, SINGLE, K1, LAYOUT, EXT>::value)))
 tile_sweep_kernel_packed(SweepArgs a, uint32_t mcs, uint32_t alpha, int parity)
 {
     const int tile = xcd_tile(a.tg, blockIdx.x);

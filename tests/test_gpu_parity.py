@@ -128,6 +128,25 @@ def test_act_sub_and_attempts(torch_cuda, ndim, dims, s, k):
     assert st.stats[2] > 0 and (st.act > 0).any()
 
 
+@pytest.mark.parametrize("ndim,dims,s,k,layout", [
+    (2, (32, 24, 1), 2, 1, "box"), (2, (32, 24, 1), 2, 4, "auto"), (2, (36, 36, 1), 3, 9, "auto"),
+    (3, (16, 12, 12), 2, 1, "in_place"), (3, (16, 12, 12), 2, 1, "full_rows"), (3, (16, 12, 12), 2, 1, "box"),
+    (3, (16, 16, 8), 2, 8, "auto"), (3, (12, 12, 12), 3, 27, "auto"),
+])
+def test_single_type_act(torch_cuda, ndim, dims, s, k, layout):
+    # every cell of one type with the Act term: label-type-activity words,
+    # the type's J rows read once per workgroup, in each layout and with
+    # several attempts per activation (each instantiation built with its own
+    # register budget)
+    w = _multi(dims, ndim, seed=71 + 5 * s + k, s=s, k=k, act=True, obstacles=0.03, T=20.0)
+    w.cell_type = np.where(w.cell_type > 0, 1, 0).astype(np.int32)
+    lab = w.lattice
+    w.act = np.where(lab > 0, w.max_act[w.cell_type[np.maximum(lab, 0)]], 0).astype(np.uint8)
+    st, sim = run_both(torch_cuda, w, 6, layout=layout)
+    assert_same(st, sim, torch_cuda)
+    assert st.stats[2] > 0 and (st.act > 0).any()
+
+
 @pytest.mark.parametrize("ndim,dims,s,k", [(2, (32, 32, 1), 4, 16), (3, (12, 12, 12), 3, 27)])
 def test_many_own_copies(torch_cuda, ndim, dims, s, k):
     # labels drawn per site and a hot, weakly constrained model: nearly every
