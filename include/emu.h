@@ -89,9 +89,9 @@ int emu_get_params(emu_handle *h, float *d_params, void *stream);
  * deviations must be positive; not checked on the device), or fit it to a
  * data set: column means and population standard deviations of x (n x 6) and
  * targets (n x 8), in fp64 sums; a column with no spread gets 1.  Target
- * columns j with bit j of log_mask set get off_j = (column mean) / 100 (1 if
- * the mean is not positive) and are fitted as log(t + off_j); targets must
- * then exceed -off_j. */
+ * columns j with bit j of log_mask set get off_j = G_j / 100, G_j the
+ * geometric mean of the column's positive values (off_j = 1 if it has none),
+ * and are fitted as log(t + off_j); targets must then exceed -off_j. */
 int emu_set_norm(emu_handle *h, const float *d_norm, void *stream);
 int emu_get_norm(emu_handle *h, float *d_norm, void *stream);
 int emu_fit_norm(emu_handle *h, const float *d_x, const float *d_targets, int32_t n, int32_t log_mask,

@@ -250,8 +250,11 @@ __device__ void block_sums(double &s1, double &s2, double *r1, double *r2)
 
 // Column means and population standard deviations (FP64 sums) of the inputs
 // (6 columns) and the targets (8 columns), the targets of the columns set in
-// log_mask first mapped to log(t + off) with off = (column mean of t) / 100
-// (1 if that is not positive): norm = [mean_x, sd_x, mean_t, sd_t, off_t].
+// log_mask first mapped to log(t + off) with off = G / 100, G the geometric
+// mean of the column's positive values (off = 1 if it has none):
+// norm = [mean_x, sd_x, mean_t, sd_t, off_t].  The offset follows the bulk
+// of a column that spans decades, where its arithmetic mean follows the
+// largest values.
 // A column with zero spread gets sd = 1.
 __global__ void __launch_bounds__(256) fit_norm_kernel(const float *x, const float *t, int n, int log_mask,
                                                        float *norm)
@@ -265,11 +268,16 @@ __global__ void __launch_bounds__(256) fit_norm_kernel(const float *x, const flo
     const bool logt = !is_x && ((log_mask >> c) & 1);
     float off = 0.f;
     if (logt) {
-        double s1 = 0.0, s2 = 0.0;
-        for (int i = threadIdx.x; i < n; i += 256) s1 += (double)src[(size_t)i * w + c];
+        double s1 = 0.0, s2 = 0.0;  // sum of log t and count over t > 0
+        for (int i = threadIdx.x; i < n; i += 256) {
+            const float v = src[(size_t)i * w + c];
+            if (v > 0.f) {
+                s1 += log((double)v);
+                s2 += 1.0;
+            }
+        }
         block_sums(s1, s2, r1, r2);
-        const double m = s1 / n;
-        off = m > 0.0 ? (float)(m / 100.0) : 1.f;
+        off = s2 > 0.0 ? (float)(exp(s1 / s2) / 100.0) : 1.f;
     }
     double s1 = 0.0, s2 = 0.0;
     for (int i = threadIdx.x; i < n; i += 256) {

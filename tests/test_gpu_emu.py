@@ -237,7 +237,7 @@ def test_errors(torch):
 
 def test_log_targets(torch):
     # targets spanning decades, some zero: columns in the mask are learnt as
-    # log(t + off), off = column mean / 100
+    # log(t + off), off = (geometric mean of the column's positive values) / 100
     emu, e = _emu(torch)
     W, b = mlp.init(seed=17)
     e.set_params(emu.pack(W, b))
@@ -249,7 +249,8 @@ def test_log_targets(torch):
     e.fit_norm(x, t, log_mask=mask)
     norm = e.norm().cpu().numpy().astype(np.float64)
     x32, t32 = x.astype(np.float32).astype(np.float64), t.astype(np.float32).astype(np.float64)
-    off = np.where([(mask >> j) & 1 for j in range(8)], t32.mean(0) / 100.0, 0.0)
+    geo = np.array([np.exp(np.log(c[c > 0]).mean()) for c in t32.T])
+    off = np.where([(mask >> j) & 1 for j in range(8)], geo / 100.0, 0.0)
     u = np.where(off > 0, np.log(t32 + np.where(off > 0, off, 1.0)), t32)
     np.testing.assert_allclose(norm[:12], np.concatenate([x32.mean(0), x32.std(0)]), rtol=1e-6, atol=1e-6)
     np.testing.assert_allclose(norm[28:], off, rtol=1e-6)
