@@ -164,7 +164,7 @@ struct JRows {
 // Per-workgroup LDS copies of the model tables an attempt reads: J
 // (multi-type models), the Act log table and the per-type parameters.
 struct SharedTables {
-    const int64_t *J;
+    const int32_t *J;  // J in 2^-16 fixed point: |J| < 2^15, so each entry fits 32 bits
     const int64_t *lg;
     const TypeParams *tp;
 };
@@ -398,7 +398,7 @@ __device__ __forceinline__ void sweep_tile(const A &a, int tile, uint32_t mcs, u
     __shared__ int4 queue[kQ];
     __shared__ int4 queue_cnt[COMPACT ? 1 : kQ];
     __shared__ uint32_t queue_ws[COMPACT && kWideCell ? kBlock : 1];
-    __shared__ int64_t j_lds[SINGLE ? 1 : kMaxTypes * kMaxTypes];
+    __shared__ int32_t j_lds[SINGLE ? 1 : kMaxTypes * kMaxTypes];
     // the Act log table: 16-bit label-activity words index its first 32 entries
     constexpr int kLgLds = std::is_same<Cell, char16_t>::value ? kMaxAct16Activity + 1 : 256;
     __shared__ int64_t lg_lds[ACT ? kLgLds : 1];
@@ -458,7 +458,7 @@ __device__ __forceinline__ void sweep_tile(const A &a, int tile, uint32_t mcs, u
         const bool j_mine = !SINGLE && tid < a.n_types * kMaxTypes;
         const bool lg_mine = ACT && tid < min(a.lg_entries, kLgLds);
         const bool tp_mine = tid < kTpWords;
-        const int64_t jv = j_mine ? mdl->J[tid] : 0;
+        const int32_t jv = j_mine ? (int32_t)mdl->J[tid] : 0;
         const int64_t lgv = lg_mine ? mdl->LG[tid] : 0;
         const int4 tpv = tp_mine ? reinterpret_cast<const int4 *>(mdl->lam_v)[tid] : make_int4(0, 0, 0, 0);
         if (j_mine) j_lds[tid] = jv;
@@ -900,23 +900,25 @@ __global__ void __launch_bounds__(kBlock) tile_sweep_kernel(SweepArgs a, uint32_
 // point where the register budget the cap leaves (512 / waves per lane)
 // forces spills to scratch memory.  Each cap below is the largest that
 // leaves its instantiations spill-free: a 3D multi-type sweep in place holds
-// the 26 neighbour words and their J entries at once (loaded in one round);
-// k > 1 attempts per activation keep the attempt loop's state; 3D Act terms
-// and the persistence / chemotaxis terms of 2D Act models need more than 64
+// the 26 neighbour words and their J entries at once (loaded in one round;
+// with the Act term, the words' activities too); k > 1 attempts per
+// activation keep the attempt loop's state; 3D Act terms, the persistence /
+// chemotaxis terms in 3D and those of 2D Act models need more than 64
 // registers.
 #ifndef CPM_PACKED_WAVES
 #define CPM_PACKED_WAVES 8
 #endif
 #ifndef CPM_PACKED_WAVES_3D
-#define CPM_PACKED_WAVES_3D 3
+#define CPM_PACKED_WAVES_3D 5
 #endif
 template <typename Word, int D, bool ACT, bool SINGLE, bool K1, int LAYOUT, bool EXT>
 struct PackedWaves {
     static constexpr bool kWordAct = std::is_same<Word, char32_t>::value;
     static constexpr int value =
         !K1 ? (ACT && (D == 3 || (SINGLE && EXT)) ? 3 : 4)
-        : D == 3 && LAYOUT == kDirect && !SINGLE ? (ACT && !kWordAct ? 2 : CPM_PACKED_WAVES_3D)
+        : D == 3 && LAYOUT == kDirect && !SINGLE ? (kWordAct ? CPM_PACKED_WAVES_3D : ACT ? 4 : 6)
         : D == 3 && ACT ? (SINGLE ? 5 : 6)
+        : D == 3 && EXT ? 6
         : D == 2 && ACT && (EXT || (LAYOUT == kDirect && !kWordAct)) ? 6
         : CPM_PACKED_WAVES;
 };
